@@ -1,0 +1,202 @@
+"""FP64 CPU oracle (test infrastructure).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It wraps ``oracle.c`` (plain C, double precision), which
+shares no code with the GPU library.  See the header of ``oracle.c`` for the
+method and the paper passages each step follows.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ST_INVALID_STRUT = 1
+ST_NON_ELLIPTIC = 2
+ST_LOOP = 4
+ST_TOPOLOGY = 8
+ST_ISOLATED = 16
+ST_VALENCE = 32
+ST_DUPLICATE = 64
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc into liboracle.so (next to the source)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=gnu11", "-shared", "-fPIC", "-pthread", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    lib.orc_run.restype = P
+    lib.orc_run.argtypes = [ctypes.c_int64, ctypes.c_int64] + [P] * 6 + [ctypes.c_int, ctypes.c_int]
+    lib.orc_free.argtypes = [P]
+    lib.orc_sizes.argtypes = [P, P]
+    lib.orc_nodes.argtypes = [P, P, P]
+    lib.orc_vertices.argtypes = [P, P, P]
+    lib.orc_arcs.argtypes = [P, P, P]
+    lib.orc_loops.argtypes = [P, P, P, P]
+    lib.orc_adjacency.argtypes = [P, P, P]
+    lib.orc_mesh.argtypes = [P] * 8
+    lib.orc_ellipse.restype = ctypes.c_int
+    lib.orc_ellipse.argtypes = [P, ctypes.c_double, P, ctypes.c_double, P, ctypes.c_double, P]
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclasses.dataclass
+class OracleResult:
+    k: int
+    n_nodes: int
+    n_struts: int
+    # per node
+    status: np.ndarray  # int32 [N]
+    valence: np.ndarray
+    nv: np.ndarray
+    ne: np.ndarray
+    nc: np.ndarray
+    nmesh: np.ndarray
+    nfan: np.ndarray
+    margin: np.ndarray  # float64 [N]
+    margin_kind: np.ndarray  # int32 [N] (MK_* codes of oracle.c)
+    # meta-mesh (node order; per-node offsets from nv / ne)
+    vert_off: np.ndarray
+    vert_name: np.ndarray  # uint32 [V]
+    vert_w: np.ndarray  # float64 [V,3] local to the node
+    arc_off: np.ndarray
+    arc_int: np.ndarray  # int32 [E,7]: p q vs ve nseg contour full
+    arc_dbl: np.ndarray  # float64 [E,11]: o a b t1 t2 (local)
+    loop_off: np.ndarray  # int64 [2S+1]
+    loop_arc: np.ndarray
+    loop_dir: np.ndarray
+    adj_off: np.ndarray
+    adj: np.ndarray
+    # mesh
+    mesh: np.ndarray  # float64 [M,3]
+    tris: np.ndarray  # int64 [T,3]; bands (strut order) then fans (node order)
+    mesh_off: np.ndarray  # int64 [N+1]
+    band_off: np.ndarray  # int64 [S+1]
+    fan_off: np.ndarray  # int64 [N+1] (relative to the first fan triangle)
+    strut_margin: np.ndarray
+    strut_status: np.ndarray
+
+    @property
+    def n_band(self) -> int:
+        return int(self.band_off[-1])
+
+    @property
+    def ok(self) -> np.ndarray:
+        return self.status == 0
+
+
+def run(lat, k: int, threads: int | None = None) -> OracleResult:
+    """Meta-mesh and triangulate ``lat`` (a latgen.Lattice) at k segments per turn."""
+    lib = _load()
+    if threads is None:
+        threads = os.cpu_count() or 1
+    x = np.ascontiguousarray(lat.x, dtype=np.float32)
+    y = np.ascontiguousarray(lat.y, dtype=np.float32)
+    z = np.ascontiguousarray(lat.z, dtype=np.float32)
+    r = np.ascontiguousarray(lat.radius, dtype=np.float32)
+    sa = np.ascontiguousarray(lat.strut_a, dtype=np.int32)
+    sb = np.ascontiguousarray(lat.strut_b, dtype=np.int32)
+    N, S = x.shape[0], sa.shape[0]
+    h = lib.orc_run(N, S, _p(x), _p(y), _p(z), _p(r), _p(sa), _p(sb), int(k), int(threads))
+    if not h:
+        raise ValueError("oracle rejected the lattice (strut index out of range or k < 1)")
+    try:
+        sz = np.zeros(7, np.int64)
+        lib.orc_sizes(h, _p(sz))
+        nV, nE, nC, nM, nB, nF, nL = (int(v) for v in sz)
+        cnt = np.zeros((N, 8), np.int32)
+        mg = np.zeros(N, np.float64)
+        lib.orc_nodes(h, _p(cnt), _p(mg))
+        vn = np.zeros(nV, np.uint32)
+        vw = np.zeros((nV, 3), np.float64)
+        lib.orc_vertices(h, _p(vn), _p(vw))
+        ai = np.zeros((nE, 7), np.int32)
+        ad = np.zeros((nE, 11), np.float64)
+        lib.orc_arcs(h, _p(ai), _p(ad))
+        lo = np.zeros(2 * S + 1, np.int64)
+        la = np.zeros(max(nL, 1), np.int32)
+        ld = np.zeros(max(nL, 1), np.int32)
+        lib.orc_loops(h, _p(lo), _p(la), _p(ld))
+        aoff = np.zeros(N + 1, np.int64)
+        adj = np.zeros(max(int(2 * S), 1), np.int32)
+        lib.orc_adjacency(h, _p(aoff), _p(adj))
+        mesh = np.zeros((nM, 3), np.float64)
+        tris = np.zeros((nB + nF, 3), np.int64)
+        moff = np.zeros(N + 1, np.int64)
+        boff = np.zeros(S + 1, np.int64)
+        foff = np.zeros(N + 1, np.int64)
+        smg = np.zeros(S, np.float64)
+        sst = np.zeros(S, np.int32)
+        lib.orc_mesh(h, _p(mesh), _p(tris), _p(moff), _p(boff), _p(foff), _p(smg), _p(sst))
+    finally:
+        lib.orc_free(h)
+    off = lambda c: np.concatenate([[0], np.cumsum(c.astype(np.int64))])  # noqa: E731
+    return OracleResult(
+        k=int(k), n_nodes=N, n_struts=S,
+        status=cnt[:, 0].copy(), valence=cnt[:, 1].copy(), nv=cnt[:, 2].copy(), ne=cnt[:, 3].copy(),
+        nc=cnt[:, 4].copy(), nmesh=cnt[:, 5].copy(), nfan=cnt[:, 6].copy(), margin=mg,
+        margin_kind=cnt[:, 7].copy(),
+        vert_off=off(cnt[:, 2]), vert_name=vn, vert_w=vw,
+        arc_off=off(cnt[:, 3]), arc_int=ai, arc_dbl=ad,
+        loop_off=lo, loop_arc=la[:nL], loop_dir=ld[:nL], adj_off=aoff, adj=adj[: 2 * S],
+        mesh=mesh, tris=tris, mesh_off=moff, band_off=boff, fan_off=foff,
+        strut_margin=smg, strut_status=sst,
+    )
+
+
+def ellipse(c, r0, cp, rp, cq, rq):
+    """Eq. 7 ellipse of strut (c -> cp) cut by its auxiliary plane with strut
+    (c -> cq).  Returns (o, a, b) local to c, or None if not an ellipse."""
+    lib = _load()
+    c = np.ascontiguousarray(c, np.float64)
+    cp = np.ascontiguousarray(cp, np.float64)
+    cq = np.ascontiguousarray(cq, np.float64)
+    out = np.zeros(9, np.float64)
+    rc = lib.orc_ellipse(_p(c), float(r0), _p(cp), float(rp), _p(cq), float(rq), _p(out))
+    if rc < 0:
+        return None
+    return out[0:3], out[3:6], out[6:9]
+
+
+# ---------------------------------------------------------------------------
+# mesh-level quantities (plain numpy on the oracle's output)
+
+
+def mesh_area(verts: np.ndarray, tris: np.ndarray) -> float:
+    v = verts[tris]
+    return float(0.5 * np.linalg.norm(np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0]), axis=1).sum())
+
+
+def mesh_volume(verts: np.ndarray, tris: np.ndarray) -> float:
+    ref = verts.mean(axis=0) if len(verts) else np.zeros(3)
+    v = verts[tris] - ref
+    return float(np.einsum("ij,ij->i", v[:, 0], np.cross(v[:, 1], v[:, 2])).sum() / 6.0)
