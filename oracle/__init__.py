@@ -54,7 +54,7 @@ def _load():
     lib.orc_free.argtypes = [P]
     lib.orc_sizes.argtypes = [P, P]
     lib.orc_nodes.argtypes = [P, P, P]
-    lib.orc_vertices.argtypes = [P, P, P]
+    lib.orc_vertices.argtypes = [P, P, P, P]
     lib.orc_arcs.argtypes = [P, P, P]
     lib.orc_loops.argtypes = [P, P, P, P]
     lib.orc_adjacency.argtypes = [P, P, P]
@@ -88,6 +88,7 @@ class OracleResult:
     vert_off: np.ndarray
     vert_name: np.ndarray  # uint32 [V]
     vert_w: np.ndarray  # float64 [V,3] local to the node
+    vert_cond: np.ndarray  # float64 [V,2] root separation, runner-up gap (rho units)
     arc_off: np.ndarray
     arc_int: np.ndarray  # int32 [E,7]: p q vs ve nseg contour full
     arc_dbl: np.ndarray  # float64 [E,11]: o a b t1 t2 (local)
@@ -138,7 +139,8 @@ def run(lat, k: int, threads: int | None = None) -> OracleResult:
         lib.orc_nodes(h, _p(cnt), _p(mg))
         vn = np.zeros(nV, np.uint32)
         vw = np.zeros((nV, 3), np.float64)
-        lib.orc_vertices(h, _p(vn), _p(vw))
+        vc = np.zeros((nV, 2), np.float64)
+        lib.orc_vertices(h, _p(vn), _p(vw), _p(vc))
         ai = np.zeros((nE, 7), np.int32)
         ad = np.zeros((nE, 11), np.float64)
         lib.orc_arcs(h, _p(ai), _p(ad))
@@ -165,7 +167,7 @@ def run(lat, k: int, threads: int | None = None) -> OracleResult:
         status=cnt[:, 0].copy(), valence=cnt[:, 1].copy(), nv=cnt[:, 2].copy(), ne=cnt[:, 3].copy(),
         nc=cnt[:, 4].copy(), nmesh=cnt[:, 5].copy(), nfan=cnt[:, 6].copy(), margin=mg,
         margin_kind=cnt[:, 7].copy(),
-        vert_off=off(cnt[:, 2]), vert_name=vn, vert_w=vw,
+        vert_off=off(cnt[:, 2]), vert_name=vn, vert_w=vw, vert_cond=vc,
         arc_off=off(cnt[:, 3]), arc_int=ai, arc_dbl=ad,
         loop_off=lo, loop_arc=la[:nL], loop_dir=ld[:nL], adj_off=aoff, adj=adj[: 2 * S],
         mesh=mesh, tris=tris, mesh_off=moff, band_off=boff, fan_off=foff,

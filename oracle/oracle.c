@@ -107,6 +107,7 @@ typedef struct {
 typedef struct {
     uint32_t name;
     V3 w;
+    double sep, gap; /* root separation and runner-up gap (units of rho) */
 } Vert;
 
 typedef struct {
@@ -558,6 +559,7 @@ static void node_compute(Ctx *X, int64_t n)
             if (nv == vcap) { vcap *= 2; verts = realloc(verts, sizeof(Vert) * vcap); }
             verts[nv].name = nm;
             verts[nv].w = conic_pt(A->o, A->a, A->b, 0.0);
+            verts[nv].sep = verts[nv].gap = 1e300;
             ++nv;
             if (A->p == 0) { /* dummy position depends on the strut frame */
                 LOWER(L->frame_gap[A->q], MK_FRAME);
@@ -588,6 +590,7 @@ static void node_compute(Ctx *X, int64_t n)
                 if (nv == vcap) { vcap *= 2; verts = realloc(verts, sizeof(Vert) * vcap); }
                 verts[nv].name = nm;
                 verts[nv].w = roots[root];
+                verts[nv].sep = sep;
                 ++nv;
                 /* gap to the runner-up strut at the tie point */
                 double ptie = Pval(L, tr[0], roots[root]);
@@ -597,6 +600,7 @@ static void node_compute(Ctx *X, int64_t n)
                     double ps = Pval(L, s2, roots[root]);
                     if (ps > best) best = ps;
                 }
+                verts[nv - 1].gap = (ptie - best) / L->rho;
                 LOWER((ptie - best) / L->rho, MK_GAP);
             }
         }
@@ -888,17 +892,24 @@ static void node_compute(Ctx *X, int64_t n)
             for (int li = loop_off[m - 1]; li < loop_off[m]; ++li) {
                 Arc *A = &arcs[loop_arc[li]];
                 int d = loop_dir[li];
-                /* loop-start vertex then interior points in loop direction */
-                int sv = d > 0 ? A->vs : A->ve;
-                lv_idx[pos++] = sv;
-                for (int j = 1; j < A->nseg; ++j) {
+                /* loop-start vertex then interior points in loop direction;
+                 * on a tangency circle phi is the circle parameter itself
+                 * (the circle is parametrised in the strut frame), elsewhere
+                 * it is measured from the point */
+                for (int j = 0; j < A->nseg; ++j) {
                     int ii = d > 0 ? j : A->nseg - j;
-                    lv_idx[pos++] = INTERIOR(A, ii);
+                    int mi = j == 0 ? (d > 0 ? A->vs : A->ve) : INTERIOR(A, ii);
+                    lv_idx[pos] = mi;
+                    if (A->p == 0) {
+                        double t = A->t1 + (A->t2 - A->t1) * ii / A->nseg;
+                        if (t >= TWO_PI) t -= TWO_PI;
+                        if (t > M_PI) t -= TWO_PI;
+                        lv_phi[pos] = t;
+                    } else {
+                        lv_phi[pos] = phi_of(L, m, mk(mw[3 * mi], mw[3 * mi + 1], mw[3 * mi + 2]));
+                    }
+                    ++pos;
                 }
-            }
-            for (int i = b0; i < pos; ++i) {
-                int mi = lv_idx[i];
-                lv_phi[i] = phi_of(L, m, mk(mw[3 * mi], mw[3 * mi + 1], mw[3 * mi + 2]));
             }
             /* the loop must be a graph over phi: strictly increasing, one turn */
             double wind = 0.0, minstep = 1e300;
@@ -1141,14 +1152,17 @@ void orc_nodes(const Ctx *X, int32_t *cnt, double *margin)
     }
 }
 
-/* meta-mesh vertices, concatenated in node order: name, local position */
-void orc_vertices(const Ctx *X, uint32_t *name, double *w)
+/* meta-mesh vertices, concatenated in node order: name, local position,
+ * conditioning (root separation, runner-up gap; both in units of rho) */
+void orc_vertices(const Ctx *X, uint32_t *name, double *w, double *cond)
 {
     int64_t o = 0;
     for (int64_t i = 0; i < X->N; ++i) {
         const NodeRes *R = &X->nodes[i];
         for (int j = 0; j < R->nv; ++j, ++o) {
             name[o] = R->verts[j].name;
+            cond[2 * o] = R->verts[j].sep;
+            cond[2 * o + 1] = R->verts[j].gap;
             w[3 * o] = R->verts[j].w.x; w[3 * o + 1] = R->verts[j].w.y; w[3 * o + 2] = R->verts[j].w.z;
         }
     }
