@@ -1,0 +1,180 @@
+"""Benchmark: meta-meshing + triangulation of the BCC 64^3 lattice on one GPU.
+
+One step is the whole path on one synthetic lattice already resident in HBM:
+validation and adjacency (lm_prepare), per-node meta-meshing and counts,
+prefix sums, the fill pass (meta-mesh, mesh vertices, hole fans) and the
+strut bands (lm_forward), into preallocated device buffers.
+
+Prints one JSON line (see README of the benchmark contract in the design
+notes): struts/s as the value, triangles/s beside it, the roofline entry of
+the dominant kernel measured with HIP events inside the library, and the
+FP64 CPU oracle timed on a bounded sample of the same lattice family.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def algorithmic_bytes(lat, t):
+    """Bytes the method must move once per step: read the lattice, write the
+    meta-mesh (16 B per vertex: name + xyz; 56 B per arc: o, a, b, t1, t2,
+    labels, end vertices, node) and the indexed mesh (12 B per vertex, 12 B
+    per triangle)."""
+    read = 16 * lat.n_nodes + 8 * lat.n_struts
+    meta = 16 * t["n_vertices"] + 56 * t["n_arcs"]
+    mesh = 12 * t["n_mesh_vertices"] + 12 * t["n_triangles"]
+    return read, meta, mesh
+
+
+def fill_kernel_bytes(lat, t):
+    """Algorithmic bytes of the FP32 fill pass: it reads the lattice and
+    writes the meta-mesh, the mesh vertices and the hole-fan triangles (the
+    strut bands are written by the band kernel)."""
+    read = 16 * lat.n_nodes + 8 * lat.n_struts
+    return read + 16 * t["n_vertices"] + 56 * t["n_arcs"] + 12 * t["n_mesh_vertices"] + 12 * t["n_fan_triangles"]
+
+
+def cpu_baseline(scale: int, k: int, threads: int):
+    import latgen
+    import oracle
+
+    oracle.build(force=False)
+    lat = latgen.config(2, scale=scale, seed=1)
+    t0 = time.perf_counter()
+    R = oracle.run(lat, k, threads=threads)
+    dt = time.perf_counter() - t0
+    return {
+        "value": lat.n_struts / dt,
+        "unit": "struts/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"BCC {scale}^3 cells ({lat.n_nodes} nodes, {lat.n_struts} struts), k={k}, same seeded "
+        f"distributions as the GPU workload, meta-mesh + triangulation, FP64 C oracle, {dt:.1f} s wall",
+        "triangles_per_s": len(R.tris) / dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--k", type=int, default=16)
+    ap.add_argument("--scale", type=int, default=64, help="BCC cells per side (64 = the benchmarked lattice)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-scale", type=int, default=48)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is in the "
+              "design notes and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import latgen
+    from paper_2405_15197_amd.latmesh import Mesher, lm_get_profile, lm_prepare, lm_read_totals, lm_set_profiling
+
+    print(f"[bench] building BCC {args.scale}^3 lattice", file=sys.stderr, flush=True)
+    lat = latgen.config(2, scale=args.scale, seed=1)
+    M = Mesher(lat)
+    t = M.count(args.k)
+    buf = M.alloc(t, meta=True)
+    out = M.outputs(buf)
+    from paper_2405_15197_amd.latmesh import lm_forward
+
+    def step():
+        lm_prepare(M.plan)
+        lm_forward(M.plan, args.k, out)
+
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lm_read_totals(M.plan)  # raises on device-side errors
+    lm_get_profile(M.plan)  # drop anything recorded so far
+    lm_set_profiling(M.plan, True)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    start.record()
+    for _ in range(args.steps):
+        step()
+    end.record()
+    torch.cuda.synchronize()
+    ms_total = start.elapsed_time(end)
+    prof = lm_get_profile(M.plan)
+    lm_set_profiling(M.plan, False)
+    tot = lm_read_totals(M.plan).as_dict()
+    assert tot == t or all(tot[key] == t[key] for key in t if key != "n_fp64_nodes"), (tot, t)
+    ms = ms_total / args.steps
+    struts_s = lat.n_struts / (ms * 1e-3)
+    tris_s = tot["n_triangles"] / (ms * 1e-3)
+    read, meta, mesh = algorithmic_bytes(lat, tot)
+    phase_ms = {p: (v[0] / max(v[1], 1)) for p, v in prof.items()}
+    dominant = max(phase_ms, key=phase_ms.get)
+    fb = fill_kernel_bytes(lat, tot)
+    kern_ms = phase_ms["fill_fp32"]
+    achieved = fb / (kern_ms * 1e-3) / 1e9
+    res = {
+        "metric": "struts meta-meshed/s (and triangles emitted/s) at resolution k",
+        "value": struts_s,
+        "unit": "struts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 for ill-conditioned nodes)",
+        "data": "synthetic (seeded BCC lattice)",
+        "config": {
+            "workload": f"BCC {args.scale}^3 cells, {lat.n_nodes} nodes, {lat.n_struts} struts, node radii "
+            f"U[0.05,0.12], jitter 0.05, k={args.k}, stored meta-mesh + indexed mesh",
+            "k": args.k,
+            "nodes": lat.n_nodes,
+            "struts": lat.n_struts,
+        },
+        "triangles_per_s": tris_s,
+        "triangles": tot["n_triangles"],
+        "mesh_vertices": tot["n_mesh_vertices"],
+        "fp64_nodes": tot["n_fp64_nodes"],
+        "path_algorithmic_bytes": read + meta + mesh,
+        "path_hbm_frac": (read + meta + mesh) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "phase_ms": phase_ms,
+        "dominant_phase": dominant,
+        "roofline": {
+            "kernel": "fill_fp32 (k_node32<fill>)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_launch": fb,
+            "ms_per_launch": kern_ms,
+        },
+    }
+    M.close()
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        print(f"[bench] CPU oracle baseline on {threads} threads", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(args.cpu_scale, args.k, threads)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * latmesh: meta-meshing and arc-subdivision triangulation of strut lattices
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Zou & Gao, "Warp-centric GPU meta-meshing and fast triangulation of
+ * billion-scale lattice structures".  A lattice is a set of nodes (centre,
+ * nodal-sphere radius) joined by struts; every strut is the round cone tangent
+ * to the spheres of its two end nodes (Sec. 4.1).  Around each node the
+ * incident struts are intersected pairwise on auxiliary planes into elliptic
+ * arcs (Sec. 4.3.1, Eq. 7), trimmed against the node's other struts
+ * (Eqs. 8-9), and assembled into the node's meta-mesh: vertices, arcs, one
+ * arc loop per strut end and hole contours bounded by circular arcs.  The
+ * meta-mesh is then subdivided at k segments per full turn (Eqs. 11-12), each
+ * strut band is triangulated between its two end loops and each hole is
+ * filled by a fan from its projected barycentre (Sec. 5, Eq. 13).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are DEVICE pointers owned by the caller; the library
+ *     reads inputs and writes outputs through them and keeps no reference
+ *     after the call returns, except that a plan keeps its lattice pointers
+ *     until lm_plan_destroy (the caller must keep them alive and unchanged).
+ *   - Work is ordered on the plan's HIP stream.  Calls that return host
+ *     values (lm_count, lm_read_totals) synchronise that stream.
+ *   - Functions return LM_OK (0) or a negative LM_ERR_* code and never throw.
+ *     Problems with single nodes do not fail a call: they are reported per
+ *     node as LM_NODE_* bits and such nodes emit nothing.
+ *   - A plan is not thread safe; use one plan per host thread.
+ */
+#ifndef LATMESH_H
+#define LATMESH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define LM_OK 0
+#define LM_ERR_INVALID_ARG (-1)    /* null pointer, negative size, bad k */
+#define LM_ERR_BAD_LATTICE (-2)    /* strut endpoint index outside [0, n_nodes) */
+#define LM_ERR_CAPACITY (-3)       /* an output buffer is smaller than the totals */
+#define LM_ERR_UNSUPPORTED (-4)    /* size beyond what this build handles */
+#define LM_ERR_HIP (-5)            /* a HIP runtime call failed */
+#define LM_ERR_STATE (-6)          /* call out of order (e.g. fill before count) */
+#define LM_ERR_INTERNAL (-7)       /* device-side consistency check failed */
+
+/* ---- per-node status bits (node_status output) ------------------------- */
+#define LM_NODE_INVALID_STRUT 1u   /* |r_a - r_b| >= length, zero length or self loop */
+#define LM_NODE_NON_ELLIPTIC 2u    /* a seam plane cuts a cone in a non-ellipse */
+#define LM_NODE_LOOP 4u            /* a strut end loop is not one closed curve
+                                      monotone in the strut angle */
+#define LM_NODE_TOPOLOGY 8u        /* arc/vertex incidence or Euler check failed
+                                      (e.g. an annular hole), or no hole-fan apex */
+#define LM_NODE_ISOLATED 16u       /* no incident strut */
+#define LM_NODE_VALENCE 32u        /* more incident struts than this build handles */
+#define LM_NODE_DUPLICATE 64u      /* two struts join the same pair of nodes */
+#define LM_NODE_CAPACITY 128u      /* per-node arc / vertex / piece capacity exceeded */
+
+/* Lattice: n_nodes nodes with centre (x, y, z) and nodal-sphere radius
+ * radius (FP32, one value per node, Sec. 4.1: struts are tangent to the nodal
+ * spheres), and n_struts struts joining nodes strut_a[i] and strut_b[i].
+ * Struct of arrays, device memory, caller owned. */
+typedef struct lm_lattice {
+    int64_t n_nodes;
+    int64_t n_struts;
+    const float *d_x, *d_y, *d_z, *d_radius; /* [n_nodes] */
+    const int32_t *d_strut_a, *d_strut_b;    /* [n_struts] */
+} lm_lattice;
+
+/* Sizes produced by lm_count for resolution k. */
+typedef struct lm_totals {
+    int64_t n_vertices;      /* meta-mesh vertices (arc junctions) */
+    int64_t n_arcs;          /* meta-mesh arcs */
+    int64_t n_holes;         /* hole contours */
+    int64_t n_mesh_vertices; /* triangle-mesh vertices */
+    int64_t n_triangles;     /* = n_band_triangles + n_fan_triangles */
+    int64_t n_band_triangles;
+    int64_t n_fan_triangles;
+    int64_t n_loop_entries;  /* internal: strut end loop samples */
+    int64_t n_bad_nodes;     /* nodes with a nonzero status */
+    int64_t n_skipped_struts;/* struts not triangulated (an end node is bad) */
+    int64_t n_fp64_nodes;    /* nodes meshed in FP64 (see lm_set_precision) */
+} lm_totals;
+
+/* Output buffers for lm_fill (device memory, caller owned).
+ *
+ * Mesh (required):
+ *   d_mesh_xyz [cap_mesh_vertices][3] FP32 absolute vertex positions;
+ *   d_tri      [cap_triangles][3] int32 vertex indices, counter-clockwise seen
+ *              from outside.  Order: the band triangles of strut 0, 1, ...,
+ *              then the hole-fan triangles of node 0, 1, ...
+ *   Mesh vertices are numbered node by node; within a node: meta-vertices
+ *   (by name), then the interior subdivision points of each arc (arcs in
+ *   meta-mesh order, points from the endpoint with the smaller name), then
+ *   one hole centre per hole contour.
+ *
+ * Meta-mesh (optional; pass NULL to skip), positions local to their node
+ * (add the node centre for absolute coordinates):
+ *   d_vert_name [cap_vertices] uint32 name (p<<24 | q<<16 | r<<8 | root):
+ *               the vertex is where struts p<q<r tie (label 0 = nodal sphere,
+ *               labels 1..v = incident struts in increasing strut id), root
+ *               = rank of the two tie points along (g_p-g_q)x(g_p-g_r);
+ *               r = 255 marks the start point of an arc that is a whole conic;
+ *   d_vert_xyz  [3][cap_vertices] FP32 (field-major);
+ *   d_arc_f32   [11][cap_arcs] FP32 field-major: o.xyz, a.xyz, b.xyz, t1, t2
+ *               with x(t) = o + a sin t + b cos t for t in [t1, t2] (Eq. 1,
+ *               a = semi-major, b = semi-minor axis);
+ *   d_arc_u32   [3][cap_arcs] uint32 field-major: (p | q<<8 | whole<<16),
+ *               (start vertex | end vertex<<16) as node-local vertex indices
+ *               (start = end at t1 / t2), node index;
+ *   d_node_off  [5][n_nodes+1] int64 field-major exclusive prefix sums of the
+ *               per-node counts: vertices, arcs, holes, mesh vertices, fan
+ *               triangles;
+ *   d_node_status [n_nodes] uint8 LM_NODE_* bits;
+ *   d_strut_off [n_struts+1] int64 exclusive prefix sum of the band
+ *               triangles per strut (0 for a strut with a bad end node).
+ */
+typedef struct lm_outputs {
+    float *d_mesh_xyz;
+    int32_t *d_tri;
+    int64_t cap_mesh_vertices;
+    int64_t cap_triangles;
+    uint32_t *d_vert_name;
+    float *d_vert_xyz;
+    int64_t cap_vertices;
+    float *d_arc_f32;
+    uint32_t *d_arc_u32;
+    int64_t cap_arcs;
+    int64_t *d_node_off;
+    uint8_t *d_node_status;
+    int64_t *d_strut_off;
+} lm_outputs;
+
+typedef struct lm_plan lm_plan;
+
+/* Create a plan for one lattice: validates strut indices (A0), builds the
+ * node adjacency with incident struts in increasing strut id (A1).  The plan
+ * allocates its own device workspace (about 40 bytes per node plus 40 bytes
+ * per strut, more after lm_count for the loop samples).  stream is a
+ * hipStream_t (NULL = default stream).  On success *plan is set; on error it
+ * is NULL.  Returns LM_ERR_BAD_LATTICE for out-of-range endpoints,
+ * LM_ERR_UNSUPPORTED if 2 * n_struts >= 2^31. */
+int lm_plan_create(lm_plan **plan, const lm_lattice *lat, void *stream);
+
+/* Redo the validation and adjacency build of lm_plan_create on the device,
+ * asynchronously (the lattice arrays may have changed in place; the sizes
+ * may not).  An out-of-range endpoint is reported by the next
+ * lm_read_totals as LM_ERR_BAD_LATTICE. */
+int lm_prepare(lm_plan *plan);
+
+/* Meta-mesh every node and size the triangulation at k segments per full
+ * turn (Eq. 11 with step 2 pi / k; 3 <= k <= 4096): per-node arcs,
+ * vertices, holes, loops and counts, prefix sums.  Synchronises the stream
+ * and writes the totals to *totals (host memory).  Re-callable with another
+ * k on the same plan. */
+int lm_count(lm_plan *plan, int k, lm_totals *totals);
+
+/* Write the meta-mesh and the triangle mesh for the k of the last lm_count
+ * (A9, B1-B3).  Asynchronous on the plan's stream.  Returns LM_ERR_CAPACITY
+ * (writing nothing) if a required buffer is smaller than the totals,
+ * LM_ERR_STATE if lm_count has not run. */
+int lm_fill(lm_plan *plan, const lm_outputs *out);
+
+/* lm_count and lm_fill without the host synchronisation: sizes are taken on
+ * the device, outputs whose capacity is too small are not written, and
+ * lm_read_totals reports LM_ERR_CAPACITY afterwards.  For repeated runs with
+ * buffers sized by an earlier lm_count. */
+int lm_forward(lm_plan *plan, int k, const lm_outputs *out);
+
+/* Synchronise the stream and return the totals of the last lm_forward or
+ * lm_count; LM_ERR_CAPACITY if that lm_forward skipped writes,
+ * LM_ERR_INTERNAL if a device-side consistency check failed. */
+int lm_read_totals(lm_plan *plan, lm_totals *totals);
+
+/* Mixed precision.  Nodes are meshed in FP32; a node is meshed again in
+ * FP64 when an FP32 consistency check fails or when one of its vertices has
+ * a condition number above kappa_max (kappa = |n1||n2||n3| / |det(n1,n2,n3)|
+ * for the normals of the three surfaces meeting there, which bounds how much
+ * FP32 rounding is amplified in the vertex position).  Default 32; 0 meshes
+ * every node in FP64.  Invalidates the last lm_count. */
+int lm_set_precision(lm_plan *plan, float kappa_max);
+
+/* Profiling: when on, every library call records HIP events on the plan's
+ * stream around its phases; lm_get_profile synchronises the stream and
+ * returns, per phase, the summed milliseconds and the number of timed calls
+ * since the last lm_get_profile.  Phases (n >= 7): 0 lm_prepare, 1 FP32
+ * count pass, 2 FP64 count pass, 3 band counts + prefix sums + totals,
+ * 4 FP32 fill pass, 5 FP64 fill pass, 6 strut bands. */
+int lm_set_profiling(lm_plan *plan, int on);
+int lm_get_profile(lm_plan *plan, double *ms, int64_t *calls, int n);
+
+/* Release the plan and its workspace (synchronises its stream). */
+void lm_plan_destroy(lm_plan *plan);
+
+/* Text for an LM_OK / LM_ERR_* code (static storage). */
+const char *lm_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LATMESH_H */

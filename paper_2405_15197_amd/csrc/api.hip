@@ -1,0 +1,401 @@
+// Host side of the C ABI declared in include/latmesh.h.
+#include <new>
+#include <string.h>
+#include <vector>
+
+#include "../../include/latmesh.h"
+#include "common.h"
+
+// Phases timed with HIP events when profiling is on (lm_set_profiling).
+enum Phase { PH_PREPARE, PH_COUNT32, PH_COUNT64, PH_SIZES, PH_FILL32, PH_FILL64, PH_ZIP, PH_N };
+
+struct lm_plan {
+    lm::Inputs in;
+    lm::Work w;
+    hipStream_t st;
+    void *ws;       // one allocation for the fixed-size workspace
+    int k;          // resolution of the last count (0: none)
+    float kappa_max;// FP32 -> FP64 hand-over threshold
+    lm_totals last; // totals of the last lm_count
+    bool profiling;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+    std::vector<hipEvent_t> pool;
+};
+
+__global__ void lm_k_status_u8(const int32_t *s, uint8_t *d, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = (uint8_t)s[i];
+}
+
+namespace {
+
+hipEvent_t take_event(lm_plan *P)
+{
+    if (!P->pool.empty()) {
+        hipEvent_t e = P->pool.back();
+        P->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records an event pair around one phase when profiling.
+struct PhaseTimer {
+    lm_plan *P;
+    int ph;
+    hipEvent_t a = nullptr, b = nullptr;
+    PhaseTimer(lm_plan *P_, int ph_) : P(P_), ph(ph_)
+    {
+        if (P->profiling) {
+            a = take_event(P);
+            b = take_event(P);
+            if (a) hipEventRecord(a, P->st);
+        }
+    }
+    ~PhaseTimer()
+    {
+        if (a && b) {
+            hipEventRecord(b, P->st);
+            P->ev.push_back({ph, {a, b}});
+        }
+    }
+};
+
+#define HIPCHK(x)                                   \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return LM_ERR_HIP;    \
+    } while (0)
+
+inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Carve the workspace; with base == nullptr only the size is computed.
+size_t carve(lm::Work &w, char *base, int64_t N, int64_t S)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    const int64_t H = 2 * S;
+    w.node4 = (float4 *)take(sizeof(float4) * (N + 1));
+    w.row = (int64_t *)take(sizeof(int64_t) * (N + 1));
+    w.he = (int2 *)take(sizeof(int2) * (H + 1));
+    w.deg = (int32_t *)take(sizeof(int32_t) * (N + 1));
+    w.strut_he = (int64_t *)take(sizeof(int64_t) * (H + 1));
+    w.node_cnt = (int32_t *)take(sizeof(int32_t) * lm::kNodeCols * (N + 1));
+    w.node_off = (int64_t *)take(sizeof(int64_t) * lm::kNodeScanCols * (N + 1));
+    w.he_len = (int32_t *)take(sizeof(int32_t) * (H + 1));
+    w.he_off = (int64_t *)take(sizeof(int64_t) * (H + 1));
+    w.band_cnt = (int32_t *)take(sizeof(int32_t) * (S + 1));
+    w.band_off = (int64_t *)take(sizeof(int64_t) * (S + 1));
+    int64_t tl = lm::scan_tmp_needed(N, lm::kNodeScanCols);
+    int64_t t2 = lm::scan_tmp_needed(H, 1);
+    if (t2 > tl) tl = t2;
+    w.scan_tmp = (int64_t *)take(sizeof(int64_t) * tl);
+    w.scan_tmp_len = tl;
+    w.flags = (int32_t *)take(sizeof(int32_t) * 4);
+    w.totals = (int64_t *)take(sizeof(int64_t) * 16);
+    w.fb_list = (int32_t *)take(sizeof(int32_t) * (N + 1));
+    w.node_prec = (uint8_t *)take(sizeof(uint8_t) * (N + 1));
+    return off;
+}
+
+lm::FillOut to_fill(const lm_outputs *o)
+{
+    lm::FillOut f;
+    f.mesh_xyz = o->d_mesh_xyz;
+    f.tri = o->d_tri;
+    f.cap_mesh = o->cap_mesh_vertices;
+    f.cap_tri = o->cap_triangles;
+    f.vert_name = o->d_vert_name;
+    f.vert_xyz = o->d_vert_xyz;
+    f.cap_vert = o->cap_vertices;
+    f.arc_f32 = o->d_arc_f32;
+    f.arc_u32 = o->d_arc_u32;
+    f.cap_arc = o->cap_arcs;
+    if (!f.vert_name || !f.vert_xyz) {
+        f.vert_name = nullptr;
+        f.vert_xyz = nullptr;
+    }
+    if (!f.arc_f32 || !f.arc_u32) {
+        f.arc_f32 = nullptr;
+        f.arc_u32 = nullptr;
+    }
+    return f;
+}
+
+// Count pass: per-node meta-meshing and counts, band counts, prefix sums,
+// device totals (and capacity flags when out != nullptr).
+int run_count(lm_plan *P, int k, const lm::FillOut *out)
+{
+    const int64_t N = P->in.n_nodes, S = P->in.n_struts;
+    lm::Work &w = P->w;
+    // flags[0] (count / fill) and flags[2] (FP64 hand-over count)
+    HIPCHK(hipMemsetAsync(w.flags, 0, sizeof(int32_t), P->st));
+    HIPCHK(hipMemsetAsync(w.flags + 2, 0, sizeof(int32_t), P->st));
+    HIPCHK(hipMemsetAsync(w.totals, 0, sizeof(int64_t) * 16, P->st));
+    {
+        PhaseTimer t(P, PH_COUNT32);
+        HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, nullptr, 0, P->st));
+    }
+    {
+        PhaseTimer t(P, PH_COUNT64);
+        HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, nullptr, 1, P->st));
+    }
+    PhaseTimer t(P, PH_SIZES);
+    HIPCHK(lm::launch_band_count(P->in, w, P->st));
+    HIPCHK(lm::launch_scan(w.node_cnt, w.node_off, N, lm::kNodeScanCols, N, N + 1, w.scan_tmp, w.scan_tmp_len,
+                           P->st));
+    HIPCHK(lm::launch_scan(w.he_len, w.he_off, 2 * S, 1, 0, 0, w.scan_tmp, w.scan_tmp_len, P->st));
+    HIPCHK(lm::launch_scan(w.band_cnt, w.band_off, S, 1, 0, 0, w.scan_tmp, w.scan_tmp_len, P->st));
+    HIPCHK(lm::launch_totals(P->in, w, out, P->st));
+    return LM_OK;
+}
+
+int read_totals(lm_plan *P, lm_totals *t, int32_t *flags_out)
+{
+    int64_t tv[16];
+    int32_t fl[4];
+    HIPCHK(hipMemcpyAsync(tv, P->w.totals, sizeof(tv), hipMemcpyDeviceToHost, P->st));
+    HIPCHK(hipMemcpyAsync(fl, P->w.flags, sizeof(fl), hipMemcpyDeviceToHost, P->st));
+    HIPCHK(hipStreamSynchronize(P->st));
+    t->n_vertices = tv[0];
+    t->n_arcs = tv[1];
+    t->n_holes = tv[2];
+    t->n_mesh_vertices = tv[3];
+    t->n_triangles = tv[4];
+    t->n_band_triangles = tv[5];
+    t->n_fan_triangles = tv[6];
+    t->n_loop_entries = tv[7];
+    t->n_bad_nodes = tv[8];
+    t->n_skipped_struts = tv[9];
+    t->n_fp64_nodes = tv[10];
+    *flags_out = fl[0] | fl[1];
+    return LM_OK;
+}
+
+int ensure_loop(lm_plan *P, int64_t need)
+{
+    if (need <= P->w.loop_cap) return LM_OK;
+    HIPCHK(hipStreamSynchronize(P->st));
+    if (P->w.loop) HIPCHK(hipFree(P->w.loop));
+    P->w.loop = nullptr;
+    P->w.loop_cap = 0;
+    int64_t cap = need + need / 8 + 1024;
+    HIPCHK(hipMalloc((void **)&P->w.loop, sizeof(int2) * cap));
+    P->w.loop_cap = cap;
+    return LM_OK;
+}
+
+int fill_common(lm_plan *P, const lm::FillOut &f, const lm_outputs *out)
+{
+    const int64_t N = P->in.n_nodes;
+    {
+        PhaseTimer t(P, PH_FILL32);
+        HIPCHK(lm::launch_node(P->in, P->w, P->k, P->kappa_max, &f, 0, P->st));
+    }
+    {
+        PhaseTimer t(P, PH_FILL64);
+        HIPCHK(lm::launch_node(P->in, P->w, P->k, P->kappa_max, &f, 1, P->st));
+    }
+    {
+        PhaseTimer t(P, PH_ZIP);
+        HIPCHK(lm::launch_zip(P->in, P->w, f, P->st));
+    }
+    if (out->d_node_off)
+        HIPCHK(hipMemcpyAsync(out->d_node_off, P->w.node_off, sizeof(int64_t) * lm::kNodeScanCols * (N + 1),
+                              hipMemcpyDeviceToDevice, P->st));
+    if (out->d_strut_off)
+        HIPCHK(hipMemcpyAsync(out->d_strut_off, P->w.band_off, sizeof(int64_t) * (P->in.n_struts + 1),
+                              hipMemcpyDeviceToDevice, P->st));
+    if (out->d_node_status && N > 0) {
+        // int32 status column -> uint8 (values fit in 8 bits)
+        lm_k_status_u8<<<(unsigned)((N + 255) / 256), 256, 0, P->st>>>(
+            P->w.node_cnt + (int64_t)lm::NC_STATUS * N, out->d_node_status, N);
+        HIPCHK(hipGetLastError());
+    }
+    return LM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lm_plan_create(lm_plan **plan, const lm_lattice *lat, void *stream)
+{
+    if (!plan) return LM_ERR_INVALID_ARG;
+    *plan = nullptr;
+    if (!lat || lat->n_nodes < 0 || lat->n_struts < 0) return LM_ERR_INVALID_ARG;
+    if (lat->n_nodes > 0 && (!lat->d_x || !lat->d_y || !lat->d_z || !lat->d_radius)) return LM_ERR_INVALID_ARG;
+    if (lat->n_struts > 0 && (!lat->d_strut_a || !lat->d_strut_b)) return LM_ERR_INVALID_ARG;
+    if (lat->n_nodes >= ((int64_t)1 << 31) || 2 * lat->n_struts >= ((int64_t)1 << 31)) return LM_ERR_UNSUPPORTED;
+    lm_plan *P = new (std::nothrow) lm_plan();
+    if (!P) return LM_ERR_INTERNAL;
+    P->st = (hipStream_t)stream;
+    P->in.n_nodes = lat->n_nodes;
+    P->in.n_struts = lat->n_struts;
+    P->in.x = lat->d_x;
+    P->in.y = lat->d_y;
+    P->in.z = lat->d_z;
+    P->in.r = lat->d_radius;
+    P->in.sa = lat->d_strut_a;
+    P->in.sb = lat->d_strut_b;
+    size_t bytes = carve(P->w, nullptr, lat->n_nodes, lat->n_struts);
+    if (hipMalloc(&P->ws, bytes) != hipSuccess) {
+        delete P;
+        return LM_ERR_HIP;
+    }
+    carve(P->w, (char *)P->ws, lat->n_nodes, lat->n_struts);
+    P->w.loop = nullptr;
+    P->w.loop_cap = 0;
+    P->kappa_max = 32.0f;
+    P->profiling = false;
+    int rc = LM_OK;
+    int32_t fl = 0;
+    if (hipMemsetAsync(P->w.flags, 0, sizeof(int32_t) * 4, P->st) != hipSuccess ||
+        lm::launch_prepare(P->in, P->w, P->st) != hipSuccess ||
+        hipMemcpyAsync(&fl, P->w.flags + 1, sizeof(int32_t), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
+        hipStreamSynchronize(P->st) != hipSuccess) {
+        rc = LM_ERR_HIP;
+    } else if (fl & lm::DF_BADLAT) {  // set in flags[1]
+        rc = LM_ERR_BAD_LATTICE;
+    }
+    if (rc != LM_OK) {
+        hipFree(P->ws);
+        delete P;
+        return rc;
+    }
+    *plan = P;
+    return LM_OK;
+}
+
+int lm_count(lm_plan *P, int k, lm_totals *totals)
+{
+    if (!P || !totals || k < 3 || k > 4096) return LM_ERR_INVALID_ARG;
+    int rc = run_count(P, k, nullptr);
+    if (rc) return rc;
+    int32_t fl;
+    rc = read_totals(P, totals, &fl);
+    if (rc) return rc;
+    if (totals->n_mesh_vertices > 0x7fffffffLL) return LM_ERR_UNSUPPORTED;
+    rc = ensure_loop(P, totals->n_loop_entries);
+    if (rc) return rc;
+    // the loop buffer now fits: clear the flags the sizing pass may have set
+    HIPCHK(hipMemsetAsync(P->w.flags, 0, sizeof(int32_t), P->st));
+    P->k = k;
+    P->last = *totals;
+    return LM_OK;
+}
+
+int lm_fill(lm_plan *P, const lm_outputs *out)
+{
+    if (!P || !out || !out->d_mesh_xyz || !out->d_tri) return LM_ERR_INVALID_ARG;
+    if (P->k == 0) return LM_ERR_STATE;
+    const lm_totals &t = P->last;
+    if (out->cap_mesh_vertices < t.n_mesh_vertices || out->cap_triangles < t.n_triangles) return LM_ERR_CAPACITY;
+    lm::FillOut f = to_fill(out);
+    if (f.vert_name && out->cap_vertices < t.n_vertices) return LM_ERR_CAPACITY;
+    if (f.arc_f32 && out->cap_arcs < t.n_arcs) return LM_ERR_CAPACITY;
+    return fill_common(P, f, out);
+}
+
+int lm_forward(lm_plan *P, int k, const lm_outputs *out)
+{
+    if (!P || !out || !out->d_mesh_xyz || !out->d_tri || k < 3 || k > 4096) return LM_ERR_INVALID_ARG;
+    lm::FillOut f = to_fill(out);
+    int rc = run_count(P, k, &f);
+    if (rc) return rc;
+    P->k = k;
+    return fill_common(P, f, out);
+}
+
+int lm_read_totals(lm_plan *P, lm_totals *totals)
+{
+    if (!P || !totals) return LM_ERR_INVALID_ARG;
+    int32_t fl;
+    int rc = read_totals(P, totals, &fl);
+    if (rc) return rc;
+    if (fl & lm::DF_MISMATCH) return LM_ERR_INTERNAL;
+    if (fl & (lm::DF_CAPACITY | lm::DF_LOOPCAP)) return LM_ERR_CAPACITY;
+    return LM_OK;
+}
+
+int lm_prepare(lm_plan *P)
+{
+    if (!P) return LM_ERR_INVALID_ARG;
+    PhaseTimer t(P, PH_PREPARE);
+    HIPCHK(hipMemsetAsync(P->w.flags + 1, 0, sizeof(int32_t), P->st));
+    HIPCHK(lm::launch_prepare(P->in, P->w, P->st));
+    return LM_OK;
+}
+
+int lm_set_profiling(lm_plan *P, int on)
+{
+    if (!P) return LM_ERR_INVALID_ARG;
+    P->profiling = on != 0;
+    return LM_OK;
+}
+
+int lm_get_profile(lm_plan *P, double *ms, int64_t *calls, int n)
+{
+    if (!P || !ms || !calls || n < PH_N) return LM_ERR_INVALID_ARG;
+    for (int i = 0; i < PH_N; ++i) {
+        ms[i] = 0.0;
+        calls[i] = 0;
+    }
+    HIPCHK(hipStreamSynchronize(P->st));
+    for (auto &e : P->ev) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, e.second.first, e.second.second));
+        ms[e.first] += t;
+        calls[e.first] += 1;
+        P->pool.push_back(e.second.first);
+        P->pool.push_back(e.second.second);
+    }
+    P->ev.clear();
+    return LM_OK;
+}
+
+int lm_set_precision(lm_plan *P, float kappa_max)
+{
+    if (!P || !(kappa_max >= 0.0f)) return LM_ERR_INVALID_ARG;
+    P->kappa_max = kappa_max;
+    P->k = 0;  // counts must be redone
+    return LM_OK;
+}
+
+void lm_plan_destroy(lm_plan *P)
+{
+    if (!P) return;
+    hipStreamSynchronize(P->st);
+    for (auto &e : P->ev) {
+        hipEventDestroy(e.second.first);
+        hipEventDestroy(e.second.second);
+    }
+    for (auto e : P->pool) hipEventDestroy(e);
+    if (P->w.loop) hipFree(P->w.loop);
+    hipFree(P->ws);
+    delete P;
+}
+
+const char *lm_status_string(int code)
+{
+    switch (code) {
+    case LM_OK: return "ok";
+    case LM_ERR_INVALID_ARG: return "invalid argument";
+    case LM_ERR_BAD_LATTICE: return "strut endpoint out of range";
+    case LM_ERR_CAPACITY: return "output buffer too small";
+    case LM_ERR_UNSUPPORTED: return "size not supported by this build";
+    case LM_ERR_HIP: return "HIP runtime error";
+    case LM_ERR_STATE: return "call out of order";
+    case LM_ERR_INTERNAL: return "device consistency check failed";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

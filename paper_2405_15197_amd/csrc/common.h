@@ -1,0 +1,108 @@
+// Internal declarations shared by the latmesh HIP sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lm {
+
+// Per-node limits of this build.  A node beyond them is flagged (its status
+// bit is set) and emits nothing.
+constexpr int kVmax = 16;       // incident struts per node
+constexpr int kAcap = 64;       // arcs per node
+constexpr int kVcap = 64;       // meta-vertices per node
+constexpr int kPieces = 4;      // kept arcs per conic
+
+constexpr float kTwoPi = 6.28318530717958647692f;
+constexpr float kInvTwoPi = 0.159154943091895335769f;
+
+enum NodeStatus : int {
+    NS_INVALID_STRUT = 1,
+    NS_NON_ELLIPTIC = 2,
+    NS_LOOP = 4,
+    NS_TOPOLOGY = 8,
+    NS_ISOLATED = 16,
+    NS_VALENCE = 32,
+    NS_DUPLICATE = 64,
+    NS_CAPACITY = 128,
+    NS_PREC = 256,  // internal: FP32 result not trusted, redo in FP64
+};
+
+// Per-node count columns (int32, field-major [kNodeCols][N]).
+enum NodeCol : int {
+    NC_VERT = 0,
+    NC_ARC = 1,
+    NC_HOLE = 2,
+    NC_MESH = 3,
+    NC_FAN = 4,
+    NC_STATUS = 5,
+    kNodeCols = 6,
+};
+constexpr int kNodeScanCols = 5;  // columns 0..4 are prefix-summed
+
+// Device-side flag words: flags[0] DevFlag bits of the last count / fill,
+// flags[1] DevFlag bits of the lattice preparation, flags[2] number of nodes
+// handed to the FP64 pass.
+enum DevFlag : int {
+    DF_CAPACITY = 1,   // an output was too small, writes skipped
+    DF_MISMATCH = 2,   // fill pass disagreed with the count pass
+    DF_BADLAT = 4,     // a strut endpoint is out of range
+    DF_LOOPCAP = 8,    // loop-sample buffer too small or mesh too large for int32
+};
+
+struct Inputs {
+    int64_t n_nodes, n_struts;
+    const float *x, *y, *z, *r;
+    const int32_t *sa, *sb;
+};
+
+// Workspace pointers (device).
+struct Work {
+    float4 *node4;          // [N] x, y, z, radius
+    int64_t *row;           // [N+1] adjacency offsets
+    int2 *he;               // [2S] (far node, strut id), strut id ascending per node
+    int32_t *deg;           // [N] scratch: degree / fill cursor
+    int64_t *strut_he;      // [2S] half-edge index at the lower / higher node id
+    int32_t *node_cnt;      // [kNodeCols][N]
+    int64_t *node_off;      // [kNodeScanCols][N+1]
+    int32_t *he_len;        // [2S] loop samples per half-edge
+    int64_t *he_off;        // [2S+1]
+    int32_t *band_cnt;      // [S]
+    int64_t *band_off;      // [S+1]
+    int2 *loop;             // [n_loop] (global mesh vertex, phi bits)
+    int64_t loop_cap;
+    int64_t *scan_tmp;      // block partials
+    int64_t scan_tmp_len;
+    int32_t *flags;         // [4] see DevFlag
+    int64_t *totals;        // [16] device copy of totals
+    int32_t *fb_list;       // [N] nodes for the FP64 pass
+    uint8_t *node_prec;     // [N] 1: node meshed in FP64
+};
+
+struct FillOut {
+    float *mesh_xyz;
+    int32_t *tri;
+    int64_t cap_mesh, cap_tri;
+    uint32_t *vert_name;
+    float *vert_xyz;
+    int64_t cap_vert;
+    float *arc_f32;
+    uint32_t *arc_u32;
+    int64_t cap_arc;
+};
+
+// launchers (return hipError_t)
+hipError_t launch_prepare(const Inputs &in, const Work &w, hipStream_t st);
+hipError_t launch_scan(const int32_t *src, int64_t *dst, int64_t n, int ncols, int64_t src_stride,
+                       int64_t dst_stride, int64_t *tmp, int64_t tmp_len, hipStream_t st);
+// Per-node kernel: count pass (o == nullptr) or fill pass, FP32 over all
+// nodes or FP64 over the hand-over list.
+hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, const FillOut *o, int fp64,
+                       hipStream_t st);
+hipError_t launch_band_count(const Inputs &in, const Work &w, hipStream_t st);
+hipError_t launch_zip(const Inputs &in, const Work &w, const FillOut &o, hipStream_t st);
+hipError_t launch_totals(const Inputs &in, const Work &w, const FillOut *o, hipStream_t st);
+
+int64_t scan_tmp_needed(int64_t n, int ncols);
+
+}  // namespace lm

@@ -1,0 +1,1074 @@
+// Per-node meta-meshing and node-local triangulation (one wave per node).
+//
+// Geometry (Sec. 4.1, Sec. 4.3.1): around node c with nodal-sphere radius rho,
+// incident strut m (far node c_m, radius rho_m, L = |c_m - c|) has
+//   e_m = (c_m - c)/L, sigma_m = (rho - rho_m)/L, kappa_m = sqrt(1 - sigma_m^2)
+// and the affine function P_m(w) = g_m . w - h_m (w = x - c) with
+// g_m = e_m / kappa_m, h_m = rho sigma_m / kappa_m: the arc length along a
+// generator of the tangent cone, measured from the tangency circle.  Cone m
+// is |w|^2 - rho^2 = P_m^2, two cones meet on the auxiliary plane P_p = P_q,
+// and the surface near the node is |w|^2 - rho^2 = max(0, P_1..P_v)^2.
+// Label 0 stands for the nodal sphere (P_0 = 0).
+//
+// Work per node, lanes over the v(v+1)/2 conics (p, q), p < q, in
+// lexicographic order:
+//   1. conic: the tangency circle for (0, q); for p >= 1 the section of cone
+//      p by its auxiliary plane with q, in principal axes (the ellipse of
+//      Eq. 7, obtained here by completing the square in the plane);
+//   2. trimming (Eqs. 8-9): keep P_p >= P_r for every other label r; each r
+//      gives R cos(t - psi) >= -C, one circular interval; the intervals are
+//      intersected in registers into at most kPieces arcs;
+//   3. arc ends are triple ties (p, q, r); the tie point's rank along
+//      (g_p - g_q) x (g_p - g_r) comes from the chord direction of the
+//      interval, so every vertex gets the same name from its three arcs; the
+//      conic (p, q) of the two smallest labels owns (emits) it.
+// Lane order makes arcs and vertices come out in canonical order.  Then, per
+// strut lane, the arcs of the strut are chained into its end loop ordered by
+// the strut-frame angle phi (Sec. 4.3.1: arcs merged into an arc loop), and
+// the circular arcs are grouped into hole contours (Sec. 5).  Subdivision
+// uses Eq. 11 with step 2 pi / k and Eq. 12 sub-parameters; hole centres use
+// Eq. 13.
+//
+// Precision: every node is first meshed in FP32.  A node goes to a second,
+// FP64 pass of the same code when one of its vertices is ill-conditioned
+// (the three surfaces meeting there have nearly dependent normals, so FP32
+// rounding is amplified by the condition number kappa = |n1||n2||n3| /
+// |det(n1, n2, n3)|) or when an FP32 consistency check fails.
+#include "common.h"
+
+namespace lm {
+namespace {
+
+// ---------------------------------------------------------------------------
+// scalar helpers (float / double)
+
+__device__ inline float m_sqrt(float x) { return sqrtf(x); }
+__device__ inline double m_sqrt(double x) { return sqrt(x); }
+__device__ inline float m_abs(float x) { return fabsf(x); }
+__device__ inline double m_abs(double x) { return fabs(x); }
+__device__ inline float m_atan2(float y, float x) { return atan2f(y, x); }
+__device__ inline double m_atan2(double y, double x) { return atan2(y, x); }
+__device__ inline float m_acos(float x) { return acosf(x); }
+__device__ inline double m_acos(double x) { return acos(x); }
+__device__ inline float m_fmod(float x, float y) { return fmodf(x, y); }
+__device__ inline double m_fmod(double x, double y) { return fmod(x, y); }
+__device__ inline float m_floor(float x) { return floorf(x); }
+__device__ inline double m_floor(double x) { return floor(x); }
+__device__ inline float m_max(float a, float b) { return fmaxf(a, b); }
+__device__ inline double m_max(double a, double b) { return fmax(a, b); }
+__device__ inline float m_min(float a, float b) { return fminf(a, b); }
+__device__ inline double m_min(double a, double b) { return fmin(a, b); }
+__device__ inline void m_sincos(float t, float *s, float *c) { sincosf(t, s, c); }
+__device__ inline void m_sincos(double t, double *s, double *c) { sincos(t, s, c); }
+
+template <typename T>
+struct Cst {
+    static constexpr T two_pi = (T)6.283185307179586476925286766559;
+    static constexpr T pi = (T)3.1415926535897932384626433832795;
+    static constexpr T inv_two_pi = (T)0.15915494309189533576888376337251;
+};
+
+template <typename T>
+struct V3 {
+    T x, y, z;
+};
+template <typename T>
+__device__ inline V3<T> v3(T x, T y, T z) { return V3<T>{x, y, z}; }
+template <typename T>
+__device__ inline V3<T> operator+(V3<T> a, V3<T> b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
+template <typename T>
+__device__ inline V3<T> operator-(V3<T> a, V3<T> b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+template <typename T>
+__device__ inline V3<T> operator*(V3<T> a, T s) { return v3(a.x * s, a.y * s, a.z * s); }
+template <typename T>
+__device__ inline T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <typename T>
+__device__ inline V3<T> cross(V3<T> a, V3<T> b)
+{
+    return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+template <typename T>
+__device__ inline V3<T> zero3() { return v3((T)0, (T)0, (T)0); }
+
+// ---------------------------------------------------------------------------
+// per-node data in LDS
+
+template <typename T>
+struct SL {
+    T gx, gy, gz, h;   // P_m(w) = g . w - h
+    T ex, ey, ez, sig; // unit direction node -> far node, sigma
+    T rx, ry, rz, kap; // strut frame r, kappa
+    T qx, qy, qz, len; // strut frame q, length
+    T sx, sy, sz;      // canonical strut direction (lower -> higher node id)
+    int lower, sid, far;
+};
+
+template <typename T>
+struct ArcL {
+    T o[3], a[3], b[3];
+    T t1, t2;
+    uint32_t ns, ne; // vertex names at t1 / t2
+    int vs, ve;      // local vertex indices
+    int p, q, full;
+    int nseg, mbase, contour;
+};
+
+template <typename T>
+struct Shared {
+    SL<T> S[kVmax + 1];
+    ArcL<T> A[kAcap];
+    uint32_t vname[kVcap];
+    T vx[kVcap], vy[kVcap], vz[kVcap];
+    uint8_t loop_arc[2 * kAcap];
+    int8_t loop_dir[2 * kAcap];
+    uint8_t loop_ord[2 * kAcap];
+    int loop_base[kVmax + 2];
+    int loop_len[kVmax + 1];  // samples |L_m|
+    uint32_t clabel[kAcap];
+    T hc[kAcap][3];           // hole centre (local) per contour
+    int status, n_arc, n_vert, n_contour;
+    int wsum;
+};
+
+template <typename T>
+__device__ inline V3<T> gvec(const SL<T> &s) { return v3(s.gx, s.gy, s.gz); }
+
+__device__ inline uint32_t vname3(int a, int b, int c, int root)
+{
+    return ((uint32_t)a << 24) | ((uint32_t)b << 16) | ((uint32_t)c << 8) | (uint32_t)root;
+}
+
+// sorted triple of {p, q, r} (p < q already)
+__device__ inline void sort3(int p, int q, int r, int &x, int &y, int &z)
+{
+    x = p; y = q; z = r;
+    if (z < x) { int t = z; z = y; y = x; x = t; }
+    else if (z < y) { int t = z; z = y; y = t; }
+}
+
+__device__ inline uint32_t tie_name(int p, int q, int r, int root)
+{
+    int x, y, z;
+    sort3(p, q, r, x, y, z);
+    return vname3(x, y, z, root);
+}
+
+__device__ inline int wave_excl_scan(int x, int *total)
+{
+    const int lane = threadIdx.x;
+    int inc = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += y;
+    }
+    *total = __shfl(inc, 63, 64);
+    return inc - x;
+}
+
+template <typename T>
+__device__ inline T wrap2pi(T t)
+{
+    t = m_fmod(t, Cst<T>::two_pi);
+    if (t < (T)0) t += Cst<T>::two_pi;
+    if (t >= Cst<T>::two_pi) t -= Cst<T>::two_pi;
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// conics
+
+template <typename T>
+struct Con {
+    V3<T> o, a, b;
+};
+
+template <typename T>
+__device__ inline V3<T> conic_at(const Con<T> &C, T t)
+{
+    T s, c;
+    m_sincos(t, &s, &c);
+    return C.o + C.a * s + C.b * c;
+}
+
+// Conic (p, q) of the node.  Returns false if the section is not an ellipse.
+template <typename T>
+__device__ bool conic_of(const SL<T> *S, T rho, int p, int q, Con<T> &C)
+{
+    if (p == 0) {
+        const SL<T> &s = S[q];
+        T rad = rho * s.kap;
+        C.o = v3(s.ex, s.ey, s.ez) * (rho * s.sig);
+        C.a = v3(s.qx, s.qy, s.qz) * rad;
+        C.b = v3(s.rx, s.ry, s.rz) * rad;
+        return true;
+    }
+    const SL<T> &P = S[p], &Q = S[q];
+    V3<T> gp = gvec(P);
+    V3<T> n = gp - gvec(Q);
+    T nn = m_sqrt(dot(n, n));
+    V3<T> nh = n * ((T)1 / nn);
+    T d0 = (P.h - Q.h) / nn;            // plane: nh . w = d0
+    T gpn = dot(gp, nh);
+    T epn = m_abs(gpn * P.kap);         // |e_p . nh|
+    T as = m_abs(P.sig);
+    T om = (epn - as) * (epn + as) / (P.kap * P.kap); // 1 - |in-plane g_p|^2
+    if (!(om > (T)0)) return false;
+    V3<T> gam = gp - nh * gpn;          // in-plane part of g_p: major axis direction
+    T gl = m_sqrt(dot(gam, gam));
+    V3<T> u1;
+    if (gl > (T)1e-20) {
+        u1 = gam * ((T)1 / gl);
+        // gam is a small difference when the plane is nearly perpendicular
+        // to the axis; keep u1 exactly in the plane (its in-plane rotation
+        // error only reparametrises an almost circular ellipse)
+        u1 = u1 - nh * dot(u1, nh);
+        u1 = u1 * ((T)1 / m_sqrt(dot(u1, u1)));
+    } else {
+        V3<T> t = m_abs(nh.x) < (T)0.9 ? v3((T)1, (T)0, (T)0) : v3((T)0, (T)1, (T)0);
+        u1 = cross(nh, t);
+        u1 = u1 * ((T)1 / m_sqrt(dot(u1, u1)));
+    }
+    // in-plane coordinates w = d0 nh + al u1 + be u2:
+    //   (1 - gl^2) al^2 - 2 gl k0 al + be^2 = rho^2 - d0^2 + k0^2,
+    // k0 = P_p at the foot point d0 nh; complete the square.
+    T k0 = d0 * gpn - P.h;
+    T al0 = gl * k0 / om;
+    T R2 = rho * rho - d0 * d0 + k0 * k0 / om;
+    T R = m_sqrt(m_max(R2, (T)0));
+    C.o = nh * d0 + u1 * al0;
+    C.a = u1 * (R / m_sqrt(om));
+    C.b = cross(u1, nh) * R;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// trimming of one conic: intersection of circular intervals
+
+template <typename T>
+struct Pc {
+    T s, e, len;
+    int rs, re;
+    int roots; // bit 0: root of the start tie, bit 1: root of the end tie
+};
+
+template <typename T>
+struct TrimOut {
+    int n;        // arcs
+    int full;     // whole conic kept
+    int ovf;      // too many pieces
+    Pc<T> pc[kPieces];
+};
+
+template <typename T>
+__device__ void trim_conic(const SL<T> *S, int v, int p, int q, const Con<T> &C, TrimOut<T> &TR)
+{
+    const T tp = Cst<T>::two_pi;
+    TR.n = 1;
+    TR.full = 1;
+    TR.ovf = 0;
+    const SL<T> &P = S[p];
+    V3<T> gp = p ? gvec(P) : zero3<T>();
+    T hp = p ? P.h : (T)0;
+    for (int r = 0; r <= v; ++r) {
+        if (r == p || r == q) continue;
+        V3<T> gr = r ? gvec(S[r]) : zero3<T>();
+        T hr = r ? S[r].h : (T)0;
+        V3<T> dg = gp - gr;
+        T A = dot(dg, C.a), B = dot(dg, C.b), Cc = dot(dg, C.o) - (hp - hr);
+        T R = m_sqrt(A * A + B * B);
+        if (Cc >= R) continue;          // never active
+        if (Cc <= -R) {                  // removes the whole conic
+            TR.n = 0;
+            TR.full = 0;
+            return;
+        }
+        T psi = m_atan2(A, B);
+        T beta = m_acos(-Cc / R);
+        T lo = wrap2pi(psi - beta), hi = wrap2pi(psi + beta), lc = (T)2 * beta;
+        // rank of the far tie point along d = (g_x - g_y) x (g_x - g_z),
+        // (x, y, z) = sorted (p, q, r); the chord x(hi) - x(lo) is parallel
+        // to the tie line and to a B - b A.
+        int x, y, z;
+        sort3(p, q, r, x, y, z);
+        V3<T> gx = x ? gvec(S[x]) : zero3<T>();
+        V3<T> d = cross(gx - gvec(S[y]), gx - gvec(S[z]));
+        int sgn = dot(C.a * B - C.b * A, d) > (T)0 ? 1 : 0;
+        int root_lo = 1 - sgn, root_hi = sgn;
+        Pc<T> out[kPieces] = {};
+        int no = 0;
+        bool ovf = false;
+        auto push = [&](const Pc<T> &pcx) {
+#pragma unroll
+            for (int j = 0; j < kPieces; ++j)
+                if (j == no) out[j] = pcx;
+            if (no < kPieces) ++no;
+            else ovf = true;
+        };
+        if (TR.full) {
+            Pc<T> pcx;
+            pcx.s = lo; pcx.e = hi; pcx.len = lc; pcx.rs = r; pcx.re = r;
+            pcx.roots = root_lo | (root_hi << 1);
+            push(pcx);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kPieces; ++i) {
+                if (i < TR.n) {
+                    Pc<T> Pp = TR.pc[i];
+                    T c0 = lo - Pp.s;
+                    if (c0 < (T)0) c0 += tp;
+                    T c1 = c0 + lc;
+                    if (c0 < Pp.len) {
+                        Pc<T> pcx;
+                        if (c0 > (T)0) { pcx.s = lo; pcx.rs = r; pcx.roots = root_lo; }
+                        else { pcx.s = Pp.s; pcx.rs = Pp.rs; pcx.roots = Pp.roots & 1; }
+                        if (c1 < Pp.len) { pcx.e = hi; pcx.re = r; pcx.roots |= root_hi << 1; pcx.len = c1 - c0; }
+                        else { pcx.e = Pp.e; pcx.re = Pp.re; pcx.roots |= Pp.roots & 2; pcx.len = Pp.len - c0; }
+                        push(pcx);
+                    }
+                    if (c1 > tp) {
+                        T w1 = c1 - tp;
+                        Pc<T> pcx;
+                        pcx.s = Pp.s; pcx.rs = Pp.rs; pcx.roots = Pp.roots & 1;
+                        if (w1 < Pp.len) { pcx.e = hi; pcx.re = r; pcx.roots |= root_hi << 1; pcx.len = w1; }
+                        else { pcx.e = Pp.e; pcx.re = Pp.re; pcx.roots |= Pp.roots & 2; pcx.len = Pp.len; }
+                        push(pcx);
+                    }
+                }
+            }
+        }
+        TR.full = 0;
+        TR.n = no;
+        if (ovf) TR.ovf = 1;
+#pragma unroll
+        for (int j = 0; j < kPieces; ++j) TR.pc[j] = out[j];
+        if (no == 0) return;
+    }
+}
+
+// Condition number of a tie point: the three surfaces through it are cone p
+// (normal w - P_p g_p, or w for the sphere), and the planes P_p = P_q and
+// P_p = P_r; returns |n1||n2||n3| / |det(n1, n2, n3)|.
+template <typename T>
+__device__ inline T tie_kappa(const SL<T> *S, int p, int q, int r, V3<T> w)
+{
+    V3<T> gp = p ? gvec(S[p]) : zero3<T>();
+    T pp = p ? dot(gp, w) - S[p].h : (T)0;
+    V3<T> n1 = w - gp * pp;
+    V3<T> n2 = gp - gvec(S[q]);
+    V3<T> n3 = gp - (r ? gvec(S[r]) : zero3<T>());
+    T det = m_abs(dot(n1, cross(n2, n3)));
+    T den = m_sqrt(dot(n1, n1) * dot(n2, n2) * dot(n3, n3));
+    return det > (T)0 ? den / det : (T)1e30;
+}
+
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ inline T phi_of(const SL<T> &s, V3<T> w)
+{
+    return m_atan2(dot(w, v3(s.qx, s.qy, s.qz)), dot(w, v3(s.rx, s.ry, s.rz)));
+}
+
+template <typename T>
+__device__ inline Con<T> arc_con(const ArcL<T> &A)
+{
+    Con<T> C;
+    C.o = v3(A.o[0], A.o[1], A.o[2]);
+    C.a = v3(A.a[0], A.a[1], A.a[2]);
+    C.b = v3(A.b[0], A.b[1], A.b[2]);
+    return C;
+}
+
+template <typename T>
+__device__ inline int find_vert(const Shared<T> &sh, uint32_t name)
+{
+    int lo = 0, hi = sh.n_vert - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        uint32_t m = sh.vname[mid];
+        if (m == name) return mid;
+        if (m < name) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+// Eq. 12 index ii (1..nseg-1) of an interior point -> node-local mesh index
+template <typename T>
+__device__ inline int interior_idx(const ArcL<T> &A, int ii)
+{
+    bool fwd = A.full || A.ns <= A.ne;
+    return A.mbase + (fwd ? ii - 1 : A.nseg - 1 - ii);
+}
+
+template <typename T>
+__device__ inline T sub_param(const ArcL<T> &A, int ii)
+{
+    return A.t1 + (A.t2 - A.t1) * (T)ii / (T)A.nseg;
+}
+
+template <typename T>
+__device__ inline V3<T> interior_pt(const ArcL<T> &A, int ii) { return conic_at(arc_con(A), sub_param(A, ii)); }
+
+template <typename T>
+__device__ inline V3<T> vert_pos(const Shared<T> &sh, int i) { return v3(sh.vx[i], sh.vy[i], sh.vz[i]); }
+
+struct Params {
+    Inputs in;
+    Work w;
+    FillOut o;
+    int k;
+    float kappa_max;  // FP32 nodes with a vertex above this go to FP64
+};
+
+// statuses that FP64 may resolve
+constexpr int kRetry = NS_NON_ELLIPTIC | NS_LOOP | NS_TOPOLOGY | NS_PREC;
+
+// The whole per-node computation; FILL adds the writes.
+template <bool FILL, typename T>
+__device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
+{
+    constexpr bool F32 = sizeof(T) == 4;
+    const T tp = Cst<T>::two_pi;
+    const int lane = threadIdx.x;
+    const Work &W = P.w;
+    const int64_t N = P.in.n_nodes;
+    const int k = P.k;
+    if (FILL) {
+        if (W.node_cnt[NC_STATUS * N + n] != 0) return;
+        if (W.flags[0] & (DF_CAPACITY | DF_BADLAT | DF_LOOPCAP)) return;
+    }
+    const int64_t row = W.row[n];
+    const int v = (int)(W.row[n + 1] - row);
+    const float4 c4 = W.node4[n];
+    const T rho = (T)c4.w;
+    const V3<T> cen = v3((T)c4.x, (T)c4.y, (T)c4.z);
+    if (lane == 0) {
+        sh.status = 0;
+        sh.n_arc = 0;
+        sh.n_vert = 0;
+        sh.n_contour = 0;
+        sh.wsum = 0;
+    }
+    __syncthreads();
+    if (v == 0 || v > kVmax) {
+        if (!FILL) {
+            if (lane == 0) {
+                for (int c = 0; c < kNodeCols; ++c) W.node_cnt[c * N + n] = 0;
+                W.node_cnt[NC_STATUS * N + n] = v == 0 ? NS_ISOLATED : NS_VALENCE;
+                if (F32) W.node_prec[n] = 0;
+            }
+            for (int i = lane; i < v; i += 64) W.he_len[row + i] = 0;
+        }
+        return;
+    }
+
+    // ---- strut table -----------------------------------------------------
+    if (lane < v) {
+        int2 he = W.he[row + lane];
+        int far = he.x;
+        float4 f4 = W.node4[far];
+        const V3<T> cf = v3((T)f4.x, (T)f4.y, (T)f4.z);
+        SL<T> s;
+        s.sid = he.y;
+        s.far = far;
+        V3<T> d = cf - cen;
+        T L = m_sqrt(dot(d, d));
+        T sig = (rho - (T)f4.w) / L;
+        int bad = (far == n) || !(L > (T)0) || !(m_abs(sig) < (T)1);
+        if (bad) {
+            atomicOr(&sh.status, NS_INVALID_STRUT);
+            L = (T)1;
+            sig = (T)0;
+        }
+        T kap = m_sqrt(((T)1 - sig) * ((T)1 + sig));
+        V3<T> e = d * ((T)1 / L);
+        s.ex = e.x; s.ey = e.y; s.ez = e.z; s.sig = sig; s.kap = kap; s.len = L;
+        s.gx = e.x / kap; s.gy = e.y / kap; s.gz = e.z / kap;
+        s.h = rho * sig / kap;
+        // canonical strut frame from the lower to the higher node id; both
+        // ends compute it from the same two input positions
+        int lower = (int64_t)far > n;
+        s.lower = lower;
+        V3<T> clo = lower ? cen : cf;
+        V3<T> chi = lower ? cf : cen;
+        V3<T> es = chi - clo;
+        es = es * ((T)1 / m_sqrt(dot(es, es)));
+        s.sx = es.x; s.sy = es.y; s.sz = es.z;
+        T ax = m_abs(es.x), ay = m_abs(es.y), az = m_abs(es.z);
+        int j = 0;
+        T am = ax;
+        if (ay < am) { j = 1; am = ay; }
+        if (az < am) { j = 2; }
+        V3<T> axis = v3((T)(j == 0), (T)(j == 1), (T)(j == 2));
+        V3<T> rr = cross(es, axis);
+        rr = rr * ((T)1 / m_sqrt(dot(rr, rr)));
+        V3<T> qq = cross(es, rr);
+        s.rx = rr.x; s.ry = rr.y; s.rz = rr.z;
+        s.qx = qq.x; s.qy = qq.y; s.qz = qq.z;
+        sh.S[lane + 1] = s;
+    }
+    __syncthreads();
+    if (lane < v) {
+        for (int j = 0; j < v; ++j)
+            if (j != lane && sh.S[j + 1].far == sh.S[lane + 1].far) atomicOr(&sh.status, NS_DUPLICATE);
+    }
+    if (F32 && !FILL && lane == 0 && !(P.kappa_max > 0.f)) atomicOr(&sh.status, NS_PREC);  // all FP64
+    __syncthreads();
+    if (sh.status) goto finish;
+
+    // ---- conics, trimming, arcs and owned vertices ------------------------
+    {
+        const int nconic = v * (v + 1) / 2;
+        for (int c0 = 0; c0 < nconic; c0 += 64) {
+            int ci = c0 + lane;
+            int p = 0, q = 0;
+            bool act = ci < nconic;
+            if (act) {
+                int rem = ci;
+                while (rem >= v - p) { rem -= v - p; ++p; }
+                q = p + 1 + rem;
+            }
+            Con<T> C;
+            TrimOut<T> TR;
+            TR.n = 0;
+            TR.full = 0;
+            TR.ovf = 0;
+            if (act) {
+                if (!conic_of(sh.S, rho, p, q, C)) {
+                    atomicOr(&sh.status, NS_NON_ELLIPTIC);
+                } else {
+                    trim_conic(sh.S, v, p, q, C, TR);
+                    if (TR.ovf) atomicOr(&sh.status, NS_CAPACITY);
+                }
+            }
+            // arcs of this conic, sorted by the smaller endpoint name
+            uint32_t ns_[kPieces], ne_[kPieces], key[kPieces];
+#pragma unroll
+            for (int i = 0; i < kPieces; ++i) {
+                if (TR.full) {
+                    ns_[i] = ne_[i] = vname3(p, q, 255, 0);
+                } else {
+                    ns_[i] = tie_name(p, q, TR.pc[i].rs, TR.pc[i].roots & 1);
+                    ne_[i] = tie_name(p, q, TR.pc[i].re, (TR.pc[i].roots >> 1) & 1);
+                }
+                key[i] = i < TR.n ? (ns_[i] < ne_[i] ? ns_[i] : ne_[i]) : 0xffffffffu;
+            }
+            int ord[kPieces];
+#pragma unroll
+            for (int i = 0; i < kPieces; ++i) {
+                int rank = 0;
+#pragma unroll
+                for (int j = 0; j < kPieces; ++j) rank += (key[j] < key[i]) || (key[j] == key[i] && j < i);
+                ord[i] = rank;
+            }
+            int cnt = act ? TR.n : 0, tot;
+            int base = wave_excl_scan(cnt, &tot) + sh.n_arc;
+            if (sh.n_arc + tot > kAcap) {
+                if (lane == 0) atomicOr(&sh.status, NS_CAPACITY);
+            } else {
+#pragma unroll
+                for (int i = 0; i < kPieces; ++i) {
+                    if (i < cnt) {
+                        ArcL<T> &A = sh.A[base + ord[i]];
+                        A.o[0] = C.o.x; A.o[1] = C.o.y; A.o[2] = C.o.z;
+                        A.a[0] = C.a.x; A.a[1] = C.a.y; A.a[2] = C.a.z;
+                        A.b[0] = C.b.x; A.b[1] = C.b.y; A.b[2] = C.b.z;
+                        A.p = p; A.q = q; A.full = TR.full;
+                        if (TR.full) {
+                            A.t1 = (T)0;
+                            A.t2 = tp;
+                        } else {
+                            A.t1 = TR.pc[i].s;
+                            A.t2 = TR.pc[i].e > TR.pc[i].s ? TR.pc[i].e : TR.pc[i].e + tp;
+                        }
+                        A.ns = ns_[i];
+                        A.ne = ne_[i];
+                    }
+                }
+            }
+            // owned vertices: ties (p, q, r) with r > q, and whole-conic starts
+            uint32_t on[2 * kPieces];
+            T ot[2 * kPieces];
+            int orr[2 * kPieces];
+            int own = 0;
+#pragma unroll
+            for (int i = 0; i < kPieces; ++i) {
+#pragma unroll
+                for (int end = 0; end < 2; ++end) {
+                    bool mine = false;
+                    uint32_t nm = 0;
+                    T t = (T)0;
+                    int r = -1;
+                    if (i < cnt) {
+                        if (TR.full) {
+                            mine = (end == 0 && i == 0);
+                            nm = ns_[i];
+                        } else {
+                            r = end ? TR.pc[i].re : TR.pc[i].rs;
+                            mine = r > q;
+                            nm = end ? ne_[i] : ns_[i];
+                            t = end ? TR.pc[i].e : TR.pc[i].s;
+                        }
+                    }
+                    // drop repeats within the conic (degenerate tangencies)
+#pragma unroll
+                    for (int j = 0; j < 2 * kPieces; ++j)
+                        if (j < own && on[j] == nm) mine = false;
+#pragma unroll
+                    for (int j = 0; j < 2 * kPieces; ++j)
+                        if (mine && j == own) { on[j] = nm; ot[j] = t; orr[j] = r; }
+                    if (mine) ++own;
+                }
+            }
+            int ntot;
+            int vbase = wave_excl_scan(own, &ntot) + sh.n_vert;
+            if (sh.n_vert + ntot > kVcap) {
+                if (lane == 0) atomicOr(&sh.status, NS_CAPACITY);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 2 * kPieces; ++i) {
+                    if (i < own) {
+                        int rank = 0;
+#pragma unroll
+                        for (int j = 0; j < 2 * kPieces; ++j) rank += (j < own) && (on[j] < on[i]);
+                        V3<T> w = conic_at(C, ot[i]);
+                        sh.vname[vbase + rank] = on[i];
+                        sh.vx[vbase + rank] = w.x;
+                        sh.vy[vbase + rank] = w.y;
+                        sh.vz[vbase + rank] = w.z;
+                        if (F32 && !FILL && orr[i] >= 0 && tie_kappa(sh.S, p, q, orr[i], w) > (T)P.kappa_max)
+                            atomicOr(&sh.status, NS_PREC);
+                    }
+                }
+            }
+            __syncthreads();
+            // advance the running counts (tot / ntot are wave-uniform)
+            if (lane == 0) {
+                if (sh.n_arc + tot <= kAcap) sh.n_arc += tot;
+                if (sh.n_vert + ntot <= kVcap) sh.n_vert += ntot;
+            }
+            __syncthreads();
+        }
+    }
+    if (sh.status) goto finish;
+
+    // ---- arc ends -> vertex indices, vertex degrees, segment counts -------
+    {
+        const int E = sh.n_arc, V = sh.n_vert;
+        for (int j = lane; j < E; j += 64) {
+            ArcL<T> &A = sh.A[j];
+            A.vs = find_vert(sh, A.ns);
+            A.ve = find_vert(sh, A.ne);
+            if (A.vs < 0 || A.ve < 0) atomicOr(&sh.status, NS_TOPOLOGY);
+            if (A.full) {
+                A.nseg = k;
+            } else {
+                T u = (A.t2 - A.t1) * ((T)k * Cst<T>::inv_two_pi);
+                int ns = (int)m_floor(u) + 1;
+                A.nseg = ns < k ? ns : k;
+            }
+            A.contour = -1;
+        }
+        __syncthreads();
+        for (int i = lane; i < V; i += 64) {
+            if ((sh.vname[i] & 0xff00u) == 0xff00u) continue;
+            int d = 0;
+            for (int j = 0; j < E; ++j) d += (sh.A[j].vs == i && !sh.A[j].full) + (sh.A[j].ve == i && !sh.A[j].full);
+            if (d != 3) atomicOr(&sh.status, NS_TOPOLOGY);
+        }
+        __syncthreads();
+        if (sh.status) goto finish;
+    }
+
+    // ---- end loops per strut ----------------------------------------------
+    {
+        const int E = sh.n_arc;
+        int m = lane + 1;
+        int cnt = 0;
+        if (m <= v)
+            for (int j = 0; j < E; ++j) cnt += (sh.A[j].p == m || sh.A[j].q == m);
+        int tot;
+        int base = wave_excl_scan(cnt, &tot);
+        if (lane < v) sh.loop_base[m] = base;
+        if (lane == 0) sh.loop_base[v + 1] = tot;
+        if (tot > 2 * kAcap) {
+            if (lane == 0) atomicOr(&sh.status, NS_CAPACITY);
+        } else if (m <= v) {
+            const SL<T> &s = sh.S[m];
+            V3<T> es = v3(s.sx, s.sy, s.sz);
+            int pos = base, nfull = 0;
+            for (int j = 0; j < E; ++j) {
+                const ArcL<T> &A = sh.A[j];
+                if (A.p != m && A.q != m) continue;
+                T tm = (T)0.5 * (A.t1 + A.t2);
+                T st, ct;
+                m_sincos(tm, &st, &ct);
+                Con<T> C = arc_con(A);
+                V3<T> w = C.o + C.a * st + C.b * ct;
+                V3<T> dw = C.a * ct - C.b * st;
+                sh.loop_arc[pos] = (uint8_t)j;
+                sh.loop_dir[pos] = dot(cross(w, dw), es) > (T)0 ? 1 : -1;
+                nfull += A.full;
+                ++pos;
+            }
+            bool bad = cnt == 0 || (nfull && cnt != 1);
+            int samples = 0;
+            if (!bad) {
+                // chain: start at the arc whose loop-start vertex has the
+                // smallest name, follow shared vertices
+                auto sname = [&](int pp) {
+                    const ArcL<T> &A = sh.A[sh.loop_arc[pp]];
+                    return sh.loop_dir[pp] > 0 ? A.ns : A.ne;
+                };
+                auto ename = [&](int pp) {
+                    const ArcL<T> &A = sh.A[sh.loop_arc[pp]];
+                    return sh.loop_dir[pp] > 0 ? A.ne : A.ns;
+                };
+                int first = base;
+                for (int pp = base + 1; pp < base + cnt; ++pp)
+                    if (sname(pp) < sname(first)) first = pp;
+                int cur = first, steps = 0;
+                while (true) {
+                    sh.loop_ord[base + steps] = (uint8_t)(cur - base);
+                    ++steps;
+                    samples += sh.A[sh.loop_arc[cur]].nseg;
+                    if (cnt == 1) break;
+                    uint32_t en = ename(cur);
+                    int nxt = -1, hits = 0;
+                    for (int pp = base; pp < base + cnt; ++pp)
+                        if (sname(pp) == en) { nxt = pp; ++hits; }
+                    if (hits != 1) { bad = true; break; }
+                    if (nxt == first) break;
+                    if (steps >= cnt) { bad = true; break; }
+                    cur = nxt;
+                }
+                if (steps != cnt) bad = true;
+            }
+            if (bad) atomicOr(&sh.status, NS_LOOP);
+            sh.loop_len[m] = samples;
+        }
+        __syncthreads();
+        if (sh.status) goto finish;
+    }
+
+    // ---- hole contours ------------------------------------------------------
+    {
+        const int E = sh.n_arc;
+        int ncirc = 0;
+        while (ncirc < E && sh.A[ncirc].p == 0) ++ncirc;  // circular arcs sort first
+        for (int i = lane; i < ncirc; i += 64) {
+            const ArcL<T> &A = sh.A[i];
+            uint32_t lab = A.ns < A.ne ? A.ns : A.ne;
+            if (!A.full) {
+                int cur = i, from = A.vs, steps = 0;
+                while (true) {
+                    const ArcL<T> &B = sh.A[cur];
+                    int to = B.vs == from ? B.ve : B.vs;
+                    uint32_t tn = sh.vname[to];
+                    if (tn < lab) lab = tn;
+                    int nxt = -1, hits = 0;
+                    for (int j = 0; j < ncirc; ++j) {
+                        if (j == cur || sh.A[j].full) continue;
+                        if (sh.A[j].vs == to || sh.A[j].ve == to) { nxt = j; ++hits; }
+                    }
+                    if (hits != 1 || ++steps > ncirc) { atomicOr(&sh.status, NS_TOPOLOGY); break; }
+                    from = to;
+                    cur = nxt;
+                    if (cur == i) break;
+                }
+            }
+            sh.clabel[i] = lab;
+        }
+        __syncthreads();
+        for (int i = lane; i < ncirc; i += 64) {
+            uint32_t lab = sh.clabel[i];
+            int rank = 0;
+            for (int j = 0; j < ncirc; ++j) {
+                uint32_t lj = sh.clabel[j];
+                bool first = true;
+                for (int t = 0; t < j; ++t)
+                    if (sh.clabel[t] == lj) first = false;
+                if (first && lj < lab) ++rank;
+            }
+            sh.A[i].contour = rank;
+            bool first = true;
+            for (int t = 0; t < i; ++t)
+                if (sh.clabel[t] == lab) first = false;
+            if (first) atomicAdd(&sh.n_contour, 1);
+        }
+        __syncthreads();
+        if (lane == 0 && sh.n_vert - sh.n_arc + sh.n_contour != 2 - v) atomicOr(&sh.status, NS_TOPOLOGY);
+        __syncthreads();
+        if (sh.status) goto finish;
+    }
+
+    // ---- mesh-vertex layout, hole centres, loop phi check -------------------
+    {
+        const int E = sh.n_arc, V = sh.n_vert, NC = sh.n_contour;
+        if (lane == 0) {
+            int mb = V;
+            for (int j = 0; j < E; ++j) {
+                sh.A[j].mbase = mb;
+                mb += sh.A[j].nseg - 1;
+            }
+            sh.wsum = mb;  // first hole-centre index
+        }
+        __syncthreads();
+        // Eq. 13: barycentre of each contour's vertices (each once: half of
+        // both ends of every arc plus its interior points), projected on the
+        // nodal sphere; the point opposite is used when the projection falls
+        // under a strut, and -sum(e_m) when the barycentre is within 1e-3 rho
+        // of the centre.
+        for (int c = lane; c < NC; c += 64) {
+            V3<T> sum = zero3<T>();
+            int cntv = 0;
+            for (int j = 0; j < E && sh.A[j].p == 0; ++j) {
+                const ArcL<T> &A = sh.A[j];
+                if (A.contour != c) continue;
+                sum = sum + (vert_pos(sh, A.vs) + vert_pos(sh, A.ve)) * (T)0.5;
+                for (int ii = 1; ii < A.nseg; ++ii) sum = sum + interior_pt(A, ii);
+                cntv += A.nseg;
+            }
+            V3<T> b = sum * ((T)1 / (T)cntv);
+            T bl = m_sqrt(dot(b, b));
+            // the apex direction b/|b| amplifies rounding by rho/|b|; the
+            // fallback decision near |b| = 1e-3 rho is fragile as well
+            if (F32 && !FILL && bl * (T)P.kappa_max < rho) atomicOr(&sh.status, NS_PREC);
+            V3<T> dir;
+            if (bl >= (T)1e-3 * rho) {
+                dir = b * ((T)1 / bl);
+            } else {
+                V3<T> se = zero3<T>();
+                for (int m = 1; m <= v; ++m) se = se + v3(sh.S[m].ex, sh.S[m].ey, sh.S[m].ez);
+                T sl = m_sqrt(dot(se, se));
+                if (sl < (T)1e-3) { atomicOr(&sh.status, NS_TOPOLOGY); sl = (T)1; }
+                dir = se * ((T)-1 / sl);
+            }
+            for (int flip = 0; flip < 2; ++flip) {
+                T pm = (T)-1e30;
+                for (int m = 1; m <= v; ++m) pm = m_max(pm, dot(gvec(sh.S[m]), dir * rho) - sh.S[m].h);
+                if (pm <= (T)0) break;
+                if (flip) atomicOr(&sh.status, NS_TOPOLOGY);
+                dir = dir * (T)-1;
+            }
+            sh.hc[c][0] = dir.x * rho;
+            sh.hc[c][1] = dir.y * rho;
+            sh.hc[c][2] = dir.z * rho;
+        }
+        // strut end loops must be graphs over phi: strictly increasing, one
+        // turn; FILL also writes the loop samples for the strut bands
+        int m = lane + 1;
+        if (m <= v) {
+            const SL<T> &s = sh.S[m];
+            int b0 = sh.loop_base[m], cnt = sh.loop_base[m + 1] - b0;
+            int64_t lbase = FILL ? W.he_off[row + lane] : 0;
+            const int lcap = FILL ? W.he_len[row + lane] : 0;
+            int32_t mbase_g = 0;
+            if (FILL) mbase_g = (int32_t)W.node_off[3 * (N + 1) + n];
+            T first = (T)0, prev = (T)0, wind = (T)0, minstep = (T)1e30;
+            int idx = 0;
+            for (int t = 0; t < cnt; ++t) {
+                int pp = b0 + sh.loop_ord[b0 + t];
+                const ArcL<T> &A = sh.A[sh.loop_arc[pp]];
+                int d = sh.loop_dir[pp];
+                for (int j = 0; j < A.nseg; ++j) {
+                    int ii = d > 0 ? j : A.nseg - j;
+                    int li = j == 0 ? (d > 0 ? A.vs : A.ve) : interior_idx(A, ii);
+                    T ph;
+                    if (A.p == 0) {
+                        // tangency circles are parametrised in the strut
+                        // frame: phi is the parameter itself
+                        T tt = sub_param(A, ii);
+                        if (tt >= tp) tt -= tp;
+                        if (tt > Cst<T>::pi) tt -= tp;
+                        ph = tt;
+                    } else {
+                        V3<T> w = j == 0 ? vert_pos(sh, li) : interior_pt(A, ii);
+                        ph = phi_of(s, w);
+                    }
+                    if (idx == 0) {
+                        first = ph;
+                    } else {
+                        T dp = ph - prev;
+                        if (dp <= -Cst<T>::pi) dp += tp;
+                        if (dp > Cst<T>::pi) dp -= tp;
+                        wind += dp;
+                        minstep = m_min(minstep, dp);
+                    }
+                    if (FILL && idx < lcap) W.loop[lbase + idx] = make_int2(mbase_g + li, __float_as_int((float)ph));
+                    prev = ph;
+                    ++idx;
+                }
+            }
+            if (idx == 1) {
+                wind = tp;
+                minstep = tp;
+            } else {
+                T dp = first - prev;
+                if (dp <= -Cst<T>::pi) dp += tp;
+                if (dp > Cst<T>::pi) dp -= tp;
+                wind += dp;
+                minstep = m_min(minstep, dp);
+            }
+            if (!(minstep > (T)0) || m_abs(wind - tp) > (T)1e-3) atomicOr(&sh.status, NS_LOOP);
+        }
+        __syncthreads();
+    }
+
+finish:
+    __syncthreads();
+    {
+        const int status = sh.status;
+        const int E = sh.n_arc, V = sh.n_vert, NC = sh.n_contour;
+        int Msum = 0, Fsum = 0;
+        if (!status) {
+            Msum = sh.wsum + NC;
+            for (int j = 0; j < E; ++j)
+                if (sh.A[j].p == 0) Fsum += sh.A[j].nseg;
+        }
+        if (!FILL) {
+            if (lane == 0) {
+                W.node_cnt[NC_VERT * N + n] = status ? 0 : V;
+                W.node_cnt[NC_ARC * N + n] = status ? 0 : E;
+                W.node_cnt[NC_HOLE * N + n] = status ? 0 : NC;
+                W.node_cnt[NC_MESH * N + n] = Msum;
+                W.node_cnt[NC_FAN * N + n] = Fsum;
+                W.node_cnt[NC_STATUS * N + n] = status & ~NS_PREC;
+                if (F32) {
+                    // hand the node to the FP64 pass when precision may be at fault
+                    int retry = (status & kRetry) != 0;
+                    W.node_prec[n] = (uint8_t)retry;
+                    if (retry) W.fb_list[atomicAdd(&W.flags[2], 1)] = (int32_t)n;
+                }
+            }
+            if (lane < v) W.he_len[row + lane] = status ? 0 : sh.loop_len[lane + 1];
+            return;
+        }
+        // FILL: the recomputation must reproduce the counted node
+        if (status || W.node_cnt[NC_VERT * N + n] != V || W.node_cnt[NC_ARC * N + n] != E ||
+            W.node_cnt[NC_MESH * N + n] != Msum || W.node_cnt[NC_FAN * N + n] != Fsum) {
+            if (lane == 0) atomicOr(W.flags, DF_MISMATCH);
+            return;
+        }
+        const int64_t Np1 = N + 1;
+        const int64_t voff = W.node_off[0 * Np1 + n], aoff = W.node_off[1 * Np1 + n];
+        const int64_t moff = W.node_off[3 * Np1 + n], foff = W.node_off[4 * Np1 + n];
+        const FillOut &O = P.o;
+        // meta-mesh vertices and arcs (local coordinates)
+        if (O.vert_name) {
+            for (int i = lane; i < V; i += 64) {
+                O.vert_name[voff + i] = sh.vname[i];
+                O.vert_xyz[0 * O.cap_vert + voff + i] = (float)sh.vx[i];
+                O.vert_xyz[1 * O.cap_vert + voff + i] = (float)sh.vy[i];
+                O.vert_xyz[2 * O.cap_vert + voff + i] = (float)sh.vz[i];
+            }
+        }
+        if (O.arc_f32) {
+            for (int j = lane; j < E; j += 64) {
+                const ArcL<T> &A = sh.A[j];
+                const int64_t cA = O.cap_arc;
+                T f[11] = {A.o[0], A.o[1], A.o[2], A.a[0], A.a[1], A.a[2], A.b[0], A.b[1], A.b[2], A.t1, A.t2};
+#pragma unroll
+                for (int t = 0; t < 11; ++t) O.arc_f32[t * cA + aoff + j] = (float)f[t];
+                O.arc_u32[0 * cA + aoff + j] = (uint32_t)A.p | ((uint32_t)A.q << 8) | ((uint32_t)A.full << 16);
+                O.arc_u32[1 * cA + aoff + j] = (uint32_t)A.vs | ((uint32_t)A.ve << 16);
+                O.arc_u32[2 * cA + aoff + j] = (uint32_t)n;
+            }
+        }
+        // mesh vertices: meta-vertices, interior points, hole centres
+        for (int i = lane; i < Msum; i += 64) {
+            V3<T> w;
+            if (i < V) {
+                w = vert_pos(sh, i);
+            } else if (i < sh.wsum) {
+                int lo = 0, hi = E - 1;  // last arc with mbase <= i
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (sh.A[mid].mbase <= i) lo = mid;
+                    else hi = mid - 1;
+                }
+                const ArcL<T> &A = sh.A[lo];
+                int jc = i - A.mbase;
+                bool fwd = A.full || A.ns <= A.ne;
+                int ii = fwd ? jc + 1 : A.nseg - 1 - jc;
+                w = interior_pt(A, ii);
+            } else {
+                int c = i - sh.wsum;
+                w = v3(sh.hc[c][0], sh.hc[c][1], sh.hc[c][2]);
+            }
+            V3<T> x = cen + w;
+            float *dst = O.mesh_xyz + 3 * (moff + i);
+            dst[0] = (float)x.x;
+            dst[1] = (float)x.y;
+            dst[2] = (float)x.z;
+        }
+        // hole fans: one triangle per circular-arc segment
+        const int64_t fan0 = W.band_off[P.in.n_struts] + foff;
+        int fbase = 0;
+        for (int j = 0; j < E && sh.A[j].p == 0; ++j) {
+            const ArcL<T> &A = sh.A[j];
+            bool fwd = A.full || A.ns <= A.ne;
+            bool lower = sh.S[A.q].lower;
+            int ctr = sh.wsum + A.contour;
+            for (int s = lane; s < A.nseg; s += 64) {
+                int i0 = fwd ? s : A.nseg - s, i1 = fwd ? s + 1 : A.nseg - s - 1;
+                int lo_i = i0 < i1 ? i0 : i1, hi_i = i0 < i1 ? i1 : i0;
+                int u = lo_i == 0 ? A.vs : interior_idx(A, lo_i);
+                int u2 = hi_i == A.nseg ? A.ve : interior_idx(A, hi_i);
+                int32_t *t = O.tri + 3 * (fan0 + fbase + s);
+                t[0] = (int32_t)(moff + ctr);
+                t[1] = (int32_t)(moff + (lower ? u2 : u));
+                t[2] = (int32_t)(moff + (lower ? u : u2));
+            }
+            fbase += A.nseg;
+        }
+    }
+}
+
+// FP32: one node per block
+template <bool FILL>
+__global__ void __launch_bounds__(64) k_node32(Params P)
+{
+    __shared__ Shared<float> sh;
+    const int64_t n = blockIdx.x;
+    if (n >= P.in.n_nodes) return;
+    if (FILL && P.w.node_prec[n]) return;
+    node_body<FILL, float>(P, sh, n);
+}
+
+// FP64: the nodes the FP32 pass handed over, looped over by a fixed grid
+template <bool FILL>
+__global__ void __launch_bounds__(64) k_node64(Params P)
+{
+    __shared__ Shared<double> sh;
+    const int cnt = P.w.flags[2];
+    for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+        node_body<FILL, double>(P, sh, (int64_t)P.w.fb_list[i]);
+        __syncthreads();
+    }
+}
+
+constexpr unsigned kFp64Grid = 2048;
+
+}  // namespace
+
+hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, const FillOut *o, int fp64,
+                       hipStream_t st)
+{
+    if (in.n_nodes == 0) return hipSuccess;
+    Params P;
+    P.in = in;
+    P.w = w;
+    P.o = o ? *o : FillOut{};
+    P.k = k;
+    P.kappa_max = kappa_max;
+    if (!o && !fp64) k_node32<false><<<(unsigned)in.n_nodes, 64, 0, st>>>(P);
+    if (!o && fp64) k_node64<false><<<kFp64Grid, 64, 0, st>>>(P);
+    if (o && !fp64) k_node32<true><<<(unsigned)in.n_nodes, 64, 0, st>>>(P);
+    if (o && fp64) k_node64<true><<<kFp64Grid, 64, 0, st>>>(P);
+    return hipGetLastError();
+}
+
+}  // namespace lm

@@ -1,0 +1,211 @@
+// Lattice preparation (validation and node adjacency) and the device-wide
+// exclusive scans used for every offset array.
+#include "common.h"
+
+namespace lm {
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ void k_pack(Inputs in, float4 *node4, int32_t *deg)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= in.n_nodes) return;
+    node4[i] = make_float4(in.x[i], in.y[i], in.z[i], in.r[i]);
+    deg[i] = 0;
+}
+
+// Degree histogram; out-of-range endpoints raise DF_BADLAT.
+__global__ void k_degree(Inputs in, int32_t *deg, int32_t *flags)
+{
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= in.n_struts) return;
+    int32_t a = in.sa[s], b = in.sb[s];
+    if (a < 0 || b < 0 || (int64_t)a >= in.n_nodes || (int64_t)b >= in.n_nodes) {
+        atomicOr(&flags[1], DF_BADLAT);
+        return;
+    }
+    atomicAdd(&deg[a], 1);
+    if (b != a) atomicAdd(&deg[b], 1);
+}
+
+__global__ void k_zero(int32_t *p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void k_scatter(Inputs in, const int64_t *row, int32_t *cursor, int2 *he)
+{
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= in.n_struts) return;
+    int32_t a = in.sa[s], b = in.sb[s];
+    if (a < 0 || b < 0 || (int64_t)a >= in.n_nodes || (int64_t)b >= in.n_nodes) return;
+    int64_t pa = row[a] + atomicAdd(&cursor[a], 1);
+    he[pa] = make_int2(b, (int32_t)s);
+    if (b != a) {
+        int64_t pb = row[b] + atomicAdd(&cursor[b], 1);
+        he[pb] = make_int2(a, (int32_t)s);
+    }
+}
+
+// Incident struts of each node in increasing strut id (canonical labels
+// 1..v), then the half-edge index of every strut at its lower and higher
+// node id.
+__global__ void k_sort_rows(int64_t n_nodes, const int64_t *row, int2 *he, int64_t *strut_he, const int32_t *sa,
+                            const int32_t *sb)
+{
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_nodes) return;
+    int64_t b = row[n], e = row[n + 1];
+    for (int64_t i = b + 1; i < e; ++i) {
+        int2 x = he[i];
+        int64_t j = i - 1;
+        while (j >= b && he[j].y > x.y) {
+            he[j + 1] = he[j];
+            --j;
+        }
+        he[j + 1] = x;
+    }
+    for (int64_t i = b; i < e; ++i) {
+        int32_t s = he[i].y;
+        int32_t a = sa[s], c = sb[s];
+        int32_t lo = a < c ? a : c;
+        if (a == c) {
+            strut_he[2 * (int64_t)s] = i;
+            strut_he[2 * (int64_t)s + 1] = i;
+        } else {
+            strut_he[2 * (int64_t)s + (n == lo ? 0 : 1)] = i;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Multi-column exclusive scan, int32 -> int64: reduce, scan partials, scan
+// tiles.  Column c of the source starts at src + c*src_stride, of the
+// destination at dst + c*dst_stride; dst[c][n] receives the column total.
+
+constexpr int kScanItems = 8;
+constexpr int kTile = kBlock * kScanItems;
+
+__device__ inline int64_t wave_incl_scan(int64_t x)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of one value per thread across the block; returns the
+// exclusive prefix and writes the block total to *total.
+__device__ inline int64_t block_excl_scan(int64_t x, int64_t *total)
+{
+    __shared__ int64_t wsum[kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int64_t inc = wave_incl_scan(x);
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int64_t base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        if (w < wid) base += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - x;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_reduce(const int32_t *src, int64_t n, int64_t src_stride, int64_t *part,
+                                                        int64_t nb)
+{
+    const int32_t *s = src + blockIdx.y * src_stride;
+    int64_t base = (int64_t)blockIdx.x * kTile;
+    int64_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+        if (i < n) acc += s[i];
+    }
+    int64_t tot;
+    block_excl_scan(acc, &tot);
+    if (threadIdx.x == 0) part[blockIdx.y * nb + blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_partials(int64_t *part, int64_t nb, int64_t *dst, int64_t n,
+                                                          int64_t dst_stride)
+{
+    int64_t *p = part + blockIdx.y * nb;
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
+        int64_t i = b0 + threadIdx.x;
+        int64_t x = i < nb ? p[i] : 0;
+        int64_t tot;
+        int64_t ex = block_excl_scan(x, &tot);
+        if (i < nb) p[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) dst[blockIdx.y * dst_stride + n] = carry;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_tiles(const int32_t *src, int64_t n, int64_t src_stride,
+                                                       const int64_t *part, int64_t nb, int64_t *dst,
+                                                       int64_t dst_stride)
+{
+    const int32_t *s = src + blockIdx.y * src_stride;
+    int64_t *d = dst + blockIdx.y * dst_stride;
+    int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t v[kScanItems];
+    int64_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t i = base + j;
+        v[j] = i < n ? s[i] : 0;
+        acc += v[j];
+    }
+    int64_t tot;
+    int64_t ex = block_excl_scan(acc, &tot) + part[blockIdx.y * nb + blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t i = base + j;
+        if (i < n) d[i] = ex;
+        ex += v[j];
+    }
+}
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+}  // namespace
+
+int64_t scan_tmp_needed(int64_t n, int ncols) { return ((n + kTile - 1) / kTile + 1) * ncols; }
+
+hipError_t launch_scan(const int32_t *src, int64_t *dst, int64_t n, int ncols, int64_t src_stride,
+                       int64_t dst_stride, int64_t *tmp, int64_t tmp_len, hipStream_t st)
+{
+    int64_t nb = (n + kTile - 1) / kTile;
+    if (nb < 1) nb = 1;
+    if (nb * ncols > tmp_len) return hipErrorInvalidValue;
+    dim3 g((unsigned)nb, (unsigned)ncols);
+    k_scan_reduce<<<g, kBlock, 0, st>>>(src, n, src_stride, tmp, nb);
+    k_scan_partials<<<dim3(1, ncols), kBlock, 0, st>>>(tmp, nb, dst, n, dst_stride);
+    k_scan_tiles<<<g, kBlock, 0, st>>>(src, n, src_stride, tmp, nb, dst, dst_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare(const Inputs &in, const Work &w, hipStream_t st)
+{
+    int64_t N = in.n_nodes, S = in.n_struts;
+    if (N > 0) k_pack<<<grid_for(N, kBlock), kBlock, 0, st>>>(in, w.node4, w.deg);
+    if (S > 0) k_degree<<<grid_for(S, kBlock), kBlock, 0, st>>>(in, w.deg, w.flags);
+    hipError_t e = launch_scan(w.deg, w.row, N, 1, 0, 0, w.scan_tmp, w.scan_tmp_len, st);
+    if (e != hipSuccess) return e;
+    if (N > 0) k_zero<<<grid_for(N, kBlock), kBlock, 0, st>>>(w.deg, N);
+    if (S > 0) k_scatter<<<grid_for(S, kBlock), kBlock, 0, st>>>(in, w.row, w.deg, w.he);
+    if (N > 0) k_sort_rows<<<grid_for(N, kBlock), kBlock, 0, st>>>(N, w.row, w.he, w.strut_he, in.sa, in.sb);
+    return hipGetLastError();
+}
+
+}  // namespace lm

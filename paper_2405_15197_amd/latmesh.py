@@ -1,0 +1,357 @@
+"""ctypes binding of liblatmesh.so (include/latmesh.h) plus a thin torch-side
+helper that allocates device buffers.  All computation happens in the HIP
+kernels of the library; this module only marshals arguments.  There is no
+CPU fallback: if the library or a GPU is missing, calls raise."""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblatmesh.so")
+
+LM_OK = 0
+LM_ERR_INVALID_ARG = -1
+LM_ERR_BAD_LATTICE = -2
+LM_ERR_CAPACITY = -3
+LM_ERR_UNSUPPORTED = -4
+LM_ERR_HIP = -5
+LM_ERR_STATE = -6
+LM_ERR_INTERNAL = -7
+
+LM_NODE_INVALID_STRUT = 1
+LM_NODE_NON_ELLIPTIC = 2
+LM_NODE_LOOP = 4
+LM_NODE_TOPOLOGY = 8
+LM_NODE_ISOLATED = 16
+LM_NODE_VALENCE = 32
+LM_NODE_DUPLICATE = 64
+LM_NODE_CAPACITY = 128
+
+# every function the header declares (checked by the CPU tests)
+EXPORTS = (
+    "lm_plan_create",
+    "lm_prepare",
+    "lm_count",
+    "lm_fill",
+    "lm_forward",
+    "lm_read_totals",
+    "lm_set_precision",
+    "lm_set_profiling",
+    "lm_get_profile",
+    "lm_plan_destroy",
+    "lm_status_string",
+)
+
+
+class lm_lattice(ctypes.Structure):
+    _fields_ = [
+        ("n_nodes", ctypes.c_int64),
+        ("n_struts", ctypes.c_int64),
+        ("d_x", ctypes.c_void_p),
+        ("d_y", ctypes.c_void_p),
+        ("d_z", ctypes.c_void_p),
+        ("d_radius", ctypes.c_void_p),
+        ("d_strut_a", ctypes.c_void_p),
+        ("d_strut_b", ctypes.c_void_p),
+    ]
+
+
+_TOTAL_FIELDS = [
+    "n_vertices",
+    "n_arcs",
+    "n_holes",
+    "n_mesh_vertices",
+    "n_triangles",
+    "n_band_triangles",
+    "n_fan_triangles",
+    "n_loop_entries",
+    "n_bad_nodes",
+    "n_skipped_struts",
+    "n_fp64_nodes",
+]
+
+
+class lm_totals(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in _TOTAL_FIELDS]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f in _TOTAL_FIELDS}
+
+
+class lm_outputs(ctypes.Structure):
+    _fields_ = [
+        ("d_mesh_xyz", ctypes.c_void_p),
+        ("d_tri", ctypes.c_void_p),
+        ("cap_mesh_vertices", ctypes.c_int64),
+        ("cap_triangles", ctypes.c_int64),
+        ("d_vert_name", ctypes.c_void_p),
+        ("d_vert_xyz", ctypes.c_void_p),
+        ("cap_vertices", ctypes.c_int64),
+        ("d_arc_f32", ctypes.c_void_p),
+        ("d_arc_u32", ctypes.c_void_p),
+        ("cap_arcs", ctypes.c_int64),
+        ("d_node_off", ctypes.c_void_p),
+        ("d_node_status", ctypes.c_void_p),
+        ("d_strut_off", ctypes.c_void_p),
+    ]
+
+
+class LatmeshError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {lm_status_string(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load liblatmesh.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run paper_2405_15197_amd/build.py (or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.lm_plan_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(lm_lattice), P]
+    lib.lm_plan_create.restype = ctypes.c_int
+    lib.lm_count.argtypes = [P, ctypes.c_int, ctypes.POINTER(lm_totals)]
+    lib.lm_count.restype = ctypes.c_int
+    lib.lm_fill.argtypes = [P, ctypes.POINTER(lm_outputs)]
+    lib.lm_fill.restype = ctypes.c_int
+    lib.lm_forward.argtypes = [P, ctypes.c_int, ctypes.POINTER(lm_outputs)]
+    lib.lm_forward.restype = ctypes.c_int
+    lib.lm_read_totals.argtypes = [P, ctypes.POINTER(lm_totals)]
+    lib.lm_read_totals.restype = ctypes.c_int
+    lib.lm_prepare.argtypes = [P]
+    lib.lm_prepare.restype = ctypes.c_int
+    lib.lm_set_profiling.argtypes = [P, ctypes.c_int]
+    lib.lm_set_profiling.restype = ctypes.c_int
+    lib.lm_get_profile.argtypes = [P, P, P, ctypes.c_int]
+    lib.lm_get_profile.restype = ctypes.c_int
+    lib.lm_set_precision.argtypes = [P, ctypes.c_float]
+    lib.lm_set_precision.restype = ctypes.c_int
+    lib.lm_plan_destroy.argtypes = [P]
+    lib.lm_plan_destroy.restype = None
+    lib.lm_status_string.argtypes = [ctypes.c_int]
+    lib.lm_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+# ---- same-named thin wrappers -------------------------------------------
+
+
+def lm_status_string(code: int) -> str:
+    return load().lm_status_string(int(code)).decode()
+
+
+def lm_plan_create(lat: lm_lattice, stream: int | None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    rc = load().lm_plan_create(ctypes.byref(h), ctypes.byref(lat), ctypes.c_void_p(stream or 0))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_plan_create")
+    return h
+
+
+def lm_count(plan, k: int) -> lm_totals:
+    t = lm_totals()
+    rc = load().lm_count(plan, int(k), ctypes.byref(t))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_count")
+    return t
+
+
+def lm_fill(plan, out: lm_outputs) -> None:
+    rc = load().lm_fill(plan, ctypes.byref(out))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_fill")
+
+
+def lm_forward(plan, k: int, out: lm_outputs) -> None:
+    rc = load().lm_forward(plan, int(k), ctypes.byref(out))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_forward")
+
+
+def lm_read_totals(plan) -> lm_totals:
+    t = lm_totals()
+    rc = load().lm_read_totals(plan, ctypes.byref(t))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_read_totals")
+    return t
+
+
+PHASES = ("prepare", "count_fp32", "count_fp64", "sizes", "fill_fp32", "fill_fp64", "bands")
+
+
+def lm_prepare(plan) -> None:
+    rc = load().lm_prepare(plan)
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_prepare")
+
+
+def lm_set_profiling(plan, on: bool) -> None:
+    rc = load().lm_set_profiling(plan, 1 if on else 0)
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_set_profiling")
+
+
+def lm_get_profile(plan) -> dict:
+    """{phase: (milliseconds summed, calls)} since the last call."""
+    ms = np.zeros(len(PHASES), np.float64)
+    calls = np.zeros(len(PHASES), np.int64)
+    rc = load().lm_get_profile(plan, ms.ctypes.data_as(ctypes.c_void_p), calls.ctypes.data_as(ctypes.c_void_p),
+                               len(PHASES))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_get_profile")
+    return {p: (float(m), int(c)) for p, m, c in zip(PHASES, ms, calls)}
+
+
+def lm_set_precision(plan, kappa_max: float) -> None:
+    rc = load().lm_set_precision(plan, float(kappa_max))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_set_precision")
+
+
+def lm_plan_destroy(plan) -> None:
+    load().lm_plan_destroy(plan)
+
+
+# ---- torch helper ----------------------------------------------------------
+
+
+@dataclasses.dataclass
+class MeshResult:
+    totals: dict
+    mesh_xyz: object  # torch float32 [M, 3]
+    tri: object  # torch int32 [T, 3]
+    vert_name: object | None = None  # torch int32 (uint32 bits) [V]
+    vert_xyz: object | None = None  # torch float32 [3, V] (node local)
+    arc_f32: object | None = None  # torch float32 [11, E]
+    arc_u32: object | None = None  # torch int32 (uint32 bits) [3, E]
+    node_off: object | None = None  # torch int64 [5, N+1]
+    node_status: object | None = None  # torch uint8 [N]
+    strut_off: object | None = None  # torch int64 [S+1]
+
+
+class Mesher:
+    """Owns device copies of a lattice and one plan.  ``lat`` is any object
+    with x, y, z, radius (float32) and strut_a, strut_b (int32) arrays."""
+
+    def __init__(self, lat, device: str = "cuda:0", kappa_max: float | None = None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("latmesh needs a GPU (torch.cuda.is_available() is False)")
+        load()
+        self.torch = torch
+        self.device = torch.device(device)
+        f = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(self.device)  # noqa: E731
+        self.x = f(lat.x, torch.float32)
+        self.y = f(lat.y, torch.float32)
+        self.z = f(lat.z, torch.float32)
+        self.r = f(lat.radius, torch.float32)
+        self.sa = f(lat.strut_a, torch.int32)
+        self.sb = f(lat.strut_b, torch.int32)
+        self.n_nodes = int(self.x.shape[0])
+        self.n_struts = int(self.sa.shape[0])
+        self._lat = lm_lattice(
+            self.n_nodes,
+            self.n_struts,
+            self.x.data_ptr(),
+            self.y.data_ptr(),
+            self.z.data_ptr(),
+            self.r.data_ptr(),
+            self.sa.data_ptr(),
+            self.sb.data_ptr(),
+        )
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream().cuda_stream
+            self.plan = lm_plan_create(self._lat, self.stream)
+        if kappa_max is not None:
+            lm_set_precision(self.plan, kappa_max)
+        self.totals = None
+
+    def count(self, k: int) -> dict:
+        self.totals = lm_count(self.plan, k).as_dict()
+        self.k = k
+        return self.totals
+
+    def alloc(self, totals: dict | None = None, meta: bool = True) -> MeshResult:
+        torch = self.torch
+        t = totals or self.totals
+        dev = self.device
+        r = MeshResult(
+            totals=dict(t),
+            mesh_xyz=torch.empty((max(t["n_mesh_vertices"], 1), 3), dtype=torch.float32, device=dev),
+            tri=torch.empty((max(t["n_triangles"], 1), 3), dtype=torch.int32, device=dev),
+        )
+        if meta:
+            r.vert_name = torch.empty(max(t["n_vertices"], 1), dtype=torch.int32, device=dev)
+            r.vert_xyz = torch.empty((3, max(t["n_vertices"], 1)), dtype=torch.float32, device=dev)
+            r.arc_f32 = torch.empty((11, max(t["n_arcs"], 1)), dtype=torch.float32, device=dev)
+            r.arc_u32 = torch.empty((3, max(t["n_arcs"], 1)), dtype=torch.int32, device=dev)
+        r.node_off = torch.empty((5, self.n_nodes + 1), dtype=torch.int64, device=dev)
+        r.node_status = torch.empty(max(self.n_nodes, 1), dtype=torch.uint8, device=dev)
+        r.strut_off = torch.empty(self.n_struts + 1, dtype=torch.int64, device=dev)
+        return r
+
+    def outputs(self, r: MeshResult) -> lm_outputs:
+        p = lambda x: x.data_ptr() if x is not None else None  # noqa: E731
+        return lm_outputs(
+            p(r.mesh_xyz),
+            p(r.tri),
+            r.mesh_xyz.shape[0],
+            r.tri.shape[0],
+            p(r.vert_name),
+            p(r.vert_xyz),
+            r.vert_name.shape[0] if r.vert_name is not None else 0,
+            p(r.arc_f32),
+            p(r.arc_u32),
+            r.arc_f32.shape[1] if r.arc_f32 is not None else 0,
+            p(r.node_off),
+            p(r.node_status),
+            p(r.strut_off),
+        )
+
+    def fill(self, r: MeshResult) -> MeshResult:
+        lm_fill(self.plan, self.outputs(r))
+        return r
+
+    def run(self, k: int, meta: bool = True) -> MeshResult:
+        """count + allocate + fill; returns device tensors trimmed to size."""
+        t = self.count(k)
+        r = self.fill(self.alloc(t, meta=meta))
+        self.torch.cuda.synchronize(self.device)
+        err = lm_read_totals(self.plan)  # raises on device-side errors
+        r.totals = err.as_dict()
+        r.mesh_xyz = r.mesh_xyz[: t["n_mesh_vertices"]]
+        r.tri = r.tri[: t["n_triangles"]]
+        if meta:
+            r.vert_name = r.vert_name[: t["n_vertices"]]
+            r.vert_xyz = r.vert_xyz[:, : t["n_vertices"]]
+            r.arc_f32 = r.arc_f32[:, : t["n_arcs"]]
+            r.arc_u32 = r.arc_u32[:, : t["n_arcs"]]
+        r.node_status = r.node_status[: self.n_nodes]
+        return r
+
+    def forward(self, k: int, r: MeshResult) -> None:
+        lm_forward(self.plan, k, self.outputs(r))
+
+    def close(self):
+        if getattr(self, "plan", None) is not None:
+            lm_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,68 @@
+"""The C ABI: the library loads and exports every function include/latmesh.h
+declares (no GPU needed: nothing is launched)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+import latgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "latmesh.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(lm_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    from paper_2405_15197_amd import latmesh
+
+    lib = latmesh.load()
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in latmesh.h but not exported"
+    assert set(names) == set(latmesh.EXPORTS), "binding and header disagree"
+
+
+def test_status_strings_and_invalid_args():
+    from paper_2405_15197_amd import latmesh
+
+    lib = latmesh.load()
+    for code in range(-7, 1):
+        assert latmesh.lm_status_string(code) != "unknown status"
+    # null plan pointer is rejected without touching the GPU
+    assert lib.lm_count(None, 8, ctypes.byref(latmesh.lm_totals())) == latmesh.LM_ERR_INVALID_ARG
+    assert lib.lm_fill(None, None) == latmesh.LM_ERR_INVALID_ARG
+    assert lib.lm_plan_create(None, None, None) == latmesh.LM_ERR_INVALID_ARG
+    h = ctypes.c_void_p()
+    lat = latmesh.lm_lattice(-1, 0, None, None, None, None, None, None)
+    assert lib.lm_plan_create(ctypes.byref(h), ctypes.byref(lat), None) == latmesh.LM_ERR_INVALID_ARG
+    lat = latmesh.lm_lattice(4, 1 << 31, 1, 1, 1, 1, 1, 1)
+    assert lib.lm_plan_create(ctypes.byref(h), ctypes.byref(lat), None) == latmesh.LM_ERR_UNSUPPORTED
+
+
+def test_structs_match_header_layout():
+    from paper_2405_15197_amd import latmesh
+
+    assert ctypes.sizeof(latmesh.lm_lattice) == 8 * 8
+    assert ctypes.sizeof(latmesh.lm_totals) == 8 * len(latmesh._TOTAL_FIELDS)
+    assert ctypes.sizeof(latmesh.lm_outputs) == 8 * 13
+
+
+def test_generators_are_seeded_and_counted():
+    a = latgen.config(2, scale=4, seed=3)
+    b = latgen.config(2, scale=4, seed=3)
+    c = latgen.config(2, scale=4, seed=4)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.radius, b.radius)
+    assert not np.array_equal(a.x, c.x)
+    assert (latgen.config(1).n_nodes, latgen.config(1).n_struts) == (343, 882)
+    n = 64
+    assert ((n + 1) ** 3 + n**3, 8 * n**3) == (536769, 2097152)
+    o = latgen.config(4, scale=3)
+    deg = np.bincount(np.concatenate([o.strut_a, o.strut_b]))
+    assert deg.max() == 12
