@@ -91,6 +91,7 @@ size_t carve(lm::Work &w, char *base, int64_t N, int64_t S)
     w.node_off = (int64_t *)take(sizeof(int64_t) * lm::kNodeScanCols * (N + 1));
     w.he_len = (int32_t *)take(sizeof(int32_t) * (H + 1));
     w.he_off = (int64_t *)take(sizeof(int64_t) * (H + 1));
+    w.he_rot = (int32_t *)take(sizeof(int32_t) * (H + 1));
     w.band_cnt = (int32_t *)take(sizeof(int32_t) * (S + 1));
     w.band_off = (int64_t *)take(sizeof(int64_t) * (S + 1));
     int64_t tl = lm::scan_tmp_needed(N, lm::kNodeScanCols);

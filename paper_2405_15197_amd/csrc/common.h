@@ -67,6 +67,7 @@ struct Work {
     int64_t *node_off;      // [kNodeScanCols][N+1]
     int32_t *he_len;        // [2S] loop samples per half-edge
     int64_t *he_off;        // [2S+1]
+    int32_t *he_rot;        // [2S] loop position of the smallest phi
     int32_t *band_cnt;      // [S]
     int64_t *band_off;      // [S+1]
     int2 *loop;             // [n_loop] (global mesh vertex, phi bits)

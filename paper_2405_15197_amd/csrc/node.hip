@@ -124,8 +124,17 @@ struct Shared {
     uint8_t loop_ord[2 * kAcap];
     int loop_base[kVmax + 2];
     int loop_len[kVmax + 1];  // samples |L_m|
+    int loop_cnt[kVmax + 1];  // arcs per loop, then fill cursor
+    int loop_first[kVmax + 1];
+    int loop_full[kVmax + 1];
+    uint8_t loop_next[2 * kAcap];
+    int vdeg[kVcap];
     uint32_t clabel[kAcap];
     T hc[kAcap][3];           // hole centre (local) per contour
+    int entry_off[2 * kAcap + 1];   // first loop sample of each loop entry
+    uint8_t entry_m[2 * kAcap];     // strut label of each loop entry
+    int loop_desc[kVmax + 1];       // descents of phi along each loop
+    unsigned long long loop_rot[kVmax + 1];  // (ordered phi bits, sample) minimum
     int status, n_arc, n_vert, n_contour;
     int wsum;
 };
@@ -166,10 +175,10 @@ __device__ inline int wave_excl_scan(int x, int *total)
     return inc - x;
 }
 
+// reduce t in (-2 pi, 4 pi) to [0, 2 pi)
 template <typename T>
 __device__ inline T wrap2pi(T t)
 {
-    t = m_fmod(t, Cst<T>::two_pi);
     if (t < (T)0) t += Cst<T>::two_pi;
     if (t >= Cst<T>::two_pi) t -= Cst<T>::two_pi;
     return t;
@@ -245,6 +254,12 @@ __device__ bool conic_of(const SL<T> *S, T rho, int p, int q, Con<T> &C)
 // ---------------------------------------------------------------------------
 // trimming of one conic: intersection of circular intervals
 
+// kept arcs per conic: 2 in FP32 (a third sends the node to FP64), 4 in FP64
+template <typename T>
+struct NPieces {
+    static constexpr int n = sizeof(T) == 4 ? 2 : kPieces;
+};
+
 template <typename T>
 struct Pc {
     T s, e, len;
@@ -257,7 +272,7 @@ struct TrimOut {
     int n;        // arcs
     int full;     // whole conic kept
     int ovf;      // too many pieces
-    Pc<T> pc[kPieces];
+    Pc<T> pc[NPieces<T>::n];
 };
 
 template <typename T>
@@ -295,14 +310,14 @@ __device__ void trim_conic(const SL<T> *S, int v, int p, int q, const Con<T> &C,
         V3<T> d = cross(gx - gvec(S[y]), gx - gvec(S[z]));
         int sgn = dot(C.a * B - C.b * A, d) > (T)0 ? 1 : 0;
         int root_lo = 1 - sgn, root_hi = sgn;
-        Pc<T> out[kPieces] = {};
+        Pc<T> out[NPieces<T>::n] = {};
         int no = 0;
         bool ovf = false;
         auto push = [&](const Pc<T> &pcx) {
 #pragma unroll
-            for (int j = 0; j < kPieces; ++j)
+            for (int j = 0; j < NPieces<T>::n; ++j)
                 if (j == no) out[j] = pcx;
-            if (no < kPieces) ++no;
+            if (no < NPieces<T>::n) ++no;
             else ovf = true;
         };
         if (TR.full) {
@@ -312,7 +327,7 @@ __device__ void trim_conic(const SL<T> *S, int v, int p, int q, const Con<T> &C,
             push(pcx);
         } else {
 #pragma unroll
-            for (int i = 0; i < kPieces; ++i) {
+            for (int i = 0; i < NPieces<T>::n; ++i) {
                 if (i < TR.n) {
                     Pc<T> Pp = TR.pc[i];
                     T c0 = lo - Pp.s;
@@ -341,7 +356,7 @@ __device__ void trim_conic(const SL<T> *S, int v, int p, int q, const Con<T> &C,
         TR.n = no;
         if (ovf) TR.ovf = 1;
 #pragma unroll
-        for (int j = 0; j < kPieces; ++j) TR.pc[j] = out[j];
+        for (int j = 0; j < NPieces<T>::n; ++j) TR.pc[j] = out[j];
         if (no == 0) return;
     }
 }
@@ -430,6 +445,7 @@ template <bool FILL, typename T>
 __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
 {
     constexpr bool F32 = sizeof(T) == 4;
+    constexpr int NP = NPieces<T>::n;
     const T tp = Cst<T>::two_pi;
     const int lane = threadIdx.x;
     const Work &W = P.w;
@@ -540,13 +556,13 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                     atomicOr(&sh.status, NS_NON_ELLIPTIC);
                 } else {
                     trim_conic(sh.S, v, p, q, C, TR);
-                    if (TR.ovf) atomicOr(&sh.status, NS_CAPACITY);
+                    if (TR.ovf) atomicOr(&sh.status, F32 ? NS_PREC : NS_CAPACITY);
                 }
             }
             // arcs of this conic, sorted by the smaller endpoint name
-            uint32_t ns_[kPieces], ne_[kPieces], key[kPieces];
+            uint32_t ns_[NP], ne_[NP], key[NP];
 #pragma unroll
-            for (int i = 0; i < kPieces; ++i) {
+            for (int i = 0; i < NP; ++i) {
                 if (TR.full) {
                     ns_[i] = ne_[i] = vname3(p, q, 255, 0);
                 } else {
@@ -555,12 +571,12 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                 }
                 key[i] = i < TR.n ? (ns_[i] < ne_[i] ? ns_[i] : ne_[i]) : 0xffffffffu;
             }
-            int ord[kPieces];
+            int ord[NP];
 #pragma unroll
-            for (int i = 0; i < kPieces; ++i) {
+            for (int i = 0; i < NP; ++i) {
                 int rank = 0;
 #pragma unroll
-                for (int j = 0; j < kPieces; ++j) rank += (key[j] < key[i]) || (key[j] == key[i] && j < i);
+                for (int j = 0; j < NP; ++j) rank += (key[j] < key[i]) || (key[j] == key[i] && j < i);
                 ord[i] = rank;
             }
             int cnt = act ? TR.n : 0, tot;
@@ -569,7 +585,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                 if (lane == 0) atomicOr(&sh.status, NS_CAPACITY);
             } else {
 #pragma unroll
-                for (int i = 0; i < kPieces; ++i) {
+                for (int i = 0; i < NP; ++i) {
                     if (i < cnt) {
                         ArcL<T> &A = sh.A[base + ord[i]];
                         A.o[0] = C.o.x; A.o[1] = C.o.y; A.o[2] = C.o.z;
@@ -589,12 +605,12 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                 }
             }
             // owned vertices: ties (p, q, r) with r > q, and whole-conic starts
-            uint32_t on[2 * kPieces];
-            T ot[2 * kPieces];
-            int orr[2 * kPieces];
+            uint32_t on[2 * NP];
+            T ot[2 * NP];
+            int orr[2 * NP];
             int own = 0;
 #pragma unroll
-            for (int i = 0; i < kPieces; ++i) {
+            for (int i = 0; i < NP; ++i) {
 #pragma unroll
                 for (int end = 0; end < 2; ++end) {
                     bool mine = false;
@@ -614,10 +630,10 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                     }
                     // drop repeats within the conic (degenerate tangencies)
 #pragma unroll
-                    for (int j = 0; j < 2 * kPieces; ++j)
+                    for (int j = 0; j < 2 * NP; ++j)
                         if (j < own && on[j] == nm) mine = false;
 #pragma unroll
-                    for (int j = 0; j < 2 * kPieces; ++j)
+                    for (int j = 0; j < 2 * NP; ++j)
                         if (mine && j == own) { on[j] = nm; ot[j] = t; orr[j] = r; }
                     if (mine) ++own;
                 }
@@ -628,11 +644,11 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                 if (lane == 0) atomicOr(&sh.status, NS_CAPACITY);
             } else {
 #pragma unroll
-                for (int i = 0; i < 2 * kPieces; ++i) {
+                for (int i = 0; i < 2 * NP; ++i) {
                     if (i < own) {
                         int rank = 0;
 #pragma unroll
-                        for (int j = 0; j < 2 * kPieces; ++j) rank += (j < own) && (on[j] < on[i]);
+                        for (int j = 0; j < 2 * NP; ++j) rank += (j < own) && (on[j] < on[i]);
                         V3<T> w = conic_at(C, ot[i]);
                         sh.vname[vbase + rank] = on[i];
                         sh.vx[vbase + rank] = w.x;
@@ -671,84 +687,131 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
             }
             A.contour = -1;
         }
+        for (int i = lane; i < V; i += 64) sh.vdeg[i] = 0;
         __syncthreads();
-        for (int i = lane; i < V; i += 64) {
-            if ((sh.vname[i] & 0xff00u) == 0xff00u) continue;
-            int d = 0;
-            for (int j = 0; j < E; ++j) d += (sh.A[j].vs == i && !sh.A[j].full) + (sh.A[j].ve == i && !sh.A[j].full);
-            if (d != 3) atomicOr(&sh.status, NS_TOPOLOGY);
+        for (int j = lane; j < E; j += 64) {
+            const ArcL<T> &A = sh.A[j];
+            if (A.full || A.vs < 0 || A.ve < 0) continue;
+            atomicAdd(&sh.vdeg[A.vs], 1);
+            atomicAdd(&sh.vdeg[A.ve], 1);
         }
+        __syncthreads();
+        for (int i = lane; i < V; i += 64)
+            if ((sh.vname[i] & 0xff00u) != 0xff00u && sh.vdeg[i] != 3) atomicOr(&sh.status, NS_TOPOLOGY);
         __syncthreads();
         if (sh.status) goto finish;
     }
 
     // ---- end loops per strut ----------------------------------------------
+    // Every arc lies on the loops of its two labels p, q (one loop for a
+    // tangency circle).  Lanes over (arc, side) memberships: orientation
+    // along the strut angle, successor by shared vertex, then the position
+    // in the loop counted from the arc whose loop-start vertex has the
+    // smallest name.
     {
         const int E = sh.n_arc;
-        int m = lane + 1;
-        int cnt = 0;
-        if (m <= v)
-            for (int j = 0; j < E; ++j) cnt += (sh.A[j].p == m || sh.A[j].q == m);
-        int tot;
-        int base = wave_excl_scan(cnt, &tot);
-        if (lane < v) sh.loop_base[m] = base;
-        if (lane == 0) sh.loop_base[v + 1] = tot;
-        if (tot > 2 * kAcap) {
-            if (lane == 0) atomicOr(&sh.status, NS_CAPACITY);
-        } else if (m <= v) {
-            const SL<T> &s = sh.S[m];
-            V3<T> es = v3(s.sx, s.sy, s.sz);
-            int pos = base, nfull = 0;
-            for (int j = 0; j < E; ++j) {
-                const ArcL<T> &A = sh.A[j];
-                if (A.p != m && A.q != m) continue;
-                T tm = (T)0.5 * (A.t1 + A.t2);
-                T st, ct;
-                m_sincos(tm, &st, &ct);
-                Con<T> C = arc_con(A);
-                V3<T> w = C.o + C.a * st + C.b * ct;
-                V3<T> dw = C.a * ct - C.b * st;
-                sh.loop_arc[pos] = (uint8_t)j;
-                sh.loop_dir[pos] = dot(cross(w, dw), es) > (T)0 ? 1 : -1;
-                nfull += A.full;
-                ++pos;
-            }
-            bool bad = cnt == 0 || (nfull && cnt != 1);
-            int samples = 0;
-            if (!bad) {
-                // chain: start at the arc whose loop-start vertex has the
-                // smallest name, follow shared vertices
-                auto sname = [&](int pp) {
-                    const ArcL<T> &A = sh.A[sh.loop_arc[pp]];
-                    return sh.loop_dir[pp] > 0 ? A.ns : A.ne;
-                };
-                auto ename = [&](int pp) {
-                    const ArcL<T> &A = sh.A[sh.loop_arc[pp]];
-                    return sh.loop_dir[pp] > 0 ? A.ne : A.ns;
-                };
-                int first = base;
-                for (int pp = base + 1; pp < base + cnt; ++pp)
-                    if (sname(pp) < sname(first)) first = pp;
-                int cur = first, steps = 0;
-                while (true) {
-                    sh.loop_ord[base + steps] = (uint8_t)(cur - base);
-                    ++steps;
-                    samples += sh.A[sh.loop_arc[cur]].nseg;
-                    if (cnt == 1) break;
-                    uint32_t en = ename(cur);
-                    int nxt = -1, hits = 0;
-                    for (int pp = base; pp < base + cnt; ++pp)
-                        if (sname(pp) == en) { nxt = pp; ++hits; }
-                    if (hits != 1) { bad = true; break; }
-                    if (nxt == first) break;
-                    if (steps >= cnt) { bad = true; break; }
-                    cur = nxt;
-                }
-                if (steps != cnt) bad = true;
-            }
-            if (bad) atomicOr(&sh.status, NS_LOOP);
-            sh.loop_len[m] = samples;
+        if (lane <= v) {
+            sh.loop_cnt[lane] = 0;
+            sh.loop_len[lane] = 0;
+            sh.loop_full[lane] = 0;
         }
+        __syncthreads();
+        for (int j = lane; j < E; j += 64) {
+            const ArcL<T> &A = sh.A[j];
+            if (A.p) atomicAdd(&sh.loop_cnt[A.p], 1);
+            atomicAdd(&sh.loop_cnt[A.q], 1);
+        }
+        __syncthreads();
+        {
+            int c = (lane >= 1 && lane <= v) ? sh.loop_cnt[lane] : 0, tot;
+            int base = wave_excl_scan(c, &tot);
+            if (lane >= 1 && lane <= v) sh.loop_base[lane] = base;
+            if (lane == 0) sh.loop_base[v + 1] = tot;
+        }
+        __syncthreads();
+        if (lane <= v) sh.loop_cnt[lane] = 0;  // reused as fill cursor
+        __syncthreads();
+        for (int j = lane; j < E; j += 64) {
+            const ArcL<T> &A = sh.A[j];
+            T tm = (T)0.5 * (A.t1 + A.t2);
+            T st, ct;
+            m_sincos(tm, &st, &ct);
+            Con<T> C = arc_con(A);
+            V3<T> w = C.o + C.a * st + C.b * ct;
+            V3<T> dw = C.a * ct - C.b * st;
+            V3<T> wdw = cross(w, dw);
+            for (int side = 0; side < 2; ++side) {
+                int m = side ? A.q : A.p;
+                if (m == 0) continue;
+                const SL<T> &s = sh.S[m];
+                int pp = sh.loop_base[m] + atomicAdd(&sh.loop_cnt[m], 1);
+                sh.loop_arc[pp] = (uint8_t)j;
+                sh.loop_dir[pp] = dot(wdw, v3(s.sx, s.sy, s.sz)) > (T)0 ? 1 : -1;
+                atomicAdd(&sh.loop_len[m], A.nseg);
+                if (A.full) atomicAdd(&sh.loop_full[m], 1);
+            }
+        }
+        __syncthreads();
+        const int tot = sh.loop_base[v + 1];
+        auto sname = [&](int pp) {
+            const ArcL<T> &A = sh.A[sh.loop_arc[pp]];
+            return sh.loop_dir[pp] > 0 ? A.ns : A.ne;
+        };
+        auto ename = [&](int pp) {
+            const ArcL<T> &A = sh.A[sh.loop_arc[pp]];
+            return sh.loop_dir[pp] > 0 ? A.ne : A.ns;
+        };
+        auto strut_of = [&](int pp) {
+            int m = 1;
+            while (sh.loop_base[m + 1] <= pp) ++m;
+            return m;
+        };
+        for (int pp = lane; pp < tot; pp += 64) {
+            const int m = strut_of(pp);
+            const int b0 = sh.loop_base[m], b1 = sh.loop_base[m + 1];
+            const uint32_t en = ename(pp), sn = sname(pp);
+            int nxt = -1, hits = 0;
+            bool first = true;
+            for (int q2 = b0; q2 < b1; ++q2) {
+                uint32_t s2 = sname(q2);
+                if (s2 == en) { nxt = q2; ++hits; }
+                if (s2 < sn || (s2 == sn && q2 < pp)) first = false;
+            }
+            if (hits != 1) atomicOr(&sh.status, NS_LOOP);
+            sh.loop_next[pp] = (uint8_t)(nxt < 0 ? pp : nxt);
+            if (first) sh.loop_first[m] = pp;
+        }
+        if (lane >= 1 && lane <= v) {
+            const int c = sh.loop_base[lane + 1] - sh.loop_base[lane];
+            if (c == 0 || (sh.loop_full[lane] && c != 1)) atomicOr(&sh.status, NS_LOOP);
+        }
+        __syncthreads();
+        if (sh.status) goto finish;
+        // position of each arc in its loop; the first arc also checks that
+        // the successor chain closes after exactly the loop's arc count
+        for (int pp = lane; pp < tot; pp += 64) {
+            const int m = strut_of(pp);
+            const int b0 = sh.loop_base[m], c = sh.loop_base[m + 1] - b0;
+            int cur = sh.loop_first[m], t = 0;
+            while (cur != pp && t < c) {
+                cur = sh.loop_next[cur];
+                ++t;
+            }
+            if (t >= c) {
+                atomicOr(&sh.status, NS_LOOP);
+                continue;
+            }
+            sh.loop_ord[b0 + t] = (uint8_t)(pp - b0);
+            if (pp == sh.loop_first[m]) {
+                int x = sh.loop_next[pp], steps = 1;
+                while (x != pp && steps <= c) {
+                    x = sh.loop_next[x];
+                    ++steps;
+                }
+                if (steps != c) atomicOr(&sh.status, NS_LOOP);
+            }
+        }
+        if (tot > 2 * kAcap && lane == 0) atomicOr(&sh.status, NS_CAPACITY);
         __syncthreads();
         if (sh.status) goto finish;
     }
@@ -857,62 +920,104 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
             sh.hc[c][1] = dir.y * rho;
             sh.hc[c][2] = dir.z * rho;
         }
-        // strut end loops must be graphs over phi: strictly increasing, one
-        // turn; FILL also writes the loop samples for the strut bands
-        int m = lane + 1;
-        if (m <= v) {
-            const SL<T> &s = sh.S[m];
-            int b0 = sh.loop_base[m], cnt = sh.loop_base[m + 1] - b0;
-            int64_t lbase = FILL ? W.he_off[row + lane] : 0;
-            const int lcap = FILL ? W.he_len[row + lane] : 0;
-            int32_t mbase_g = 0;
-            if (FILL) mbase_g = (int32_t)W.node_off[3 * (N + 1) + n];
-            T first = (T)0, prev = (T)0, wind = (T)0, minstep = (T)1e30;
-            int idx = 0;
-            for (int t = 0; t < cnt; ++t) {
-                int pp = b0 + sh.loop_ord[b0 + t];
-                const ArcL<T> &A = sh.A[sh.loop_arc[pp]];
-                int d = sh.loop_dir[pp];
-                for (int j = 0; j < A.nseg; ++j) {
-                    int ii = d > 0 ? j : A.nseg - j;
-                    int li = j == 0 ? (d > 0 ? A.vs : A.ve) : interior_idx(A, ii);
-                    T ph;
-                    if (A.p == 0) {
-                        // tangency circles are parametrised in the strut
-                        // frame: phi is the parameter itself
-                        T tt = sub_param(A, ii);
-                        if (tt >= tp) tt -= tp;
-                        if (tt > Cst<T>::pi) tt -= tp;
-                        ph = tt;
-                    } else {
-                        V3<T> w = j == 0 ? vert_pos(sh, li) : interior_pt(A, ii);
-                        ph = phi_of(s, w);
-                    }
-                    if (idx == 0) {
-                        first = ph;
-                    } else {
-                        T dp = ph - prev;
-                        if (dp <= -Cst<T>::pi) dp += tp;
-                        if (dp > Cst<T>::pi) dp -= tp;
-                        wind += dp;
-                        minstep = m_min(minstep, dp);
-                    }
-                    if (FILL && idx < lcap) W.loop[lbase + idx] = make_int2(mbase_g + li, __float_as_int((float)ph));
-                    prev = ph;
-                    ++idx;
+        // strut end loops must be graphs over phi: every step (mod 2 pi)
+        // positive and exactly one descent, i.e. one turn.  Lanes run over
+        // all loop samples of the node; FILL also writes them for the bands.
+        if (lane == 0) {
+            int off = 0;
+            for (int m = 1; m <= v; ++m) {
+                const int b0 = sh.loop_base[m], cnt = sh.loop_base[m + 1] - b0;
+                for (int t = 0; t < cnt; ++t) {
+                    sh.entry_off[b0 + t] = off;
+                    sh.entry_m[b0 + t] = (uint8_t)m;
+                    off += sh.A[sh.loop_arc[b0 + sh.loop_ord[b0 + t]]].nseg;
                 }
             }
-            if (idx == 1) {
-                wind = tp;
-                minstep = tp;
-            } else {
-                T dp = first - prev;
-                if (dp <= -Cst<T>::pi) dp += tp;
-                if (dp > Cst<T>::pi) dp -= tp;
-                wind += dp;
-                minstep = m_min(minstep, dp);
+            sh.entry_off[sh.loop_base[v + 1]] = off;
+        }
+        if (lane < v) {
+            sh.loop_desc[lane + 1] = 0;
+            sh.loop_rot[lane + 1] = ~0ull;
+        }
+        __syncthreads();
+        {
+            const int nent = sh.loop_base[v + 1];
+            const int ns_tot = sh.entry_off[nent];
+            int32_t mbase_g = 0;
+            if (FILL) mbase_g = (int32_t)W.node_off[3 * (N + 1) + n];
+            // phi and local mesh index of sample j of loop entry e
+            auto sample = [&](int e, int j, int &li) -> T {
+                const int m = sh.entry_m[e];
+                const int pp = sh.loop_base[m] + sh.loop_ord[e];
+                const ArcL<T> &A = sh.A[sh.loop_arc[pp]];
+                const int d = sh.loop_dir[pp];
+                const int ii = d > 0 ? j : A.nseg - j;
+                li = j == 0 ? (d > 0 ? A.vs : A.ve) : interior_idx(A, ii);
+                if (A.p == 0) {
+                    // tangency circles are parametrised in the strut frame:
+                    // phi is the parameter itself
+                    T tt = sub_param(A, ii);
+                    if (tt >= tp) tt -= tp;
+                    if (tt > Cst<T>::pi) tt -= tp;
+                    return tt;
+                }
+                V3<T> w = j == 0 ? vert_pos(sh, li) : interior_pt(A, ii);
+                return phi_of(sh.S[m], w);
+            };
+            for (int base = 0; base < ns_tot; base += 64) {
+                const int sidx = base + lane;
+                const bool act = sidx < ns_tot;
+                int e = 0, m = 1, j = 0, idx = 0, nloop = 1, li = 0;
+                T ph = (T)0;
+                if (act) {
+                    int lo = 0, hi = nent - 1;  // last entry with entry_off <= sidx
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) >> 1;
+                        if (sh.entry_off[mid] <= sidx) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    e = lo;
+                    m = sh.entry_m[e];
+                    j = sidx - sh.entry_off[e];
+                    idx = sidx - sh.entry_off[sh.loop_base[m]];
+                    nloop = sh.loop_len[m];
+                    ph = sample(e, j, li);
+                }
+                // the next sample along the loop is usually the next lane's
+                T ph2 = __shfl_down(ph, 1, 64);
+                const bool loop_end = idx + 1 == nloop;
+                if (act && (loop_end || lane == 63)) {
+                    int e2 = e, j2 = j + 1, li2;
+                    if (loop_end) {
+                        e2 = sh.loop_base[m];
+                        j2 = 0;
+                    } else if (sidx + 1 == sh.entry_off[e + 1]) {
+                        e2 = e + 1;
+                        j2 = 0;
+                    }
+                    ph2 = sample(e2, j2, li2);
+                }
+                if (act) {
+                    T dp = ph2 - ph;
+                    if (dp <= -Cst<T>::pi) dp += tp;
+                    if (dp > Cst<T>::pi) dp -= tp;
+                    if (!(dp > (T)0)) atomicOr(&sh.status, NS_LOOP);
+                    if (ph2 < ph) atomicAdd(&sh.loop_desc[m], 1);
+                    if (FILL) {
+                        const int64_t lbase = W.he_off[row + m - 1];
+                        if (idx < W.he_len[row + m - 1])
+                            W.loop[lbase + idx] = make_int2(mbase_g + li, __float_as_int((float)ph));
+                        unsigned int u = __float_as_uint((float)ph);
+                        u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);  // order-preserving
+                        atomicMin(&sh.loop_rot[m], ((unsigned long long)u << 32) | (unsigned int)idx);
+                    }
+                }
             }
-            if (!(minstep > (T)0) || m_abs(wind - tp) > (T)1e-3) atomicOr(&sh.status, NS_LOOP);
+        }
+        __syncthreads();
+        if (lane < v) {
+            if (sh.loop_desc[lane + 1] != 1) atomicOr(&sh.status, NS_LOOP);
+            if (FILL) W.he_rot[row + lane] = (int32_t)(sh.loop_rot[lane + 1] & 0xffffffffull);
         }
         __syncthreads();
     }

@@ -36,59 +36,81 @@ __global__ void k_bad_nodes(int64_t N, const int32_t *node_status, int64_t *tota
     if (n < N && node_status[n] != 0) atomicAdd((unsigned long long *)&totals[8], 1ull);
 }
 
-__global__ void k_zip(int64_t S, const int64_t *strut_he, const int64_t *he_off, const int32_t *he_len,
-                      const int32_t *band_cnt, const int64_t *band_off, const int2 *loop, int32_t *tri,
-                      const int32_t *flags)
+// One thread per band triangle, in output order (coalesced writes).  The
+// apex of a loop-edge triangle is the cyclic predecessor of the edge's end
+// among the other loop's samples in (phi, end) order, found by binary search
+// on that loop read from its smallest phi onwards.
+__device__ inline int pred_sorted(const int2 *L, int n, int rot, float x, bool inclusive)
 {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S || band_cnt[s] == 0) return;
-    if (flags[0] & (DF_CAPACITY | DF_BADLAT | DF_LOOPCAP)) return;
+    // number of samples with phi < x (or <= x), in sorted order
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        int pos = rot + mid;
+        if (pos >= n) pos -= n;
+        float p = __int_as_float(L[pos].y);
+        bool before = inclusive ? (p <= x) : (p < x);
+        if (before) lo = mid + 1;
+        else hi = mid;
+    }
+    int i = lo == 0 ? n - 1 : lo - 1;
+    int pos = rot + i;
+    return pos >= n ? pos - n : pos;
+}
+
+__global__ void __launch_bounds__(kBlock) k_zip(int64_t S, const int64_t *band_off, const int64_t *strut_he,
+                                                const int64_t *he_off, const int32_t *he_len, const int32_t *he_rot,
+                                                const int2 *loop, int32_t *tri, const int32_t *flags)
+{
+    if (flags[0] & (DF_CAPACITY | DF_BADLAT | DF_LOOPCAP | DF_MISMATCH)) return;
+    const int64_t nband = band_off[S];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x;  // first triangle of the block
+    if (t0 >= nband) return;
+    // strut of the block's first triangle, then of this thread's (searching
+    // forward from there)
+    __shared__ int64_t s_first;
+    if (threadIdx.x == 0) {
+        int64_t lo = 0, hi = S - 1;  // last s with band_off[s] <= t0
+        while (lo < hi) {
+            int64_t mid = (lo + hi + 1) >> 1;
+            if (band_off[mid] <= t0) lo = mid;
+            else hi = mid - 1;
+        }
+        s_first = lo;
+    }
+    __syncthreads();
+    if (t >= nband) return;
+    int64_t lo = s_first, hi = S - 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if (band_off[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t s = lo;
+    const int j = (int)(t - band_off[s]);
     const int64_t ha = strut_he[2 * s], hb = strut_he[2 * s + 1];
     const int2 *A = loop + he_off[ha];
     const int2 *B = loop + he_off[hb];
     const int na = he_len[ha], nb = he_len[hb];
-    if (na <= 0 || nb <= 0) return;
-    int32_t *T = tri + 3 * band_off[s];
-    // rotate each loop to its smallest phi
-    int ia0 = 0, ib0 = 0;
-    float pa0 = __int_as_float(A[0].y), pb0 = __int_as_float(B[0].y);
-    for (int i = 1; i < na; ++i) {
-        float p = __int_as_float(A[i].y);
-        if (p < pa0) { pa0 = p; ia0 = i; }
-    }
-    for (int i = 1; i < nb; ++i) {
-        float p = __int_as_float(B[i].y);
-        if (p < pb0) { pb0 = p; ib0 = i; }
-    }
-    // before the first sample of the merge, the last samples are the maxima
-    int lastA = ia0 == 0 ? na - 1 : ia0 - 1;
-    int lastB = ib0 == 0 ? nb - 1 : ib0 - 1;
-    int i = 0, j = 0;
-    int pa = ia0, pb = ib0;
-    while (i < na || j < nb) {
-        bool takeA;
-        if (j >= nb) takeA = true;
-        else if (i >= na) takeA = false;
-        else takeA = __int_as_float(A[pa].y) <= __int_as_float(B[pb].y);
-        if (takeA) {
-            int e = pa == 0 ? na - 1 : pa - 1;  // edge A[e] -> A[pa]
-            int32_t *t = T + 3 * e;
-            t[0] = A[e].x;
-            t[1] = A[pa].x;
-            t[2] = B[lastB].x;
-            lastA = pa;
-            pa = pa + 1 == na ? 0 : pa + 1;
-            ++i;
-        } else {
-            int e = pb == 0 ? nb - 1 : pb - 1;  // edge B[e] -> B[pb]
-            int32_t *t = T + 3 * (na + e);
-            t[0] = B[pb].x;
-            t[1] = B[e].x;
-            t[2] = A[lastA].x;
-            lastB = pb;
-            pb = pb + 1 == nb ? 0 : pb + 1;
-            ++j;
-        }
+    int32_t *T = tri + 3 * t;
+    if (j < na) {
+        // edge A[j] -> A[j+1]; apex: last B sample strictly before A[j+1]
+        int j2 = j + 1 == na ? 0 : j + 1;
+        int2 u2 = A[j2];
+        int ap = pred_sorted(B, nb, he_rot[hb], __int_as_float(u2.y), false);
+        T[0] = A[j].x;
+        T[1] = u2.x;
+        T[2] = B[ap].x;
+    } else {
+        // edge B[e] -> B[e+1]; apex: last A sample at or before B[e+1]
+        int e = j - na;
+        int e2 = e + 1 == nb ? 0 : e + 1;
+        int2 w2 = B[e2];
+        int ap = pred_sorted(A, na, he_rot[ha], __int_as_float(w2.y), true);
+        T[0] = w2.x;
+        T[1] = B[e].x;
+        T[2] = A[ap].x;
     }
 }
 
@@ -139,9 +161,11 @@ hipError_t launch_band_count(const Inputs &in, const Work &w, hipStream_t st)
 hipError_t launch_zip(const Inputs &in, const Work &w, const FillOut &o, hipStream_t st)
 {
     const int64_t S = in.n_struts;
-    if (S > 0)
-        k_zip<<<grid_for(S), kBlock, 0, st>>>(S, w.strut_he, w.he_off, w.he_len, w.band_cnt, w.band_off, w.loop,
-                                              o.tri, w.flags);
+    // grid sized for the capacity; blocks past the band total exit at once
+    int64_t cap = o.cap_tri;
+    if (S > 0 && cap > 0)
+        k_zip<<<grid_for(cap), kBlock, 0, st>>>(S, w.band_off, w.strut_he, w.he_off, w.he_len, w.he_rot, w.loop,
+                                                o.tri, w.flags);
     return hipGetLastError();
 }
 
