@@ -137,8 +137,8 @@ typedef struct lm_plan lm_plan;
 
 /* Create a plan for one lattice: validates strut indices (A0), builds the
  * node adjacency with incident struts in increasing strut id (A1).  The plan
- * allocates its own device workspace (about 40 bytes per node plus 40 bytes
- * per strut, more after lm_count for the loop samples).  stream is a
+ * allocates its own device workspace (about 100 bytes per node plus 80 bytes
+ * per strut, and 8 bytes per strut end loop sample after lm_count).  stream is a
  * hipStream_t (NULL = default stream).  On success *plan is set; on error it
  * is NULL.  Returns LM_ERR_BAD_LATTICE for out-of-range endpoints,
  * LM_ERR_UNSUPPORTED if 2 * n_struts >= 2^31. */
