@@ -44,7 +44,7 @@ extern "C" {
 #define LM_ERR_UNSUPPORTED (-4)    /* size beyond what this build handles */
 #define LM_ERR_HIP (-5)            /* a HIP runtime call failed */
 #define LM_ERR_STATE (-6)          /* call out of order (e.g. fill before count) */
-#define LM_ERR_INTERNAL (-7)       /* device-side consistency check failed */
+#define LM_ERR_INTERNAL (-7)       /* the workspace could not be sized */
 
 /* ---- per-node status bits (node_status output) ------------------------- */
 #define LM_NODE_INVALID_STRUT 1u   /* |r_a - r_b| >= length, zero length or self loop */
@@ -78,7 +78,7 @@ typedef struct lm_totals {
     int64_t n_triangles;     /* = n_band_triangles + n_fan_triangles */
     int64_t n_band_triangles;
     int64_t n_fan_triangles;
-    int64_t n_loop_entries;  /* internal: strut end loop samples */
+    int64_t n_record_bytes;  /* internal: workspace bytes of the node records */
     int64_t n_bad_nodes;     /* nodes with a nonzero status */
     int64_t n_skipped_struts;/* struts not triangulated (an end node is bad) */
     int64_t n_fp64_nodes;    /* nodes meshed in FP64 (see lm_set_precision) */
@@ -137,8 +137,11 @@ typedef struct lm_plan lm_plan;
 
 /* Create a plan for one lattice: validates strut indices (A0), builds the
  * node adjacency with incident struts in increasing strut id (A1).  The plan
- * allocates its own device workspace (about 100 bytes per node plus 80 bytes
- * per strut, and 8 bytes per strut end loop sample after lm_count).  stream is a
+ * allocates its own device workspace (about 110 bytes per node plus 80 bytes
+ * per strut) and, at the first lm_count or lm_forward, the node-record space
+ * (each meshed node's meta-mesh and strut end loops: about 1.2 kB per node
+ * plus 8 bytes per loop sample, about 2.5 kB per node of the BCC lattice at
+ * k = 16).  stream is a
  * hipStream_t (NULL = default stream).  On success *plan is set; on error it
  * is NULL.  Returns LM_ERR_BAD_LATTICE for out-of-range endpoints,
  * LM_ERR_UNSUPPORTED if 2 * n_struts >= 2^31. */
@@ -152,26 +155,28 @@ int lm_prepare(lm_plan *plan);
 
 /* Meta-mesh every node and size the triangulation at k segments per full
  * turn (Eq. 11 with step 2 pi / k; 3 <= k <= 4096): per-node arcs,
- * vertices, holes, loops and counts, prefix sums.  Synchronises the stream
- * and writes the totals to *totals (host memory).  Re-callable with another
- * k on the same plan. */
+ * vertices, holes, end loops and counts, prefix sums.  Each node's result is
+ * kept in the plan's node-record space for lm_fill (the space grows, and the
+ * pass runs again, if it was too small).  Synchronises the stream and writes
+ * the totals to *totals (host memory).  Re-callable with another k on the
+ * same plan. */
 int lm_count(lm_plan *plan, int k, lm_totals *totals);
 
 /* Write the meta-mesh and the triangle mesh for the k of the last lm_count
- * (A9, B1-B3).  Asynchronous on the plan's stream.  Returns LM_ERR_CAPACITY
- * (writing nothing) if a required buffer is smaller than the totals,
- * LM_ERR_STATE if lm_count has not run. */
+ * (A9, B1-B3) from the node records.  Asynchronous on the plan's stream.
+ * Returns LM_ERR_CAPACITY (writing nothing) if a required buffer is smaller
+ * than the totals, LM_ERR_STATE if lm_count has not run. */
 int lm_fill(lm_plan *plan, const lm_outputs *out);
 
 /* lm_count and lm_fill without the host synchronisation: sizes are taken on
- * the device, outputs whose capacity is too small are not written, and
- * lm_read_totals reports LM_ERR_CAPACITY afterwards.  For repeated runs with
- * buffers sized by an earlier lm_count. */
+ * the device; if an output or the node-record space is too small nothing is
+ * written and lm_read_totals reports LM_ERR_CAPACITY afterwards.  For
+ * repeated runs with buffers (and record space) sized by an earlier
+ * lm_count at the same or a larger k. */
 int lm_forward(lm_plan *plan, int k, const lm_outputs *out);
 
 /* Synchronise the stream and return the totals of the last lm_forward or
- * lm_count; LM_ERR_CAPACITY if that lm_forward skipped writes,
- * LM_ERR_INTERNAL if a device-side consistency check failed. */
+ * lm_count; LM_ERR_CAPACITY if that lm_forward skipped writes. */
 int lm_read_totals(lm_plan *plan, lm_totals *totals);
 
 /* Mixed precision.  Nodes are meshed in FP32; a node is meshed again in
@@ -185,9 +190,10 @@ int lm_set_precision(lm_plan *plan, float kappa_max);
 /* Profiling: when on, every library call records HIP events on the plan's
  * stream around its phases; lm_get_profile synchronises the stream and
  * returns, per phase, the summed milliseconds and the number of timed calls
- * since the last lm_get_profile.  Phases (n >= 7): 0 lm_prepare, 1 FP32
- * count pass, 2 FP64 count pass, 3 band counts + prefix sums + totals,
- * 4 FP32 fill pass, 5 FP64 fill pass, 6 strut bands. */
+ * since the last lm_get_profile.  Phases (n >= 6): 0 lm_prepare, 1 FP32
+ * meta-meshing of every node, 2 FP64 meta-meshing of the handed-over nodes,
+ * 3 band counts + prefix sums + totals, 4 expansion of the node results into
+ * the meta-mesh, mesh vertices and hole fans, 5 strut bands. */
 int lm_set_profiling(lm_plan *plan, int on);
 int lm_get_profile(lm_plan *plan, double *ms, int64_t *calls, int n);
 

@@ -7,13 +7,14 @@
 #include "common.h"
 
 // Phases timed with HIP events when profiling is on (lm_set_profiling).
-enum Phase { PH_PREPARE, PH_COUNT32, PH_COUNT64, PH_SIZES, PH_FILL32, PH_FILL64, PH_ZIP, PH_N };
+enum Phase { PH_PREPARE, PH_NODE32, PH_NODE64, PH_SIZES, PH_EXPAND, PH_ZIP, PH_N };
 
 struct lm_plan {
     lm::Inputs in;
     lm::Work w;
     hipStream_t st;
     void *ws;       // one allocation for the fixed-size workspace
+    int64_t rec_alloc_words;  // words allocated for node records
     int k;          // resolution of the last count (0: none)
     float kappa_max;// FP32 -> FP64 hand-over threshold
     lm_totals last; // totals of the last lm_count
@@ -52,13 +53,13 @@ struct PhaseTimer {
         if (P->profiling) {
             a = take_event(P);
             b = take_event(P);
-            if (a) hipEventRecord(a, P->st);
+            if (a) (void)hipEventRecord(a, P->st);
         }
     }
     ~PhaseTimer()
     {
         if (a && b) {
-            hipEventRecord(b, P->st);
+            (void)hipEventRecord(b, P->st);
             P->ev.push_back({ph, {a, b}});
         }
     }
@@ -90,19 +91,20 @@ size_t carve(lm::Work &w, char *base, int64_t N, int64_t S)
     w.node_cnt = (int32_t *)take(sizeof(int32_t) * lm::kNodeCols * (N + 1));
     w.node_off = (int64_t *)take(sizeof(int64_t) * lm::kNodeScanCols * (N + 1));
     w.he_len = (int32_t *)take(sizeof(int32_t) * (H + 1));
-    w.he_off = (int64_t *)take(sizeof(int64_t) * (H + 1));
+    w.he_loop = (int64_t *)take(sizeof(int64_t) * (H + 1));
     w.he_rot = (int32_t *)take(sizeof(int32_t) * (H + 1));
     w.band_cnt = (int32_t *)take(sizeof(int32_t) * (S + 1));
     w.band_off = (int64_t *)take(sizeof(int64_t) * (S + 1));
     int64_t tl = lm::scan_tmp_needed(N, lm::kNodeScanCols);
-    int64_t t2 = lm::scan_tmp_needed(H, 1);
+    int64_t t2 = lm::scan_tmp_needed(S, 1);
     if (t2 > tl) tl = t2;
     w.scan_tmp = (int64_t *)take(sizeof(int64_t) * tl);
     w.scan_tmp_len = tl;
     w.flags = (int32_t *)take(sizeof(int32_t) * 4);
     w.totals = (int64_t *)take(sizeof(int64_t) * 16);
     w.fb_list = (int32_t *)take(sizeof(int32_t) * (N + 1));
-    w.node_prec = (uint8_t *)take(sizeof(uint8_t) * (N + 1));
+    w.node_rec = (int64_t *)take(sizeof(int64_t) * (N + 1));
+    w.rec_top = (unsigned long long *)take(sizeof(unsigned long long) * lm::kRecRegions);
     return off;
 }
 
@@ -140,19 +142,19 @@ int run_count(lm_plan *P, int k, const lm::FillOut *out)
     HIPCHK(hipMemsetAsync(w.flags, 0, sizeof(int32_t), P->st));
     HIPCHK(hipMemsetAsync(w.flags + 2, 0, sizeof(int32_t), P->st));
     HIPCHK(hipMemsetAsync(w.totals, 0, sizeof(int64_t) * 16, P->st));
+    HIPCHK(hipMemsetAsync(w.rec_top, 0, sizeof(unsigned long long) * lm::kRecRegions, P->st));
     {
-        PhaseTimer t(P, PH_COUNT32);
-        HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, nullptr, 0, P->st));
+        PhaseTimer t(P, PH_NODE32);
+        HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, 0, P->st));
     }
     {
-        PhaseTimer t(P, PH_COUNT64);
-        HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, nullptr, 1, P->st));
+        PhaseTimer t(P, PH_NODE64);
+        HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, 1, P->st));
     }
     PhaseTimer t(P, PH_SIZES);
     HIPCHK(lm::launch_band_count(P->in, w, P->st));
     HIPCHK(lm::launch_scan(w.node_cnt, w.node_off, N, lm::kNodeScanCols, N, N + 1, w.scan_tmp, w.scan_tmp_len,
                            P->st));
-    HIPCHK(lm::launch_scan(w.he_len, w.he_off, 2 * S, 1, 0, 0, w.scan_tmp, w.scan_tmp_len, P->st));
     HIPCHK(lm::launch_scan(w.band_cnt, w.band_off, S, 1, 0, 0, w.scan_tmp, w.scan_tmp_len, P->st));
     HIPCHK(lm::launch_totals(P->in, w, out, P->st));
     return LM_OK;
@@ -172,7 +174,7 @@ int read_totals(lm_plan *P, lm_totals *t, int32_t *flags_out)
     t->n_triangles = tv[4];
     t->n_band_triangles = tv[5];
     t->n_fan_triangles = tv[6];
-    t->n_loop_entries = tv[7];
+    t->n_record_bytes = tv[7];
     t->n_bad_nodes = tv[8];
     t->n_skipped_struts = tv[9];
     t->n_fp64_nodes = tv[10];
@@ -180,29 +182,38 @@ int read_totals(lm_plan *P, lm_totals *t, int32_t *flags_out)
     return LM_OK;
 }
 
-int ensure_loop(lm_plan *P, int64_t need)
+// Node-record space: at least `words` (rounded so the regions are equal and
+// 16-byte aligned).  Synchronises the stream before replacing the buffer.
+int ensure_rec(lm_plan *P, int64_t words)
 {
-    if (need <= P->w.loop_cap) return LM_OK;
+    const int64_t unit = 4 * lm::kRecRegions;
+    words = (words + unit - 1) / unit * unit;
+    if (words <= P->w.rec_words) return LM_OK;
     HIPCHK(hipStreamSynchronize(P->st));
-    if (P->w.loop) HIPCHK(hipFree(P->w.loop));
-    P->w.loop = nullptr;
-    P->w.loop_cap = 0;
-    int64_t cap = need + need / 8 + 1024;
-    HIPCHK(hipMalloc((void **)&P->w.loop, sizeof(int2) * cap));
-    P->w.loop_cap = cap;
+    if (P->w.rec) HIPCHK(hipFree(P->w.rec));
+    P->w.rec = nullptr;
+    P->w.rec_words = 0;
+    HIPCHK(hipMalloc((void **)&P->w.rec, sizeof(uint32_t) * words));
+    P->w.rec_words = words;
     return LM_OK;
+}
+
+// First guess of the record space at resolution k: per node the header and
+// about 2 vertices, 3 arcs and a hole per incident strut; per half-edge a
+// loop of about k samples.
+int64_t rec_estimate(const lm_plan *P, int k)
+{
+    const int64_t N = P->in.n_nodes, H = 2 * P->in.n_struts;
+    int64_t words = N * (lm::kRecHead + 4) + H * (2 * 4 + 3 * lm::kRecArcFields + 3 + 2 * (int64_t)(k + 4));
+    return words + words / 8 + 4096;
 }
 
 int fill_common(lm_plan *P, const lm::FillOut &f, const lm_outputs *out)
 {
     const int64_t N = P->in.n_nodes;
     {
-        PhaseTimer t(P, PH_FILL32);
-        HIPCHK(lm::launch_node(P->in, P->w, P->k, P->kappa_max, &f, 0, P->st));
-    }
-    {
-        PhaseTimer t(P, PH_FILL64);
-        HIPCHK(lm::launch_node(P->in, P->w, P->k, P->kappa_max, &f, 1, P->st));
+        PhaseTimer t(P, PH_EXPAND);
+        HIPCHK(lm::launch_expand(P->in, P->w, f, P->st));
     }
     {
         PhaseTimer t(P, PH_ZIP);
@@ -252,8 +263,8 @@ int lm_plan_create(lm_plan **plan, const lm_lattice *lat, void *stream)
         return LM_ERR_HIP;
     }
     carve(P->w, (char *)P->ws, lat->n_nodes, lat->n_struts);
-    P->w.loop = nullptr;
-    P->w.loop_cap = 0;
+    P->w.rec = nullptr;
+    P->w.rec_words = 0;
     P->kappa_max = 32.0f;
     P->profiling = false;
     int rc = LM_OK;
@@ -267,7 +278,7 @@ int lm_plan_create(lm_plan **plan, const lm_lattice *lat, void *stream)
         rc = LM_ERR_BAD_LATTICE;
     }
     if (rc != LM_OK) {
-        hipFree(P->ws);
+        (void)hipFree(P->ws);
         delete P;
         return rc;
     }
@@ -278,16 +289,18 @@ int lm_plan_create(lm_plan **plan, const lm_lattice *lat, void *stream)
 int lm_count(lm_plan *P, int k, lm_totals *totals)
 {
     if (!P || !totals || k < 3 || k > 4096) return LM_ERR_INVALID_ARG;
-    int rc = run_count(P, k, nullptr);
-    if (rc) return rc;
-    int32_t fl;
-    rc = read_totals(P, totals, &fl);
-    if (rc) return rc;
-    if (totals->n_mesh_vertices > 0x7fffffffLL) return LM_ERR_UNSUPPORTED;
-    rc = ensure_loop(P, totals->n_loop_entries);
-    if (rc) return rc;
-    // the loop buffer now fits: clear the flags the sizing pass may have set
-    HIPCHK(hipMemsetAsync(P->w.flags, 0, sizeof(int32_t), P->st));
+    int rc = LM_OK;
+    if (P->w.rec_words == 0 && (rc = ensure_rec(P, rec_estimate(P, k)))) return rc;
+    int32_t fl = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if ((rc = run_count(P, k, nullptr))) return rc;
+        if ((rc = read_totals(P, totals, &fl))) return rc;
+        if (totals->n_mesh_vertices > 0x7fffffffLL) return LM_ERR_UNSUPPORTED;
+        if (!(fl & lm::DF_RECCAP)) break;
+        // the records did not fit: the totals hold the space they need
+        if ((rc = ensure_rec(P, totals->n_record_bytes / 4 + totals->n_record_bytes / 64))) return rc;
+    }
+    if (fl & lm::DF_RECCAP) return LM_ERR_INTERNAL;
     P->k = k;
     P->last = *totals;
     return LM_OK;
@@ -309,7 +322,9 @@ int lm_forward(lm_plan *P, int k, const lm_outputs *out)
 {
     if (!P || !out || !out->d_mesh_xyz || !out->d_tri || k < 3 || k > 4096) return LM_ERR_INVALID_ARG;
     lm::FillOut f = to_fill(out);
-    int rc = run_count(P, k, &f);
+    int rc = LM_OK;
+    if (P->w.rec_words == 0 && (rc = ensure_rec(P, rec_estimate(P, k)))) return rc;
+    rc = run_count(P, k, &f);
     if (rc) return rc;
     P->k = k;
     return fill_common(P, f, out);
@@ -321,8 +336,7 @@ int lm_read_totals(lm_plan *P, lm_totals *totals)
     int32_t fl;
     int rc = read_totals(P, totals, &fl);
     if (rc) return rc;
-    if (fl & lm::DF_MISMATCH) return LM_ERR_INTERNAL;
-    if (fl & (lm::DF_CAPACITY | lm::DF_LOOPCAP)) return LM_ERR_CAPACITY;
+    if (fl & (lm::DF_CAPACITY | lm::DF_RECCAP)) return LM_ERR_CAPACITY;
     return LM_OK;
 }
 
@@ -373,14 +387,14 @@ int lm_set_precision(lm_plan *P, float kappa_max)
 void lm_plan_destroy(lm_plan *P)
 {
     if (!P) return;
-    hipStreamSynchronize(P->st);
+    (void)hipStreamSynchronize(P->st);
     for (auto &e : P->ev) {
-        hipEventDestroy(e.second.first);
-        hipEventDestroy(e.second.second);
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
     }
-    for (auto e : P->pool) hipEventDestroy(e);
-    if (P->w.loop) hipFree(P->w.loop);
-    hipFree(P->ws);
+    for (auto e : P->pool) (void)hipEventDestroy(e);
+    if (P->w.rec) (void)hipFree(P->w.rec);
+    (void)hipFree(P->ws);
     delete P;
 }
 
@@ -394,7 +408,7 @@ const char *lm_status_string(int code)
     case LM_ERR_UNSUPPORTED: return "size not supported by this build";
     case LM_ERR_HIP: return "HIP runtime error";
     case LM_ERR_STATE: return "call out of order";
-    case LM_ERR_INTERNAL: return "device consistency check failed";
+    case LM_ERR_INTERNAL: return "workspace could not be sized";
     default: return "unknown status";
     }
 }

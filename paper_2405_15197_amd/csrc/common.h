@@ -45,10 +45,33 @@ constexpr int kNodeScanCols = 5;  // columns 0..4 are prefix-summed
 // handed to the FP64 pass.
 enum DevFlag : int {
     DF_CAPACITY = 1,   // an output was too small, writes skipped
-    DF_MISMATCH = 2,   // fill pass disagreed with the count pass
     DF_BADLAT = 4,     // a strut endpoint is out of range
-    DF_LOOPCAP = 8,    // loop-sample buffer too small or mesh too large for int32
+    DF_RECCAP = 8,     // node-record space too small, or mesh too large for int32
 };
+
+// Node records.  The count pass leaves every meshed node's result in the
+// record space, 32-bit words, allocated in kRecRegions regions (node n uses
+// region n mod kRecRegions, each with its own bump counter):
+//   header  [kRecHead]  V, E, H (holes), ncirc (circular arcs, stored first),
+//                       wsum (first hole-centre mesh index), M (mesh
+//                       vertices), F (fan triangles), 0
+//   vertices [4][V]     name, x, y, z (node-local)
+//   arcs    [16][E]     o.xyz, a.xyz, b.xyz, t1, t2 (float bits),
+//                       p | q<<8 | whole<<16 | fwd<<17 | lower<<18,
+//                       vs | ve<<16, nseg | contour<<16, mbase, fbase
+//   holes   [3][H]      hole centres (node-local)
+//   loops               from a multiple of 4 words: for each incident strut
+//                       in label order, its end loop as int2 (node-local mesh
+//                       vertex, phi bits), in loop order
+// fwd: the arc is subdivided from t1 (its smaller-name end is at t1);
+// lower: the arc's strut q runs to a higher node id.
+constexpr int kRecHead = 8;
+constexpr int kRecArcFields = 16;
+constexpr int kRecRegions = 16;
+__host__ __device__ inline int64_t rec_loop_word(int V, int E, int H)
+{
+    return ((int64_t)kRecHead + 4 * V + kRecArcFields * E + 3 * H + 3) & ~(int64_t)3;
+}
 
 struct Inputs {
     int64_t n_nodes, n_struts;
@@ -66,18 +89,19 @@ struct Work {
     int32_t *node_cnt;      // [kNodeCols][N]
     int64_t *node_off;      // [kNodeScanCols][N+1]
     int32_t *he_len;        // [2S] loop samples per half-edge
-    int64_t *he_off;        // [2S+1]
+    int64_t *he_loop;       // [2S] first loop sample (int2 index into rec)
     int32_t *he_rot;        // [2S] loop position of the smallest phi
     int32_t *band_cnt;      // [S]
     int64_t *band_off;      // [S+1]
-    int2 *loop;             // [n_loop] (global mesh vertex, phi bits)
-    int64_t loop_cap;
+    int64_t *node_rec;      // [N] first word of the node's record, -1: none
+    uint32_t *rec;          // node records (see above)
+    int64_t rec_words;      // capacity in words (kRecRegions equal regions)
+    unsigned long long *rec_top;  // [kRecRegions] words used per region
     int64_t *scan_tmp;      // block partials
     int64_t scan_tmp_len;
     int32_t *flags;         // [4] see DevFlag
     int64_t *totals;        // [16] device copy of totals
     int32_t *fb_list;       // [N] nodes for the FP64 pass
-    uint8_t *node_prec;     // [N] 1: node meshed in FP64
 };
 
 struct FillOut {
@@ -96,10 +120,11 @@ struct FillOut {
 hipError_t launch_prepare(const Inputs &in, const Work &w, hipStream_t st);
 hipError_t launch_scan(const int32_t *src, int64_t *dst, int64_t n, int ncols, int64_t src_stride,
                        int64_t dst_stride, int64_t *tmp, int64_t tmp_len, hipStream_t st);
-// Per-node kernel: count pass (o == nullptr) or fill pass, FP32 over all
-// nodes or FP64 over the hand-over list.
-hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, const FillOut *o, int fp64,
-                       hipStream_t st);
+// Per-node meta-meshing (counts and node records), FP32 over all nodes or
+// FP64 over the hand-over list.
+hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, int fp64, hipStream_t st);
+// Node records -> meta-mesh, mesh vertices and hole fans.
+hipError_t launch_expand(const Inputs &in, const Work &w, const FillOut &o, hipStream_t st);
 hipError_t launch_band_count(const Inputs &in, const Work &w, hipStream_t st);
 hipError_t launch_zip(const Inputs &in, const Work &w, const FillOut &o, hipStream_t st);
 hipError_t launch_totals(const Inputs &in, const Work &w, const FillOut *o, hipStream_t st);

@@ -1,0 +1,146 @@
+// Expansion of the node records into the outputs: meta-mesh vertices and
+// arcs (Sec. 4.2 stores them per node), the triangle-mesh vertices — the
+// meta-vertices, the Eq. 12 interior points of every arc and one Eq. 13 hole
+// centre per hole contour — and the hole fans (Sec. 5).  One wave per node;
+// every store of a wave goes to consecutive addresses.
+#include "common.h"
+
+namespace lm {
+namespace {
+
+struct XParams {
+    Inputs in;
+    Work w;
+    FillOut o;
+};
+
+__device__ inline float fbits(uint32_t u) { return __uint_as_float(u); }
+
+__global__ void __launch_bounds__(64) k_expand(XParams P)
+{
+    __shared__ int s_mbase[kAcap];
+    __shared__ int s_fbase[kAcap];
+    const Work &W = P.w;
+    const FillOut &O = P.o;
+    const int64_t N = P.in.n_nodes;
+    const int64_t n = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (n >= N) return;
+    if (W.flags[0] & (DF_CAPACITY | DF_BADLAT | DF_RECCAP)) return;
+    const int64_t rb = W.node_rec[n];
+    if (rb < 0) return;
+    const uint32_t *R = W.rec + rb;
+    const int V = (int)R[0], E = (int)R[1], NC = (int)R[2], ncirc = (int)R[3];
+    const int wsum = (int)R[4], M = (int)R[5], F = (int)R[6];
+    const uint32_t *RV = R + kRecHead;
+    const uint32_t *RA = RV + 4 * V;
+    const uint32_t *RH = RA + kRecArcFields * E;
+    const int64_t Np1 = N + 1;
+    const int64_t voff = W.node_off[0 * Np1 + n], aoff = W.node_off[1 * Np1 + n];
+    const int64_t moff = W.node_off[3 * Np1 + n], foff = W.node_off[4 * Np1 + n];
+    const float4 c4 = W.node4[n];
+
+    for (int j = lane; j < E; j += 64) {
+        s_mbase[j] = (int)RA[14 * E + j];
+        s_fbase[j] = (int)RA[15 * E + j];
+    }
+    if (O.vert_name) {
+        for (int i = lane; i < V; i += 64) {
+            O.vert_name[voff + i] = RV[i];
+            O.vert_xyz[0 * O.cap_vert + voff + i] = fbits(RV[V + i]);
+            O.vert_xyz[1 * O.cap_vert + voff + i] = fbits(RV[2 * V + i]);
+            O.vert_xyz[2 * O.cap_vert + voff + i] = fbits(RV[3 * V + i]);
+        }
+    }
+    if (O.arc_f32) {
+        const int64_t cA = O.cap_arc;
+        for (int j = lane; j < E; j += 64) {
+#pragma unroll
+            for (int t = 0; t < 11; ++t) O.arc_f32[t * cA + aoff + j] = fbits(RA[t * E + j]);
+            O.arc_u32[0 * cA + aoff + j] = RA[11 * E + j] & 0x1ffffu;  // p | q<<8 | whole<<16
+            O.arc_u32[1 * cA + aoff + j] = RA[12 * E + j];
+            O.arc_u32[2 * cA + aoff + j] = (uint32_t)n;
+        }
+    }
+    __syncthreads();
+
+    // Eq. 12 sub-parameter ii (1..nseg-1) of arc j, and its point
+    auto interior = [&](int j, int ii) {
+        const float t1 = fbits(RA[9 * E + j]), t2 = fbits(RA[10 * E + j]);
+        const int nseg = (int)(RA[13 * E + j] & 0xffffu);
+        const float t = t1 + (t2 - t1) * (float)ii / (float)nseg;
+        float s, c;
+        sincosf(t, &s, &c);
+        float w[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) w[d] = fbits(RA[d * E + j]) + fbits(RA[(3 + d) * E + j]) * s + fbits(RA[(6 + d) * E + j]) * c;
+        return make_float3(w[0], w[1], w[2]);
+    };
+    // mesh vertices: meta-vertices, interior points, hole centres
+    for (int i = lane; i < M; i += 64) {
+        float3 w;
+        if (i < V) {
+            w = make_float3(fbits(RV[V + i]), fbits(RV[2 * V + i]), fbits(RV[3 * V + i]));
+        } else if (i < wsum) {
+            int lo = 0, hi = E - 1;  // last arc with mbase <= i
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_mbase[mid] <= i) lo = mid;
+                else hi = mid - 1;
+            }
+            const int nseg = (int)(RA[13 * E + lo] & 0xffffu);
+            const bool fwd = (RA[11 * E + lo] >> 17) & 1u;
+            const int jc = i - s_mbase[lo];
+            w = interior(lo, fwd ? jc + 1 : nseg - 1 - jc);
+        } else {
+            const int c = i - wsum;
+            w = make_float3(fbits(RH[c]), fbits(RH[NC + c]), fbits(RH[2 * NC + c]));
+        }
+        float *dst = O.mesh_xyz + 3 * (moff + i);
+        dst[0] = c4.x + w.x;
+        dst[1] = c4.y + w.y;
+        dst[2] = c4.z + w.z;
+    }
+    // hole fans: one triangle per circular-arc segment, apex at the contour's
+    // hole centre, oriented outward
+    const int64_t fan0 = W.band_off[P.in.n_struts] + foff;
+    for (int i = lane; i < F; i += 64) {
+        int lo = 0, hi = ncirc - 1;  // last circular arc with fbase <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_fbase[mid] <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const int j = lo;
+        const uint32_t u0 = RA[11 * E + j], u1 = RA[12 * E + j], u2 = RA[13 * E + j];
+        const bool fwd = (u0 >> 17) & 1u, lower = (u0 >> 18) & 1u;
+        const int nseg = (int)(u2 & 0xffffu), contour = (int)(u2 >> 16);
+        const int vs = (int)(u1 & 0xffffu), ve = (int)(u1 >> 16);
+        const int mbase = s_mbase[j];
+        const int s = i - s_fbase[j];
+        const int i0 = fwd ? s : nseg - s, i1 = fwd ? s + 1 : nseg - s - 1;
+        const int lo_i = i0 < i1 ? i0 : i1, hi_i = i0 < i1 ? i1 : i0;
+        // interior point ii sits at mbase + (fwd ? ii - 1 : nseg - 1 - ii)
+        const int u = lo_i == 0 ? vs : mbase + (fwd ? lo_i - 1 : nseg - 1 - lo_i);
+        const int u2i = hi_i == nseg ? ve : mbase + (fwd ? hi_i - 1 : nseg - 1 - hi_i);
+        int32_t *t = O.tri + 3 * (fan0 + i);
+        t[0] = (int32_t)(moff + wsum + contour);
+        t[1] = (int32_t)(moff + (lower ? u2i : u));
+        t[2] = (int32_t)(moff + (lower ? u : u2i));
+    }
+}
+
+}  // namespace
+
+hipError_t launch_expand(const Inputs &in, const Work &w, const FillOut &o, hipStream_t st)
+{
+    if (in.n_nodes == 0) return hipSuccess;
+    XParams P;
+    P.in = in;
+    P.w = w;
+    P.o = o;
+    k_expand<<<(unsigned)in.n_nodes, 64, 0, st>>>(P);
+    return hipGetLastError();
+}
+
+}  // namespace lm

@@ -110,7 +110,7 @@ struct ArcL {
     uint32_t ns, ne; // vertex names at t1 / t2
     int vs, ve;      // local vertex indices
     int p, q, full;
-    int nseg, mbase, contour;
+    int nseg, mbase, contour, fbase;
 };
 
 template <typename T>
@@ -135,8 +135,10 @@ struct Shared {
     uint8_t entry_m[2 * kAcap];     // strut label of each loop entry
     int loop_desc[kVmax + 1];       // descents of phi along each loop
     unsigned long long loop_rot[kVmax + 1];  // (ordered phi bits, sample) minimum
+    int lbase[kVmax + 2];           // loop samples before each strut's loop
     int status, n_arc, n_vert, n_contour;
-    int wsum;
+    int wsum, fsum, ncirc;
+    int64_t rec;                    // first word of the node record, -1: none
 };
 
 template <typename T>
@@ -432,7 +434,6 @@ __device__ inline V3<T> vert_pos(const Shared<T> &sh, int i) { return v3(sh.vx[i
 struct Params {
     Inputs in;
     Work w;
-    FillOut o;
     int k;
     float kappa_max;  // FP32 nodes with a vertex above this go to FP64
 };
@@ -440,8 +441,9 @@ struct Params {
 // statuses that FP64 may resolve
 constexpr int kRetry = NS_NON_ELLIPTIC | NS_LOOP | NS_TOPOLOGY | NS_PREC;
 
-// The whole per-node computation; FILL adds the writes.
-template <bool FILL, typename T>
+// The whole per-node computation: counts, and the node record for the
+// expansion pass.
+template <typename T>
 __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
 {
     constexpr bool F32 = sizeof(T) == 4;
@@ -451,10 +453,6 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
     const Work &W = P.w;
     const int64_t N = P.in.n_nodes;
     const int k = P.k;
-    if (FILL) {
-        if (W.node_cnt[NC_STATUS * N + n] != 0) return;
-        if (W.flags[0] & (DF_CAPACITY | DF_BADLAT | DF_LOOPCAP)) return;
-    }
     const int64_t row = W.row[n];
     const int v = (int)(W.row[n + 1] - row);
     const float4 c4 = W.node4[n];
@@ -466,17 +464,18 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
         sh.n_vert = 0;
         sh.n_contour = 0;
         sh.wsum = 0;
+        sh.fsum = 0;
+        sh.ncirc = 0;
+        sh.rec = -1;
     }
     __syncthreads();
     if (v == 0 || v > kVmax) {
-        if (!FILL) {
-            if (lane == 0) {
-                for (int c = 0; c < kNodeCols; ++c) W.node_cnt[c * N + n] = 0;
-                W.node_cnt[NC_STATUS * N + n] = v == 0 ? NS_ISOLATED : NS_VALENCE;
-                if (F32) W.node_prec[n] = 0;
-            }
-            for (int i = lane; i < v; i += 64) W.he_len[row + i] = 0;
+        if (lane == 0) {
+            for (int c = 0; c < kNodeCols; ++c) W.node_cnt[c * N + n] = 0;
+            W.node_cnt[NC_STATUS * N + n] = v == 0 ? NS_ISOLATED : NS_VALENCE;
+            W.node_rec[n] = -1;
         }
+        for (int i = lane; i < v; i += 64) W.he_len[row + i] = 0;
         return;
     }
 
@@ -530,7 +529,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
         for (int j = 0; j < v; ++j)
             if (j != lane && sh.S[j + 1].far == sh.S[lane + 1].far) atomicOr(&sh.status, NS_DUPLICATE);
     }
-    if (F32 && !FILL && lane == 0 && !(P.kappa_max > 0.f)) atomicOr(&sh.status, NS_PREC);  // all FP64
+    if (F32 && lane == 0 && !(P.kappa_max > 0.f)) atomicOr(&sh.status, NS_PREC);  // all FP64
     __syncthreads();
     if (sh.status) goto finish;
 
@@ -654,7 +653,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                         sh.vx[vbase + rank] = w.x;
                         sh.vy[vbase + rank] = w.y;
                         sh.vz[vbase + rank] = w.z;
-                        if (F32 && !FILL && orr[i] >= 0 && tie_kappa(sh.S, p, q, orr[i], w) > (T)P.kappa_max)
+                        if (F32 && orr[i] >= 0 && tie_kappa(sh.S, p, q, orr[i], w) > (T)P.kappa_max)
                             atomicOr(&sh.status, NS_PREC);
                     }
                 }
@@ -871,12 +870,20 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
     {
         const int E = sh.n_arc, V = sh.n_vert, NC = sh.n_contour;
         if (lane == 0) {
-            int mb = V;
+            int mb = V, fb = 0, nc = 0;
             for (int j = 0; j < E; ++j) {
-                sh.A[j].mbase = mb;
-                mb += sh.A[j].nseg - 1;
+                ArcL<T> &A = sh.A[j];
+                A.mbase = mb;
+                mb += A.nseg - 1;
+                A.fbase = fb;
+                if (A.p == 0) {  // circular arcs sort first; one fan triangle per segment
+                    fb += A.nseg;
+                    ++nc;
+                }
             }
             sh.wsum = mb;  // first hole-centre index
+            sh.fsum = fb;
+            sh.ncirc = nc;
         }
         __syncthreads();
         // Eq. 13: barycentre of each contour's vertices (each once: half of
@@ -898,7 +905,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
             T bl = m_sqrt(dot(b, b));
             // the apex direction b/|b| amplifies rounding by rho/|b|; the
             // fallback decision near |b| = 1e-3 rho is fragile as well
-            if (F32 && !FILL && bl * (T)P.kappa_max < rho) atomicOr(&sh.status, NS_PREC);
+            if (F32 && bl * (T)P.kappa_max < rho) atomicOr(&sh.status, NS_PREC);
             V3<T> dir;
             if (bl >= (T)1e-3 * rho) {
                 dir = b * ((T)1 / bl);
@@ -920,20 +927,35 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
             sh.hc[c][1] = dir.y * rho;
             sh.hc[c][2] = dir.z * rho;
         }
+        __syncthreads();
+        if (sh.status) goto finish;
         // strut end loops must be graphs over phi: every step (mod 2 pi)
         // positive and exactly one descent, i.e. one turn.  Lanes run over
-        // all loop samples of the node; FILL also writes them for the bands.
+        // all loop samples of the node and store them in the node record.
         if (lane == 0) {
             int off = 0;
             for (int m = 1; m <= v; ++m) {
                 const int b0 = sh.loop_base[m], cnt = sh.loop_base[m + 1] - b0;
+                sh.lbase[m] = off;
                 for (int t = 0; t < cnt; ++t) {
                     sh.entry_off[b0 + t] = off;
                     sh.entry_m[b0 + t] = (uint8_t)m;
                     off += sh.A[sh.loop_arc[b0 + sh.loop_ord[b0 + t]]].nseg;
                 }
             }
+            sh.lbase[v + 1] = off;
             sh.entry_off[sh.loop_base[v + 1]] = off;
+            // record space: bump allocation in the node's region
+            const int64_t words = rec_loop_word(V, E, NC) + (((int64_t)2 * off + 3) & ~(int64_t)3);
+            const int g = (int)(n & (kRecRegions - 1));
+            const int64_t region = W.rec_words / kRecRegions;
+            const unsigned long long old = atomicAdd(&W.rec_top[g], (unsigned long long)words);
+            if ((int64_t)old + words <= region) {
+                sh.rec = (int64_t)g * region + (int64_t)old;
+            } else {
+                sh.rec = -1;
+                atomicOr(&W.flags[0], DF_RECCAP);
+            }
         }
         if (lane < v) {
             sh.loop_desc[lane + 1] = 0;
@@ -943,8 +965,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
         {
             const int nent = sh.loop_base[v + 1];
             const int ns_tot = sh.entry_off[nent];
-            int32_t mbase_g = 0;
-            if (FILL) mbase_g = (int32_t)W.node_off[3 * (N + 1) + n];
+            int2 *rl = sh.rec >= 0 ? (int2 *)(W.rec + sh.rec + rec_loop_word(V, E, NC)) : nullptr;
             // phi and local mesh index of sample j of loop entry e
             auto sample = [&](int e, int j, int &li) -> T {
                 const int m = sh.entry_m[e];
@@ -1003,21 +1024,17 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                     if (dp > Cst<T>::pi) dp -= tp;
                     if (!(dp > (T)0)) atomicOr(&sh.status, NS_LOOP);
                     if (ph2 < ph) atomicAdd(&sh.loop_desc[m], 1);
-                    if (FILL) {
-                        const int64_t lbase = W.he_off[row + m - 1];
-                        if (idx < W.he_len[row + m - 1])
-                            W.loop[lbase + idx] = make_int2(mbase_g + li, __float_as_int((float)ph));
-                        unsigned int u = __float_as_uint((float)ph);
-                        u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);  // order-preserving
-                        atomicMin(&sh.loop_rot[m], ((unsigned long long)u << 32) | (unsigned int)idx);
-                    }
+                    if (rl) rl[sh.lbase[m] + idx] = make_int2(li, __float_as_int((float)ph));
+                    unsigned int u = __float_as_uint((float)ph);
+                    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);  // order-preserving
+                    atomicMin(&sh.loop_rot[m], ((unsigned long long)u << 32) | (unsigned int)idx);
                 }
             }
         }
         __syncthreads();
         if (lane < v) {
             if (sh.loop_desc[lane + 1] != 1) atomicOr(&sh.status, NS_LOOP);
-            if (FILL) W.he_rot[row + lane] = (int32_t)(sh.loop_rot[lane + 1] & 0xffffffffull);
+            W.he_rot[row + lane] = (int32_t)(sh.loop_rot[lane + 1] & 0xffffffffull);
         }
         __syncthreads();
     }
@@ -1027,130 +1044,92 @@ finish:
     {
         const int status = sh.status;
         const int E = sh.n_arc, V = sh.n_vert, NC = sh.n_contour;
-        int Msum = 0, Fsum = 0;
-        if (!status) {
-            Msum = sh.wsum + NC;
-            for (int j = 0; j < E; ++j)
-                if (sh.A[j].p == 0) Fsum += sh.A[j].nseg;
-        }
-        if (!FILL) {
+        if (status) {
             if (lane == 0) {
-                W.node_cnt[NC_VERT * N + n] = status ? 0 : V;
-                W.node_cnt[NC_ARC * N + n] = status ? 0 : E;
-                W.node_cnt[NC_HOLE * N + n] = status ? 0 : NC;
-                W.node_cnt[NC_MESH * N + n] = Msum;
-                W.node_cnt[NC_FAN * N + n] = Fsum;
+                for (int c = 0; c < kNodeCols; ++c) W.node_cnt[c * N + n] = 0;
                 W.node_cnt[NC_STATUS * N + n] = status & ~NS_PREC;
-                if (F32) {
-                    // hand the node to the FP64 pass when precision may be at fault
-                    int retry = (status & kRetry) != 0;
-                    W.node_prec[n] = (uint8_t)retry;
-                    if (retry) W.fb_list[atomicAdd(&W.flags[2], 1)] = (int32_t)n;
-                }
+                W.node_rec[n] = -1;
+                // hand the node to the FP64 pass when precision may be at fault
+                if (F32 && (status & kRetry)) W.fb_list[atomicAdd(&W.flags[2], 1)] = (int32_t)n;
             }
-            if (lane < v) W.he_len[row + lane] = status ? 0 : sh.loop_len[lane + 1];
+            if (lane < v) W.he_len[row + lane] = 0;
             return;
         }
-        // FILL: the recomputation must reproduce the counted node
-        if (status || W.node_cnt[NC_VERT * N + n] != V || W.node_cnt[NC_ARC * N + n] != E ||
-            W.node_cnt[NC_MESH * N + n] != Msum || W.node_cnt[NC_FAN * N + n] != Fsum) {
-            if (lane == 0) atomicOr(W.flags, DF_MISMATCH);
-            return;
+        const int Msum = sh.wsum + NC, Fsum = sh.fsum;
+        const int64_t rb = sh.rec;
+        const int64_t lw = rec_loop_word(V, E, NC);
+        if (lane == 0) {
+            W.node_cnt[NC_VERT * N + n] = V;
+            W.node_cnt[NC_ARC * N + n] = E;
+            W.node_cnt[NC_HOLE * N + n] = NC;
+            W.node_cnt[NC_MESH * N + n] = Msum;
+            W.node_cnt[NC_FAN * N + n] = Fsum;
+            W.node_cnt[NC_STATUS * N + n] = 0;
+            W.node_rec[n] = rb;
         }
-        const int64_t Np1 = N + 1;
-        const int64_t voff = W.node_off[0 * Np1 + n], aoff = W.node_off[1 * Np1 + n];
-        const int64_t moff = W.node_off[3 * Np1 + n], foff = W.node_off[4 * Np1 + n];
-        const FillOut &O = P.o;
-        // meta-mesh vertices and arcs (local coordinates)
-        if (O.vert_name) {
-            for (int i = lane; i < V; i += 64) {
-                O.vert_name[voff + i] = sh.vname[i];
-                O.vert_xyz[0 * O.cap_vert + voff + i] = (float)sh.vx[i];
-                O.vert_xyz[1 * O.cap_vert + voff + i] = (float)sh.vy[i];
-                O.vert_xyz[2 * O.cap_vert + voff + i] = (float)sh.vz[i];
-            }
+        if (lane < v) {
+            W.he_len[row + lane] = sh.loop_len[lane + 1];
+            W.he_loop[row + lane] = rb >= 0 ? (rb + lw) / 2 + sh.lbase[lane + 1] : 0;
         }
-        if (O.arc_f32) {
-            for (int j = lane; j < E; j += 64) {
-                const ArcL<T> &A = sh.A[j];
-                const int64_t cA = O.cap_arc;
-                T f[11] = {A.o[0], A.o[1], A.o[2], A.a[0], A.a[1], A.a[2], A.b[0], A.b[1], A.b[2], A.t1, A.t2};
-#pragma unroll
-                for (int t = 0; t < 11; ++t) O.arc_f32[t * cA + aoff + j] = (float)f[t];
-                O.arc_u32[0 * cA + aoff + j] = (uint32_t)A.p | ((uint32_t)A.q << 8) | ((uint32_t)A.full << 16);
-                O.arc_u32[1 * cA + aoff + j] = (uint32_t)A.vs | ((uint32_t)A.ve << 16);
-                O.arc_u32[2 * cA + aoff + j] = (uint32_t)n;
-            }
+        if (rb < 0) return;
+        uint32_t *R = W.rec + rb;
+        if (lane == 0) {
+            R[0] = (uint32_t)V;
+            R[1] = (uint32_t)E;
+            R[2] = (uint32_t)NC;
+            R[3] = (uint32_t)sh.ncirc;
+            R[4] = (uint32_t)sh.wsum;
+            R[5] = (uint32_t)Msum;
+            R[6] = (uint32_t)Fsum;
+            R[7] = 0u;
         }
-        // mesh vertices: meta-vertices, interior points, hole centres
-        for (int i = lane; i < Msum; i += 64) {
-            V3<T> w;
-            if (i < V) {
-                w = vert_pos(sh, i);
-            } else if (i < sh.wsum) {
-                int lo = 0, hi = E - 1;  // last arc with mbase <= i
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (sh.A[mid].mbase <= i) lo = mid;
-                    else hi = mid - 1;
-                }
-                const ArcL<T> &A = sh.A[lo];
-                int jc = i - A.mbase;
-                bool fwd = A.full || A.ns <= A.ne;
-                int ii = fwd ? jc + 1 : A.nseg - 1 - jc;
-                w = interior_pt(A, ii);
-            } else {
-                int c = i - sh.wsum;
-                w = v3(sh.hc[c][0], sh.hc[c][1], sh.hc[c][2]);
-            }
-            V3<T> x = cen + w;
-            float *dst = O.mesh_xyz + 3 * (moff + i);
-            dst[0] = (float)x.x;
-            dst[1] = (float)x.y;
-            dst[2] = (float)x.z;
+        uint32_t *RV = R + kRecHead;
+        for (int i = lane; i < V; i += 64) {
+            RV[i] = sh.vname[i];
+            RV[V + i] = __float_as_uint((float)sh.vx[i]);
+            RV[2 * V + i] = __float_as_uint((float)sh.vy[i]);
+            RV[3 * V + i] = __float_as_uint((float)sh.vz[i]);
         }
-        // hole fans: one triangle per circular-arc segment
-        const int64_t fan0 = W.band_off[P.in.n_struts] + foff;
-        int fbase = 0;
-        for (int j = 0; j < E && sh.A[j].p == 0; ++j) {
+        uint32_t *RA = RV + 4 * V;
+        for (int j = lane; j < E; j += 64) {
             const ArcL<T> &A = sh.A[j];
-            bool fwd = A.full || A.ns <= A.ne;
-            bool lower = sh.S[A.q].lower;
-            int ctr = sh.wsum + A.contour;
-            for (int s = lane; s < A.nseg; s += 64) {
-                int i0 = fwd ? s : A.nseg - s, i1 = fwd ? s + 1 : A.nseg - s - 1;
-                int lo_i = i0 < i1 ? i0 : i1, hi_i = i0 < i1 ? i1 : i0;
-                int u = lo_i == 0 ? A.vs : interior_idx(A, lo_i);
-                int u2 = hi_i == A.nseg ? A.ve : interior_idx(A, hi_i);
-                int32_t *t = O.tri + 3 * (fan0 + fbase + s);
-                t[0] = (int32_t)(moff + ctr);
-                t[1] = (int32_t)(moff + (lower ? u2 : u));
-                t[2] = (int32_t)(moff + (lower ? u : u2));
-            }
-            fbase += A.nseg;
+            const T f[11] = {A.o[0], A.o[1], A.o[2], A.a[0], A.a[1], A.a[2], A.b[0], A.b[1], A.b[2], A.t1, A.t2};
+#pragma unroll
+            for (int t = 0; t < 11; ++t) RA[t * E + j] = __float_as_uint((float)f[t]);
+            const uint32_t fwd = (A.full || A.ns <= A.ne) ? 1u : 0u;
+            const uint32_t lower = sh.S[A.q].lower ? 1u : 0u;
+            RA[11 * E + j] = (uint32_t)A.p | ((uint32_t)A.q << 8) | ((uint32_t)A.full << 16) | (fwd << 17) |
+                             (lower << 18);
+            RA[12 * E + j] = (uint32_t)A.vs | ((uint32_t)A.ve << 16);
+            RA[13 * E + j] = (uint32_t)A.nseg | (((uint32_t)A.contour & 0xffffu) << 16);
+            RA[14 * E + j] = (uint32_t)A.mbase;
+            RA[15 * E + j] = (uint32_t)A.fbase;
+        }
+        uint32_t *RH = RA + kRecArcFields * E;
+        for (int c = lane; c < NC; c += 64) {
+            RH[c] = __float_as_uint((float)sh.hc[c][0]);
+            RH[NC + c] = __float_as_uint((float)sh.hc[c][1]);
+            RH[2 * NC + c] = __float_as_uint((float)sh.hc[c][2]);
         }
     }
 }
 
 // FP32: one node per block
-template <bool FILL>
 __global__ void __launch_bounds__(64) k_node32(Params P)
 {
     __shared__ Shared<float> sh;
     const int64_t n = blockIdx.x;
     if (n >= P.in.n_nodes) return;
-    if (FILL && P.w.node_prec[n]) return;
-    node_body<FILL, float>(P, sh, n);
+    node_body<float>(P, sh, n);
 }
 
 // FP64: the nodes the FP32 pass handed over, looped over by a fixed grid
-template <bool FILL>
 __global__ void __launch_bounds__(64) k_node64(Params P)
 {
     __shared__ Shared<double> sh;
     const int cnt = P.w.flags[2];
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
-        node_body<FILL, double>(P, sh, (int64_t)P.w.fb_list[i]);
+        node_body<double>(P, sh, (int64_t)P.w.fb_list[i]);
         __syncthreads();
     }
 }
@@ -1159,20 +1138,16 @@ constexpr unsigned kFp64Grid = 2048;
 
 }  // namespace
 
-hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, const FillOut *o, int fp64,
-                       hipStream_t st)
+hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, int fp64, hipStream_t st)
 {
     if (in.n_nodes == 0) return hipSuccess;
     Params P;
     P.in = in;
     P.w = w;
-    P.o = o ? *o : FillOut{};
     P.k = k;
     P.kappa_max = kappa_max;
-    if (!o && !fp64) k_node32<false><<<(unsigned)in.n_nodes, 64, 0, st>>>(P);
-    if (!o && fp64) k_node64<false><<<kFp64Grid, 64, 0, st>>>(P);
-    if (o && !fp64) k_node32<true><<<(unsigned)in.n_nodes, 64, 0, st>>>(P);
-    if (o && fp64) k_node64<true><<<kFp64Grid, 64, 0, st>>>(P);
+    if (!fp64) k_node32<<<(unsigned)in.n_nodes, 64, 0, st>>>(P);
+    else k_node64<<<kFp64Grid, 64, 0, st>>>(P);
     return hipGetLastError();
 }
 

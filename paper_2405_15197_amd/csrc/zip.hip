@@ -1,8 +1,9 @@
 // Strut bands (Sec. 5: a strut is triangulated by connecting the vertices of
 // its two arc loops) and the device-side totals.
 //
-// Each strut end loop arrives as a list of (mesh vertex, phi) in loop order,
-// phi increasing cyclically about the strut axis.  The band is the phi-merge
+// Each strut end loop arrives in its node's record as a list of (node-local
+// mesh vertex, phi) in loop order, phi increasing cyclically about the strut
+// axis.  The band is the phi-merge
 // zipper: with the samples of both loops sorted by (phi, end), the loop at
 // the lower node id first on ties, every loop edge u -> u' forms a triangle
 // with the last sample of the other loop that precedes u' (cyclically).
@@ -59,10 +60,11 @@ __device__ inline int pred_sorted(const int2 *L, int n, int rot, float x, bool i
 }
 
 __global__ void __launch_bounds__(kBlock) k_zip(int64_t S, const int64_t *band_off, const int64_t *strut_he,
-                                                const int64_t *he_off, const int32_t *he_len, const int32_t *he_rot,
-                                                const int2 *loop, int32_t *tri, const int32_t *flags)
+                                                const int64_t *he_loop, const int32_t *he_len, const int32_t *he_rot,
+                                                const int2 *loop, const int32_t *sa, const int32_t *sb,
+                                                const int64_t *mesh_off, int32_t *tri, const int32_t *flags)
 {
-    if (flags[0] & (DF_CAPACITY | DF_BADLAT | DF_LOOPCAP | DF_MISMATCH)) return;
+    if (flags[0] & (DF_CAPACITY | DF_BADLAT | DF_RECCAP)) return;
     const int64_t nband = band_off[S];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x;  // first triangle of the block
@@ -90,40 +92,45 @@ __global__ void __launch_bounds__(kBlock) k_zip(int64_t S, const int64_t *band_o
     const int64_t s = lo;
     const int j = (int)(t - band_off[s]);
     const int64_t ha = strut_he[2 * s], hb = strut_he[2 * s + 1];
-    const int2 *A = loop + he_off[ha];
-    const int2 *B = loop + he_off[hb];
+    const int2 *A = loop + he_loop[ha];
+    const int2 *B = loop + he_loop[hb];
     const int na = he_len[ha], nb = he_len[hb];
+    // loop A is at the lower node id
+    const int32_t a = sa[s], b = sb[s];
+    const int32_t ma = (int32_t)mesh_off[a < b ? a : b], mb = (int32_t)mesh_off[a < b ? b : a];
     int32_t *T = tri + 3 * t;
     if (j < na) {
         // edge A[j] -> A[j+1]; apex: last B sample strictly before A[j+1]
         int j2 = j + 1 == na ? 0 : j + 1;
         int2 u2 = A[j2];
         int ap = pred_sorted(B, nb, he_rot[hb], __int_as_float(u2.y), false);
-        T[0] = A[j].x;
-        T[1] = u2.x;
-        T[2] = B[ap].x;
+        T[0] = ma + A[j].x;
+        T[1] = ma + u2.x;
+        T[2] = mb + B[ap].x;
     } else {
         // edge B[e] -> B[e+1]; apex: last A sample at or before B[e+1]
         int e = j - na;
         int e2 = e + 1 == nb ? 0 : e + 1;
         int2 w2 = B[e2];
         int ap = pred_sorted(A, na, he_rot[ha], __int_as_float(w2.y), true);
-        T[0] = w2.x;
-        T[1] = B[e].x;
-        T[2] = A[ap].x;
+        T[0] = mb + w2.x;
+        T[1] = mb + B[e].x;
+        T[2] = ma + A[ap].x;
     }
 }
 
 // Totals (device) and capacity checks for the fill pass.
-__global__ void k_totals(int64_t N, int64_t S, const int64_t *node_off, const int64_t *he_off,
-                         const int64_t *band_off, int64_t loop_cap, FillOut o, int check, int64_t *totals,
-                         int32_t *flags)
+__global__ void k_totals(int64_t N, int64_t S, const int64_t *node_off, const unsigned long long *rec_top,
+                         const int64_t *band_off, FillOut o, int check, int64_t *totals, int32_t *flags)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const int64_t Np1 = N + 1;
     int64_t nv = node_off[0 * Np1 + N], na = node_off[1 * Np1 + N], nh = node_off[2 * Np1 + N];
     int64_t nm = node_off[3 * Np1 + N], nf = node_off[4 * Np1 + N];
-    int64_t nb = band_off[S], nl = he_off[2 * S];
+    int64_t nb = band_off[S];
+    unsigned long long top = 0;  // record words: the fullest region times the region count
+    for (int g = 0; g < kRecRegions; ++g) top = rec_top[g] > top ? rec_top[g] : top;
+    const int64_t nl = (int64_t)top * kRecRegions * 4;
     totals[0] = nv;
     totals[1] = na;
     totals[2] = nh;
@@ -133,8 +140,7 @@ __global__ void k_totals(int64_t N, int64_t S, const int64_t *node_off, const in
     totals[6] = nf;
     totals[7] = nl;
     totals[10] = flags[2];
-    if (nl > loop_cap) atomicOr(flags, DF_LOOPCAP);
-    if (nm > 0x7fffffffLL) atomicOr(flags, DF_LOOPCAP);
+    if (nm > 0x7fffffffLL) atomicOr(flags, DF_RECCAP);
     if (check) {
         bool bad = nm > o.cap_mesh || nb + nf > o.cap_tri;
         if (o.vert_name && nv > o.cap_vert) bad = true;
@@ -164,16 +170,17 @@ hipError_t launch_zip(const Inputs &in, const Work &w, const FillOut &o, hipStre
     // grid sized for the capacity; blocks past the band total exit at once
     int64_t cap = o.cap_tri;
     if (S > 0 && cap > 0)
-        k_zip<<<grid_for(cap), kBlock, 0, st>>>(S, w.band_off, w.strut_he, w.he_off, w.he_len, w.he_rot, w.loop,
-                                                o.tri, w.flags);
+        k_zip<<<grid_for(cap), kBlock, 0, st>>>(S, w.band_off, w.strut_he, w.he_loop, w.he_len, w.he_rot,
+                                                (const int2 *)w.rec, in.sa, in.sb,
+                                                w.node_off + (int64_t)NC_MESH * (in.n_nodes + 1), o.tri, w.flags);
     return hipGetLastError();
 }
 
 hipError_t launch_totals(const Inputs &in, const Work &w, const FillOut *o, hipStream_t st)
 {
     FillOut oo = o ? *o : FillOut{};
-    k_totals<<<1, 64, 0, st>>>(in.n_nodes, in.n_struts, w.node_off, w.he_off, w.band_off, w.loop_cap, oo,
-                               o ? 1 : 0, w.totals, w.flags);
+    k_totals<<<1, 64, 0, st>>>(in.n_nodes, in.n_struts, w.node_off, w.rec_top, w.band_off, oo, o ? 1 : 0,
+                               w.totals, w.flags);
     return hipGetLastError();
 }
 

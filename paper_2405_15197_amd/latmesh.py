@@ -69,7 +69,7 @@ _TOTAL_FIELDS = [
     "n_triangles",
     "n_band_triangles",
     "n_fan_triangles",
-    "n_loop_entries",
+    "n_record_bytes",
     "n_bad_nodes",
     "n_skipped_struts",
     "n_fp64_nodes",
@@ -188,7 +188,7 @@ def lm_read_totals(plan) -> lm_totals:
     return t
 
 
-PHASES = ("prepare", "count_fp32", "count_fp64", "sizes", "fill_fp32", "fill_fp64", "bands")
+PHASES = ("prepare", "node_fp32", "node_fp64", "sizes", "expand", "bands")
 
 
 def lm_prepare(plan) -> None:
