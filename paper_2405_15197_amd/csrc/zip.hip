@@ -37,85 +37,170 @@ __global__ void k_bad_nodes(int64_t N, const int32_t *node_status, int64_t *tota
     if (n < N && node_status[n] != 0) atomicAdd((unsigned long long *)&totals[8], 1ull);
 }
 
-// One thread per band triangle, in output order (coalesced writes).  The
-// apex of a loop-edge triangle is the cyclic predecessor of the edge's end
-// among the other loop's samples in (phi, end) order, found by binary search
-// on that loop read from its smallest phi onwards.
-__device__ inline int pred_sorted(const int2 *L, int n, int rot, float x, bool inclusive)
+// One wave per kZipGroup consecutive struts.  Lanes load the struts' loop
+// descriptors, the loops are staged in LDS in sorted (phi) order when they
+// fit, then lanes run over the group's band triangles in output order
+// (coalesced writes).  The apex of a loop-edge triangle is the cyclic
+// predecessor of the edge's end among the other loop's samples in
+// (phi, end) order, found by binary search on the sorted samples.
+constexpr int kZipGroup = 8;
+constexpr int kZipStage = 768;  // staged samples per wave (6 KB of LDS)
+
+// Loop access in sorted order: from LDS (already rotated) or from the node
+// record (rotated on the fly).
+struct LoopLds {
+    const int2 *p;
+    int n;
+    __device__ int2 at(int k) const { return p[k]; }
+};
+struct LoopGlobal {
+    const int2 *p;
+    int n, rot;
+    __device__ int2 at(int k) const
+    {
+        int i = rot + k;
+        return p[i >= n ? i - n : i];
+    }
+};
+
+// number of samples with phi < x (or <= x) minus one, cyclically: the sorted
+// index of the predecessor of x
+template <typename L>
+__device__ inline int pred_sorted(const L &lp, float x, bool inclusive)
 {
-    // number of samples with phi < x (or <= x), in sorted order
-    int lo = 0, hi = n;
+    int lo = 0, hi = lp.n;
     while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        int pos = rot + mid;
-        if (pos >= n) pos -= n;
-        float p = __int_as_float(L[pos].y);
-        bool before = inclusive ? (p <= x) : (p < x);
-        if (before) lo = mid + 1;
+        const int mid = (lo + hi) >> 1;
+        const float p = __int_as_float(lp.at(mid).y);
+        if (inclusive ? (p <= x) : (p < x)) lo = mid + 1;
         else hi = mid;
     }
-    int i = lo == 0 ? n - 1 : lo - 1;
-    int pos = rot + i;
-    return pos >= n ? pos - n : pos;
+    return lo == 0 ? lp.n - 1 : lo - 1;
 }
 
-__global__ void __launch_bounds__(kBlock) k_zip(int64_t S, const int64_t *band_off, const int64_t *strut_he,
-                                                const int64_t *he_loop, const int32_t *he_len, const int32_t *he_rot,
-                                                const int2 *loop, const int32_t *sa, const int32_t *sb,
-                                                const int64_t *mesh_off, int32_t *tri, const int32_t *flags)
+// Triangle j of a band: j < na are the edges of loop A (lower node id), in
+// loop order from A's loop position 0; then the edges of loop B.
+template <typename L>
+__device__ inline void band_tri(const L &A, const L &B, int ra, int rb, int j, int32_t ma, int32_t mb, int32_t *T)
 {
-    if (flags[0] & (DF_CAPACITY | DF_BADLAT | DF_RECCAP)) return;
-    const int64_t nband = band_off[S];
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x;  // first triangle of the block
-    if (t0 >= nband) return;
-    // strut of the block's first triangle, then of this thread's (searching
-    // forward from there)
-    __shared__ int64_t s_first;
-    if (threadIdx.x == 0) {
-        int64_t lo = 0, hi = S - 1;  // last s with band_off[s] <= t0
-        while (lo < hi) {
-            int64_t mid = (lo + hi + 1) >> 1;
-            if (band_off[mid] <= t0) lo = mid;
-            else hi = mid - 1;
-        }
-        s_first = lo;
-    }
-    __syncthreads();
-    if (t >= nband) return;
-    int64_t lo = s_first, hi = S - 1;
-    while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
-        if (band_off[mid] <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    const int64_t s = lo;
-    const int j = (int)(t - band_off[s]);
-    const int64_t ha = strut_he[2 * s], hb = strut_he[2 * s + 1];
-    const int2 *A = loop + he_loop[ha];
-    const int2 *B = loop + he_loop[hb];
-    const int na = he_len[ha], nb = he_len[hb];
-    // loop A is at the lower node id
-    const int32_t a = sa[s], b = sb[s];
-    const int32_t ma = (int32_t)mesh_off[a < b ? a : b], mb = (int32_t)mesh_off[a < b ? b : a];
-    int32_t *T = tri + 3 * t;
+    const int na = A.n, nb = B.n;
     if (j < na) {
         // edge A[j] -> A[j+1]; apex: last B sample strictly before A[j+1]
-        int j2 = j + 1 == na ? 0 : j + 1;
-        int2 u2 = A[j2];
-        int ap = pred_sorted(B, nb, he_rot[hb], __int_as_float(u2.y), false);
-        T[0] = ma + A[j].x;
+        int k0 = j - ra;
+        if (k0 < 0) k0 += na;
+        const int k1 = k0 + 1 == na ? 0 : k0 + 1;
+        const int2 u = A.at(k0), u2 = A.at(k1);
+        const int ap = pred_sorted(B, __int_as_float(u2.y), false);
+        T[0] = ma + u.x;
         T[1] = ma + u2.x;
-        T[2] = mb + B[ap].x;
+        T[2] = mb + B.at(ap).x;
     } else {
         // edge B[e] -> B[e+1]; apex: last A sample at or before B[e+1]
-        int e = j - na;
-        int e2 = e + 1 == nb ? 0 : e + 1;
-        int2 w2 = B[e2];
-        int ap = pred_sorted(A, na, he_rot[ha], __int_as_float(w2.y), true);
+        int k0 = j - na - rb;
+        if (k0 < 0) k0 += nb;
+        const int k1 = k0 + 1 == nb ? 0 : k0 + 1;
+        const int2 w = B.at(k0), w2 = B.at(k1);
+        const int ap = pred_sorted(A, __int_as_float(w2.y), true);
         T[0] = mb + w2.x;
-        T[1] = mb + B[e].x;
-        T[2] = ma + A[ap].x;
+        T[1] = mb + w.x;
+        T[2] = ma + A.at(ap).x;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_zip(int64_t S, const int64_t *band_off, const int64_t *strut_he,
+                                            const int64_t *he_loop, const int32_t *he_len, const int32_t *he_rot,
+                                            const int2 *loop, const int32_t *sa, const int32_t *sb,
+                                            const int64_t *mesh_off, int32_t *tri, const int32_t *flags)
+{
+    __shared__ int2 st[kZipStage];
+    __shared__ int64_t g_la[kZipGroup], g_lb[kZipGroup];
+    __shared__ int g_na[kZipGroup], g_nb[kZipGroup], g_ra[kZipGroup], g_rb[kZipGroup];
+    __shared__ int g_ma[kZipGroup], g_mb[kZipGroup], g_t[kZipGroup + 1], g_q[kZipGroup + 1];
+    if (flags[0] & (DF_CAPACITY | DF_BADLAT | DF_RECCAP)) return;
+    const int lane = threadIdx.x;
+    const int64_t s0 = (int64_t)blockIdx.x * kZipGroup;
+    if (s0 >= S) return;
+    const int ns = S - s0 < kZipGroup ? (int)(S - s0) : kZipGroup;
+    const int64_t t0 = band_off[s0];
+    int cnt = 0, q = 0;
+    if (lane < ns) {
+        const int64_t s = s0 + lane;
+        cnt = (int)(band_off[s + 1] - band_off[s]);
+        int na = 0, nb = 0;
+        if (cnt > 0) {
+            const int64_t ha = strut_he[2 * s], hb = strut_he[2 * s + 1];
+            na = he_len[ha];
+            nb = he_len[hb];
+            g_la[lane] = he_loop[ha];
+            g_lb[lane] = he_loop[hb];
+            g_ra[lane] = he_rot[ha];
+            g_rb[lane] = he_rot[hb];
+            const int32_t a = sa[s], b = sb[s];
+            g_ma[lane] = (int32_t)mesh_off[a < b ? a : b];
+            g_mb[lane] = (int32_t)mesh_off[a < b ? b : a];
+        }
+        g_na[lane] = na;
+        g_nb[lane] = nb;
+        q = na + nb;
+    }
+    // prefix sums of the triangle and sample counts over the group
+    int ct = cnt, cq = q;
+#pragma unroll
+    for (int d = 1; d < kZipGroup; d <<= 1) {
+        const int yt = __shfl_up(ct, d, 64), yq = __shfl_up(cq, d, 64);
+        if (lane >= d) {
+            ct += yt;
+            cq += yq;
+        }
+    }
+    if (lane < ns) {
+        g_t[lane + 1] = ct;
+        g_q[lane + 1] = cq;
+    }
+    if (lane == 0) {
+        g_t[0] = 0;
+        g_q[0] = 0;
+    }
+    __syncthreads();
+    const int ntri = g_t[ns], nsamp = g_q[ns];
+    const bool staged = nsamp <= kZipStage;
+    if (staged) {
+        // samples of strut i: loop A sorted, then loop B sorted
+        for (int x = lane; x < nsamp; x += 64) {
+            int i = 0;
+            while (g_q[i + 1] <= x) ++i;
+            int k = x - g_q[i];
+            const int na = g_na[i];
+            int64_t base;
+            int n, r;
+            if (k < na) {
+                base = g_la[i];
+                n = na;
+                r = g_ra[i];
+            } else {
+                k -= na;
+                base = g_lb[i];
+                n = g_nb[i];
+                r = g_rb[i];
+            }
+            int idx = r + k;
+            if (idx >= n) idx -= n;
+            st[x] = loop[base + idx];
+        }
+        __syncthreads();
+    }
+    for (int x = lane; x < ntri; x += 64) {
+        int i = 0;
+        while (g_t[i + 1] <= x) ++i;
+        const int j = x - g_t[i];
+        int32_t *T = tri + 3 * (t0 + x);
+        if (staged) {
+            const LoopLds A{st + g_q[i], g_na[i]}, B{st + g_q[i] + g_na[i], g_nb[i]};
+            band_tri(A, B, g_ra[i], g_rb[i], j, g_ma[i], g_mb[i], T);
+        } else {
+            const LoopGlobal A{loop + g_la[i], g_na[i], g_ra[i]}, B{loop + g_lb[i], g_nb[i], g_rb[i]};
+            band_tri(A, B, g_ra[i], g_rb[i], j, g_ma[i], g_mb[i], T);
+        }
     }
 }
 
@@ -167,10 +252,8 @@ hipError_t launch_band_count(const Inputs &in, const Work &w, hipStream_t st)
 hipError_t launch_zip(const Inputs &in, const Work &w, const FillOut &o, hipStream_t st)
 {
     const int64_t S = in.n_struts;
-    // grid sized for the capacity; blocks past the band total exit at once
-    int64_t cap = o.cap_tri;
-    if (S > 0 && cap > 0)
-        k_zip<<<grid_for(cap), kBlock, 0, st>>>(S, w.band_off, w.strut_he, w.he_loop, w.he_len, w.he_rot,
+    if (S > 0)
+        k_zip<<<(unsigned)((S + kZipGroup - 1) / kZipGroup), 64, 0, st>>>(S, w.band_off, w.strut_he, w.he_loop, w.he_len, w.he_rot,
                                                 (const int2 *)w.rec, in.sa, in.sb,
                                                 w.node_off + (int64_t)NC_MESH * (in.n_nodes + 1), o.tri, w.flags);
     return hipGetLastError();
