@@ -48,16 +48,13 @@ __device__ inline float m_abs(float x) { return fabsf(x); }
 __device__ inline double m_abs(double x) { return fabs(x); }
 __device__ inline float m_atan2(float y, float x) { return atan2f(y, x); }
 __device__ inline double m_atan2(double y, double x) { return atan2(y, x); }
-__device__ inline float m_acos(float x) { return acosf(x); }
-__device__ inline double m_acos(double x) { return acos(x); }
-__device__ inline float m_fmod(float x, float y) { return fmodf(x, y); }
-__device__ inline double m_fmod(double x, double y) { return fmod(x, y); }
+// quotient for keys that only order angles (a few ulp suffice)
+__device__ inline float m_qdiv(float x, float y) { return __fdividef(x, y); }
+__device__ inline double m_qdiv(double x, double y) { return x / y; }
 __device__ inline float m_floor(float x) { return floorf(x); }
 __device__ inline double m_floor(double x) { return floor(x); }
 __device__ inline float m_max(float a, float b) { return fmaxf(a, b); }
 __device__ inline double m_max(double a, double b) { return fmax(a, b); }
-__device__ inline float m_min(float a, float b) { return fminf(a, b); }
-__device__ inline double m_min(double a, double b) { return fmin(a, b); }
 __device__ inline void m_sincos(float t, float *s, float *c) { sincosf(t, s, c); }
 __device__ inline void m_sincos(double t, double *s, double *c) { sincos(t, s, c); }
 
@@ -149,19 +146,20 @@ __device__ inline uint32_t vname3(int a, int b, int c, int root)
     return ((uint32_t)a << 24) | ((uint32_t)b << 16) | ((uint32_t)c << 8) | (uint32_t)root;
 }
 
-// sorted triple of {p, q, r} (p < q already)
-__device__ inline void sort3(int p, int q, int r, int &x, int &y, int &z)
+// sorted triple of {p, q, r} (p < q already), branch free
+struct Tri3 {
+    int x, y, z;
+};
+__device__ inline Tri3 sort3(int p, int q, int r)
 {
-    x = p; y = q; z = r;
-    if (z < x) { int t = z; z = y; y = x; x = t; }
-    else if (z < y) { int t = z; z = y; y = t; }
+    const int x = min(p, r), z = max(q, r);
+    return Tri3{x, p + q + r - x - z, z};
 }
 
 __device__ inline uint32_t tie_name(int p, int q, int r, int root)
 {
-    int x, y, z;
-    sort3(p, q, r, x, y, z);
-    return vname3(x, y, z, root);
+    const Tri3 t = sort3(p, q, r);
+    return vname3(t.x, t.y, t.z, root);
 }
 
 __device__ inline int wave_excl_scan(int x, int *total)
@@ -175,15 +173,6 @@ __device__ inline int wave_excl_scan(int x, int *total)
     }
     *total = __shfl(inc, 63, 64);
     return inc - x;
-}
-
-// reduce t in (-2 pi, 4 pi) to [0, 2 pi)
-template <typename T>
-__device__ inline T wrap2pi(T t)
-{
-    if (t < (T)0) t += Cst<T>::two_pi;
-    if (t >= Cst<T>::two_pi) t -= Cst<T>::two_pi;
-    return t;
 }
 
 // ---------------------------------------------------------------------------
@@ -256,6 +245,18 @@ __device__ bool conic_of(const SL<T> *S, T rho, int p, int q, Con<T> &C)
 // ---------------------------------------------------------------------------
 // trimming of one conic: intersection of circular intervals
 
+// Pseudo-angle of the direction (sin t, cos t) ~ (s, c): a value in [0, 4)
+// that increases with t in [0, 2 pi) (a half turn adds exactly 2), computed
+// with one division instead of an arctangent.  Interval bookkeeping on the
+// circle only compares and adds such values, so it runs in this measure.
+template <typename T>
+__device__ inline T pang(T s, T c)
+{
+    const T u = m_qdiv(c, m_abs(s) + m_abs(c));
+    T p = s >= (T)0 ? (T)1 - u : (T)3 + u;
+    return p >= (T)4 ? (T)0 : p;
+}
+
 // kept arcs per conic: 2 in FP32 (a third sends the node to FP64), 4 in FP64
 template <typename T>
 struct NPieces {
@@ -264,9 +265,17 @@ struct NPieces {
 
 template <typename T>
 struct Pc {
-    T s, e, len;
+    T s, len;  // pseudo-angle of the start, pseudo length
+    int rs, re;  // constraints whose lower / upper end bound the piece
+};
+
+// A kept piece in final form.
+template <typename T>
+struct Piece {
+    T ss, sc, es, ec;  // directions (sin t, cos t) of the ends, unnormalised
+    T len;
     int rs, re;
-    int roots; // bit 0: root of the start tie, bit 1: root of the end tie
+    int roots;  // bit 0: root of the start tie, bit 1: root of the end tie
 };
 
 template <typename T>
@@ -274,93 +283,175 @@ struct TrimOut {
     int n;        // arcs
     int full;     // whole conic kept
     int ovf;      // too many pieces
-    Pc<T> pc[NPieces<T>::n];
+    Piece<T> pc[NPieces<T>::n];
 };
+
+// Constraint r on conic (p, q): P_p - P_r = A sin t + B cos t + Cc.  Keeping
+// P_p >= P_r is R cos(t - psi) >= -Cc with psi = atan2(A, B) (Eqs. 8-9),
+// i.e. t - psi in [-beta, beta] with cos beta = -Cc / R.
+template <typename T>
+struct Cons {
+    T A, B, Cc, R;
+};
+
+template <typename T>
+__device__ inline Cons<T> cons_of(const SL<T> *S, V3<T> gp, T hp, int r, const Con<T> &C)
+{
+    V3<T> gr = r ? gvec(S[r]) : zero3<T>();
+    T hr = r ? S[r].h : (T)0;
+    V3<T> dg = gp - gr;
+    Cons<T> k;
+    k.A = dot(dg, C.a);
+    k.B = dot(dg, C.b);
+    k.Cc = dot(dg, C.o) - (hp - hr);
+    k.R = m_sqrt(k.A * k.A + k.B * k.B);
+    return k;
+}
+
+// Directions of the kept interval's ends: (A, B) / R turned by -beta (lo)
+// and +beta (hi), scaled by R^2.
+template <typename T>
+__device__ inline void cons_ends(const Cons<T> &k, T &los, T &loc, T &his, T &hic)
+{
+    const T Sn = m_sqrt((k.R - k.Cc) * (k.R + k.Cc));  // R sin(beta)
+    los = -k.A * k.Cc - k.B * Sn;
+    loc = -k.B * k.Cc + k.A * Sn;
+    his = -k.A * k.Cc + k.B * Sn;
+    hic = -k.B * k.Cc - k.A * Sn;
+}
+
+// Rank (0/1) of the upper end of constraint r's interval among the two tie
+// points of (p, q, r) along d = (g_x - g_y) x (g_x - g_z), (x, y, z) =
+// sorted (p, q, r): the chord x(hi) - x(lo) is parallel to the tie line and
+// to a B - b A.
+template <typename T>
+__device__ inline int hi_root(const SL<T> *S, int p, int q, int r, const Con<T> &C, const Cons<T> &k)
+{
+    const Tri3 xyz = sort3(p, q, r);
+    V3<T> gx = xyz.x ? gvec(S[xyz.x]) : zero3<T>();
+    V3<T> d = cross(gx - gvec(S[xyz.y]), gx - gvec(S[xyz.z]));
+    return dot(C.a * k.B - C.b * k.A, d) > (T)0 ? 1 : 0;
+}
 
 template <typename T>
 __device__ void trim_conic(const SL<T> *S, int v, int p, int q, const Con<T> &C, TrimOut<T> &TR)
 {
-    const T tp = Cst<T>::two_pi;
-    TR.n = 1;
-    TR.full = 1;
-    TR.ovf = 0;
-    const SL<T> &P = S[p];
-    V3<T> gp = p ? gvec(P) : zero3<T>();
-    T hp = p ? P.h : (T)0;
+    constexpr int NP = NPieces<T>::n;
+    const T tp = (T)4;  // full turn in pseudo-angle
+    const V3<T> gp = p ? gvec(S[p]) : zero3<T>();
+    const T hp = p ? S[p].h : (T)0;
+    Pc<T> pc[NP];
+    int n = 1, full = 1;
+    bool ovf = false;
     for (int r = 0; r <= v; ++r) {
         if (r == p || r == q) continue;
-        V3<T> gr = r ? gvec(S[r]) : zero3<T>();
-        T hr = r ? S[r].h : (T)0;
-        V3<T> dg = gp - gr;
-        T A = dot(dg, C.a), B = dot(dg, C.b), Cc = dot(dg, C.o) - (hp - hr);
-        T R = m_sqrt(A * A + B * B);
-        if (Cc >= R) continue;          // never active
-        if (Cc <= -R) {                  // removes the whole conic
-            TR.n = 0;
-            TR.full = 0;
-            return;
+        const Cons<T> k = cons_of(S, gp, hp, r, C);
+        if (k.Cc >= k.R) continue;      // never active
+        if (k.Cc <= -k.R) {              // removes the whole conic
+            n = 0;
+            full = 0;
+            break;
         }
-        T psi = m_atan2(A, B);
-        T beta = m_acos(-Cc / R);
-        T lo = wrap2pi(psi - beta), hi = wrap2pi(psi + beta), lc = (T)2 * beta;
-        // rank of the far tie point along d = (g_x - g_y) x (g_x - g_z),
-        // (x, y, z) = sorted (p, q, r); the chord x(hi) - x(lo) is parallel
-        // to the tie line and to a B - b A.
-        int x, y, z;
-        sort3(p, q, r, x, y, z);
-        V3<T> gx = x ? gvec(S[x]) : zero3<T>();
-        V3<T> d = cross(gx - gvec(S[y]), gx - gvec(S[z]));
-        int sgn = dot(C.a * B - C.b * A, d) > (T)0 ? 1 : 0;
-        int root_lo = 1 - sgn, root_hi = sgn;
-        Pc<T> out[NPieces<T>::n] = {};
+        T los, loc, his, hic;
+        cons_ends(k, los, loc, his, hic);
+        const T lo = pang(los, loc), hi = pang(his, hic);
+        T lc = hi - lo;
+        if (lc < (T)0) lc += tp;
+        // more than a half turn exactly when Cc > 0; a contradiction means
+        // the gap (or the kept interval) is below rounding
+        if (k.Cc > (T)0 && lc < (T)2) continue;
+        if (k.Cc < (T)0 && lc > (T)2) {
+            n = 0;
+            full = 0;
+            break;
+        }
+        if (full) {
+            pc[0] = Pc<T>{lo, lc, r, r};
+            n = 1;
+            full = 0;
+            continue;
+        }
+        // intersect the current pieces with [lo, lo + lc]
+        Pc<T> out[NP];
         int no = 0;
-        bool ovf = false;
-        auto push = [&](const Pc<T> &pcx) {
+        auto push = [&](T s0, T l0, int rs, int re) {
 #pragma unroll
-            for (int j = 0; j < NPieces<T>::n; ++j)
-                if (j == no) out[j] = pcx;
-            if (no < NPieces<T>::n) ++no;
+            for (int j = 0; j < NP; ++j)
+                if (j == no) out[j] = Pc<T>{s0, l0, rs, re};
+            if (no < NP) ++no;
             else ovf = true;
         };
-        if (TR.full) {
-            Pc<T> pcx;
-            pcx.s = lo; pcx.e = hi; pcx.len = lc; pcx.rs = r; pcx.re = r;
-            pcx.roots = root_lo | (root_hi << 1);
-            push(pcx);
-        } else {
 #pragma unroll
-            for (int i = 0; i < NPieces<T>::n; ++i) {
-                if (i < TR.n) {
-                    Pc<T> Pp = TR.pc[i];
-                    T c0 = lo - Pp.s;
-                    if (c0 < (T)0) c0 += tp;
-                    T c1 = c0 + lc;
-                    if (c0 < Pp.len) {
-                        Pc<T> pcx;
-                        if (c0 > (T)0) { pcx.s = lo; pcx.rs = r; pcx.roots = root_lo; }
-                        else { pcx.s = Pp.s; pcx.rs = Pp.rs; pcx.roots = Pp.roots & 1; }
-                        if (c1 < Pp.len) { pcx.e = hi; pcx.re = r; pcx.roots |= root_hi << 1; pcx.len = c1 - c0; }
-                        else { pcx.e = Pp.e; pcx.re = Pp.re; pcx.roots |= Pp.roots & 2; pcx.len = Pp.len - c0; }
-                        push(pcx);
-                    }
-                    if (c1 > tp) {
-                        T w1 = c1 - tp;
-                        Pc<T> pcx;
-                        pcx.s = Pp.s; pcx.rs = Pp.rs; pcx.roots = Pp.roots & 1;
-                        if (w1 < Pp.len) { pcx.e = hi; pcx.re = r; pcx.roots |= root_hi << 1; pcx.len = w1; }
-                        else { pcx.e = Pp.e; pcx.re = Pp.re; pcx.roots |= Pp.roots & 2; pcx.len = Pp.len; }
-                        push(pcx);
-                    }
+        for (int i = 0; i < NP; ++i) {
+            if (i < n) {
+                const Pc<T> Pp = pc[i];
+                T c0 = lo - Pp.s;
+                if (c0 < (T)0) c0 += tp;
+                const T c1 = c0 + lc;
+                if (c0 < Pp.len) {
+                    const bool ns = c0 > (T)0, ne = c1 < Pp.len;
+                    push(ns ? lo : Pp.s, (ne ? c1 : Pp.len) - c0, ns ? r : Pp.rs, ne ? r : Pp.re);
+                }
+                if (c1 > tp) {
+                    const T w1 = c1 - tp;
+                    const bool ne = w1 < Pp.len;
+                    push(Pp.s, ne ? w1 : Pp.len, Pp.rs, ne ? r : Pp.re);
                 }
             }
         }
-        TR.full = 0;
-        TR.n = no;
-        if (ovf) TR.ovf = 1;
+        n = no;
 #pragma unroll
-        for (int j = 0; j < NPieces<T>::n; ++j) TR.pc[j] = out[j];
-        if (no == 0) return;
+        for (int j = 0; j < NP; ++j) pc[j] = out[j];
+        if (no == 0) break;
     }
+    TR.n = n;
+    TR.full = full;
+    TR.ovf = ovf ? 1 : 0;
+    if (full) return;
+    // final form: end directions and tie roots of every piece
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        if (i < n) {
+            Piece<T> &o = TR.pc[i];
+            T a0, a1, a2, a3;
+            const Cons<T> ks = cons_of(S, gp, hp, pc[i].rs, C);
+            cons_ends(ks, o.ss, o.sc, a2, a3);
+            const int root_s = 1 - hi_root(S, p, q, pc[i].rs, C, ks);
+            const Cons<T> ke = cons_of(S, gp, hp, pc[i].re, C);
+            cons_ends(ke, a0, a1, o.es, o.ec);
+            const int root_e = hi_root(S, p, q, pc[i].re, C, ke);
+            o.len = pc[i].len;
+            o.rs = pc[i].rs;
+            o.re = pc[i].re;
+            o.roots = root_s | (root_e << 1);
+        }
+    }
+}
+
+// Conic point at the direction (sin t, cos t) ~ (s, c)
+template <typename T>
+__device__ inline V3<T> conic_dir(const Con<T> &C, T s, T c)
+{
+    const T inv = (T)1 / m_sqrt(s * s + c * c);
+    return C.o + C.a * (s * inv) + C.b * (c * inv);
+}
+
+// Parameter range [t1, t2] (t1 in [0, 2 pi)) of a kept piece
+template <typename T>
+__device__ inline void piece_range(const Piece<T> &pc, T &t1, T &t2)
+{
+    const T tp = Cst<T>::two_pi;
+    T ts = m_atan2(pc.ss, pc.sc), te = m_atan2(pc.es, pc.ec);
+    if (ts < (T)0) ts += tp;
+    if (te < (T)0) te += tp;
+    T span = te - ts;
+    if (span < (T)0) span += tp;
+    // agree with the pseudo length where rounding puts the ends of an
+    // almost empty or almost full piece on the wrong side of each other
+    if (pc.len < (T)1 && span > (T)1.5 * Cst<T>::pi) span = (T)0;
+    if (pc.len > (T)3 && span < (T)0.5 * Cst<T>::pi) span = tp;
+    t1 = ts;
+    t2 = ts + span;
 }
 
 // Condition number of a tie point: the three surfaces through it are cone p
@@ -381,10 +472,14 @@ __device__ inline T tie_kappa(const SL<T> *S, int p, int q, int r, V3<T> w)
 
 // ---------------------------------------------------------------------------
 
+// Ordering key of the strut angle phi = atan2(y, x): a pseudo-angle in
+// (-2, 2] (a half turn is 2), increasing with phi in (-pi, pi].  The band
+// zipper only compares angles about one strut axis, so it uses this key.
 template <typename T>
-__device__ inline T phi_of(const SL<T> &s, V3<T> w)
+__device__ inline T phi_key(T y, T x)
 {
-    return m_atan2(dot(w, v3(s.qx, s.qy, s.qz)), dot(w, v3(s.rx, s.ry, s.rz)));
+    const T u = m_qdiv(x, m_abs(y) + m_abs(x));
+    return y >= (T)0 ? (T)1 - u : u - (T)1;
 }
 
 template <typename T>
@@ -595,8 +690,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                             A.t1 = (T)0;
                             A.t2 = tp;
                         } else {
-                            A.t1 = TR.pc[i].s;
-                            A.t2 = TR.pc[i].e > TR.pc[i].s ? TR.pc[i].e : TR.pc[i].e + tp;
+                            piece_range(TR.pc[i], A.t1, A.t2);
                         }
                         A.ns = ns_[i];
                         A.ne = ne_[i];
@@ -605,7 +699,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
             }
             // owned vertices: ties (p, q, r) with r > q, and whole-conic starts
             uint32_t on[2 * NP];
-            T ot[2 * NP];
+            T os_[2 * NP], oc_[2 * NP];
             int orr[2 * NP];
             int own = 0;
 #pragma unroll
@@ -614,7 +708,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                 for (int end = 0; end < 2; ++end) {
                     bool mine = false;
                     uint32_t nm = 0;
-                    T t = (T)0;
+                    T ds = (T)0, dc = (T)1;  // direction of the point: t = 0 for a whole conic
                     int r = -1;
                     if (i < cnt) {
                         if (TR.full) {
@@ -624,7 +718,8 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                             r = end ? TR.pc[i].re : TR.pc[i].rs;
                             mine = r > q;
                             nm = end ? ne_[i] : ns_[i];
-                            t = end ? TR.pc[i].e : TR.pc[i].s;
+                            ds = end ? TR.pc[i].es : TR.pc[i].ss;
+                            dc = end ? TR.pc[i].ec : TR.pc[i].sc;
                         }
                     }
                     // drop repeats within the conic (degenerate tangencies)
@@ -633,7 +728,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                         if (j < own && on[j] == nm) mine = false;
 #pragma unroll
                     for (int j = 0; j < 2 * NP; ++j)
-                        if (mine && j == own) { on[j] = nm; ot[j] = t; orr[j] = r; }
+                        if (mine && j == own) { on[j] = nm; os_[j] = ds; oc_[j] = dc; orr[j] = r; }
                     if (mine) ++own;
                 }
             }
@@ -648,7 +743,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                         int rank = 0;
 #pragma unroll
                         for (int j = 0; j < 2 * NP; ++j) rank += (j < own) && (on[j] < on[i]);
-                        V3<T> w = conic_at(C, ot[i]);
+                        V3<T> w = conic_dir(C, os_[i], oc_[i]);
                         sh.vname[vbase + rank] = on[i];
                         sh.vx[vbase + rank] = w.x;
                         sh.vy[vbase + rank] = w.y;
@@ -966,7 +1061,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
             const int nent = sh.loop_base[v + 1];
             const int ns_tot = sh.entry_off[nent];
             int2 *rl = sh.rec >= 0 ? (int2 *)(W.rec + sh.rec + rec_loop_word(V, E, NC)) : nullptr;
-            // phi and local mesh index of sample j of loop entry e
+            // phi key and local mesh index of sample j of loop entry e
             auto sample = [&](int e, int j, int &li) -> T {
                 const int m = sh.entry_m[e];
                 const int pp = sh.loop_base[m] + sh.loop_ord[e];
@@ -974,16 +1069,14 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                 const int d = sh.loop_dir[pp];
                 const int ii = d > 0 ? j : A.nseg - j;
                 li = j == 0 ? (d > 0 ? A.vs : A.ve) : interior_idx(A, ii);
-                if (A.p == 0) {
-                    // tangency circles are parametrised in the strut frame:
-                    // phi is the parameter itself
-                    T tt = sub_param(A, ii);
-                    if (tt >= tp) tt -= tp;
-                    if (tt > Cst<T>::pi) tt -= tp;
-                    return tt;
-                }
-                V3<T> w = j == 0 ? vert_pos(sh, li) : interior_pt(A, ii);
-                return phi_of(sh.S[m], w);
+                T st, ct;
+                m_sincos(sub_param(A, ii), &st, &ct);
+                // tangency circles are parametrised in the strut frame: phi
+                // is the parameter itself
+                if (A.p == 0) return phi_key(st, ct);
+                V3<T> w = j == 0 ? vert_pos(sh, li) : arc_con(A).o + arc_con(A).a * st + arc_con(A).b * ct;
+                const SL<T> &sm = sh.S[m];
+                return phi_key(dot(w, v3(sm.qx, sm.qy, sm.qz)), dot(w, v3(sm.rx, sm.ry, sm.rz)));
             };
             for (int base = 0; base < ns_tot; base += 64) {
                 const int sidx = base + lane;
@@ -1019,9 +1112,9 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                     ph2 = sample(e2, j2, li2);
                 }
                 if (act) {
-                    T dp = ph2 - ph;
-                    if (dp <= -Cst<T>::pi) dp += tp;
-                    if (dp > Cst<T>::pi) dp -= tp;
+                    T dp = ph2 - ph;  // in key units: a full turn is 4
+                    if (dp <= (T)-2) dp += (T)4;
+                    if (dp > (T)2) dp -= (T)4;
                     if (!(dp > (T)0)) atomicOr(&sh.status, NS_LOOP);
                     if (ph2 < ph) atomicAdd(&sh.loop_desc[m], 1);
                     if (rl) rl[sh.lbase[m] + idx] = make_int2(li, __float_as_int((float)ph));
