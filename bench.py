@@ -66,6 +66,20 @@ def cpu_baseline(scale: int, k: int, threads: int):
     }
 
 
+def copy_probe(mib: int):
+    """A plain device-to-device copy of known size, for scaling the profiler's
+    FETCH_SIZE / WRITE_SIZE readings to bytes."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": 4 * n, "launches": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,7 +89,12 @@ def main():
     ap.add_argument("--scale", type=int, default=64, help="BCC cells per side (64 = the benchmarked lattice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-scale", type=int, default=64, help="BCC cells per side of the oracle's lattice")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB a few times (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is in the "
               "design notes and not built", file=sys.stderr)

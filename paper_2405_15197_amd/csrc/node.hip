@@ -131,7 +131,8 @@ struct Shared {
     int entry_off[2 * kAcap + 1];   // first loop sample of each loop entry
     uint8_t entry_m[2 * kAcap];     // strut label of each loop entry
     int loop_desc[kVmax + 1];       // descents of phi along each loop
-    unsigned long long loop_rot[kVmax + 1];  // (ordered phi bits, sample) minimum
+    int loop_rot[kVmax + 1];        // loop position of the smallest phi
+    T ph_first[kVmax + 1], ph_last[kVmax + 1];  // phi keys of each loop's ends
     int lbase[kVmax + 2];           // loop samples before each strut's loop
     int status, n_arc, n_vert, n_contour;
     int wsum, fsum, ncirc;
@@ -1054,7 +1055,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
         }
         if (lane < v) {
             sh.loop_desc[lane + 1] = 0;
-            sh.loop_rot[lane + 1] = ~0ull;
+            sh.loop_rot[lane + 1] = 0;
         }
         __syncthreads();
         {
@@ -1078,10 +1079,15 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                 const SL<T> &sm = sh.S[m];
                 return phi_key(dot(w, v3(sm.qx, sm.qy, sm.qz)), dot(w, v3(sm.rx, sm.ry, sm.rz)));
             };
+            // each lane checks the step from the previous sample of its loop
+            // (the previous lane's, or the last of the previous chunk); the
+            // step that closes a loop is checked afterwards.  A valid loop
+            // has exactly one descent, just before its smallest phi.
+            T carry = (T)0;
             for (int base = 0; base < ns_tot; base += 64) {
                 const int sidx = base + lane;
                 const bool act = sidx < ns_tot;
-                int e = 0, m = 1, j = 0, idx = 0, nloop = 1, li = 0;
+                int m = 1, idx = 0, nloop = 1, li = 0;
                 T ph = (T)0;
                 if (act) {
                     int lo = 0, hi = nent - 1;  // last entry with entry_off <= sidx
@@ -1090,44 +1096,50 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                         if (sh.entry_off[mid] <= sidx) lo = mid;
                         else hi = mid - 1;
                     }
-                    e = lo;
+                    const int e = lo;
                     m = sh.entry_m[e];
-                    j = sidx - sh.entry_off[e];
                     idx = sidx - sh.entry_off[sh.loop_base[m]];
                     nloop = sh.loop_len[m];
-                    ph = sample(e, j, li);
+                    ph = sample(e, sidx - sh.entry_off[e], li);
                 }
-                // the next sample along the loop is usually the next lane's
-                T ph2 = __shfl_down(ph, 1, 64);
-                const bool loop_end = idx + 1 == nloop;
-                if (act && (loop_end || lane == 63)) {
-                    int e2 = e, j2 = j + 1, li2;
-                    if (loop_end) {
-                        e2 = sh.loop_base[m];
-                        j2 = 0;
-                    } else if (sidx + 1 == sh.entry_off[e + 1]) {
-                        e2 = e + 1;
-                        j2 = 0;
-                    }
-                    ph2 = sample(e2, j2, li2);
-                }
+                T prev = __shfl_up(ph, 1, 64);
+                if (lane == 0) prev = carry;
+                carry = __shfl(ph, 63, 64);
                 if (act) {
-                    T dp = ph2 - ph;  // in key units: a full turn is 4
-                    if (dp <= (T)-2) dp += (T)4;
-                    if (dp > (T)2) dp -= (T)4;
-                    if (!(dp > (T)0)) atomicOr(&sh.status, NS_LOOP);
-                    if (ph2 < ph) atomicAdd(&sh.loop_desc[m], 1);
-                    if (rl) rl[sh.lbase[m] + idx] = make_int2(li, __float_as_int((float)ph));
-                    unsigned int u = __float_as_uint((float)ph);
-                    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);  // order-preserving
-                    atomicMin(&sh.loop_rot[m], ((unsigned long long)u << 32) | (unsigned int)idx);
+                    if (idx == 0) {
+                        sh.ph_first[m] = ph;
+                    } else {
+                        T dp = ph - prev;  // in key units: a full turn is 4
+                        if (dp <= (T)-2) dp += (T)4;
+                        if (dp > (T)2) dp -= (T)4;
+                        if (!(dp > (T)0)) atomicOr(&sh.status, NS_LOOP);
+                        if (ph < prev) {
+                            atomicAdd(&sh.loop_desc[m], 1);
+                            sh.loop_rot[m] = idx;
+                        }
+                    }
+                    if (idx == nloop - 1) sh.ph_last[m] = ph;
+                    if (rl) rl[sidx] = make_int2(li, __float_as_int((float)ph));
                 }
             }
         }
         __syncthreads();
         if (lane < v) {
+            const int m = lane + 1;
+            const T a = sh.ph_last[m], b = sh.ph_first[m];
+            T dp = b - a;
+            if (dp <= (T)-2) dp += (T)4;
+            if (dp > (T)2) dp -= (T)4;
+            if (!(dp > (T)0)) atomicOr(&sh.status, NS_LOOP);
+            if (b < a) {
+                atomicAdd(&sh.loop_desc[m], 1);
+                sh.loop_rot[m] = 0;
+            }
+        }
+        __syncthreads();
+        if (lane < v) {
             if (sh.loop_desc[lane + 1] != 1) atomicOr(&sh.status, NS_LOOP);
-            W.he_rot[row + lane] = (int32_t)(sh.loop_rot[lane + 1] & 0xffffffffull);
+            W.he_rot[row + lane] = sh.loop_rot[lane + 1];
         }
         __syncthreads();
     }
