@@ -51,6 +51,8 @@ def _load():
     P = ctypes.c_void_p
     lib.orc_run.restype = P
     lib.orc_run.argtypes = [ctypes.c_int64, ctypes.c_int64] + [P] * 6 + [ctypes.c_int, ctypes.c_int]
+    lib.orc_run_f64.restype = P
+    lib.orc_run_f64.argtypes = [ctypes.c_int64, ctypes.c_int64] + [P] * 6 + [ctypes.c_int, ctypes.c_int]
     lib.orc_free.argtypes = [P]
     lib.orc_sizes.argtypes = [P, P]
     lib.orc_nodes.argtypes = [P, P, P]
@@ -120,14 +122,18 @@ def run(lat, k: int, threads: int | None = None) -> OracleResult:
     lib = _load()
     if threads is None:
         threads = os.cpu_count() or 1
-    x = np.ascontiguousarray(lat.x, dtype=np.float32)
-    y = np.ascontiguousarray(lat.y, dtype=np.float32)
-    z = np.ascontiguousarray(lat.z, dtype=np.float32)
-    r = np.ascontiguousarray(lat.radius, dtype=np.float32)
+    # FP32 lattices are promoted; FP64 arrays (finite differences) are used as given
+    f64 = np.asarray(lat.x).dtype == np.float64
+    dt = np.float64 if f64 else np.float32
+    x = np.ascontiguousarray(lat.x, dtype=dt)
+    y = np.ascontiguousarray(lat.y, dtype=dt)
+    z = np.ascontiguousarray(lat.z, dtype=dt)
+    r = np.ascontiguousarray(lat.radius, dtype=dt)
     sa = np.ascontiguousarray(lat.strut_a, dtype=np.int32)
     sb = np.ascontiguousarray(lat.strut_b, dtype=np.int32)
     N, S = x.shape[0], sa.shape[0]
-    h = lib.orc_run(N, S, _p(x), _p(y), _p(z), _p(r), _p(sa), _p(sb), int(k), int(threads))
+    entry = lib.orc_run_f64 if f64 else lib.orc_run
+    h = entry(N, S, _p(x), _p(y), _p(z), _p(r), _p(sa), _p(sb), int(k), int(threads))
     if not h:
         raise ValueError("oracle rejected the lattice (strut index out of range or k < 1)")
     try:
@@ -202,3 +208,116 @@ def mesh_volume(verts: np.ndarray, tris: np.ndarray) -> float:
     ref = verts.mean(axis=0) if len(verts) else np.zeros(3)
     v = verts[tris] - ref
     return float(np.einsum("ij,ij->i", v[:, 0], np.cross(v[:, 1], v[:, 2])).sum() / 6.0)
+
+
+def mesh_sq(verts: np.ndarray) -> float:
+    """Sum of squared norms of the mesh vertices (each stored once)."""
+    return float((verts * verts).sum())
+
+
+# ---------------------------------------------------------------------------
+# gradients at fixed topology (the adjoint's reference)
+#
+# The loss is L = w_area * Area + w_vol * Vol + w_sq * sum |v|^2 over the
+# triangle mesh, Vol taken about a fixed point p0.  Its derivative with
+# respect to a node coordinate or radius is the limit of difference
+# quotients with the mesh topology (labels, arcs, segment counts, triangles)
+# held fixed; here it is evaluated by central differences in FP64 with one
+# Richardson step, on the stars around the perturbed node, and only where
+# the perturbed meshes keep the topology.
+
+
+def _star_lattice(lat64, centre):
+    """Stars of the nodes in ``centre`` with node and strut order kept."""
+    import latgen
+
+    sa, sb = lat64.strut_a.astype(np.int64), lat64.strut_b.astype(np.int64)
+    cen = np.zeros(lat64.n_nodes, bool)
+    cen[centre] = True
+    keep = np.nonzero(cen[sa] | cen[sb])[0]
+    nodes = np.unique(np.concatenate([sa[keep], sb[keep], np.asarray(centre, np.int64)]))
+    nmap = np.full(lat64.n_nodes, -1, np.int64)
+    nmap[nodes] = np.arange(len(nodes))
+    sub = latgen.Lattice(
+        x=lat64.x[nodes].copy(), y=lat64.y[nodes].copy(), z=lat64.z[nodes].copy(),
+        radius=lat64.radius[nodes].copy(),
+        strut_a=nmap[sa[keep]].astype(np.int32), strut_b=nmap[sb[keep]].astype(np.int32),
+    )
+    return sub, nodes, nmap
+
+
+def _local_loss(R, owner_mask_local, weights, p0):
+    """Loss terms over the triangles that touch a vertex of an owner node,
+    and the squared norms of the owner nodes' vertices (one value per row
+    of ``weights``)."""
+    node_of = np.repeat(np.arange(R.n_nodes), np.diff(R.mesh_off))
+    own_v = owner_mask_local[node_of]
+    t = R.tris
+    sel = own_v[t].any(axis=1)
+    v = R.mesh[t[sel]] - p0
+    cr = np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0])
+    area = 0.5 * np.linalg.norm(cr, axis=1).sum()
+    vol = np.einsum("ij,ij->i", v[:, 0], np.cross(v[:, 1], v[:, 2])).sum() / 6.0
+    sq = (R.mesh[own_v] ** 2).sum()
+    return weights @ np.array([area, vol, sq])
+
+
+def _topology(R, owner_mask_local):
+    node_of = np.repeat(np.arange(R.n_nodes), np.diff(R.mesh_off))
+    sel = owner_mask_local[node_of][R.tris].any(axis=1)
+    t = R.tris[sel]
+    return np.stack([node_of[t], t - R.mesh_off[node_of[t]]], -1), R.status[owner_mask_local]
+
+
+def fd_gradient(lat, k, params, weights=(1.0, 0.0, 0.0), h=1e-6, p0=None):
+    """Derivative of the loss with respect to each (node, component)
+    in ``params`` (component 0..2: x, y, z; 3: radius) at fixed topology.
+    ``weights`` is one (w_area, w_vol, w_sq) or a list of them.  Returns
+    (values [len(params)] or [len(params), len(weights)], ok) where ok is
+    False where a perturbation changed the topology (or left a node
+    unmeshed)."""
+    import latgen
+
+    lat64 = latgen.Lattice(
+        x=np.asarray(lat.x, np.float64), y=np.asarray(lat.y, np.float64), z=np.asarray(lat.z, np.float64),
+        radius=np.asarray(lat.radius, np.float64), strut_a=lat.strut_a, strut_b=lat.strut_b,
+    )
+    if p0 is None:
+        p0 = np.zeros(3)
+    sa, sb = lat64.strut_a.astype(np.int64), lat64.strut_b.astype(np.int64)
+    nbr = [[] for _ in range(lat64.n_nodes)]
+    for a_, b_ in zip(sa, sb):
+        nbr[a_].append(b_)
+        nbr[b_].append(a_)
+    weights = np.asarray(weights, np.float64)
+    single = weights.ndim == 1
+    weights = np.atleast_2d(weights)
+    out = np.zeros((len(params), len(weights)))
+    ok = np.ones(len(params), bool)
+    for i, (node, comp) in enumerate(params):
+        owners = np.unique(np.array([node] + nbr[node], np.int64))
+        ring = np.unique(np.concatenate([owners] + [np.array(nbr[o], np.int64) for o in owners]))
+        sub, nodes, nmap = _star_lattice(lat64, ring)
+        own_local = np.zeros(len(nodes), bool)
+        own_local[nmap[owners]] = True
+        j = nmap[node]
+        field = (sub.x, sub.y, sub.z, sub.radius)[comp]
+        base = field[j]
+        R0 = run(sub, k, threads=1)
+        topo0, st0 = _topology(R0, own_local)
+        vals = {}
+        for step in (h, -h, 2 * h, -2 * h):
+            field[j] = base + step
+            Rs = run(sub, k, threads=1)
+            field[j] = base
+            topo, st = _topology(Rs, own_local)
+            if topo.shape != topo0.shape or not np.array_equal(topo, topo0) or (st != 0).any() or (st0 != 0).any():
+                ok[i] = False
+                break
+            vals[step] = _local_loss(Rs, own_local, weights, p0)
+        if not ok[i]:
+            continue
+        d1 = (vals[h] - vals[-h]) / (2 * h)
+        d2 = (vals[2 * h] - vals[-2 * h]) / (4 * h)
+        out[i] = (4 * d1 - d2) / 3  # Richardson: O(h^4)
+    return (out[:, 0] if single else out), ok

@@ -1029,10 +1029,11 @@ static void run_phase(Ctx *X, int phase)
 
 void orc_free(Ctx *X);
 
-/* Runs the whole method on a lattice given as FP32 arrays (promoted to FP64).
- * Returns NULL on bad arguments (indices out of range). */
-Ctx *orc_run(int64_t N, int64_t S, const float *x, const float *y, const float *z, const float *rad,
-             const int32_t *sa, const int32_t *sb, int k, int nthreads)
+/* Runs the whole method on a lattice given as FP64 arrays (used directly
+ * for finite differences).  Returns NULL on bad arguments (indices out of
+ * range). */
+Ctx *orc_run_f64(int64_t N, int64_t S, const double *x, const double *y, const double *z, const double *rad,
+                 const int32_t *sa, const int32_t *sb, int k, int nthreads)
 {
     if (N < 0 || S < 0 || k < 1) return NULL;
     for (int64_t s = 0; s < S; ++s)
@@ -1108,6 +1109,23 @@ Ctx *orc_run(int64_t N, int64_t S, const float *x, const float *y, const float *
         for (int j = 0; j < 3 * R->nfan; ++j) T[j] = X->mesh_off[i] + R->fan[j];
     }
     run_phase(X, 1);
+    return X;
+}
+
+/* The same on a lattice given as FP32 arrays (promoted to FP64). */
+Ctx *orc_run(int64_t N, int64_t S, const float *x, const float *y, const float *z, const float *rad,
+             const int32_t *sa, const int32_t *sb, int k, int nthreads)
+{
+    if (N < 0) return NULL;
+    double *d = malloc(sizeof(double) * 4 * (N + 1));
+    for (int64_t i = 0; i < N; ++i) {
+        d[i] = x[i];
+        d[(N + 1) + i] = y[i];
+        d[2 * (N + 1) + i] = z[i];
+        d[3 * (N + 1) + i] = rad[i];
+    }
+    Ctx *X = orc_run_f64(N, S, d, d + (N + 1), d + 2 * (N + 1), d + 3 * (N + 1), sa, sb, k, nthreads);
+    free(d);
     return X;
 }
 
