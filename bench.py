@@ -97,6 +97,61 @@ def copy_probe(mib: int):
     print(json.dumps({"copy_probe_bytes_each_way": 4 * n, "launches": 5}), flush=True)
 
 
+def adjoint_bench(steps: int, warmup: int, k: int = 16):
+    """Forward, and forward + loss + adjoint, on the octet-truss 32^3 lattice
+    (FCC sites, 12 nearest neighbours, radii U[0.04, 0.10], jitter 0.03):
+    the loss is Area + Vol + 1e-3 sum|v|^2 over the mesh."""
+    import torch
+
+    import latgen
+    from paper_2405_15197_amd.latmesh import (Mesher, lm_backward, lm_forward, lm_loss, lm_loss_weights,
+                                              lm_prepare, lm_read_totals)
+    import ctypes
+
+    lat = latgen.config(4, seed=1)
+    M = Mesher(lat)
+    t = M.count(k)
+    r = M.alloc(t, meta=False)
+    out = M.outputs(r)
+    terms = torch.zeros(3, dtype=torch.float64, device="cuda")
+    dl = torch.empty((r.mesh_xyz.shape[0], 3), dtype=torch.float32, device="cuda")
+    gx = torch.empty((lat.n_nodes, 3), dtype=torch.float32, device="cuda")
+    gr = torch.empty(lat.n_nodes, dtype=torch.float32, device="cuda")
+    w = lm_loss_weights(1.0, 1.0, 1e-3, (ctypes.c_float * 3)(0.0, 0.0, 0.0))
+
+    def fwd():
+        lm_prepare(M.plan)
+        lm_forward(M.plan, k, out)
+
+    def fwd_bwd():
+        fwd()
+        lm_loss(M.plan, out, w, terms.data_ptr(), dl.data_ptr())
+        lm_backward(M.plan, dl.data_ptr(), gx.data_ptr(), gr.data_ptr())
+
+    res = {}
+    for name, fn in (("fwd", fwd), ("fwd_bwd", fwd_bwd)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        res[name] = a.elapsed_time(b) / steps
+    lm_read_totals(M.plan)
+    M.close()
+    return {
+        "workload": f"octet 32^3 cells, {lat.n_nodes} nodes, {lat.n_struts} struts, radii U[0.04,0.10], jitter 0.03, "
+        f"k={k}, loss Area + Vol + 1e-3 sum|v|^2",
+        "fwd_ms": res["fwd"],
+        "fwd_bwd_ms": res["fwd_bwd"],
+        "fwd_bwd_per_s": 1e3 / res["fwd_bwd"],
+        "ratio": res["fwd_bwd"] / res["fwd"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +161,7 @@ def main():
     ap.add_argument("--scale", type=int, default=64, help="BCC cells per side (64 = the benchmarked lattice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-scale", type=int, default=64, help="BCC cells per side of the oracle's lattice")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint leg (octet 32^3)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB a few times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -207,6 +263,9 @@ def main():
         },
     }
     M.close()
+    if not args.no_adjoint:
+        print("[bench] forward + adjoint on octet 32^3", file=sys.stderr, flush=True)
+        res["fwd_bwd"] = adjoint_bench(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         print(f"[bench] CPU oracle baseline on {threads} threads", file=sys.stderr, flush=True)

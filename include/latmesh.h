@@ -190,12 +190,67 @@ int lm_set_precision(lm_plan *plan, float kappa_max);
 /* Profiling: when on, every library call records HIP events on the plan's
  * stream around its phases; lm_get_profile synchronises the stream and
  * returns, per phase, the summed milliseconds and the number of timed calls
- * since the last lm_get_profile.  Phases (n >= 6): 0 lm_prepare, 1 FP32
+ * since the last lm_get_profile.  Phases (n >= 8): 0 lm_prepare, 1 FP32
  * meta-meshing of every node, 2 FP64 meta-meshing of the handed-over nodes,
  * 3 band counts + prefix sums + totals, 4 expansion of the node results into
- * the meta-mesh, mesh vertices and hole fans, 5 strut bands. */
+ * the meta-mesh, mesh vertices and hole fans, 5 strut bands, 6 lm_loss,
+ * 7 lm_backward. */
 int lm_set_profiling(lm_plan *plan, int on);
 int lm_get_profile(lm_plan *plan, double *ms, int64_t *calls, int n);
+
+/* ---- sink mode: chunked meshing reduced to counts and hashes ---------- */
+
+/* Words per chunk written by lm_forward_sink. */
+#define LM_SINK_WORDS 8
+
+/* Mesh the lattice at resolution k in chunks of chunk_nodes consecutive node
+ * ids and, instead of storing the mesh, write per chunk LM_SINK_WORDS
+ * uint64 words to d_out[chunk][LM_SINK_WORDS] (device):
+ *   0 triangles (hole fans of the chunk's nodes, bands of struts whose lower
+ *     node id is in the chunk), 1 sum of triangle keys, 2 mesh vertices of
+ *     the chunk's nodes, 3 sum of vertex keys, 4..6 sums of round(2^20 x),
+ *     round(2^20 y), round(2^20 z) over those vertices (two's complement),
+ *     7 nodes of the chunk without a mesh (nonzero status).
+ * A mesh vertex is named vid = node << 21 | node-local index (the index of
+ * the stored mode); a triangle's key is m(m(m(v0 + G) ^ v1) ^ v2) with its
+ * vids rotated so that the smallest comes first (orientation kept), a
+ * vertex's key m(m(m(vid) ^ (bits(x) | bits(y) << 32)) ^ bits(z)) over its
+ * FP32 position, m the SplitMix64 finaliser and G = 0x9E3779B97F4A7C15.
+ * Sums are modulo 2^64, so totals over chunks are chunking independent.
+ * Each chunk also meshes the higher-id neighbours of its nodes (for the
+ * bands).  Synchronises the stream once per chunk; LM_ERR_CAPACITY if
+ * n_chunks_cap < ceil(n_nodes / chunk_nodes).  The node records then hold
+ * the last chunk only: lm_fill and lm_backward need a new lm_count. */
+int lm_forward_sink(lm_plan *plan, int k, int64_t chunk_nodes, uint64_t *d_out, int64_t n_chunks_cap);
+
+/* ---- adjoint at fixed topology (gradients of a mesh loss) ------------- */
+
+/* Weights of the loss L = area * Area + volume * Vol + sq_norm * sum |v|^2
+ * over the triangle mesh; Vol is the signed volume enclosed about the point
+ * p0 (sum over triangles of (a-p0) . ((b-p0) x (c-p0)) / 6). */
+typedef struct lm_loss_weights {
+    float area, volume, sq_norm;
+    float p0[3];
+} lm_loss_weights;
+
+/* Loss terms of the mesh written by the last lm_fill / lm_forward into
+ * `out` (its d_mesh_xyz and d_tri): d_terms (device, 3 doubles) receives
+ * Area, Vol and sum |v|^2 (unweighted), d_dl_dx (device, [cap_mesh_vertices]
+ * [3] FP32) receives dL/dx for every mesh vertex (overwritten).
+ * Asynchronous.  Not a step of the method: a convenience loss for the
+ * adjoint. */
+int lm_loss(lm_plan *plan, const lm_outputs *out, const lm_loss_weights *w, double *d_terms, float *d_dl_dx);
+
+/* Gradient of a loss with respect to the node centres and radii, given its
+ * gradient d_dl_dx ([n_mesh_vertices][3], device) with respect to the mesh
+ * vertices of the last lm_fill / lm_forward on this plan, at that pass's
+ * topology (labels, arcs, segment counts and triangles fixed; every mesh
+ * vertex moves with the inputs as the method defines it: vertices as triple
+ * ties, Eq. 12 interior points, Eq. 13 hole centres).  Writes
+ * d_grad_xyz [n_nodes][3] and d_grad_radius [n_nodes] (device, FP32;
+ * nodes with a nonzero status contribute nothing).  The plan must not have
+ * been counted again since that pass.  Asynchronous. */
+int lm_backward(lm_plan *plan, const float *d_dl_dx, float *d_grad_xyz, float *d_grad_radius);
 
 /* Release the plan and its workspace (synchronises its stream). */
 void lm_plan_destroy(lm_plan *plan);

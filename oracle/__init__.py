@@ -321,3 +321,63 @@ def fd_gradient(lat, k, params, weights=(1.0, 0.0, 0.0), h=1e-6, p0=None):
         d2 = (vals[2 * h] - vals[-2 * h]) / (4 * h)
         out[i] = (4 * d1 - d2) / 3  # Richardson: O(h^4)
     return (out[:, 0] if single else out), ok
+
+
+# ---------------------------------------------------------------------------
+# per-chunk counts and order-independent hashes (the sink mode's reference)
+
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_G = np.uint64(0x9E3779B97F4A7C15)
+
+
+def _mix(z):
+    """SplitMix64 finaliser (Steele, Lea, Flood 2014) on uint64 arrays."""
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        return z ^ (z >> np.uint64(31))
+
+
+def tri_keys(v):
+    """Keys of triangles given as uint64 vertex ids [T, 3] (orientation kept,
+    smallest id rotated first)."""
+    r = np.argmin(v, axis=1)
+    idx = (r[:, None] + np.arange(3)[None, :]) % 3
+    w = np.take_along_axis(v, idx, axis=1)
+    with np.errstate(over="ignore"):
+        return _mix(_mix(_mix(w[:, 0] + _G) ^ w[:, 1]) ^ w[:, 2])
+
+
+def sink_words(R, chunk_nodes, strut_a, strut_b):
+    """Per chunk of node ids: [triangles, sum of triangle keys, mesh vertices,
+    0 (vertex keys need the GPU's FP32 positions), sums of round(2^20 x),
+    round(2^20 y), round(2^20 z), nodes without a mesh] as uint64 [C, 8]."""
+    N = R.n_nodes
+    nch = max((N + chunk_nodes - 1) // chunk_nodes, 1)
+    out = np.zeros((nch, 8), np.uint64)
+    node_of = np.repeat(np.arange(N), np.diff(R.mesh_off))
+    local = np.arange(len(node_of)) - R.mesh_off[node_of]
+    vid = (node_of.astype(np.uint64) << np.uint64(21)) | local.astype(np.uint64)
+    keys = tri_keys(vid[R.tris]) if len(R.tris) else np.zeros(0, np.uint64)
+    # owner node of each triangle: bands by the strut's lower node, fans by node
+    sa, sb = np.asarray(strut_a, np.int64), np.asarray(strut_b, np.int64)
+    lo = np.minimum(sa, sb)
+    band_owner = np.repeat(lo, np.diff(R.band_off))
+    fan_owner = np.repeat(np.arange(N), np.diff(R.fan_off))
+    owner = np.concatenate([band_owner, fan_owner])
+    ch = owner // chunk_nodes
+    out[:, 0] = np.bincount(ch, minlength=nch).astype(np.uint64)
+    for c in range(nch):
+        with np.errstate(over="ignore"):
+            out[c, 1] = np.sum(keys[ch == c], dtype=np.uint64)
+    vch = node_of // chunk_nodes
+    out[:, 2] = np.bincount(vch, minlength=nch).astype(np.uint64)
+    fix = np.rint(R.mesh * 1048576.0).astype(np.int64)
+    for d in range(3):
+        for c in range(nch):
+            with np.errstate(over="ignore"):
+                out[c, 4 + d] = np.sum(fix[vch == c, d].view(np.uint64), dtype=np.uint64)
+    bad = np.nonzero(R.status != 0)[0]
+    out[:, 7] = np.bincount(bad // chunk_nodes, minlength=nch).astype(np.uint64)
+    return out

@@ -7,7 +7,7 @@
 #include "common.h"
 
 // Phases timed with HIP events when profiling is on (lm_set_profiling).
-enum Phase { PH_PREPARE, PH_NODE32, PH_NODE64, PH_SIZES, PH_EXPAND, PH_ZIP, PH_N };
+enum Phase { PH_PREPARE, PH_NODE32, PH_NODE64, PH_SIZES, PH_EXPAND, PH_ZIP, PH_LOSS, PH_BACKWARD, PH_N };
 
 struct lm_plan {
     lm::Inputs in;
@@ -15,6 +15,15 @@ struct lm_plan {
     hipStream_t st;
     void *ws;       // one allocation for the fixed-size workspace
     int64_t rec_alloc_words;  // words allocated for node records
+    // sink mode (allocated at the first lm_forward_sink)
+    int32_t *sk_mark = nullptr;     // [N] epoch of the last chunk listing the node
+    int32_t *sk_lists = nullptr;    // [kClasses][N] chunk node lists
+    int32_t *sk_cnt = nullptr;      // [4] list sizes, then the strut count
+    int64_t *sk_info = nullptr;     // [8] class sizes / starts for the node kernel
+    int32_t *sk_struts = nullptr;   // [sk_struts_cap] struts owned by the chunk
+    int64_t sk_struts_cap = 0;
+    unsigned long long *sk_slots = nullptr;
+    int32_t sk_epoch = 0;
     int k;          // resolution of the last count (0: none)
     float kappa_max;// FP32 -> FP64 hand-over threshold
     lm_totals last; // totals of the last lm_count
@@ -105,6 +114,9 @@ size_t carve(lm::Work &w, char *base, int64_t N, int64_t S)
     w.fb_list = (int32_t *)take(sizeof(int32_t) * (N + 1));
     w.node_rec = (int64_t *)take(sizeof(int64_t) * (N + 1));
     w.rec_top = (unsigned long long *)take(sizeof(unsigned long long) * lm::kRecRegions);
+    w.queue = (int32_t *)take(sizeof(int32_t) * (N + 1));
+    w.cls_info = (int64_t *)take(sizeof(int64_t) * 8);
+    w.work_ctr = (int32_t *)take(sizeof(int32_t) * 4);
     return off;
 }
 
@@ -143,6 +155,7 @@ int run_count(lm_plan *P, int k, const lm::FillOut *out)
     HIPCHK(hipMemsetAsync(w.flags + 2, 0, sizeof(int32_t), P->st));
     HIPCHK(hipMemsetAsync(w.totals, 0, sizeof(int64_t) * 16, P->st));
     HIPCHK(hipMemsetAsync(w.rec_top, 0, sizeof(unsigned long long) * lm::kRecRegions, P->st));
+    HIPCHK(hipMemsetAsync(w.work_ctr, 0, sizeof(int32_t) * 4, P->st));
     {
         PhaseTimer t(P, PH_NODE32);
         HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, 0, P->st));
@@ -330,6 +343,126 @@ int lm_forward(lm_plan *P, int k, const lm_outputs *out)
     return fill_common(P, f, out);
 }
 
+int lm_loss(lm_plan *P, const lm_outputs *out, const lm_loss_weights *w, double *d_terms, float *d_dl_dx)
+{
+    if (!P || !out || !w || !d_terms || !d_dl_dx || !out->d_mesh_xyz || !out->d_tri) return LM_ERR_INVALID_ARG;
+    if (P->k == 0) return LM_ERR_STATE;
+    lm::FillOut f = to_fill(out);
+    PhaseTimer t(P, PH_LOSS);
+    HIPCHK(lm::launch_loss(P->w, f, make_float3(w->p0[0], w->p0[1], w->p0[2]), w->area, w->volume, w->sq_norm,
+                           d_dl_dx, d_terms, P->st));
+    return LM_OK;
+}
+
+int lm_backward(lm_plan *P, const float *d_dl_dx, float *d_grad_xyz, float *d_grad_radius)
+{
+    if (!P || !d_dl_dx || !d_grad_xyz || !d_grad_radius) return LM_ERR_INVALID_ARG;
+    if (P->k == 0) return LM_ERR_STATE;
+    PhaseTimer t(P, PH_BACKWARD);
+    HIPCHK(lm::launch_backward(P->in, P->w, d_dl_dx, d_grad_xyz, d_grad_radius, P->st));
+    return LM_OK;
+}
+
+namespace {
+
+int sink_alloc(lm_plan *P)
+{
+    if (P->sk_mark) return LM_OK;
+    const int64_t N = P->in.n_nodes;
+    HIPCHK(hipMalloc((void **)&P->sk_mark, sizeof(int32_t) * (N + 1)));
+    HIPCHK(hipMemsetAsync(P->sk_mark, 0, sizeof(int32_t) * (N + 1), P->st));
+    HIPCHK(hipMalloc((void **)&P->sk_lists, sizeof(int32_t) * lm::kClasses * (N + 1)));
+    HIPCHK(hipMalloc((void **)&P->sk_cnt, sizeof(int32_t) * 8));
+    HIPCHK(hipMalloc((void **)&P->sk_info, sizeof(int64_t) * 8));
+    HIPCHK(hipMalloc((void **)&P->sk_slots, sizeof(unsigned long long) * lm::sink_slots_words()));
+    HIPCHK(hipMemsetAsync(P->sk_slots, 0, sizeof(unsigned long long) * lm::sink_slots_words(), P->st));
+    return LM_OK;
+}
+
+}  // namespace
+
+int lm_forward_sink(lm_plan *P, int k, int64_t chunk_nodes, uint64_t *d_out, int64_t n_chunks_cap)
+{
+    if (!P || !d_out || k < 3 || k > 4096 || chunk_nodes < 1) return LM_ERR_INVALID_ARG;
+    const int64_t N = P->in.n_nodes, S = P->in.n_struts;
+    const int64_t nch = (N + chunk_nodes - 1) / chunk_nodes;
+    if (nch > n_chunks_cap) return LM_ERR_CAPACITY;
+    int rc = sink_alloc(P);
+    if (rc) return rc;
+    lm::Work &w = P->w;
+    const double avg_deg = N > 0 ? 2.0 * (double)S / (double)N : 0.0;
+    for (int64_t c = 0; c < nch; ++c) {
+        const int64_t n0 = c * chunk_nodes, n1 = n0 + chunk_nodes < N ? n0 + chunk_nodes : N;
+        // node list of the chunk: the range and its higher-id halo
+        HIPCHK(hipMemsetAsync(P->sk_cnt, 0, sizeof(int32_t) * 8, P->st));
+        if (++P->sk_epoch <= 0) {  // epochs wrapped: clear the marks
+            HIPCHK(hipMemsetAsync(P->sk_mark, 0, sizeof(int32_t) * (N + 1), P->st));
+            P->sk_epoch = 1;
+        }
+        {
+            PhaseTimer t(P, PH_SIZES);
+            HIPCHK(lm::launch_chunk_list(w, n0, n1, P->sk_mark, P->sk_epoch, P->sk_lists, N + 1, P->sk_cnt,
+                                         P->sk_info, P->st));
+        }
+        int32_t cnt[4];
+        int64_t r01[2];
+        HIPCHK(hipMemcpyAsync(cnt, P->sk_cnt, sizeof(cnt), hipMemcpyDeviceToHost, P->st));
+        HIPCHK(hipMemcpyAsync(&r01[0], w.row + n0, sizeof(int64_t), hipMemcpyDeviceToHost, P->st));
+        HIPCHK(hipMemcpyAsync(&r01[1], w.row + n1, sizeof(int64_t), hipMemcpyDeviceToHost, P->st));
+        HIPCHK(hipStreamSynchronize(P->st));
+        const int64_t listed = (int64_t)cnt[0] + cnt[1] + cnt[2];
+        const int64_t hcnt = r01[1] - r01[0];
+        if (hcnt > P->sk_struts_cap) {
+            if (P->sk_struts) HIPCHK(hipFree(P->sk_struts));
+            P->sk_struts = nullptr;
+            HIPCHK(hipMalloc((void **)&P->sk_struts, sizeof(int32_t) * (hcnt + 1)));
+            P->sk_struts_cap = hcnt;
+        }
+        // record space for the listed nodes (first guess, then what they used)
+        const int64_t per_node =
+            lm::kRecHead + 4 + (int64_t)(avg_deg * (8 + 3 * lm::kRecArcFields + 3 + 2 * (k + 4)) + 1);
+        if ((rc = ensure_rec(P, listed * per_node + listed * per_node / 8 + 4096))) return rc;
+        lm::Work wc = w;
+        wc.queue = P->sk_lists;
+        wc.cls_info = P->sk_info;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            HIPCHK(hipMemsetAsync(w.flags, 0, sizeof(int32_t), P->st));
+            HIPCHK(hipMemsetAsync(w.flags + 2, 0, sizeof(int32_t), P->st));
+            HIPCHK(hipMemsetAsync(w.rec_top, 0, sizeof(unsigned long long) * lm::kRecRegions, P->st));
+            HIPCHK(hipMemsetAsync(w.work_ctr, 0, sizeof(int32_t) * 4, P->st));
+            wc.rec = w.rec;
+            wc.rec_words = w.rec_words;
+            {
+                PhaseTimer t(P, PH_NODE32);
+                HIPCHK(lm::launch_node(P->in, wc, k, P->kappa_max, 0, P->st));
+            }
+            {
+                PhaseTimer t(P, PH_NODE64);
+                HIPCHK(lm::launch_node(P->in, wc, k, P->kappa_max, 1, P->st));
+            }
+            int32_t fl = 0;
+            unsigned long long top[lm::kRecRegions];
+            HIPCHK(hipMemcpyAsync(&fl, w.flags, sizeof(int32_t), hipMemcpyDeviceToHost, P->st));
+            HIPCHK(hipMemcpyAsync(top, w.rec_top, sizeof(top), hipMemcpyDeviceToHost, P->st));
+            HIPCHK(hipStreamSynchronize(P->st));
+            if (!(fl & lm::DF_RECCAP)) break;
+            if (attempt == 1) return LM_ERR_INTERNAL;
+            unsigned long long mx = 0;
+            for (int g = 0; g < lm::kRecRegions; ++g) mx = top[g] > mx ? top[g] : mx;
+            if ((rc = ensure_rec(P, (int64_t)mx * lm::kRecRegions + (int64_t)mx))) return rc;
+        }
+        HIPCHK(hipMemsetAsync(P->sk_cnt + 4, 0, sizeof(int32_t), P->st));
+        {
+            PhaseTimer t(P, PH_EXPAND);
+            HIPCHK(lm::launch_sink(P->in, w, n0, n1, hcnt, P->sk_struts, P->sk_cnt + 4, P->sk_slots,
+                                   d_out + c * LM_SINK_WORDS, P->st));
+        }
+    }
+    // the node records now hold chunks: lm_fill / lm_backward need a new count
+    P->k = 0;
+    return LM_OK;
+}
+
 int lm_read_totals(lm_plan *P, lm_totals *totals)
 {
     if (!P || !totals) return LM_ERR_INVALID_ARG;
@@ -394,6 +527,9 @@ void lm_plan_destroy(lm_plan *P)
     }
     for (auto e : P->pool) (void)hipEventDestroy(e);
     if (P->w.rec) (void)hipFree(P->w.rec);
+    for (void *p : {(void *)P->sk_mark, (void *)P->sk_lists, (void *)P->sk_cnt, (void *)P->sk_info,
+                    (void *)P->sk_struts, (void *)P->sk_slots})
+        if (p) (void)hipFree(p);
     (void)hipFree(P->ws);
     delete P;
 }

@@ -102,7 +102,14 @@ struct Work {
     int32_t *flags;         // [4] see DevFlag
     int64_t *totals;        // [16] device copy of totals
     int32_t *fb_list;       // [N] nodes for the FP64 pass
+    int32_t *queue;         // [N] node ids grouped by valence class
+    int64_t *cls_info;      // [8] nodes per class (0..2), queue start per class (4..6)
+    int32_t *work_ctr;      // [4] per-class work counters of the node kernel
 };
+
+// Valence classes of the node kernel: v <= 4, 5..8, otherwise.
+__host__ __device__ inline int valence_class(int64_t v) { return v <= 4 ? 0 : (v <= 8 ? 1 : 2); }
+constexpr int kClasses = 3;
 
 struct FillOut {
     float *mesh_xyz;
@@ -128,6 +135,20 @@ hipError_t launch_expand(const Inputs &in, const Work &w, const FillOut &o, hipS
 hipError_t launch_band_count(const Inputs &in, const Work &w, hipStream_t st);
 hipError_t launch_zip(const Inputs &in, const Work &w, const FillOut &o, hipStream_t st);
 hipError_t launch_totals(const Inputs &in, const Work &w, const FillOut *o, hipStream_t st);
+// Loss terms (area, volume about p0, sum of squared norms) of the last mesh
+// and their gradient dldx [cap_mesh][3]; then the adjoint to the inputs.
+hipError_t launch_loss(const Work &w, const FillOut &o, float3 p0, float w_area, float w_vol, float w_sq,
+                       float *dldx, double *terms, hipStream_t st);
+hipError_t launch_backward(const Inputs &in, const Work &w, const float *dldx, float *grad_xyz, float *grad_r,
+                           hipStream_t st);
+// Sink mode: chunk node lists (range + higher-id halo, in valence classes)
+// and the hashed triangles of a range.
+int64_t sink_slots_words();
+hipError_t launch_chunk_list(const Work &w, int64_t n0, int64_t n1, int32_t *mark, int32_t epoch, int32_t *lists,
+                             int64_t cap, int32_t *cnt, int64_t *info, hipStream_t st);
+hipError_t launch_sink(const Inputs &in, const Work &w, int64_t n0, int64_t n1, int64_t max_struts,
+                       int32_t *strut_list, int32_t *strut_cnt, unsigned long long *slots, uint64_t *out,
+                       hipStream_t st);
 
 int64_t scan_tmp_needed(int64_t n, int ncols);
 

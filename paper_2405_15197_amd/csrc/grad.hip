@@ -1,0 +1,611 @@
+// Adjoint of the triangulation at fixed topology.
+//
+// Loss terms over the triangle mesh (Area, the volume enclosed about a fixed
+// point p0, and the sum of squared vertex norms) and their gradient with
+// respect to the mesh vertices; then, per node, the gradient of the loss
+// with respect to the node centres and nodal-sphere radii, propagated back
+// through the node's mesh vertices while the discrete structure (labels,
+// arcs, segment counts, triangles) stays that of the forward pass:
+//
+//   hole centre (Eq. 13)  rho * b / |b|, b the mean of the contour vertices;
+//   interior point (Eq. 12)  o + a sin t_i + b cos t_i, t_i = t1 + (t2 - t1) i / N;
+//   arc ends  t1, t2 are the conic parameters of the arc's end vertices;
+//   conic (o, a, b)  the tangency circle or the Eq. 7 ellipse of struts p, q;
+//   vertex  the tie P_p = P_q = P_r, |w|^2 - rho^2 = P_p^2 (Sec. 4.3.1),
+//           differentiated implicitly;
+//   strut table  g_m, h_m, e_m from the two node centres and radii.
+//
+// Conics and strut-table entries are differentiated in forward mode with
+// dual numbers (one input direction at a time), everything else in reverse.
+#include "geom.h"
+
+namespace lm {
+namespace geo {
+
+// Dual number: value and derivative along one input direction.
+struct Dual {
+    float v, d;
+    __device__ Dual() : v(0.f), d(0.f) {}
+    __device__ Dual(double x) : v((float)x), d(0.f) {}
+    __device__ Dual(float x) : v(x), d(0.f) {}
+    __device__ Dual(int x) : v((float)x), d(0.f) {}
+    __device__ Dual(float x, float dx) : v(x), d(dx) {}
+};
+__device__ inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+__device__ inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+__device__ inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+__device__ inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+__device__ inline Dual operator/(Dual a, Dual b)
+{
+    const float q = a.v / b.v;
+    return Dual(q, (a.d - q * b.d) / b.v);
+}
+__device__ inline bool operator<(Dual a, Dual b) { return a.v < b.v; }
+__device__ inline bool operator>(Dual a, Dual b) { return a.v > b.v; }
+__device__ inline bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
+__device__ inline bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
+__device__ inline Dual m_sqrt(Dual a)
+{
+    const float r = sqrtf(a.v);
+    return Dual(r, r > 0.f ? 0.5f * a.d / r : 0.f);
+}
+__device__ inline Dual m_abs(Dual a) { return a.v < 0.f ? -a : a; }
+__device__ inline Dual m_max(Dual a, Dual b) { return a.v >= b.v ? a : b; }
+
+}  // namespace geo
+
+namespace {
+
+using namespace geo;
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// loss terms and their gradient with respect to the mesh vertices
+
+__device__ inline double block_sum(double x, double *sm)
+{
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sm[wid] = x;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kBlock / 64; ++w) t += sm[w];
+    __syncthreads();
+    return t;
+}
+
+__device__ inline float3 f3(const float *p) { return make_float3(p[0], p[1], p[2]); }
+__device__ inline float3 sub3(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ inline float3 crs3(float3 a, float3 b)
+{
+    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ inline void add3(float *p, float3 v, float s)
+{
+    atomicAdd(p, v.x * s);
+    atomicAdd(p + 1, v.y * s);
+    atomicAdd(p + 2, v.z * s);
+}
+
+// Per triangle: area 1/2 |N| with N = (b - a) x (c - a), dA/da = 1/2 n x (c - b)
+// (cyclic); volume (a' . (b' x c')) / 6 about p0, dV/da = (b' x c') / 6.
+__global__ void __launch_bounds__(kBlock) k_loss_tri(const int64_t *d_ntri, const int32_t *tri, const float *xyz,
+                                                     float3 p0, float w_area, float w_vol, float *dldx, double *terms)
+{
+    __shared__ double sm[kBlock / 64];
+    const int64_t ntri = *d_ntri;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((int64_t)blockIdx.x * blockDim.x >= ntri) return;  // whole block past the end
+    double area = 0.0, vol = 0.0;
+    if (t < ntri) {
+        const int32_t i0 = tri[3 * t], i1 = tri[3 * t + 1], i2 = tri[3 * t + 2];
+        const float3 a = sub3(f3(xyz + 3 * (int64_t)i0), p0), b = sub3(f3(xyz + 3 * (int64_t)i1), p0),
+                     c = sub3(f3(xyz + 3 * (int64_t)i2), p0);
+        const float3 N = crs3(sub3(b, a), sub3(c, a));
+        const float nl = sqrtf(N.x * N.x + N.y * N.y + N.z * N.z);
+        area = 0.5 * (double)nl;
+        const float3 bc = crs3(b, c), ca = crs3(c, a), ab = crs3(a, b);
+        vol = ((double)a.x * bc.x + (double)a.y * bc.y + (double)a.z * bc.z) / 6.0;
+        if (w_area != 0.f && nl > 0.f) {
+            const float3 n = make_float3(N.x / nl, N.y / nl, N.z / nl);
+            add3(dldx + 3 * (int64_t)i0, crs3(n, sub3(c, b)), 0.5f * w_area);
+            add3(dldx + 3 * (int64_t)i1, crs3(n, sub3(a, c)), 0.5f * w_area);
+            add3(dldx + 3 * (int64_t)i2, crs3(n, sub3(b, a)), 0.5f * w_area);
+        }
+        if (w_vol != 0.f) {
+            add3(dldx + 3 * (int64_t)i0, bc, w_vol / 6.f);
+            add3(dldx + 3 * (int64_t)i1, ca, w_vol / 6.f);
+            add3(dldx + 3 * (int64_t)i2, ab, w_vol / 6.f);
+        }
+    }
+    const double sa = block_sum(area, sm), sv = block_sum(vol, sm);
+    if (threadIdx.x == 0) {
+        atomicAdd(&terms[0], sa);
+        atomicAdd(&terms[1], sv);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_loss_vert(const int64_t *d_nv, const float *xyz, float w_sq, float *dldx,
+                                                      double *terms)
+{
+    __shared__ double sm[kBlock / 64];
+    const int64_t nv = *d_nv;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((int64_t)blockIdx.x * blockDim.x >= nv) return;
+    double q = 0.0;
+    if (i < nv) {
+        const float3 x = f3(xyz + 3 * i);
+        q = (double)x.x * x.x + (double)x.y * x.y + (double)x.z * x.z;
+        if (w_sq != 0.f) {
+            dldx[3 * i] += 2.f * w_sq * x.x;
+            dldx[3 * i + 1] += 2.f * w_sq * x.y;
+            dldx[3 * i + 2] += 2.f * w_sq * x.z;
+        }
+    }
+    const double s = block_sum(q, sm);
+    if (threadIdx.x == 0) atomicAdd(&terms[2], s);
+}
+
+__global__ void k_zero_f(float *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+__global__ void k_zero_d(double *p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// per-node adjoint
+
+struct BParams {
+    Inputs in;
+    Work w;
+    const float *dldx;  // [M][3]
+    float *grad_xyz;    // [N][3]
+    float *grad_r;      // [N]
+};
+
+// the 4 inputs (x, y, z, radius) of node `node` as dual seeds: direction k
+__device__ inline void seed(const float4 c4, int k, V3<Dual> &c, Dual &r)
+{
+    c = v3(Dual(c4.x, k == 0 ? 1.f : 0.f), Dual(c4.y, k == 1 ? 1.f : 0.f), Dual(c4.z, k == 2 ? 1.f : 0.f));
+    r = Dual(c4.w, k == 3 ? 1.f : 0.f);
+}
+
+__device__ inline float dotf(const float *a, const float *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+__global__ void __launch_bounds__(64) k_backward(BParams P)
+{
+    __shared__ SL<float> S[kVmax + 1];
+    __shared__ float lam_v[kVcap][3];
+    __shared__ float lam_arc[kAcap][11];  // o, a, b, t1, t2
+    __shared__ float lam_g[kVmax + 1][3], lam_h[kVmax + 1], lam_e[kVmax + 1][3];
+    __shared__ float lam_node[4];         // this node's x, y, z, radius
+    __shared__ int s_mbase[kAcap];
+    const Work &W = P.w;
+    const int64_t N = P.in.n_nodes;
+    const int64_t n = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (n >= N) return;
+    const int64_t rb = W.node_rec[n];
+    if (rb < 0) return;
+    const uint32_t *R = W.rec + rb;
+    const int V = (int)R[0], E = (int)R[1], NC = (int)R[2], ncirc = (int)R[3];
+    const int wsum = (int)R[4];
+    const uint32_t *RV = R + kRecHead;
+    const uint32_t *RA = RV + 4 * V;
+    const uint32_t *RH = RA + kRecArcFields * E;
+    const int64_t row = W.row[n];
+    const int v = (int)(W.row[n + 1] - row);
+    const int64_t moff = W.node_off[(int64_t)NC_MESH * (N + 1) + n];
+    const float4 c4 = W.node4[n];
+    const float rho = c4.w;
+    const V3<float> cen = v3(c4.x, c4.y, c4.z);
+    const float *L = P.dldx + 3 * moff;
+    auto af = [&](int f, int j) { return __uint_as_float(RA[f * E + j]); };
+    auto vpos = [&](int i, float *w) {
+        w[0] = __uint_as_float(RV[V + i]);
+        w[1] = __uint_as_float(RV[2 * V + i]);
+        w[2] = __uint_as_float(RV[3 * V + i]);
+    };
+
+    // ---- strut table, cleared adjoints ------------------------------------
+    if (lane < v) {
+        const int2 he = W.he[row + lane];
+        const float4 f4 = W.node4[he.x];
+        bool bad;
+        SL<float> s = strut_entry(cen, rho, v3(f4.x, f4.y, f4.z), f4.w, (int)((int64_t)he.x > n), bad);
+        s.sid = he.y;
+        s.far = he.x;
+        S[lane + 1] = s;
+    }
+    for (int i = lane; i <= kVmax; i += 64) {
+        lam_g[i][0] = lam_g[i][1] = lam_g[i][2] = 0.f;
+        lam_h[i] = 0.f;
+        lam_e[i][0] = lam_e[i][1] = lam_e[i][2] = 0.f;
+    }
+    if (lane < 4) lam_node[lane] = 0.f;
+    for (int j = lane; j < E; j += 64) {
+        s_mbase[j] = (int)RA[14 * E + j];
+#pragma unroll
+        for (int f = 0; f < 11; ++f) lam_arc[j][f] = 0.f;
+    }
+    for (int i = lane; i < V; i += 64) {
+        lam_v[i][0] = L[3 * i];
+        lam_v[i][1] = L[3 * i + 1];
+        lam_v[i][2] = L[3 * i + 2];
+    }
+    __syncthreads();
+
+    // absolute positions are c + w: every mesh vertex of the node moves with c
+    {
+        const int M = (int)R[5];
+        float sx = 0.f, sy = 0.f, sz = 0.f;
+        for (int i = lane; i < M; i += 64) {
+            sx += L[3 * i];
+            sy += L[3 * i + 1];
+            sz += L[3 * i + 2];
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            sx += __shfl_xor(sx, o, 64);
+            sy += __shfl_xor(sy, o, 64);
+            sz += __shfl_xor(sz, o, 64);
+        }
+        if (lane == 0) {
+            lam_node[0] += sx;
+            lam_node[1] += sy;
+            lam_node[2] += sz;
+        }
+    }
+
+    // Eq. 12 point ii of arc j and its derivative along t
+    auto arc_point = [&](int j, float t, float *x, float *dx) {
+        float s, c;
+        sincosf(t, &s, &c);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            x[d] = af(d, j) + af(3 + d, j) * s + af(6 + d, j) * c;
+            dx[d] = af(3 + d, j) * c - af(6 + d, j) * s;
+        }
+    };
+    // adds weight lam (a 3-vector) on interior point ii of arc j
+    auto add_interior = [&](int j, int ii, const float *lam) {
+        const int nseg = (int)(RA[13 * E + j] & 0xffffu);
+        const float t1 = af(9, j), t2 = af(10, j);
+        const float f = (float)ii / (float)nseg;
+        const float t = t1 + (t2 - t1) * (float)ii / (float)nseg;
+        float s, c;
+        sincosf(t, &s, &c);
+        float g = 0.f;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            atomicAdd(&lam_arc[j][d], lam[d]);
+            atomicAdd(&lam_arc[j][3 + d], lam[d] * s);
+            atomicAdd(&lam_arc[j][6 + d], lam[d] * c);
+            g += lam[d] * (af(3 + d, j) * c - af(6 + d, j) * s);
+        }
+        atomicAdd(&lam_arc[j][9], (1.f - f) * g);
+        atomicAdd(&lam_arc[j][10], f * g);
+    };
+
+    // ---- interior points ----------------------------------------------------
+    for (int j = lane; j < E; j += 64) {
+        const int nseg = (int)(RA[13 * E + j] & 0xffffu);
+        const bool fwd = (RA[11 * E + j] >> 17) & 1u;
+        for (int ii = 1; ii < nseg; ++ii) {
+            const int li = s_mbase[j] + (fwd ? ii - 1 : nseg - 1 - ii);
+            const float lam[3] = {L[3 * li], L[3 * li + 1], L[3 * li + 2]};
+            add_interior(j, ii, lam);
+        }
+    }
+    __syncthreads();
+
+    // ---- hole centres (Eq. 13) ----------------------------------------------
+    for (int c = lane; c < NC; c += 64) {
+        const int li = wsum + c;
+        const float lh[3] = {L[3 * li], L[3 * li + 1], L[3 * li + 2]};
+        // barycentre as in the forward pass
+        float b[3] = {0.f, 0.f, 0.f};
+        int cnt = 0;
+        for (int j = 0; j < ncirc; ++j) {
+            if ((int)(RA[13 * E + j] >> 16) != c) continue;
+            const int vs = (int)(RA[12 * E + j] & 0xffffu), ve = (int)(RA[12 * E + j] >> 16);
+            float ws[3], we[3];
+            vpos(vs, ws);
+            vpos(ve, we);
+            const int nseg = (int)(RA[13 * E + j] & 0xffffu);
+            for (int d = 0; d < 3; ++d) b[d] += 0.5f * (ws[d] + we[d]);
+            for (int ii = 1; ii < nseg; ++ii) {
+                float x[3], dx[3];
+                arc_point(j, af(9, j) + (af(10, j) - af(9, j)) * (float)ii / (float)nseg, x, dx);
+                for (int d = 0; d < 3; ++d) b[d] += x[d];
+            }
+            cnt += nseg;
+        }
+        for (int d = 0; d < 3; ++d) b[d] /= (float)cnt;
+        const float bl = sqrtf(dotf(b, b));
+        float dir[3];
+        float se[3] = {0.f, 0.f, 0.f}, sl = 1.f;
+        const bool use_b = bl >= 1e-3f * rho;
+        if (use_b) {
+            for (int d = 0; d < 3; ++d) dir[d] = b[d] / bl;
+        } else {
+            for (int m = 1; m <= v; ++m) {
+                se[0] += S[m].ex;
+                se[1] += S[m].ey;
+                se[2] += S[m].ez;
+            }
+            sl = sqrtf(dotf(se, se));
+            for (int d = 0; d < 3; ++d) dir[d] = -se[d] / sl;
+        }
+        float sgn = 1.f;
+        for (int flip = 0; flip < 2; ++flip) {
+            float pm = -1e30f;
+            for (int m = 1; m <= v; ++m)
+                pm = fmaxf(pm, (S[m].gx * dir[0] + S[m].gy * dir[1] + S[m].gz * dir[2]) * rho - S[m].h);
+            if (pm <= 0.f) break;
+            for (int d = 0; d < 3; ++d) dir[d] = -dir[d];
+            sgn = -sgn;
+        }
+        // apex rho * dir
+        atomicAdd(&lam_node[3], dotf(lh, dir));
+        float ld[3];
+        for (int d = 0; d < 3; ++d) ld[d] = rho * lh[d];
+        const float dl = dotf(dir, ld);
+        if (use_b) {
+            // dir = sgn b / |b|: lam_b = sgn (ld - dir (dir . ld)) / |b|, then 1/cnt per vertex
+            float mu[3];
+            for (int d = 0; d < 3; ++d) mu[d] = sgn * (ld[d] - dir[d] * dl) / bl / (float)cnt;
+            for (int j = 0; j < ncirc; ++j) {
+                if ((int)(RA[13 * E + j] >> 16) != c) continue;
+                const int vs = (int)(RA[12 * E + j] & 0xffffu), ve = (int)(RA[12 * E + j] >> 16);
+                for (int d = 0; d < 3; ++d) {
+                    atomicAdd(&lam_v[vs][d], 0.5f * mu[d]);
+                    atomicAdd(&lam_v[ve][d], 0.5f * mu[d]);
+                }
+                const int nseg = (int)(RA[13 * E + j] & 0xffffu);
+                for (int ii = 1; ii < nseg; ++ii) add_interior(j, ii, mu);
+            }
+        } else {
+            // dir = -sgn se / |se|
+            for (int m = 1; m <= v; ++m)
+                for (int d = 0; d < 3; ++d) {
+                    const float g = -sgn * (ld[d] - (-sgn * dir[d]) * (-sgn * dl)) / sl;
+                    atomicAdd(&lam_e[m][d], g);
+                }
+        }
+    }
+    __syncthreads();
+
+    // ---- arc ends: t1, t2 are the parameters of the end vertices ------------
+    for (int j = lane; j < E; j += 64) {
+        const uint32_t u0 = RA[11 * E + j];
+        const bool full = (u0 >> 16) & 1u;
+        const int vs = (int)(RA[12 * E + j] & 0xffffu), ve = (int)(RA[12 * E + j] >> 16);
+        if (full) {
+            // the start vertex is the conic point at t = 0: o + b
+            for (int d = 0; d < 3; ++d) {
+                atomicAdd(&lam_arc[j][d], lam_v[vs][d]);
+                atomicAdd(&lam_arc[j][6 + d], lam_v[vs][d]);
+            }
+            continue;
+        }
+        float o[3], a[3], bb[3];
+        for (int d = 0; d < 3; ++d) {
+            o[d] = af(d, j);
+            a[d] = af(3 + d, j);
+            bb[d] = af(6 + d, j);
+        }
+        const float aa = dotf(a, a), bb2 = dotf(bb, bb);
+        for (int end = 0; end < 2; ++end) {
+            const float Lt = atomicAdd(&lam_arc[j][9 + end], 0.f);
+            const int vi = end ? ve : vs;
+            float w[3], r[3];
+            vpos(vi, w);
+            for (int d = 0; d < 3; ++d) r[d] = w[d] - o[d];
+            const float u = dotf(r, a) / aa, vv = dotf(r, bb) / bb2, den = u * u + vv * vv;
+            const float lu = Lt * vv / den, lv = -Lt * u / den;
+            const float ra = dotf(r, a), rbv = dotf(r, bb);
+            for (int d = 0; d < 3; ++d) {
+                const float lw = lu * a[d] / aa + lv * bb[d] / bb2;
+                atomicAdd(&lam_v[vi][d], lw);
+                atomicAdd(&lam_arc[j][d], -lw);
+                // u = (r . a) / (a . a): du/da = r / aa - 2 a (r . a) / aa^2
+                atomicAdd(&lam_arc[j][3 + d], lu * (r[d] / aa - 2.f * a[d] * ra / (aa * aa)));
+                atomicAdd(&lam_arc[j][6 + d], lv * (r[d] / bb2 - 2.f * bb[d] * rbv / (bb2 * bb2)));
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- conics: (o, a, b) from the node and strut inputs ---------------------
+    for (int j = lane; j < E; j += 64) {
+        const uint32_t u0 = RA[11 * E + j];
+        const int p = (int)(u0 & 0xffu), q = (int)((u0 >> 8) & 0xffu);
+        float Lo[9];
+        for (int f = 0; f < 9; ++f) Lo[f] = lam_arc[j][f];
+        const int nin = p == 0 ? 2 : 3;  // input nodes: this node, q (, p)
+        for (int which = 0; which < nin; ++which) {
+            const int m = which == 0 ? 0 : (which == 1 ? q : p);
+            const int node = which == 0 ? (int)n : S[m].far;
+            const float4 in4 = which == 0 ? c4 : W.node4[node];
+            float g4[4];
+            for (int kdir = 0; kdir < 4; ++kdir) {
+                V3<Dual> cd = v3(Dual(c4.x), Dual(c4.y), Dual(c4.z));
+                Dual rd = Dual(c4.w);
+                if (which == 0) seed(c4, kdir, cd, rd);
+                // strut entries of labels p (if any) and q with the seeded input
+                SL<Dual> Sd[2];
+                bool bad;
+                for (int e2 = 0; e2 < 2; ++e2) {
+                    const int lab = e2 == 0 ? q : p;
+                    if (lab == 0) continue;
+                    const float4 f4 = W.node4[S[lab].far];
+                    V3<Dual> cf = v3(Dual(f4.x), Dual(f4.y), Dual(f4.z));
+                    Dual rf = Dual(f4.w);
+                    if (which != 0 && lab == m) seed(f4, kdir, cf, rf);
+                    Sd[e2] = strut_entry(cd, rd, cf, rf, S[lab].lower, bad);
+                }
+                Con<Dual> C;
+                if (p == 0) {
+                    const SL<Dual> &s = Sd[0];
+                    Dual rad = rd * s.kap;
+                    C.o = v3(s.ex, s.ey, s.ez) * (rd * s.sig);
+                    C.a = v3(s.qx, s.qy, s.qz) * rad;
+                    C.b = v3(s.rx, s.ry, s.rz) * rad;
+                } else {
+                    SL<Dual> tab[3];
+                    tab[1] = Sd[1];  // label p
+                    tab[2] = Sd[0];  // label q
+                    conic_of(tab, rd, 1, 2, C);
+                }
+                g4[kdir] = Lo[0] * C.o.x.d + Lo[1] * C.o.y.d + Lo[2] * C.o.z.d + Lo[3] * C.a.x.d + Lo[4] * C.a.y.d +
+                           Lo[5] * C.a.z.d + Lo[6] * C.b.x.d + Lo[7] * C.b.y.d + Lo[8] * C.b.z.d;
+            }
+            (void)in4;
+            if (which == 0) {
+                for (int kdir = 0; kdir < 4; ++kdir) atomicAdd(&lam_node[kdir], g4[kdir]);
+            } else {
+                for (int kdir = 0; kdir < 3; ++kdir) atomicAdd(&P.grad_xyz[3 * (int64_t)node + kdir], g4[kdir]);
+                atomicAdd(&P.grad_r[node], g4[3]);
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- vertices: implicit function theorem on the tie equations ------------
+    // F1 = (g_p - g_q) . w - (h_p - h_q), F2 = (g_p - g_r) . w - (h_p - h_r),
+    // F3 = g_p . w - h_p - s, F4 = |w|^2 - rho^2 - s^2 (label 0: g = 0, h = 0).
+    // J^T mu = (lam_w, 0) gives mu3 = -2 s mu4 and
+    // [n1 | n2 | 2 (w - s g_p)] (mu1, mu2, mu4) = lam_w.
+    for (int i = lane; i < V; i += 64) {
+        const uint32_t name = RV[i];
+        const int p = (int)(name >> 24), q = (int)((name >> 16) & 0xffu), r = (int)((name >> 8) & 0xffu);
+        if (r == 0xff) continue;  // start point of a whole conic (handled with its arc)
+        float w[3], gp[3] = {0.f, 0.f, 0.f}, gq[3], gr[3];
+        vpos(i, w);
+        float hp = 0.f;
+        if (p) {
+            gp[0] = S[p].gx; gp[1] = S[p].gy; gp[2] = S[p].gz;
+            hp = S[p].h;
+        }
+        gq[0] = S[q].gx; gq[1] = S[q].gy; gq[2] = S[q].gz;
+        gr[0] = S[r].gx; gr[1] = S[r].gy; gr[2] = S[r].gz;
+        const float s = dotf(gp, w) - hp;
+        float n1[3], n2[3], n3[3];
+        for (int d = 0; d < 3; ++d) {
+            n1[d] = gp[d] - gq[d];
+            n2[d] = gp[d] - gr[d];
+            n3[d] = 2.f * (w[d] - s * gp[d]);
+        }
+        const float lw[3] = {lam_v[i][0], lam_v[i][1], lam_v[i][2]};
+        // Cramer on columns n1, n2, n3
+        auto det3 = [](const float *a, const float *b, const float *c) {
+            return a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
+                   a[2] * (b[0] * c[1] - b[1] * c[0]);
+        };
+        // solve [n1 n2 n3] x = lw, with the matrix holding n1, n2, n3 as columns
+        float m1[3], m2[3], m3[3];
+        const float dt = det3(n1, n2, n3);  // det of rows n1, n2, n3 = det of columns
+        // x_k = det(matrix with column k replaced by lw) / det
+        // (the determinant of a matrix equals that of its transpose)
+        for (int d = 0; d < 3; ++d) {
+            m1[d] = n1[d];
+            m2[d] = n2[d];
+            m3[d] = n3[d];
+        }
+        const float mu1 = det3(lw, m2, m3) / dt;
+        const float mu2 = det3(m1, lw, m3) / dt;
+        const float mu4 = det3(m1, m2, lw) / dt;
+        const float mu3 = -2.f * s * mu4;
+        // dL/dtheta = -mu^T dF/dtheta
+        const float cp = mu1 + mu2 + mu3;
+        if (p) {
+            for (int d = 0; d < 3; ++d) atomicAdd(&lam_g[p][d], -cp * w[d]);
+            atomicAdd(&lam_h[p], cp);
+        }
+        for (int d = 0; d < 3; ++d) {
+            atomicAdd(&lam_g[q][d], mu1 * w[d]);
+            atomicAdd(&lam_g[r][d], mu2 * w[d]);
+        }
+        atomicAdd(&lam_h[q], -mu1);
+        atomicAdd(&lam_h[r], -mu2);
+        atomicAdd(&lam_node[3], 2.f * rho * mu4);
+    }
+    __syncthreads();
+
+    // ---- strut table: g_m, h_m, e_m from the node and far-node inputs -------
+    if (lane < v) {
+        const int m = lane + 1;
+        const float lg[3] = {lam_g[m][0], lam_g[m][1], lam_g[m][2]};
+        const float le[3] = {lam_e[m][0], lam_e[m][1], lam_e[m][2]};
+        const float lh = lam_h[m];
+        const int far = S[m].far;
+        const float4 f4 = W.node4[far];
+        for (int which = 0; which < 2; ++which) {
+            float g4[4];
+            for (int kdir = 0; kdir < 4; ++kdir) {
+                V3<Dual> cd = v3(Dual(c4.x), Dual(c4.y), Dual(c4.z)), cf = v3(Dual(f4.x), Dual(f4.y), Dual(f4.z));
+                Dual rd = Dual(c4.w), rf = Dual(f4.w);
+                if (which == 0) seed(c4, kdir, cd, rd);
+                else seed(f4, kdir, cf, rf);
+                bool bad;
+                const SL<Dual> s = strut_entry(cd, rd, cf, rf, S[m].lower, bad);
+                g4[kdir] = lg[0] * s.gx.d + lg[1] * s.gy.d + lg[2] * s.gz.d + lh * s.h.d + le[0] * s.ex.d +
+                           le[1] * s.ey.d + le[2] * s.ez.d;
+            }
+            if (which == 0) {
+                for (int kdir = 0; kdir < 4; ++kdir) atomicAdd(&lam_node[kdir], g4[kdir]);
+            } else {
+                for (int kdir = 0; kdir < 3; ++kdir) atomicAdd(&P.grad_xyz[3 * (int64_t)far + kdir], g4[kdir]);
+                atomicAdd(&P.grad_r[far], g4[3]);
+            }
+        }
+    }
+    __syncthreads();
+    if (lane < 3) atomicAdd(&P.grad_xyz[3 * n + lane], lam_node[lane]);
+    if (lane == 3) atomicAdd(&P.grad_r[n], lam_node[3]);
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_loss(const Work &w, const FillOut &o, float3 p0, float w_area, float w_vol, float w_sq,
+                       float *dldx, double *terms, hipStream_t st)
+{
+    // counts from the device totals (mesh vertices, triangles); grids sized
+    // by the capacities, blocks past the counts return at once
+    k_zero_d<<<1, 64, 0, st>>>(terms, 3);
+    if (o.cap_mesh > 0) k_zero_f<<<grid_for(3 * o.cap_mesh), kBlock, 0, st>>>(dldx, 3 * o.cap_mesh);
+    if (o.cap_tri > 0)
+        k_loss_tri<<<grid_for(o.cap_tri), kBlock, 0, st>>>(w.totals + 4, o.tri, o.mesh_xyz, p0, w_area, w_vol, dldx,
+                                                           terms);
+    if (o.cap_mesh > 0)
+        k_loss_vert<<<grid_for(o.cap_mesh), kBlock, 0, st>>>(w.totals + 3, o.mesh_xyz, w_sq, dldx, terms);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward(const Inputs &in, const Work &w, const float *dldx, float *grad_xyz, float *grad_r,
+                           hipStream_t st)
+{
+    const int64_t N = in.n_nodes;
+    if (N == 0) return hipSuccess;
+    k_zero_f<<<grid_for(3 * N), kBlock, 0, st>>>(grad_xyz, 3 * N);
+    k_zero_f<<<grid_for(N), kBlock, 0, st>>>(grad_r, N);
+    BParams P;
+    P.in = in;
+    P.w = w;
+    P.dldx = dldx;
+    P.grad_xyz = grad_xyz;
+    P.grad_r = grad_r;
+    k_backward<<<(unsigned)N, 64, 0, st>>>(P);
+    return hipGetLastError();
+}
+
+}  // namespace lm

@@ -34,71 +34,15 @@
 // (the three surfaces meeting there have nearly dependent normals, so FP32
 // rounding is amplified by the condition number kappa = |n1||n2||n3| /
 // |det(n1, n2, n3)|) or when an FP32 consistency check fails.
-#include "common.h"
+#include "geom.h"
 
 namespace lm {
 namespace {
 
-// ---------------------------------------------------------------------------
-// scalar helpers (float / double)
-
-__device__ inline float m_sqrt(float x) { return sqrtf(x); }
-__device__ inline double m_sqrt(double x) { return sqrt(x); }
-__device__ inline float m_abs(float x) { return fabsf(x); }
-__device__ inline double m_abs(double x) { return fabs(x); }
-__device__ inline float m_atan2(float y, float x) { return atan2f(y, x); }
-__device__ inline double m_atan2(double y, double x) { return atan2(y, x); }
-// quotient for keys that only order angles (a few ulp suffice)
-__device__ inline float m_qdiv(float x, float y) { return __fdividef(x, y); }
-__device__ inline double m_qdiv(double x, double y) { return x / y; }
-__device__ inline float m_floor(float x) { return floorf(x); }
-__device__ inline double m_floor(double x) { return floor(x); }
-__device__ inline float m_max(float a, float b) { return fmaxf(a, b); }
-__device__ inline double m_max(double a, double b) { return fmax(a, b); }
-__device__ inline void m_sincos(float t, float *s, float *c) { sincosf(t, s, c); }
-__device__ inline void m_sincos(double t, double *s, double *c) { sincos(t, s, c); }
-
-template <typename T>
-struct Cst {
-    static constexpr T two_pi = (T)6.283185307179586476925286766559;
-    static constexpr T pi = (T)3.1415926535897932384626433832795;
-    static constexpr T inv_two_pi = (T)0.15915494309189533576888376337251;
-};
-
-template <typename T>
-struct V3 {
-    T x, y, z;
-};
-template <typename T>
-__device__ inline V3<T> v3(T x, T y, T z) { return V3<T>{x, y, z}; }
-template <typename T>
-__device__ inline V3<T> operator+(V3<T> a, V3<T> b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
-template <typename T>
-__device__ inline V3<T> operator-(V3<T> a, V3<T> b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
-template <typename T>
-__device__ inline V3<T> operator*(V3<T> a, T s) { return v3(a.x * s, a.y * s, a.z * s); }
-template <typename T>
-__device__ inline T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-template <typename T>
-__device__ inline V3<T> cross(V3<T> a, V3<T> b)
-{
-    return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
-}
-template <typename T>
-__device__ inline V3<T> zero3() { return v3((T)0, (T)0, (T)0); }
+using namespace geo;
 
 // ---------------------------------------------------------------------------
 // per-node data in LDS
-
-template <typename T>
-struct SL {
-    T gx, gy, gz, h;   // P_m(w) = g . w - h
-    T ex, ey, ez, sig; // unit direction node -> far node, sigma
-    T rx, ry, rz, kap; // strut frame r, kappa
-    T qx, qy, qz, len; // strut frame q, length
-    T sx, sy, sz;      // canonical strut direction (lower -> higher node id)
-    int lower, sid, far;
-};
 
 template <typename T>
 struct ArcL {
@@ -110,37 +54,45 @@ struct ArcL {
     int nseg, mbase, contour, fbase;
 };
 
-template <typename T>
+// Lanes per node and per-node capacities of one valence class: W lanes
+// (64 / W nodes per wave), up to VM incident struts, AC arcs, VC vertices.
+template <int VM_, int AC_, int VC_, int W_>
+struct Cfg {
+    static constexpr int VM = VM_, AC = AC_, VC = VC_, W = W_;
+};
+using CfgV4 = Cfg<4, 16, 16, 16>;   // v <= 4: four nodes per wave
+using CfgV8 = Cfg<8, 32, 24, 32>;   // v <= 8: two nodes per wave
+using CfgV16 = Cfg<kVmax, kAcap, kVcap, 64>;
+
+template <typename T, typename C>
 struct Shared {
-    SL<T> S[kVmax + 1];
-    ArcL<T> A[kAcap];
-    uint32_t vname[kVcap];
-    T vx[kVcap], vy[kVcap], vz[kVcap];
-    uint8_t loop_arc[2 * kAcap];
-    int8_t loop_dir[2 * kAcap];
-    uint8_t loop_ord[2 * kAcap];
-    int loop_base[kVmax + 2];
-    int loop_len[kVmax + 1];  // samples |L_m|
-    int loop_cnt[kVmax + 1];  // arcs per loop, then fill cursor
-    int loop_first[kVmax + 1];
-    int loop_full[kVmax + 1];
-    uint8_t loop_next[2 * kAcap];
-    int vdeg[kVcap];
-    uint32_t clabel[kAcap];
-    T hc[kAcap][3];           // hole centre (local) per contour
-    int entry_off[2 * kAcap + 1];   // first loop sample of each loop entry
-    uint8_t entry_m[2 * kAcap];     // strut label of each loop entry
-    int loop_desc[kVmax + 1];       // descents of phi along each loop
-    int loop_rot[kVmax + 1];        // loop position of the smallest phi
-    T ph_first[kVmax + 1], ph_last[kVmax + 1];  // phi keys of each loop's ends
-    int lbase[kVmax + 2];           // loop samples before each strut's loop
+    SL<T> S[C::VM + 1];
+    ArcL<T> A[C::AC];
+    uint32_t vname[C::VC];
+    T vx[C::VC], vy[C::VC], vz[C::VC];
+    uint8_t loop_arc[2 * C::AC];
+    int8_t loop_dir[2 * C::AC];
+    uint8_t loop_ord[2 * C::AC];
+    int loop_base[C::VM + 2];
+    int loop_len[C::VM + 1];  // samples |L_m|
+    int loop_cnt[C::VM + 1];  // arcs per loop, then fill cursor
+    int loop_first[C::VM + 1];
+    int loop_full[C::VM + 1];
+    uint8_t loop_next[2 * C::AC];
+    int vdeg[C::VC];
+    uint32_t clabel[C::AC];
+    T hc[C::AC][3];           // hole centre (local) per contour
+    int entry_off[2 * C::AC + 1];   // first loop sample of each loop entry
+    uint8_t entry_m[2 * C::AC];     // strut label of each loop entry
+    int loop_desc[C::VM + 1];       // descents of phi along each loop
+    int loop_rot[C::VM + 1];        // loop position of the smallest phi
+    T ph_first[C::VM + 1], ph_last[C::VM + 1];  // phi keys of each loop's ends
+    int lbase[C::VM + 2];           // loop samples before each strut's loop
     int status, n_arc, n_vert, n_contour;
     int wsum, fsum, ncirc;
     int64_t rec;                    // first word of the node record, -1: none
 };
 
-template <typename T>
-__device__ inline V3<T> gvec(const SL<T> &s) { return v3(s.gx, s.gy, s.gz); }
 
 __device__ inline uint32_t vname3(int a, int b, int c, int root)
 {
@@ -163,84 +115,19 @@ __device__ inline uint32_t tie_name(int p, int q, int r, int root)
     return vname3(t.x, t.y, t.z, root);
 }
 
-__device__ inline int wave_excl_scan(int x, int *total)
+// exclusive scan over the W lanes of a node
+template <int W>
+__device__ inline int group_excl_scan(int x, int *total)
 {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (W - 1);
     int inc = x;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int y = __shfl_up(inc, d, 64);
+    for (int d = 1; d < W; d <<= 1) {
+        int y = __shfl_up(inc, d, W);
         if (lane >= d) inc += y;
     }
-    *total = __shfl(inc, 63, 64);
+    *total = __shfl(inc, W - 1, W);
     return inc - x;
-}
-
-// ---------------------------------------------------------------------------
-// conics
-
-template <typename T>
-struct Con {
-    V3<T> o, a, b;
-};
-
-template <typename T>
-__device__ inline V3<T> conic_at(const Con<T> &C, T t)
-{
-    T s, c;
-    m_sincos(t, &s, &c);
-    return C.o + C.a * s + C.b * c;
-}
-
-// Conic (p, q) of the node.  Returns false if the section is not an ellipse.
-template <typename T>
-__device__ bool conic_of(const SL<T> *S, T rho, int p, int q, Con<T> &C)
-{
-    if (p == 0) {
-        const SL<T> &s = S[q];
-        T rad = rho * s.kap;
-        C.o = v3(s.ex, s.ey, s.ez) * (rho * s.sig);
-        C.a = v3(s.qx, s.qy, s.qz) * rad;
-        C.b = v3(s.rx, s.ry, s.rz) * rad;
-        return true;
-    }
-    const SL<T> &P = S[p], &Q = S[q];
-    V3<T> gp = gvec(P);
-    V3<T> n = gp - gvec(Q);
-    T nn = m_sqrt(dot(n, n));
-    V3<T> nh = n * ((T)1 / nn);
-    T d0 = (P.h - Q.h) / nn;            // plane: nh . w = d0
-    T gpn = dot(gp, nh);
-    T epn = m_abs(gpn * P.kap);         // |e_p . nh|
-    T as = m_abs(P.sig);
-    T om = (epn - as) * (epn + as) / (P.kap * P.kap); // 1 - |in-plane g_p|^2
-    if (!(om > (T)0)) return false;
-    V3<T> gam = gp - nh * gpn;          // in-plane part of g_p: major axis direction
-    T gl = m_sqrt(dot(gam, gam));
-    V3<T> u1;
-    if (gl > (T)1e-20) {
-        u1 = gam * ((T)1 / gl);
-        // gam is a small difference when the plane is nearly perpendicular
-        // to the axis; keep u1 exactly in the plane (its in-plane rotation
-        // error only reparametrises an almost circular ellipse)
-        u1 = u1 - nh * dot(u1, nh);
-        u1 = u1 * ((T)1 / m_sqrt(dot(u1, u1)));
-    } else {
-        V3<T> t = m_abs(nh.x) < (T)0.9 ? v3((T)1, (T)0, (T)0) : v3((T)0, (T)1, (T)0);
-        u1 = cross(nh, t);
-        u1 = u1 * ((T)1 / m_sqrt(dot(u1, u1)));
-    }
-    // in-plane coordinates w = d0 nh + al u1 + be u2:
-    //   (1 - gl^2) al^2 - 2 gl k0 al + be^2 = rho^2 - d0^2 + k0^2,
-    // k0 = P_p at the foot point d0 nh; complete the square.
-    T k0 = d0 * gpn - P.h;
-    T al0 = gl * k0 / om;
-    T R2 = rho * rho - d0 * d0 + k0 * k0 / om;
-    T R = m_sqrt(m_max(R2, (T)0));
-    C.o = nh * d0 + u1 * al0;
-    C.a = u1 * (R / m_sqrt(om));
-    C.b = cross(u1, nh) * R;
-    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -493,8 +380,8 @@ __device__ inline Con<T> arc_con(const ArcL<T> &A)
     return C;
 }
 
-template <typename T>
-__device__ inline int find_vert(const Shared<T> &sh, uint32_t name)
+template <typename SH>
+__device__ inline int find_vert(const SH &sh, uint32_t name)
 {
     int lo = 0, hi = sh.n_vert - 1;
     while (lo <= hi) {
@@ -524,8 +411,8 @@ __device__ inline T sub_param(const ArcL<T> &A, int ii)
 template <typename T>
 __device__ inline V3<T> interior_pt(const ArcL<T> &A, int ii) { return conic_at(arc_con(A), sub_param(A, ii)); }
 
-template <typename T>
-__device__ inline V3<T> vert_pos(const Shared<T> &sh, int i) { return v3(sh.vx[i], sh.vy[i], sh.vz[i]); }
+template <typename T, typename C>
+__device__ inline V3<T> vert_pos(const Shared<T, C> &sh, int i) { return v3(sh.vx[i], sh.vy[i], sh.vz[i]); }
 
 struct Params {
     Inputs in;
@@ -535,17 +422,18 @@ struct Params {
 };
 
 // statuses that FP64 may resolve
-constexpr int kRetry = NS_NON_ELLIPTIC | NS_LOOP | NS_TOPOLOGY | NS_PREC;
+constexpr int kRetry = NS_NON_ELLIPTIC | NS_LOOP | NS_TOPOLOGY | NS_PREC | NS_CAPACITY;
 
 // The whole per-node computation: counts, and the node record for the
 // expansion pass.
-template <typename T>
-__device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
+template <typename T, typename CF>
+__device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
 {
+    constexpr int WL = CF::W;
     constexpr bool F32 = sizeof(T) == 4;
     constexpr int NP = NPieces<T>::n;
     const T tp = Cst<T>::two_pi;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (WL - 1);
     const Work &W = P.w;
     const int64_t N = P.in.n_nodes;
     const int k = P.k;
@@ -565,13 +453,13 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
         sh.rec = -1;
     }
     __syncthreads();
-    if (v == 0 || v > kVmax) {
+    if (v == 0 || v > CF::VM) {
         if (lane == 0) {
             for (int c = 0; c < kNodeCols; ++c) W.node_cnt[c * N + n] = 0;
             W.node_cnt[NC_STATUS * N + n] = v == 0 ? NS_ISOLATED : NS_VALENCE;
             W.node_rec[n] = -1;
         }
-        for (int i = lane; i < v; i += 64) W.he_len[row + i] = 0;
+        for (int i = lane; i < v; i += WL) W.he_len[row + i] = 0;
         return;
     }
 
@@ -580,44 +468,11 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
         int2 he = W.he[row + lane];
         int far = he.x;
         float4 f4 = W.node4[far];
-        const V3<T> cf = v3((T)f4.x, (T)f4.y, (T)f4.z);
-        SL<T> s;
+        bool bad;
+        SL<T> s = strut_entry(cen, rho, v3((T)f4.x, (T)f4.y, (T)f4.z), (T)f4.w, (int)((int64_t)far > n), bad);
         s.sid = he.y;
         s.far = far;
-        V3<T> d = cf - cen;
-        T L = m_sqrt(dot(d, d));
-        T sig = (rho - (T)f4.w) / L;
-        int bad = (far == n) || !(L > (T)0) || !(m_abs(sig) < (T)1);
-        if (bad) {
-            atomicOr(&sh.status, NS_INVALID_STRUT);
-            L = (T)1;
-            sig = (T)0;
-        }
-        T kap = m_sqrt(((T)1 - sig) * ((T)1 + sig));
-        V3<T> e = d * ((T)1 / L);
-        s.ex = e.x; s.ey = e.y; s.ez = e.z; s.sig = sig; s.kap = kap; s.len = L;
-        s.gx = e.x / kap; s.gy = e.y / kap; s.gz = e.z / kap;
-        s.h = rho * sig / kap;
-        // canonical strut frame from the lower to the higher node id; both
-        // ends compute it from the same two input positions
-        int lower = (int64_t)far > n;
-        s.lower = lower;
-        V3<T> clo = lower ? cen : cf;
-        V3<T> chi = lower ? cf : cen;
-        V3<T> es = chi - clo;
-        es = es * ((T)1 / m_sqrt(dot(es, es)));
-        s.sx = es.x; s.sy = es.y; s.sz = es.z;
-        T ax = m_abs(es.x), ay = m_abs(es.y), az = m_abs(es.z);
-        int j = 0;
-        T am = ax;
-        if (ay < am) { j = 1; am = ay; }
-        if (az < am) { j = 2; }
-        V3<T> axis = v3((T)(j == 0), (T)(j == 1), (T)(j == 2));
-        V3<T> rr = cross(es, axis);
-        rr = rr * ((T)1 / m_sqrt(dot(rr, rr)));
-        V3<T> qq = cross(es, rr);
-        s.rx = rr.x; s.ry = rr.y; s.rz = rr.z;
-        s.qx = qq.x; s.qy = qq.y; s.qz = qq.z;
+        if (bad || far == n) atomicOr(&sh.status, NS_INVALID_STRUT);
         sh.S[lane + 1] = s;
     }
     __syncthreads();
@@ -632,7 +487,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
     // ---- conics, trimming, arcs and owned vertices ------------------------
     {
         const int nconic = v * (v + 1) / 2;
-        for (int c0 = 0; c0 < nconic; c0 += 64) {
+        for (int c0 = 0; c0 < nconic; c0 += WL) {
             int ci = c0 + lane;
             int p = 0, q = 0;
             bool act = ci < nconic;
@@ -675,8 +530,8 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                 ord[i] = rank;
             }
             int cnt = act ? TR.n : 0, tot;
-            int base = wave_excl_scan(cnt, &tot) + sh.n_arc;
-            if (sh.n_arc + tot > kAcap) {
+            int base = group_excl_scan<WL>(cnt, &tot) + sh.n_arc;
+            if (sh.n_arc + tot > CF::AC) {
                 if (lane == 0) atomicOr(&sh.status, NS_CAPACITY);
             } else {
 #pragma unroll
@@ -734,8 +589,8 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                 }
             }
             int ntot;
-            int vbase = wave_excl_scan(own, &ntot) + sh.n_vert;
-            if (sh.n_vert + ntot > kVcap) {
+            int vbase = group_excl_scan<WL>(own, &ntot) + sh.n_vert;
+            if (sh.n_vert + ntot > CF::VC) {
                 if (lane == 0) atomicOr(&sh.status, NS_CAPACITY);
             } else {
 #pragma unroll
@@ -757,8 +612,8 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
             __syncthreads();
             // advance the running counts (tot / ntot are wave-uniform)
             if (lane == 0) {
-                if (sh.n_arc + tot <= kAcap) sh.n_arc += tot;
-                if (sh.n_vert + ntot <= kVcap) sh.n_vert += ntot;
+                if (sh.n_arc + tot <= CF::AC) sh.n_arc += tot;
+                if (sh.n_vert + ntot <= CF::VC) sh.n_vert += ntot;
             }
             __syncthreads();
         }
@@ -768,7 +623,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
     // ---- arc ends -> vertex indices, vertex degrees, segment counts -------
     {
         const int E = sh.n_arc, V = sh.n_vert;
-        for (int j = lane; j < E; j += 64) {
+        for (int j = lane; j < E; j += WL) {
             ArcL<T> &A = sh.A[j];
             A.vs = find_vert(sh, A.ns);
             A.ve = find_vert(sh, A.ne);
@@ -782,16 +637,16 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
             }
             A.contour = -1;
         }
-        for (int i = lane; i < V; i += 64) sh.vdeg[i] = 0;
+        for (int i = lane; i < V; i += WL) sh.vdeg[i] = 0;
         __syncthreads();
-        for (int j = lane; j < E; j += 64) {
+        for (int j = lane; j < E; j += WL) {
             const ArcL<T> &A = sh.A[j];
             if (A.full || A.vs < 0 || A.ve < 0) continue;
             atomicAdd(&sh.vdeg[A.vs], 1);
             atomicAdd(&sh.vdeg[A.ve], 1);
         }
         __syncthreads();
-        for (int i = lane; i < V; i += 64)
+        for (int i = lane; i < V; i += WL)
             if ((sh.vname[i] & 0xff00u) != 0xff00u && sh.vdeg[i] != 3) atomicOr(&sh.status, NS_TOPOLOGY);
         __syncthreads();
         if (sh.status) goto finish;
@@ -811,7 +666,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
             sh.loop_full[lane] = 0;
         }
         __syncthreads();
-        for (int j = lane; j < E; j += 64) {
+        for (int j = lane; j < E; j += WL) {
             const ArcL<T> &A = sh.A[j];
             if (A.p) atomicAdd(&sh.loop_cnt[A.p], 1);
             atomicAdd(&sh.loop_cnt[A.q], 1);
@@ -819,14 +674,14 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
         __syncthreads();
         {
             int c = (lane >= 1 && lane <= v) ? sh.loop_cnt[lane] : 0, tot;
-            int base = wave_excl_scan(c, &tot);
+            int base = group_excl_scan<WL>(c, &tot);
             if (lane >= 1 && lane <= v) sh.loop_base[lane] = base;
             if (lane == 0) sh.loop_base[v + 1] = tot;
         }
         __syncthreads();
         if (lane <= v) sh.loop_cnt[lane] = 0;  // reused as fill cursor
         __syncthreads();
-        for (int j = lane; j < E; j += 64) {
+        for (int j = lane; j < E; j += WL) {
             const ArcL<T> &A = sh.A[j];
             T tm = (T)0.5 * (A.t1 + A.t2);
             T st, ct;
@@ -861,7 +716,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
             while (sh.loop_base[m + 1] <= pp) ++m;
             return m;
         };
-        for (int pp = lane; pp < tot; pp += 64) {
+        for (int pp = lane; pp < tot; pp += WL) {
             const int m = strut_of(pp);
             const int b0 = sh.loop_base[m], b1 = sh.loop_base[m + 1];
             const uint32_t en = ename(pp), sn = sname(pp);
@@ -884,7 +739,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
         if (sh.status) goto finish;
         // position of each arc in its loop; the first arc also checks that
         // the successor chain closes after exactly the loop's arc count
-        for (int pp = lane; pp < tot; pp += 64) {
+        for (int pp = lane; pp < tot; pp += WL) {
             const int m = strut_of(pp);
             const int b0 = sh.loop_base[m], c = sh.loop_base[m + 1] - b0;
             int cur = sh.loop_first[m], t = 0;
@@ -906,7 +761,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                 if (steps != c) atomicOr(&sh.status, NS_LOOP);
             }
         }
-        if (tot > 2 * kAcap && lane == 0) atomicOr(&sh.status, NS_CAPACITY);
+        if (tot > 2 * CF::AC && lane == 0) atomicOr(&sh.status, NS_CAPACITY);
         __syncthreads();
         if (sh.status) goto finish;
     }
@@ -916,7 +771,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
         const int E = sh.n_arc;
         int ncirc = 0;
         while (ncirc < E && sh.A[ncirc].p == 0) ++ncirc;  // circular arcs sort first
-        for (int i = lane; i < ncirc; i += 64) {
+        for (int i = lane; i < ncirc; i += WL) {
             const ArcL<T> &A = sh.A[i];
             uint32_t lab = A.ns < A.ne ? A.ns : A.ne;
             if (!A.full) {
@@ -940,7 +795,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
             sh.clabel[i] = lab;
         }
         __syncthreads();
-        for (int i = lane; i < ncirc; i += 64) {
+        for (int i = lane; i < ncirc; i += WL) {
             uint32_t lab = sh.clabel[i];
             int rank = 0;
             for (int j = 0; j < ncirc; ++j) {
@@ -987,7 +842,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
         // nodal sphere; the point opposite is used when the projection falls
         // under a strut, and -sum(e_m) when the barycentre is within 1e-3 rho
         // of the centre.
-        for (int c = lane; c < NC; c += 64) {
+        for (int c = lane; c < NC; c += WL) {
             V3<T> sum = zero3<T>();
             int cntv = 0;
             for (int j = 0; j < E && sh.A[j].p == 0; ++j) {
@@ -1084,7 +939,7 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
             // step that closes a loop is checked afterwards.  A valid loop
             // has exactly one descent, just before its smallest phi.
             T carry = (T)0;
-            for (int base = 0; base < ns_tot; base += 64) {
+            for (int base = 0; base < ns_tot; base += WL) {
                 const int sidx = base + lane;
                 const bool act = sidx < ns_tot;
                 int m = 1, idx = 0, nloop = 1, li = 0;
@@ -1102,9 +957,9 @@ __device__ void node_body(const Params &P, Shared<T> &sh, const int64_t n)
                     nloop = sh.loop_len[m];
                     ph = sample(e, sidx - sh.entry_off[e], li);
                 }
-                T prev = __shfl_up(ph, 1, 64);
+                T prev = __shfl_up(ph, 1, WL);
                 if (lane == 0) prev = carry;
-                carry = __shfl(ph, 63, 64);
+                carry = __shfl(ph, WL - 1, WL);
                 if (act) {
                     if (idx == 0) {
                         sh.ph_first[m] = ph;
@@ -1189,14 +1044,14 @@ finish:
             R[7] = 0u;
         }
         uint32_t *RV = R + kRecHead;
-        for (int i = lane; i < V; i += 64) {
+        for (int i = lane; i < V; i += WL) {
             RV[i] = sh.vname[i];
             RV[V + i] = __float_as_uint((float)sh.vx[i]);
             RV[2 * V + i] = __float_as_uint((float)sh.vy[i]);
             RV[3 * V + i] = __float_as_uint((float)sh.vz[i]);
         }
         uint32_t *RA = RV + 4 * V;
-        for (int j = lane; j < E; j += 64) {
+        for (int j = lane; j < E; j += WL) {
             const ArcL<T> &A = sh.A[j];
             const T f[11] = {A.o[0], A.o[1], A.o[2], A.a[0], A.a[1], A.a[2], A.b[0], A.b[1], A.b[2], A.t1, A.t2};
 #pragma unroll
@@ -1211,7 +1066,7 @@ finish:
             RA[15 * E + j] = (uint32_t)A.fbase;
         }
         uint32_t *RH = RA + kRecArcFields * E;
-        for (int c = lane; c < NC; c += 64) {
+        for (int c = lane; c < NC; c += WL) {
             RH[c] = __float_as_uint((float)sh.hc[c][0]);
             RH[NC + c] = __float_as_uint((float)sh.hc[c][1]);
             RH[2 * NC + c] = __float_as_uint((float)sh.hc[c][2]);
@@ -1219,27 +1074,43 @@ finish:
     }
 }
 
-// FP32: one node per block
-__global__ void __launch_bounds__(64) k_node32(Params P)
+// FP32, one valence class: a persistent grid takes items of 64 / W queued
+// nodes from a work counter; every wave leaves once the counter has passed
+// the class's last item.
+template <typename C>
+__global__ void __launch_bounds__(64) k_node32(Params P, int cls)
 {
-    __shared__ Shared<float> sh;
-    const int64_t n = blockIdx.x;
-    if (n >= P.in.n_nodes) return;
-    node_body<float>(P, sh, n);
+    constexpr int NPW = 64 / C::W;
+    __shared__ Shared<float, C> sh[NPW];
+    __shared__ int s_item;
+    const int slot = threadIdx.x / C::W;
+    const int64_t cnt = P.w.cls_info[cls], base = P.w.cls_info[4 + cls];
+    const int64_t items = (cnt + NPW - 1) / NPW;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&P.w.work_ctr[cls], 1);
+        __syncthreads();
+        const int64_t item = s_item;
+        __syncthreads();
+        if (item >= items) break;
+        const int64_t qi = item * NPW + slot;
+        if (qi < cnt) node_body<float, C>(P, sh[slot], (int64_t)P.w.queue[base + qi]);
+        __syncthreads();
+    }
 }
 
 // FP64: the nodes the FP32 pass handed over, looped over by a fixed grid
 __global__ void __launch_bounds__(64) k_node64(Params P)
 {
-    __shared__ Shared<double> sh;
+    __shared__ Shared<double, CfgV16> sh;
     const int cnt = P.w.flags[2];
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
-        node_body<double>(P, sh, (int64_t)P.w.fb_list[i]);
+        node_body<double, CfgV16>(P, sh, (int64_t)P.w.fb_list[i]);
         __syncthreads();
     }
 }
 
 constexpr unsigned kFp64Grid = 2048;
+constexpr int64_t kNodeGrid = 256 * 32;  // waves per class launch
 
 }  // namespace
 
@@ -1251,8 +1122,18 @@ hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, 
     P.w = w;
     P.k = k;
     P.kappa_max = kappa_max;
-    if (!fp64) k_node32<<<(unsigned)in.n_nodes, 64, 0, st>>>(P);
-    else k_node64<<<kFp64Grid, 64, 0, st>>>(P);
+    if (fp64) {
+        k_node64<<<kFp64Grid, 64, 0, st>>>(P);
+        return hipGetLastError();
+    }
+    // persistent grids: enough waves to fill the chip, never more than items
+    auto grid = [&](int npw) {
+        int64_t items = (in.n_nodes + npw - 1) / npw;
+        return (unsigned)(items < kNodeGrid ? items : kNodeGrid);
+    };
+    k_node32<CfgV4><<<grid(4), 64, 0, st>>>(P, 0);
+    k_node32<CfgV8><<<grid(2), 64, 0, st>>>(P, 1);
+    k_node32<CfgV16><<<grid(1), 64, 0, st>>>(P, 2);
     return hipGetLastError();
 }
 

@@ -176,6 +176,41 @@ __global__ void __launch_bounds__(kBlock) k_scan_tiles(const int32_t *src, int64
     }
 }
 
+// Valence buckets: one 0/1 column per class, scanned, then node ids are
+// placed class by class (in node order within a class).
+__global__ void k_class_flags(int64_t N, const int64_t *row, int32_t *flags)
+{
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int c = valence_class(row[n + 1] - row[n]);
+#pragma unroll
+    for (int k = 0; k < kClasses; ++k) flags[k * N + n] = k == c;
+}
+
+__global__ void k_class_scatter(int64_t N, const int64_t *row, const int64_t *off, int32_t *queue,
+                                int64_t *cls_info)
+{
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t Np1 = N + 1;
+    int64_t base[kClasses];
+    int64_t b = 0;
+#pragma unroll
+    for (int k = 0; k < kClasses; ++k) {
+        base[k] = b;
+        b += off[k * Np1 + N];
+    }
+    if (n == 0) {
+#pragma unroll
+        for (int k = 0; k < kClasses; ++k) {
+            cls_info[k] = off[k * Np1 + N];
+            cls_info[4 + k] = base[k];
+        }
+    }
+    if (n >= N) return;
+    const int c = valence_class(row[n + 1] - row[n]);
+    queue[base[c] + off[c * Np1 + n]] = (int32_t)n;
+}
+
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 }  // namespace
@@ -205,6 +240,13 @@ hipError_t launch_prepare(const Inputs &in, const Work &w, hipStream_t st)
     if (N > 0) k_zero<<<grid_for(N, kBlock), kBlock, 0, st>>>(w.deg, N);
     if (S > 0) k_scatter<<<grid_for(S, kBlock), kBlock, 0, st>>>(in, w.row, w.deg, w.he);
     if (N > 0) k_sort_rows<<<grid_for(N, kBlock), kBlock, 0, st>>>(N, w.row, w.he, w.strut_he, in.sa, in.sb);
+    // valence buckets (the count columns and offsets are free until the node pass)
+    if (N > 0) {
+        k_class_flags<<<grid_for(N, kBlock), kBlock, 0, st>>>(N, w.row, w.node_cnt);
+        e = launch_scan(w.node_cnt, w.node_off, N, kClasses, N, N + 1, w.scan_tmp, w.scan_tmp_len, st);
+        if (e != hipSuccess) return e;
+        k_class_scatter<<<grid_for(N, kBlock), kBlock, 0, st>>>(N, w.row, w.node_off, w.queue, w.cls_info);
+    }
     return hipGetLastError();
 }
 

@@ -1,0 +1,411 @@
+// Sink mode: the lattice is meshed in chunks of node ids and the triangles
+// are reduced to per-chunk counts and order-independent hashes instead of
+// being stored (for lattices whose mesh does not fit in memory).
+//
+// A chunk is a node-id range [n0, n1).  Its node list is the range plus the
+// halo: every neighbour with a higher id outside the range (the band of a
+// strut is emitted by the chunk of its lower end, which needs the other
+// end's loop).  Mesh vertices are named (node, node-local index), so the
+// hashes do not depend on the chunking or on any global numbering:
+//   vertex id   vid = node << 21 | local;
+//   triangle    key = mix(mix(mix(v0 + G) ^ v1) ^ v2) with (v0, v1, v2) the
+//               triangle's vids rotated so that the smallest comes first
+//               (orientation kept), mix the SplitMix64 finaliser, G its
+//               increment 0x9E3779B97F4A7C15;
+//   vertex      key = mix(mix(mix(vid) ^ (bits(x) | bits(y) << 32)) ^ bits(z))
+//               over the FP32 absolute position.
+// Per chunk (LM_SINK_WORDS 64-bit words): triangles, sum of triangle keys,
+// mesh vertices, sum of vertex keys, sums of round(x 2^20), round(y 2^20),
+// round(z 2^20) (two's complement), nodes of the range without a mesh.
+#include "common.h"
+
+namespace lm {
+namespace {
+
+constexpr int kSlots = 64;  // spread of the hash atomics
+constexpr int kWords = 8;
+
+__device__ inline uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ inline uint64_t vid_of(int64_t node, int local) { return ((uint64_t)node << 21) | (uint64_t)local; }
+
+__device__ inline uint64_t tri_key(uint64_t a, uint64_t b, uint64_t c)
+{
+    // rotate the smallest id first, keeping the cyclic order
+    if (b < a && b < c) {
+        const uint64_t t = a; a = b; b = c; c = t;
+    } else if (c < a && c < b) {
+        const uint64_t t = c; c = b; b = a; a = t;
+    }
+    return mix64(mix64(mix64(a + 0x9E3779B97F4A7C15ull) ^ b) ^ c);
+}
+
+__device__ inline uint64_t vert_key(uint64_t vid, float x, float y, float z)
+{
+    const uint64_t xy = (uint64_t)__float_as_uint(x) | ((uint64_t)__float_as_uint(y) << 32);
+    return mix64(mix64(mix64(vid) ^ xy) ^ (uint64_t)__float_as_uint(z));
+}
+
+__device__ inline uint64_t wave_sum_u64(uint64_t x)
+{
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Wave-aggregated append of `value` to list `k` (when active): one atomic
+// per list and wave.  All lanes of the wave must call it.
+__device__ inline void append(bool active, int k, int32_t value, int32_t *lists, int64_t cap, int32_t *cnt)
+{
+    const int lane = threadIdx.x & 63;
+    for (int c = 0; c < kClasses; ++c) {
+        const unsigned long long m = __ballot(active && k == c);
+        if (m == 0) continue;
+        const int leader = __ffsll((long long)m) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&cnt[c], __popcll(m));
+        base = __shfl(base, leader, 64);
+        if (active && k == c) lists[c * cap + base + __popcll(m & ((1ull << lane) - 1ull))] = value;
+    }
+}
+
+// Chunk node list in valence classes: the range, then the halo (marked
+// with the chunk's epoch so that each halo node is listed once).
+__global__ void __launch_bounds__(256) k_chunk_list(int64_t n0, int64_t n1, const int64_t *row, const int2 *he,
+                                                    int32_t *mark, int32_t epoch, int32_t *lists, int64_t cap,
+                                                    int32_t *cnt)
+{
+    const int64_t n = n0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = n < n1;
+    int64_t r0 = 0, r1 = 0;
+    if (in) {
+        r0 = row[n];
+        r1 = row[n + 1];
+    }
+    append(in, valence_class(r1 - r0), (int32_t)n, lists, cap, cnt);
+    int deg = (int)(r1 - r0);
+    int maxdeg = deg;
+    for (int o = 32; o > 0; o >>= 1) maxdeg = max(maxdeg, __shfl_xor(maxdeg, o, 64));
+    for (int i = 0; i < maxdeg; ++i) {
+        bool add = false;
+        int32_t far = 0;
+        int k = 0;
+        if (i < deg) {
+            far = he[r0 + i].x;
+            if ((int64_t)far > n && (int64_t)far >= n1) {
+                add = atomicExch(&mark[far], epoch) != epoch;
+                if (add) k = valence_class(row[far + 1] - row[far]);
+            }
+        }
+        append(add, k, far, lists, cap, cnt);
+    }
+}
+
+__global__ void k_chunk_info(const int32_t *cnt, int64_t cap, int64_t *info)
+{
+    if (threadIdx.x < kClasses) {
+        info[threadIdx.x] = cnt[threadIdx.x];
+        info[4 + threadIdx.x] = (int64_t)threadIdx.x * cap;
+    }
+}
+
+struct SinkParams {
+    Work w;
+    int64_t N, n0, n1;
+    unsigned long long *slots;  // [kSlots][kWords]
+};
+
+__device__ inline void add_slot(unsigned long long *slots, int word, uint64_t v)
+{
+    atomicAdd(&slots[(blockIdx.x & (kSlots - 1)) * kWords + word], (unsigned long long)v);
+}
+
+// Mesh vertices and hole fans of the range's nodes, from their records.
+__global__ void __launch_bounds__(64) k_sink_nodes(SinkParams P)
+{
+    const Work &W = P.w;
+    const int64_t n = P.n0 + blockIdx.x;
+    const int lane = threadIdx.x;
+    if (n >= P.n1) return;
+    const int64_t rb = W.node_rec[n];
+    if (rb < 0) {
+        if (lane == 0) add_slot(P.slots, 7, 1);
+        return;
+    }
+    const uint32_t *R = W.rec + rb;
+    const int V = (int)R[0], E = (int)R[1], NC = (int)R[2], ncirc = (int)R[3];
+    const int wsum = (int)R[4], M = (int)R[5], F = (int)R[6];
+    const uint32_t *RV = R + kRecHead;
+    const uint32_t *RA = RV + 4 * V;
+    const uint32_t *RH = RA + kRecArcFields * E;
+    const float4 c4 = W.node4[n];
+    auto af = [&](int f, int j) { return __uint_as_float(RA[f * E + j]); };
+    uint64_t hv = 0, sx = 0, sy = 0, sz = 0, ht = 0;
+    for (int i = lane; i < M; i += 64) {
+        float w0, w1, w2;
+        if (i < V) {
+            w0 = __uint_as_float(RV[V + i]);
+            w1 = __uint_as_float(RV[2 * V + i]);
+            w2 = __uint_as_float(RV[3 * V + i]);
+        } else if (i < wsum) {
+            int lo = 0, hi = E - 1;  // last arc with mbase <= i
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if ((int)RA[14 * E + mid] <= i) lo = mid;
+                else hi = mid - 1;
+            }
+            const int nseg = (int)(RA[13 * E + lo] & 0xffffu);
+            const bool fwd = (RA[11 * E + lo] >> 17) & 1u;
+            const int jc = i - (int)RA[14 * E + lo];
+            const int ii = fwd ? jc + 1 : nseg - 1 - jc;
+            const float t1 = af(9, lo), t2 = af(10, lo);
+            const float t = t1 + (t2 - t1) * (float)ii / (float)nseg;
+            float s, c;
+            sincosf(t, &s, &c);
+            w0 = af(0, lo) + af(3, lo) * s + af(6, lo) * c;
+            w1 = af(1, lo) + af(4, lo) * s + af(7, lo) * c;
+            w2 = af(2, lo) + af(5, lo) * s + af(8, lo) * c;
+        } else {
+            const int c = i - wsum;
+            w0 = __uint_as_float(RH[c]);
+            w1 = __uint_as_float(RH[NC + c]);
+            w2 = __uint_as_float(RH[2 * NC + c]);
+        }
+        const float x = c4.x + w0, y = c4.y + w1, z = c4.z + w2;
+        hv += vert_key(vid_of(n, i), x, y, z);
+        sx += (uint64_t)llrint((double)x * 1048576.0);
+        sy += (uint64_t)llrint((double)y * 1048576.0);
+        sz += (uint64_t)llrint((double)z * 1048576.0);
+    }
+    for (int i = lane; i < F; i += 64) {
+        int lo = 0, hi = ncirc - 1;  // last circular arc with fbase <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if ((int)RA[15 * E + mid] <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const int j = lo;
+        const uint32_t u0 = RA[11 * E + j], u1 = RA[12 * E + j], u2 = RA[13 * E + j];
+        const bool fwd = (u0 >> 17) & 1u, lower = (u0 >> 18) & 1u;
+        const int nseg = (int)(u2 & 0xffffu), contour = (int)(u2 >> 16);
+        const int vs = (int)(u1 & 0xffffu), ve = (int)(u1 >> 16);
+        const int mbase = (int)RA[14 * E + j];
+        const int s = i - (int)RA[15 * E + j];
+        const int i0 = fwd ? s : nseg - s, i1 = fwd ? s + 1 : nseg - s - 1;
+        const int lo_i = i0 < i1 ? i0 : i1, hi_i = i0 < i1 ? i1 : i0;
+        const int u = lo_i == 0 ? vs : mbase + (fwd ? lo_i - 1 : nseg - 1 - lo_i);
+        const int u2i = hi_i == nseg ? ve : mbase + (fwd ? hi_i - 1 : nseg - 1 - hi_i);
+        ht += tri_key(vid_of(n, wsum + contour), vid_of(n, lower ? u2i : u), vid_of(n, lower ? u : u2i));
+    }
+    hv = wave_sum_u64(hv);
+    sx = wave_sum_u64(sx);
+    sy = wave_sum_u64(sy);
+    sz = wave_sum_u64(sz);
+    ht = wave_sum_u64(ht);
+    if (lane == 0) {
+        add_slot(P.slots, 0, (uint64_t)F);
+        add_slot(P.slots, 1, ht);
+        add_slot(P.slots, 2, (uint64_t)M);
+        add_slot(P.slots, 3, hv);
+        add_slot(P.slots, 4, sx);
+        add_slot(P.slots, 5, sy);
+        add_slot(P.slots, 6, sz);
+    }
+}
+
+// Struts whose lower end is in the range and whose ends both have a mesh.
+__global__ void __launch_bounds__(256) k_chunk_struts(int64_t n0, int64_t n1, const int64_t *row, const int2 *he,
+                                                      const int64_t *node_rec, int32_t *list, int32_t *cnt)
+{
+    const int64_t n = n0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = n < n1;
+    int64_t r0 = 0, r1 = 0;
+    bool ok = false;
+    if (in) {
+        r0 = row[n];
+        r1 = row[n + 1];
+        ok = node_rec[n] >= 0;
+    }
+    int deg = (int)(r1 - r0);
+    int maxdeg = deg;
+    for (int o = 32; o > 0; o >>= 1) maxdeg = max(maxdeg, __shfl_xor(maxdeg, o, 64));
+    for (int i = 0; i < maxdeg; ++i) {
+        bool add = false;
+        int32_t s = 0;
+        if (i < deg && ok) {
+            const int2 h = he[r0 + i];
+            add = (int64_t)h.x > n && node_rec[h.x] >= 0;
+            s = h.y;
+        }
+        append(add, 0, s, list, 0, cnt);
+    }
+}
+
+// Bands of the listed struts (one wave per 8), hashed.
+constexpr int kZipGroup = 8;
+constexpr int kZipStage = 768;
+
+__global__ void __launch_bounds__(64) k_sink_zip(SinkParams P, const int32_t *list, const int32_t *cnt,
+                                                 const int32_t *sa, const int32_t *sb)
+{
+    __shared__ int2 st[kZipStage];
+    __shared__ int g_na[kZipGroup], g_nb[kZipGroup], g_ra[kZipGroup], g_rb[kZipGroup];
+    __shared__ int64_t g_la[kZipGroup], g_lb[kZipGroup], g_a[kZipGroup], g_b[kZipGroup];
+    __shared__ int g_t[kZipGroup + 1];
+    const Work &W = P.w;
+    const int lane = threadIdx.x;
+    const int64_t ns_all = *cnt;
+    const int64_t g0 = (int64_t)blockIdx.x * kZipGroup;
+    if (g0 >= ns_all) return;
+    const int ns = ns_all - g0 < kZipGroup ? (int)(ns_all - g0) : kZipGroup;
+    int c = 0;
+    if (lane < ns) {
+        const int64_t s = list[g0 + lane];
+        const int64_t ha = W.strut_he[2 * s], hb = W.strut_he[2 * s + 1];
+        g_na[lane] = W.he_len[ha];
+        g_nb[lane] = W.he_len[hb];
+        g_la[lane] = W.he_loop[ha];
+        g_lb[lane] = W.he_loop[hb];
+        g_ra[lane] = W.he_rot[ha];
+        g_rb[lane] = W.he_rot[hb];
+        const int32_t a = sa[s], b = sb[s];
+        g_a[lane] = a < b ? a : b;
+        g_b[lane] = a < b ? b : a;
+        c = g_na[lane] + g_nb[lane];
+    }
+    int ct = c;
+#pragma unroll
+    for (int d = 1; d < kZipGroup; d <<= 1) {
+        const int y = __shfl_up(ct, d, 64);
+        if (lane >= d) ct += y;
+    }
+    if (lane < ns) g_t[lane + 1] = ct;
+    if (lane == 0) g_t[0] = 0;
+    __syncthreads();
+    const int ntri = g_t[ns];
+    const bool staged = ntri <= kZipStage;
+    const int2 *loops = (const int2 *)W.rec;
+    if (staged) {
+        for (int x = lane; x < ntri; x += 64) {
+            int i = 0;
+            while (g_t[i + 1] <= x) ++i;
+            int k = x - g_t[i];
+            int64_t base;
+            int n, r;
+            if (k < g_na[i]) {
+                base = g_la[i]; n = g_na[i]; r = g_ra[i];
+            } else {
+                k -= g_na[i]; base = g_lb[i]; n = g_nb[i]; r = g_rb[i];
+            }
+            int idx = r + k;
+            if (idx >= n) idx -= n;
+            st[x] = loops[base + idx];
+        }
+        __syncthreads();
+    }
+    uint64_t ht = 0;
+    for (int x = lane; x < ntri; x += 64) {
+        int i = 0;
+        while (g_t[i + 1] <= x) ++i;
+        const int j = x - g_t[i];
+        const int na = g_na[i], nb = g_nb[i], ra = g_ra[i], rb = g_rb[i];
+        // sorted-order views of both loops (LDS when staged)
+        auto A = [&](int k) -> int2 {
+            if (staged) return st[g_t[i] + k];
+            int q = ra + k;
+            return loops[g_la[i] + (q >= na ? q - na : q)];
+        };
+        auto B = [&](int k) -> int2 {
+            if (staged) return st[g_t[i] + na + k];
+            int q = rb + k;
+            return loops[g_lb[i] + (q >= nb ? q - nb : q)];
+        };
+        auto pred = [&](bool onB, float xv, bool inclusive) {
+            const int n = onB ? nb : na;
+            int lo = 0, hi = n;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                const float p = __int_as_float((onB ? B(mid) : A(mid)).y);
+                if (inclusive ? (p <= xv) : (p < xv)) lo = mid + 1;
+                else hi = mid;
+            }
+            return lo == 0 ? n - 1 : lo - 1;
+        };
+        const int64_t na_node = g_a[i], nb_node = g_b[i];
+        if (j < na) {
+            int k0 = j - ra;
+            if (k0 < 0) k0 += na;
+            const int k1 = k0 + 1 == na ? 0 : k0 + 1;
+            const int2 u = A(k0), u2 = A(k1);
+            const int ap = pred(true, __int_as_float(u2.y), false);
+            ht += tri_key(vid_of(na_node, u.x), vid_of(na_node, u2.x), vid_of(nb_node, B(ap).x));
+        } else {
+            int k0 = j - na - rb;
+            if (k0 < 0) k0 += nb;
+            const int k1 = k0 + 1 == nb ? 0 : k0 + 1;
+            const int2 w = B(k0), w2 = B(k1);
+            const int ap = pred(false, __int_as_float(w2.y), true);
+            ht += tri_key(vid_of(nb_node, w2.x), vid_of(nb_node, w.x), vid_of(na_node, A(ap).x));
+        }
+    }
+    ht = wave_sum_u64(ht);
+    if (lane == 0) {
+        add_slot(P.slots, 0, (uint64_t)ntri);
+        add_slot(P.slots, 1, ht);
+    }
+}
+
+// slots -> the chunk's output words; clears the slots
+__global__ void k_sink_reduce(unsigned long long *slots, uint64_t *out)
+{
+    const int w = threadIdx.x;
+    if (w >= kWords) return;
+    uint64_t s = 0;
+    for (int i = 0; i < kSlots; ++i) {
+        s += slots[i * kWords + w];
+        slots[i * kWords + w] = 0;
+    }
+    out[w] = s;
+}
+
+inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+int64_t sink_slots_words() { return (int64_t)kSlots * kWords; }
+
+hipError_t launch_chunk_list(const Work &w, int64_t n0, int64_t n1, int32_t *mark, int32_t epoch, int32_t *lists,
+                             int64_t cap, int32_t *cnt, int64_t *info, hipStream_t st)
+{
+    if (n1 > n0) k_chunk_list<<<grid_for(n1 - n0, 256), 256, 0, st>>>(n0, n1, w.row, w.he, mark, epoch, lists, cap, cnt);
+    k_chunk_info<<<1, 64, 0, st>>>(cnt, cap, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_sink(const Inputs &in, const Work &w, int64_t n0, int64_t n1, int64_t max_struts,
+                       int32_t *strut_list, int32_t *strut_cnt, unsigned long long *slots, uint64_t *out,
+                       hipStream_t st)
+{
+    SinkParams P;
+    P.w = w;
+    P.N = in.n_nodes;
+    P.n0 = n0;
+    P.n1 = n1;
+    P.slots = slots;
+    if (n1 > n0) {
+        k_sink_nodes<<<(unsigned)(n1 - n0), 64, 0, st>>>(P);
+        k_chunk_struts<<<grid_for(n1 - n0, 256), 256, 0, st>>>(n0, n1, w.row, w.he, w.node_rec, strut_list,
+                                                                 strut_cnt);
+        // grid for the most struts the range can own (its half-edges)
+        if (max_struts > 0)
+            k_sink_zip<<<grid_for(max_struts, kZipGroup), 64, 0, st>>>(P, strut_list, strut_cnt, in.sa, in.sb);
+    }
+    k_sink_reduce<<<1, 64, 0, st>>>(slots, out);
+    return hipGetLastError();
+}
+
+}  // namespace lm

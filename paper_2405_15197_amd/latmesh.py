@@ -43,6 +43,9 @@ EXPORTS = (
     "lm_set_precision",
     "lm_set_profiling",
     "lm_get_profile",
+    "lm_forward_sink",
+    "lm_loss",
+    "lm_backward",
     "lm_plan_destroy",
     "lm_status_string",
 )
@@ -101,6 +104,15 @@ class lm_outputs(ctypes.Structure):
     ]
 
 
+class lm_loss_weights(ctypes.Structure):
+    _fields_ = [
+        ("area", ctypes.c_float),
+        ("volume", ctypes.c_float),
+        ("sq_norm", ctypes.c_float),
+        ("p0", ctypes.c_float * 3),
+    ]
+
+
 class LatmeshError(RuntimeError):
     def __init__(self, code: int, where: str):
         super().__init__(f"{where}: {lm_status_string(code)} ({code})")
@@ -137,6 +149,12 @@ def load() -> ctypes.CDLL:
     lib.lm_get_profile.restype = ctypes.c_int
     lib.lm_set_precision.argtypes = [P, ctypes.c_float]
     lib.lm_set_precision.restype = ctypes.c_int
+    lib.lm_forward_sink.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, ctypes.c_int64]
+    lib.lm_forward_sink.restype = ctypes.c_int
+    lib.lm_loss.argtypes = [P, ctypes.POINTER(lm_outputs), ctypes.POINTER(lm_loss_weights), P, P]
+    lib.lm_loss.restype = ctypes.c_int
+    lib.lm_backward.argtypes = [P, P, P, P]
+    lib.lm_backward.restype = ctypes.c_int
     lib.lm_plan_destroy.argtypes = [P]
     lib.lm_plan_destroy.restype = None
     lib.lm_status_string.argtypes = [ctypes.c_int]
@@ -188,7 +206,30 @@ def lm_read_totals(plan) -> lm_totals:
     return t
 
 
-PHASES = ("prepare", "node_fp32", "node_fp64", "sizes", "expand", "bands")
+PHASES = ("prepare", "node_fp32", "node_fp64", "sizes", "expand", "bands", "loss", "backward")
+
+
+def lm_loss(plan, out: lm_outputs, w: lm_loss_weights, d_terms: int, d_dl_dx: int) -> None:
+    rc = load().lm_loss(plan, ctypes.byref(out), ctypes.byref(w), ctypes.c_void_p(d_terms), ctypes.c_void_p(d_dl_dx))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_loss")
+
+
+LM_SINK_WORDS = 8
+SINK_FIELDS = ("triangles", "tri_hash", "mesh_vertices", "vert_hash", "sum_x", "sum_y", "sum_z", "bad_nodes")
+
+
+def lm_forward_sink(plan, k: int, chunk_nodes: int, d_out: int, n_chunks_cap: int) -> None:
+    rc = load().lm_forward_sink(plan, int(k), int(chunk_nodes), ctypes.c_void_p(d_out), int(n_chunks_cap))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_forward_sink")
+
+
+def lm_backward(plan, d_dl_dx: int, d_grad_xyz: int, d_grad_radius: int) -> None:
+    rc = load().lm_backward(plan, ctypes.c_void_p(d_dl_dx), ctypes.c_void_p(d_grad_xyz),
+                            ctypes.c_void_p(d_grad_radius))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_backward")
 
 
 def lm_prepare(plan) -> None:
@@ -345,6 +386,47 @@ class Mesher:
     def forward(self, k: int, r: MeshResult) -> None:
         lm_forward(self.plan, k, self.outputs(r))
 
+    def loss(self, r: MeshResult, weights=(1.0, 0.0, 0.0), p0=(0.0, 0.0, 0.0)):
+        """Loss terms (area, volume about p0, sum |v|^2) of the mesh in ``r``
+        and dL/dx of the weighted loss; returns (terms float64 [3], dl_dx
+        float32 [M, 3]) as device tensors."""
+        torch = self.torch
+        terms = torch.zeros(3, dtype=torch.float64, device=self.device)
+        dl = torch.empty((r.mesh_xyz.shape[0], 3), dtype=torch.float32, device=self.device)
+        w = lm_loss_weights(float(weights[0]), float(weights[1]), float(weights[2]),
+                            (ctypes.c_float * 3)(*[float(x) for x in p0]))
+        lm_loss(self.plan, self.outputs(r), w, terms.data_ptr(), dl.data_ptr())
+        return terms, dl
+
+    def backward(self, dl_dx):
+        """Gradient with respect to node centres [N, 3] and radii [N] of a
+        loss whose gradient with respect to the last mesh is ``dl_dx``."""
+        torch = self.torch
+        dl_dx = dl_dx.contiguous()
+        gx = torch.empty((self.n_nodes, 3), dtype=torch.float32, device=self.device)
+        gr = torch.empty(self.n_nodes, dtype=torch.float32, device=self.device)
+        lm_backward(self.plan, dl_dx.data_ptr(), gx.data_ptr(), gr.data_ptr())
+        return gx, gr
+
+    def sink(self, k: int, chunk_nodes: int):
+        """Chunked meshing reduced to per-chunk counts and hashes; returns a
+        uint64 numpy array [chunks, LM_SINK_WORDS] (see SINK_FIELDS)."""
+        torch = self.torch
+        nch = max((self.n_nodes + chunk_nodes - 1) // chunk_nodes, 1)
+        out = torch.zeros((nch, LM_SINK_WORDS), dtype=torch.int64, device=self.device)
+        lm_forward_sink(self.plan, k, chunk_nodes, out.data_ptr(), nch)
+        self.torch.cuda.synchronize(self.device)
+        return out.cpu().numpy().view(np.uint64)
+
+    def set_inputs(self, xyz, radius) -> None:
+        """Copy new node centres [N, 3] and radii [N] (device tensors) into the
+        plan's lattice and redo its preparation (same struts)."""
+        self.x.copy_(xyz[:, 0])
+        self.y.copy_(xyz[:, 1])
+        self.z.copy_(xyz[:, 2])
+        self.r.copy_(radius)
+        lm_prepare(self.plan)
+
     def close(self):
         if getattr(self, "plan", None) is not None:
             lm_plan_destroy(self.plan)
@@ -355,3 +437,27 @@ class Mesher:
             self.close()
         except Exception:
             pass
+
+
+def mesh_function():
+    """torch.autograd.Function: (xyz [N, 3], radius [N]) -> mesh vertices
+    [M, 3] of ``mesher`` at resolution k; its backward is lm_backward (the
+    adjoint at the forward pass's topology).  Usage:
+    ``verts = mesh_function().apply(xyz, radius, mesher, k, result)`` with
+    ``result`` a MeshResult sized by an earlier ``mesher.count(k)``."""
+    import torch
+
+    class MeshFn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, xyz, radius, mesher, k, result):
+            mesher.set_inputs(xyz.detach(), radius.detach())
+            mesher.forward(k, result)
+            ctx.mesher = mesher
+            return result.mesh_xyz.clone()
+
+        @staticmethod
+        def backward(ctx, grad_verts):
+            gx, gr = ctx.mesher.backward(grad_verts)
+            return gx, gr, None, None, None
+
+    return MeshFn
