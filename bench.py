@@ -152,6 +152,51 @@ def adjoint_bench(steps: int, warmup: int, k: int = 16):
     }
 
 
+def billion_bench(k: int = 12, chunk_nodes: int = 1 << 23, scale: int = 512):
+    """The BCC 512^3 lattice (269,223,425 nodes, 1,073,741,824 struts; radii
+    0.08 (1 + U[-0.1, 0.1]), no jitter), generated on the device, meshed in
+    sink mode: per chunk of node ids, counts and order-independent hashes
+    instead of a stored mesh.  One pass, timed with HIP events."""
+    import torch
+
+    import latgen.device
+    from paper_2405_15197_amd.latmesh import SINK_FIELDS, Mesher
+
+    print(f"[bench] generating BCC {scale}^3 on the device", file=sys.stderr, flush=True)
+    lat = latgen.device.config(3, scale=scale)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    M = Mesher(lat)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    print(f"[bench] plan ready in {t_plan:.1f} s; sink pass", file=sys.stderr, flush=True)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    words = M.sink(k, chunk_nodes)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    with np.errstate(over="ignore"):
+        tot = words.sum(axis=0, dtype=np.uint64)
+    M.close()
+    tot = {f: int(v) for f, v in zip(SINK_FIELDS, tot)}
+    return {
+        "metric": "struts meta-meshed/s (and triangles emitted/s) at resolution k",
+        "value": lat.n_struts / (ms * 1e-3),
+        "unit": "struts/s",
+        "n_gpus": 1,
+        "ms_per_pass": ms,
+        "triangles_per_s": tot["triangles"] / (ms * 1e-3),
+        "config": {
+            "workload": f"BCC {scale}^3 cells, {lat.n_nodes} nodes, {lat.n_struts} struts, radii 0.08(1+U[-0.1,0.1]), "
+            f"no jitter, k={k}, sink mode (per-chunk counts + hashes), chunks of {chunk_nodes} node ids",
+        },
+        "plan_s": t_plan,
+        "sink_totals": tot,
+        "chunks": int(words.shape[0]),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,11 +207,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-scale", type=int, default=64, help="BCC cells per side of the oracle's lattice")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint leg (octet 32^3)")
+    ap.add_argument("--billion", action="store_true",
+                    help="only the BCC 512^3 lattice in sink mode (generated on the device), one pass")
+    ap.add_argument("--billion-scale", type=int, default=512)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB a few times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.billion:
+        print(json.dumps(billion_bench(scale=args.billion_scale)), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is in the "

@@ -144,7 +144,7 @@ typedef struct lm_plan lm_plan;
  * k = 16).  stream is a
  * hipStream_t (NULL = default stream).  On success *plan is set; on error it
  * is NULL.  Returns LM_ERR_BAD_LATTICE for out-of-range endpoints,
- * LM_ERR_UNSUPPORTED if 2 * n_struts >= 2^31. */
+ * LM_ERR_UNSUPPORTED if n_nodes or n_struts is 2^31 or more. */
 int lm_plan_create(lm_plan **plan, const lm_lattice *lat, void *stream);
 
 /* Redo the validation and adjacency build of lm_plan_create on the device,

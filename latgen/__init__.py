@@ -30,7 +30,9 @@ __all__ = [
     "lattice_from_arrays",
     "two_strut",
     "star",
+    "knn",
     "config",
+    "parts",
 ]
 
 _M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
@@ -184,6 +186,55 @@ def octet(n, radius=0.1, jitter=0.0, seed=1, cell=1.0) -> Lattice:
         b = lin[X2[ok] + g * (Y2[ok] + g * Z2[ok])]
         st.append(np.stack([np.minimum(a, b), np.maximum(a, b)], 1))
     return _finish(pos, seed, radius, jitter, cell, np.concatenate(st), f"octet{n}")
+
+
+def knn(n, kn, radius=0.1, seed=1, cell=1.0) -> Lattice:
+    """Random lattice: n^3 points uniform in an n^3-cell box (density one per
+    cell, a binomial stand-in for a Poisson process), each joined to its kn
+    nearest neighbours, symmetrised (an edge if either end chose it)."""
+    from scipy.spatial import cKDTree
+
+    N = n**3
+    ids = np.arange(N, dtype=np.uint64)
+    pos = np.stack([uniform(seed, ids, f) for f in (FIELD_JX, FIELD_JY, FIELD_JZ)], axis=1) * n
+    kk = min(kn, N - 1)
+    if kk < 1:
+        return _finish(pos, seed, radius, 0.0, cell, np.zeros((0, 2), np.int64), f"knn{n}_{kn}")
+    _, nb = cKDTree(pos).query(pos, k=kk + 1)
+    a = np.repeat(np.arange(N), kk)
+    b = nb[:, 1:].ravel()
+    e = np.unique(np.stack([np.minimum(a, b), np.maximum(a, b)], 1), axis=0)
+    return _finish(pos, seed, radius, 0.0, cell, e, f"knn{n}_{kn}")
+
+
+FIELD_PART = 16  # fields of the per-part draws
+
+
+def parts(n_parts=512, seed=1, n_max=64, n_min=4):
+    """The batched workload: ``n_parts`` lattice parts, each a cubic, BCC,
+    octet or random k-NN lattice (uniform choice) with cells per side drawn
+    from {n_min..n_max}, k-NN degree from {3..20}, node radii U[0.04, 0.12],
+    and a resolution from {8, 16, 32}.  Returns a list of (Lattice, k)."""
+    pid = np.arange(n_parts, dtype=np.uint64)
+    u = [uniform(seed, pid, FIELD_PART + f) for f in range(4)]
+    out = []
+    for p in range(n_parts):
+        kind = min(int(u[0][p] * 4), 3)
+        n = n_min + min(int(u[1][p] * (n_max - n_min + 1)), n_max - n_min)
+        res = (8, 16, 32)[min(int(u[2][p] * 3), 2)]
+        rad = ("uniform", 0.04, 0.12)
+        s = seed * 1000003 + p
+        if kind == 0:
+            lat = cubic(n, radius=rad, jitter=0.0, seed=s)
+        elif kind == 1:
+            lat = bcc(n, radius=rad, jitter=0.0, seed=s)
+        elif kind == 2:
+            lat = octet(n, radius=rad, jitter=0.0, seed=s)
+        else:
+            kn = 3 + min(int(u[3][p] * 18), 17)
+            lat = knn(n, kn, radius=rad, seed=s)
+        out.append((lat, res))
+    return out
 
 
 def two_strut(angle_deg=90.0, length=1.0, radius=0.1, radii=None) -> Lattice:

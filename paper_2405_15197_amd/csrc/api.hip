@@ -258,7 +258,8 @@ int lm_plan_create(lm_plan **plan, const lm_lattice *lat, void *stream)
     if (!lat || lat->n_nodes < 0 || lat->n_struts < 0) return LM_ERR_INVALID_ARG;
     if (lat->n_nodes > 0 && (!lat->d_x || !lat->d_y || !lat->d_z || !lat->d_radius)) return LM_ERR_INVALID_ARG;
     if (lat->n_struts > 0 && (!lat->d_strut_a || !lat->d_strut_b)) return LM_ERR_INVALID_ARG;
-    if (lat->n_nodes >= ((int64_t)1 << 31) || 2 * lat->n_struts >= ((int64_t)1 << 31)) return LM_ERR_UNSUPPORTED;
+    // node and strut ids are int32; half-edge indices are int64
+    if (lat->n_nodes >= ((int64_t)1 << 31) || lat->n_struts >= ((int64_t)1 << 31)) return LM_ERR_UNSUPPORTED;
     lm_plan *P = new (std::nothrow) lm_plan();
     if (!P) return LM_ERR_INTERNAL;
     P->st = (hipStream_t)stream;
@@ -349,7 +350,7 @@ int lm_loss(lm_plan *P, const lm_outputs *out, const lm_loss_weights *w, double 
     if (P->k == 0) return LM_ERR_STATE;
     lm::FillOut f = to_fill(out);
     PhaseTimer t(P, PH_LOSS);
-    HIPCHK(lm::launch_loss(P->w, f, make_float3(w->p0[0], w->p0[1], w->p0[2]), w->area, w->volume, w->sq_norm,
+    HIPCHK(lm::launch_loss(P->in, P->w, f, make_float3(w->p0[0], w->p0[1], w->p0[2]), w->area, w->volume, w->sq_norm,
                            d_dl_dx, d_terms, P->st));
     return LM_OK;
 }

@@ -137,8 +137,8 @@ hipError_t launch_zip(const Inputs &in, const Work &w, const FillOut &o, hipStre
 hipError_t launch_totals(const Inputs &in, const Work &w, const FillOut *o, hipStream_t st);
 // Loss terms (area, volume about p0, sum of squared norms) of the last mesh
 // and their gradient dldx [cap_mesh][3]; then the adjoint to the inputs.
-hipError_t launch_loss(const Work &w, const FillOut &o, float3 p0, float w_area, float w_vol, float w_sq,
-                       float *dldx, double *terms, hipStream_t st);
+hipError_t launch_loss(const Inputs &in, const Work &w, const FillOut &o, float3 p0, float w_area, float w_vol,
+                       float w_sq, float *dldx, double *terms, hipStream_t st);
 hipError_t launch_backward(const Inputs &in, const Work &w, const float *dldx, float *grad_xyz, float *grad_r,
                            hipStream_t st);
 // Sink mode: chunk node lists (range + higher-id halo, in valence classes)

@@ -155,7 +155,10 @@ __device__ bool conic_of(const SL<T> *S, T rho, int p, int q, Con<T> &C)
     V3<T> gam = gp - nh * gpn;          // in-plane part of g_p: major axis direction
     T gl = m_sqrt(dot(gam, gam));
     V3<T> u1;
-    if (gl > (T)1e-20) {
+    // Below a relative 1e-4 the in-plane part is rounding (exactly opposite
+    // struts make the section a circle) and its direction means nothing: any
+    // in-plane axis parametrises the (almost) circle.
+    if (gl > (T)1e-4 * m_sqrt(dot(gp, gp))) {
         u1 = gam * ((T)1 / gl);
         // gam is a small difference when the plane is nearly perpendicular
         // to the axis; keep u1 exactly in the plane (its in-plane rotation

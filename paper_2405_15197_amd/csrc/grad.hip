@@ -63,19 +63,6 @@ constexpr int kBlock = 256;
 // ---------------------------------------------------------------------------
 // loss terms and their gradient with respect to the mesh vertices
 
-__device__ inline double block_sum(double x, double *sm)
-{
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) sm[wid] = x;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kBlock / 64; ++w) t += sm[w];
-    __syncthreads();
-    return t;
-}
-
 __device__ inline float3 f3(const float *p) { return make_float3(p[0], p[1], p[2]); }
 __device__ inline float3 sub3(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
 __device__ inline float3 crs3(float3 a, float3 b)
@@ -89,63 +76,121 @@ __device__ inline void add3(float *p, float3 v, float s)
     atomicAdd(p + 2, v.z * s);
 }
 
-// Per triangle: area 1/2 |N| with N = (b - a) x (c - a), dA/da = 1/2 n x (c - b)
-// (cyclic); volume (a' . (b' x c')) / 6 about p0, dV/da = (b' x c') / 6.
-__global__ void __launch_bounds__(kBlock) k_loss_tri(const int64_t *d_ntri, const int32_t *tri, const float *xyz,
-                                                     float3 p0, float w_area, float w_vol, float *dldx, double *terms)
-{
-    __shared__ double sm[kBlock / 64];
-    const int64_t ntri = *d_ntri;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if ((int64_t)blockIdx.x * blockDim.x >= ntri) return;  // whole block past the end
-    double area = 0.0, vol = 0.0;
-    if (t < ntri) {
-        const int32_t i0 = tri[3 * t], i1 = tri[3 * t + 1], i2 = tri[3 * t + 2];
-        const float3 a = sub3(f3(xyz + 3 * (int64_t)i0), p0), b = sub3(f3(xyz + 3 * (int64_t)i1), p0),
-                     c = sub3(f3(xyz + 3 * (int64_t)i2), p0);
-        const float3 N = crs3(sub3(b, a), sub3(c, a));
-        const float nl = sqrtf(N.x * N.x + N.y * N.y + N.z * N.z);
-        area = 0.5 * (double)nl;
-        const float3 bc = crs3(b, c), ca = crs3(c, a), ab = crs3(a, b);
-        vol = ((double)a.x * bc.x + (double)a.y * bc.y + (double)a.z * bc.z) / 6.0;
-        if (w_area != 0.f && nl > 0.f) {
-            const float3 n = make_float3(N.x / nl, N.y / nl, N.z / nl);
-            add3(dldx + 3 * (int64_t)i0, crs3(n, sub3(c, b)), 0.5f * w_area);
-            add3(dldx + 3 * (int64_t)i1, crs3(n, sub3(a, c)), 0.5f * w_area);
-            add3(dldx + 3 * (int64_t)i2, crs3(n, sub3(b, a)), 0.5f * w_area);
-        }
-        if (w_vol != 0.f) {
-            add3(dldx + 3 * (int64_t)i0, bc, w_vol / 6.f);
-            add3(dldx + 3 * (int64_t)i1, ca, w_vol / 6.f);
-            add3(dldx + 3 * (int64_t)i2, ab, w_vol / 6.f);
-        }
-    }
-    const double sa = block_sum(area, sm), sv = block_sum(vol, sm);
-    if (threadIdx.x == 0) {
-        atomicAdd(&terms[0], sa);
-        atomicAdd(&terms[1], sv);
-    }
-}
+// Triangle terms: area 1/2 |N| with N = (b - a) x (c - a), dA/da =
+// 1/2 n x (c - b) (cyclic); volume (a' . (b' x c')) / 6 about p0,
+// dV/da = (b' x c') / 6.
+// Per node (one wave): the gradient of the loss with respect to the node's
+// own mesh vertices, gathered over the triangles that touch them (its hole
+// fans and the bands of its incident struts) in LDS and written once; the
+// loss terms count each band at its lower end node and each fan at its
+// node.  Nodes with more mesh vertices than the LDS holds add through
+// global atomics instead.
+constexpr int kLossLds = 1024;
 
-__global__ void __launch_bounds__(kBlock) k_loss_vert(const int64_t *d_nv, const float *xyz, float w_sq, float *dldx,
-                                                      double *terms)
+struct LParams {
+    Inputs in;
+    Work w;
+    const int32_t *tri;
+    const float *xyz;
+    float3 p0;
+    float w_area, w_vol, w_sq;
+    float *dldx;
+    double *terms;
+};
+
+__global__ void __launch_bounds__(64) k_loss_node(LParams P)
 {
-    __shared__ double sm[kBlock / 64];
-    const int64_t nv = *d_nv;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if ((int64_t)blockIdx.x * blockDim.x >= nv) return;
-    double q = 0.0;
-    if (i < nv) {
-        const float3 x = f3(xyz + 3 * i);
-        q = (double)x.x * x.x + (double)x.y * x.y + (double)x.z * x.z;
-        if (w_sq != 0.f) {
-            dldx[3 * i] += 2.f * w_sq * x.x;
-            dldx[3 * i + 1] += 2.f * w_sq * x.y;
-            dldx[3 * i + 2] += 2.f * w_sq * x.z;
+    __shared__ float g[kLossLds][3];
+    __shared__ double s_terms[3];
+    const Work &W = P.w;
+    const int64_t N = P.in.n_nodes, S = P.in.n_struts;
+    const int64_t n = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (n >= N) return;
+    const int64_t Np1 = N + 1;
+    const int64_t m0 = W.node_off[(int64_t)NC_MESH * Np1 + n], m1 = W.node_off[(int64_t)NC_MESH * Np1 + n + 1];
+    const int M = (int)(m1 - m0);
+    if (M == 0) return;
+    const bool lds = M <= kLossLds;
+    for (int i = lane; i < (lds ? M : 0); i += 64) g[i][0] = g[i][1] = g[i][2] = 0.f;
+    if (lane < 3) s_terms[lane] = 0.0;
+    __syncthreads();
+    double area = 0.0, vol = 0.0, sq = 0.0;
+    auto add = [&](int32_t vi, float3 d, float sc) {
+        if (vi < m0 || vi >= m1) return;
+        if (lds) {
+            atomicAdd(&g[vi - m0][0], d.x * sc);
+            atomicAdd(&g[vi - m0][1], d.y * sc);
+            atomicAdd(&g[vi - m0][2], d.z * sc);
+        } else {
+            add3(P.dldx + 3 * (int64_t)vi, d, sc);
+        }
+    };
+    // one triangle: gradient on this node's corners; terms when counted here
+    auto tri_do = [&](int64_t t, bool count) {
+        const int32_t i0 = P.tri[3 * t], i1 = P.tri[3 * t + 1], i2 = P.tri[3 * t + 2];
+        const float3 a = sub3(f3(P.xyz + 3 * (int64_t)i0), P.p0), b = sub3(f3(P.xyz + 3 * (int64_t)i1), P.p0),
+                     c = sub3(f3(P.xyz + 3 * (int64_t)i2), P.p0);
+        const float3 Nn = crs3(sub3(b, a), sub3(c, a));
+        const float nl = sqrtf(Nn.x * Nn.x + Nn.y * Nn.y + Nn.z * Nn.z);
+        const float3 bc = crs3(b, c), ca = crs3(c, a), ab = crs3(a, b);
+        if (count) {
+            area += 0.5 * (double)nl;
+            vol += ((double)a.x * bc.x + (double)a.y * bc.y + (double)a.z * bc.z) / 6.0;
+        }
+        if (P.w_area != 0.f && nl > 0.f) {
+            const float3 nh = make_float3(Nn.x / nl, Nn.y / nl, Nn.z / nl);
+            add(i0, crs3(nh, sub3(c, b)), 0.5f * P.w_area);
+            add(i1, crs3(nh, sub3(a, c)), 0.5f * P.w_area);
+            add(i2, crs3(nh, sub3(b, a)), 0.5f * P.w_area);
+        }
+        if (P.w_vol != 0.f) {
+            add(i0, bc, P.w_vol / 6.f);
+            add(i1, ca, P.w_vol / 6.f);
+            add(i2, ab, P.w_vol / 6.f);
+        }
+    };
+    // hole fans of the node
+    const int64_t f0 = W.band_off[S] + W.node_off[(int64_t)NC_FAN * Np1 + n];
+    const int64_t f1 = W.band_off[S] + W.node_off[(int64_t)NC_FAN * Np1 + n + 1];
+    for (int64_t t = f0 + lane; t < f1; t += 64) tri_do(t, true);
+    // bands of the incident struts (terms at the lower end)
+    const int64_t r0 = W.row[n], r1 = W.row[n + 1];
+    for (int64_t h = r0; h < r1; ++h) {
+        const int2 he = W.he[h];
+        const int64_t b0 = W.band_off[he.y], b1 = W.band_off[he.y + 1];
+        const bool lower = (int64_t)he.x > n;
+        for (int64_t t = b0 + lane; t < b1; t += 64) tri_do(t, lower);
+    }
+    // sum of squared norms over the node's vertices
+    for (int i = lane; i < M; i += 64) {
+        const float3 x = f3(P.xyz + 3 * (m0 + i));
+        sq += (double)x.x * x.x + (double)x.y * x.y + (double)x.z * x.z;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        area += __shfl_xor(area, o, 64);
+        vol += __shfl_xor(vol, o, 64);
+        sq += __shfl_xor(sq, o, 64);
+    }
+    __syncthreads();
+    for (int i = lane; i < M; i += 64) {
+        const float3 x = f3(P.xyz + 3 * (m0 + i));
+        float *d = P.dldx + 3 * (m0 + i);
+        if (lds) {
+            d[0] = g[i][0] + 2.f * P.w_sq * x.x;
+            d[1] = g[i][1] + 2.f * P.w_sq * x.y;
+            d[2] = g[i][2] + 2.f * P.w_sq * x.z;
+        } else {
+            atomicAdd(d, 2.f * P.w_sq * x.x);
+            atomicAdd(d + 1, 2.f * P.w_sq * x.y);
+            atomicAdd(d + 2, 2.f * P.w_sq * x.z);
         }
     }
-    const double s = block_sum(q, sm);
-    if (threadIdx.x == 0) atomicAdd(&terms[2], s);
+    if (lane == 0) {
+        atomicAdd(&P.terms[0], area);
+        atomicAdd(&P.terms[1], vol);
+        atomicAdd(&P.terms[2], sq);
+    }
 }
 
 __global__ void k_zero_f(float *p, int64_t n)
@@ -185,6 +230,8 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
     __shared__ float lam_v[kVcap][3];
     __shared__ float lam_arc[kAcap][11];  // o, a, b, t1, t2
     __shared__ float lam_g[kVmax + 1][3], lam_h[kVmax + 1], lam_e[kVmax + 1][3];
+    // circle adjoints per strut: sigma, kappa, frame q, frame r
+    __shared__ float lam_sig[kVmax + 1], lam_kap[kVmax + 1], lam_qf[kVmax + 1][3], lam_rf[kVmax + 1][3];
     __shared__ float lam_node[4];         // this node's x, y, z, radius
     __shared__ int s_mbase[kAcap];
     const Work &W = P.w;
@@ -228,6 +275,9 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
         lam_g[i][0] = lam_g[i][1] = lam_g[i][2] = 0.f;
         lam_h[i] = 0.f;
         lam_e[i][0] = lam_e[i][1] = lam_e[i][2] = 0.f;
+        lam_sig[i] = lam_kap[i] = 0.f;
+        lam_qf[i][0] = lam_qf[i][1] = lam_qf[i][2] = 0.f;
+        lam_rf[i][0] = lam_rf[i][1] = lam_rf[i][2] = 0.f;
     }
     if (lane < 4) lam_node[lane] = 0.f;
     for (int j = lane; j < E; j += 64) {
@@ -423,58 +473,57 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
     }
     __syncthreads();
 
-    // ---- conics: (o, a, b) from the node and strut inputs ---------------------
-    for (int j = lane; j < E; j += 64) {
-        const uint32_t u0 = RA[11 * E + j];
-        const int p = (int)(u0 & 0xffu), q = (int)((u0 >> 8) & 0xffu);
+    // ---- conics: (o, a, b) back to the strut table ----------------------------
+    // Tangency circle (0, q): o = rho sigma e, a = rho kappa q^, b = rho kappa r^.
+    for (int j = lane; j < ncirc; j += 64) {
+        const int q = (int)((RA[11 * E + j] >> 8) & 0xffu);
+        const SL<float> &sq = S[q];
         float Lo[9];
         for (int f = 0; f < 9; ++f) Lo[f] = lam_arc[j][f];
-        const int nin = p == 0 ? 2 : 3;  // input nodes: this node, q (, p)
-        for (int which = 0; which < nin; ++which) {
-            const int m = which == 0 ? 0 : (which == 1 ? q : p);
-            const int node = which == 0 ? (int)n : S[m].far;
-            const float4 in4 = which == 0 ? c4 : W.node4[node];
-            float g4[4];
-            for (int kdir = 0; kdir < 4; ++kdir) {
-                V3<Dual> cd = v3(Dual(c4.x), Dual(c4.y), Dual(c4.z));
-                Dual rd = Dual(c4.w);
-                if (which == 0) seed(c4, kdir, cd, rd);
-                // strut entries of labels p (if any) and q with the seeded input
-                SL<Dual> Sd[2];
-                bool bad;
-                for (int e2 = 0; e2 < 2; ++e2) {
-                    const int lab = e2 == 0 ? q : p;
-                    if (lab == 0) continue;
-                    const float4 f4 = W.node4[S[lab].far];
-                    V3<Dual> cf = v3(Dual(f4.x), Dual(f4.y), Dual(f4.z));
-                    Dual rf = Dual(f4.w);
-                    if (which != 0 && lab == m) seed(f4, kdir, cf, rf);
-                    Sd[e2] = strut_entry(cd, rd, cf, rf, S[lab].lower, bad);
-                }
-                Con<Dual> C;
-                if (p == 0) {
-                    const SL<Dual> &s = Sd[0];
-                    Dual rad = rd * s.kap;
-                    C.o = v3(s.ex, s.ey, s.ez) * (rd * s.sig);
-                    C.a = v3(s.qx, s.qy, s.qz) * rad;
-                    C.b = v3(s.rx, s.ry, s.rz) * rad;
-                } else {
-                    SL<Dual> tab[3];
-                    tab[1] = Sd[1];  // label p
-                    tab[2] = Sd[0];  // label q
-                    conic_of(tab, rd, 1, 2, C);
-                }
-                g4[kdir] = Lo[0] * C.o.x.d + Lo[1] * C.o.y.d + Lo[2] * C.o.z.d + Lo[3] * C.a.x.d + Lo[4] * C.a.y.d +
-                           Lo[5] * C.a.z.d + Lo[6] * C.b.x.d + Lo[7] * C.b.y.d + Lo[8] * C.b.z.d;
-            }
-            (void)in4;
-            if (which == 0) {
-                for (int kdir = 0; kdir < 4; ++kdir) atomicAdd(&lam_node[kdir], g4[kdir]);
-            } else {
-                for (int kdir = 0; kdir < 3; ++kdir) atomicAdd(&P.grad_xyz[3 * (int64_t)node + kdir], g4[kdir]);
-                atomicAdd(&P.grad_r[node], g4[3]);
-            }
+        const float e[3] = {sq.ex, sq.ey, sq.ez}, qf[3] = {sq.qx, sq.qy, sq.qz}, rf[3] = {sq.rx, sq.ry, sq.rz};
+        const float lo_e = dotf(Lo, e), la_q = dotf(Lo + 3, qf), lb_r = dotf(Lo + 6, rf);
+        atomicAdd(&lam_node[3], sq.sig * lo_e + sq.kap * (la_q + lb_r));
+        atomicAdd(&lam_sig[q], rho * lo_e);
+        atomicAdd(&lam_kap[q], rho * (la_q + lb_r));
+        for (int d = 0; d < 3; ++d) {
+            atomicAdd(&lam_e[q][d], rho * sq.sig * Lo[d]);
+            atomicAdd(&lam_qf[q][d], rho * sq.kap * Lo[3 + d]);
+            atomicAdd(&lam_rf[q][d], rho * sq.kap * Lo[6 + d]);
         }
+    }
+    // Ellipse (p, q), Eq. 7: forward mode over its 9 inputs g_p, h_p, g_q,
+    // h_q, rho (kappa_p = 1 / |g_p|, sigma_p = h_p kappa_p / rho), lanes
+    // over (arc, input) pairs.
+    for (int x = lane; x < (E - ncirc) * 9; x += 64) {
+        const int j = ncirc + x / 9, dir = x % 9;
+        const uint32_t u0 = RA[11 * E + j];
+        const int p = (int)(u0 & 0xffu), q = (int)((u0 >> 8) & 0xffu);
+        SL<Dual> tab[3];
+        for (int e2 = 1; e2 <= 2; ++e2) {
+            const SL<float> &sf = S[e2 == 1 ? p : q];
+            const int b0 = e2 == 1 ? 0 : 4;
+            SL<Dual> &t = tab[e2];
+            t.gx = Dual(sf.gx, dir == b0 ? 1.f : 0.f);
+            t.gy = Dual(sf.gy, dir == b0 + 1 ? 1.f : 0.f);
+            t.gz = Dual(sf.gz, dir == b0 + 2 ? 1.f : 0.f);
+            t.h = Dual(sf.h, dir == b0 + 3 ? 1.f : 0.f);
+        }
+        const Dual rd = Dual(rho, dir == 8 ? 1.f : 0.f);
+        {
+            SL<Dual> &t = tab[1];
+            t.kap = Dual(1.f) / m_sqrt(t.gx * t.gx + t.gy * t.gy + t.gz * t.gz);
+            t.sig = t.h * t.kap / rd;
+        }
+        Con<Dual> C;
+        conic_of(tab, rd, 1, 2, C);
+        const float g = lam_arc[j][0] * C.o.x.d + lam_arc[j][1] * C.o.y.d + lam_arc[j][2] * C.o.z.d +
+                        lam_arc[j][3] * C.a.x.d + lam_arc[j][4] * C.a.y.d + lam_arc[j][5] * C.a.z.d +
+                        lam_arc[j][6] * C.b.x.d + lam_arc[j][7] * C.b.y.d + lam_arc[j][8] * C.b.z.d;
+        if (dir < 3) atomicAdd(&lam_g[p][dir], g);
+        else if (dir == 3) atomicAdd(&lam_h[p], g);
+        else if (dir < 7) atomicAdd(&lam_g[q][dir - 4], g);
+        else if (dir == 7) atomicAdd(&lam_h[q], g);
+        else atomicAdd(&lam_node[3], g);
     }
     __syncthreads();
 
@@ -539,33 +588,26 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
     }
     __syncthreads();
 
-    // ---- strut table: g_m, h_m, e_m from the node and far-node inputs -------
-    if (lane < v) {
-        const int m = lane + 1;
-        const float lg[3] = {lam_g[m][0], lam_g[m][1], lam_g[m][2]};
-        const float le[3] = {lam_e[m][0], lam_e[m][1], lam_e[m][2]};
-        const float lh = lam_h[m];
+    // ---- strut table: g, h, e, sigma, kappa, frame from the two nodes' inputs
+    // forward mode, lanes over (strut, input) pairs: 4 inputs of this node,
+    // 4 of the far node
+    for (int x = lane; x < v * 8; x += 64) {
+        const int m = x / 8 + 1, dir = x % 8;
         const int far = S[m].far;
         const float4 f4 = W.node4[far];
-        for (int which = 0; which < 2; ++which) {
-            float g4[4];
-            for (int kdir = 0; kdir < 4; ++kdir) {
-                V3<Dual> cd = v3(Dual(c4.x), Dual(c4.y), Dual(c4.z)), cf = v3(Dual(f4.x), Dual(f4.y), Dual(f4.z));
-                Dual rd = Dual(c4.w), rf = Dual(f4.w);
-                if (which == 0) seed(c4, kdir, cd, rd);
-                else seed(f4, kdir, cf, rf);
-                bool bad;
-                const SL<Dual> s = strut_entry(cd, rd, cf, rf, S[m].lower, bad);
-                g4[kdir] = lg[0] * s.gx.d + lg[1] * s.gy.d + lg[2] * s.gz.d + lh * s.h.d + le[0] * s.ex.d +
-                           le[1] * s.ey.d + le[2] * s.ez.d;
-            }
-            if (which == 0) {
-                for (int kdir = 0; kdir < 4; ++kdir) atomicAdd(&lam_node[kdir], g4[kdir]);
-            } else {
-                for (int kdir = 0; kdir < 3; ++kdir) atomicAdd(&P.grad_xyz[3 * (int64_t)far + kdir], g4[kdir]);
-                atomicAdd(&P.grad_r[far], g4[3]);
-            }
-        }
+        V3<Dual> cd = v3(Dual(c4.x), Dual(c4.y), Dual(c4.z)), cf = v3(Dual(f4.x), Dual(f4.y), Dual(f4.z));
+        Dual rd = Dual(c4.w), rf = Dual(f4.w);
+        if (dir < 4) seed(c4, dir, cd, rd);
+        else seed(f4, dir - 4, cf, rf);
+        bool bad;
+        const SL<Dual> s = strut_entry(cd, rd, cf, rf, S[m].lower, bad);
+        const float g = lam_g[m][0] * s.gx.d + lam_g[m][1] * s.gy.d + lam_g[m][2] * s.gz.d + lam_h[m] * s.h.d +
+                        lam_e[m][0] * s.ex.d + lam_e[m][1] * s.ey.d + lam_e[m][2] * s.ez.d + lam_sig[m] * s.sig.d +
+                        lam_kap[m] * s.kap.d + lam_qf[m][0] * s.qx.d + lam_qf[m][1] * s.qy.d +
+                        lam_qf[m][2] * s.qz.d + lam_rf[m][0] * s.rx.d + lam_rf[m][1] * s.ry.d + lam_rf[m][2] * s.rz.d;
+        if (dir < 4) atomicAdd(&lam_node[dir], g);
+        else if (dir < 7) atomicAdd(&P.grad_xyz[3 * (int64_t)far + dir - 4], g);
+        else atomicAdd(&P.grad_r[far], g);
     }
     __syncthreads();
     if (lane < 3) atomicAdd(&P.grad_xyz[3 * n + lane], lam_node[lane]);
@@ -576,18 +618,25 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 
 }  // namespace
 
-hipError_t launch_loss(const Work &w, const FillOut &o, float3 p0, float w_area, float w_vol, float w_sq,
-                       float *dldx, double *terms, hipStream_t st)
+hipError_t launch_loss(const Inputs &in, const Work &w, const FillOut &o, float3 p0, float w_area, float w_vol,
+                       float w_sq, float *dldx, double *terms, hipStream_t st)
 {
-    // counts from the device totals (mesh vertices, triangles); grids sized
-    // by the capacities, blocks past the counts return at once
     k_zero_d<<<1, 64, 0, st>>>(terms, 3);
+    if (in.n_nodes == 0) return hipGetLastError();
+    // nodes whose vertices do not fit the LDS add with atomics: start from 0
     if (o.cap_mesh > 0) k_zero_f<<<grid_for(3 * o.cap_mesh), kBlock, 0, st>>>(dldx, 3 * o.cap_mesh);
-    if (o.cap_tri > 0)
-        k_loss_tri<<<grid_for(o.cap_tri), kBlock, 0, st>>>(w.totals + 4, o.tri, o.mesh_xyz, p0, w_area, w_vol, dldx,
-                                                           terms);
-    if (o.cap_mesh > 0)
-        k_loss_vert<<<grid_for(o.cap_mesh), kBlock, 0, st>>>(w.totals + 3, o.mesh_xyz, w_sq, dldx, terms);
+    LParams P;
+    P.in = in;
+    P.w = w;
+    P.tri = o.tri;
+    P.xyz = o.mesh_xyz;
+    P.p0 = p0;
+    P.w_area = w_area;
+    P.w_vol = w_vol;
+    P.w_sq = w_sq;
+    P.dldx = dldx;
+    P.terms = terms;
+    k_loss_node<<<(unsigned)in.n_nodes, 64, 0, st>>>(P);
     return hipGetLastError();
 }
 

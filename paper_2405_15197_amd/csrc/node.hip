@@ -245,10 +245,13 @@ __device__ void trim_conic(const SL<T> *S, int v, int p, int q, const Con<T> &C,
         const T lo = pang(los, loc), hi = pang(his, hic);
         T lc = hi - lo;
         if (lc < (T)0) lc += tp;
-        // more than a half turn exactly when Cc > 0; a contradiction means
-        // the gap (or the kept interval) is below rounding
-        if (k.Cc > (T)0 && lc < (T)2) continue;
-        if (k.Cc < (T)0 && lc > (T)2) {
+        // more than a half turn exactly when Cc > 0: a kept interval that
+        // comes out almost empty although Cc > 0 is almost the whole turn
+        // (its gap is below rounding), one that comes out almost whole
+        // although Cc < 0 is almost empty.  Near a half turn (Cc near 0)
+        // the computed length stands.
+        if (k.Cc > (T)0 && lc < (T)1) continue;
+        if (k.Cc < (T)0 && lc > (T)3) {
             n = 0;
             full = 0;
             break;

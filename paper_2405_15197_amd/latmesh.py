@@ -294,7 +294,11 @@ class Mesher:
         load()
         self.torch = torch
         self.device = torch.device(device)
-        f = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(self.device)  # noqa: E731
+        def f(a, dt):
+            if isinstance(a, torch.Tensor):  # already a tensor (e.g. generated on the device)
+                return a.to(device=self.device, dtype=dt).contiguous()
+            return torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(self.device)
+
         self.x = f(lat.x, torch.float32)
         self.y = f(lat.y, torch.float32)
         self.z = f(lat.z, torch.float32)

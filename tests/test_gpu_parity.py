@@ -48,6 +48,9 @@ CONFIGS = [
     ("cfg4_octet3", lambda: latgen.config(4, scale=3), 16),
     ("cubic_cones", lambda: latgen.cubic(5, radius=("uniform", 0.05, 0.15), jitter=0.04, seed=5), 12),
     ("bcc_cyl", lambda: latgen.bcc(4, radius=0.1, jitter=0.05, seed=9), 11),
+    # unjittered: exactly opposite struts and seams at exactly half turns
+    ("cfg3_bcc6_unjittered", lambda: latgen.config(3, scale=6), 12),
+    ("cfg3_bcc5_jitter", lambda: latgen.bcc(5, radius=("rel", 0.08, 0.1), jitter=0.01, seed=4), 12),
 ]
 
 
@@ -57,7 +60,8 @@ def test_config_parity(name, make, k):
     _line(f"config {name}: {lat.n_nodes} nodes {lat.n_struts} struts k={k}")
     st = compare(lat, k)
     _line(f"  {st}")
-    assert st["stable"] >= 0.95 * lat.n_nodes
+    # exact symmetry (no jitter) leaves more nodes below the margin
+    assert st["stable"] >= (0.85 if "unjittered" in name else 0.95) * lat.n_nodes
 
 
 def test_full_config2_sampled():

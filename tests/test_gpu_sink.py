@@ -79,3 +79,24 @@ def test_sink_matches_oracle_and_stored(name, make, k):
             assert np.array_equal(tot, totals), "sink totals depend on the chunking"
     finally:
         M.close()
+
+
+def test_sink_billion_family_device_generated():
+    """The billion-strut family (BCC, radii 0.08 (1 +- 0.1), no jitter) at
+    24^3 cells, generated on the device: every node is meshed (the oracle
+    meshes all of them), and the totals do not depend on the chunking."""
+    import latgen.device
+    from paper_2405_15197_amd import Mesher
+
+    lat = latgen.device.config(3, scale=24)
+    M = Mesher(lat)
+    try:
+        tots = []
+        for chunk in (lat.n_nodes, 4099):
+            w = M.sink(12, chunk)
+            assert int(w[:, 7].sum()) == 0, "nodes without a mesh"
+            with np.errstate(over="ignore"):
+                tots.append(w.sum(axis=0, dtype=np.uint64))
+        assert np.array_equal(tots[0], tots[1])
+    finally:
+        M.close()
