@@ -197,6 +197,78 @@ def billion_bench(k: int = 12, chunk_nodes: int = 1 << 23, scale: int = 512):
     }
 
 
+def batched_bench(n_parts: int = 512, n_max: int = 64, seed: int = 1):
+    """512 lattice parts (cubic, BCC, octet or random k-NN, 4..64 cells per
+    side, radii U[0.04, 0.12], resolutions 8/16/32) meshed in sink mode:
+    batched (one plan, autotuned wave mapping and group size, one node pass
+    per group of parts) against the parts one after another (a plan each,
+    its own launches).  Host-side generation and plan creation are not
+    timed; both sides time preparation (adjacency) + meshing."""
+    import torch
+
+    import latgen
+    from paper_2405_15197_amd.autotune import tune
+    from paper_2405_15197_amd.latmesh import Mesher, lm_prepare
+
+    t0 = time.perf_counter()
+    print(f"[bench] generating {n_parts} parts", file=sys.stderr, flush=True)
+    parts = latgen.parts(n_parts, seed=seed, n_max=n_max)
+    lat, off = latgen.union([p[0] for p in parts])
+    ks = np.array([p[1] for p in parts], np.int32)
+    t_gen = time.perf_counter() - t0
+    print(f"[bench] {lat.n_nodes} nodes, {lat.n_struts} struts ({t_gen:.0f} s); autotuning", file=sys.stderr,
+          flush=True)
+    best, table = tune(parts, latgen.union, sample=32)
+    M = Mesher(lat)
+    M.batched(off, ks, best)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lm_prepare(M.plan)
+    words = M.batched(off, ks, best)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    M.close()
+    print(f"[bench] batched {t_batched:.2f} s; sequential per-part baseline", file=sys.stderr, flush=True)
+    t_seq = 0.0
+    seq_words = []
+    for i, (pl, k) in enumerate(parts):
+        Mp = Mesher(pl)
+        try:
+            Mp.sink(int(k), max(pl.n_nodes, 1))  # warm-up (allocations)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lm_prepare(Mp.plan)
+            seq_words.append(Mp.sink(int(k), max(pl.n_nodes, 1))[0])
+            torch.cuda.synchronize()
+            t_seq += time.perf_counter() - t0
+        finally:
+            Mp.close()
+        if i % 64 == 63:
+            print(f"[bench]   {i + 1} parts", file=sys.stderr, flush=True)
+    same = bool(np.array_equal(np.stack(seq_words), words))
+    with np.errstate(over="ignore"):
+        tot = words.sum(axis=0, dtype=np.uint64)
+    return {
+        "metric": "struts meta-meshed/s (and triangles emitted/s) at resolution k",
+        "value": lat.n_struts / t_batched,
+        "unit": "struts/s",
+        "n_gpus": 1,
+        "config": {"workload": f"{n_parts} parts (cubic/BCC/octet/k-NN, 4..{n_max} cells, k in 8/16/32), "
+                   f"{lat.n_nodes} nodes, {lat.n_struts} struts, sink mode per part"},
+        "batched_s": t_batched,
+        "sequential_s": t_seq,
+        "speedup_vs_sequential": t_seq / t_batched,
+        "identical_to_sequential": same,
+        "tuning": {"v_four_per_wave": best.v_four_per_wave, "v_two_per_wave": best.v_two_per_wave,
+                   "group_nodes": best.group_nodes},
+        "tuning_table_ms": {f"{a},{b},{c}": v for (a, b, c), v in table.items()},
+        "triangles": int(tot[0]),
+        "triangles_per_s": int(tot[0]) / t_batched,
+        "nodes_without_mesh": int(tot[7]),
+        "generation_s": t_gen,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +282,9 @@ def main():
     ap.add_argument("--billion", action="store_true",
                     help="only the BCC 512^3 lattice in sink mode (generated on the device), one pass")
     ap.add_argument("--billion-scale", type=int, default=512)
+    ap.add_argument("--batched", action="store_true", help="only the 512-part batch (sink mode), batched vs sequential")
+    ap.add_argument("--batched-parts", type=int, default=512)
+    ap.add_argument("--batched-nmax", type=int, default=64)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB a few times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -218,6 +293,9 @@ def main():
         return
     if args.billion:
         print(json.dumps(billion_bench(scale=args.billion_scale)), flush=True)
+        return
+    if args.batched:
+        print(json.dumps(batched_bench(args.batched_parts, args.batched_nmax)), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is in the "

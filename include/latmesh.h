@@ -223,6 +223,33 @@ int lm_get_profile(lm_plan *plan, double *ms, int64_t *calls, int n);
  * the last chunk only: lm_fill and lm_backward need a new lm_count. */
 int lm_forward_sink(lm_plan *plan, int k, int64_t chunk_nodes, uint64_t *d_out, int64_t n_chunks_cap);
 
+/* ---- batched parts -------------------------------------------------------- */
+
+/* Work mapping of lm_batched: nodes of valence <= v_four_per_wave (at most 4)
+ * go four to a wave, up to v_two_per_wave (at most 8) two to a wave, the rest
+ * one to a wave; group_nodes whole parts' worth of nodes (about) share one
+ * node pass (0: 2^23). */
+typedef struct lm_tuning {
+    int32_t v_four_per_wave;
+    int32_t v_two_per_wave;
+    int64_t group_nodes;
+} lm_tuning;
+
+/* Many lattice parts in one plan: part p is the node range
+ * [part_off[p], part_off[p+1]) of the plan's lattice (host arrays; part_off[0]
+ * = 0, part_off[n_parts] = n_nodes; struts should join nodes of one part) and
+ * is meshed at its own resolution part_k[p] (3..4096).  Parts are taken in
+ * groups of about tune->group_nodes nodes; the nodes of a group, whatever
+ * their part, are meshed by one persistent launch per valence class that
+ * takes its work from a global queue.  Output per part, in sink mode:
+ * d_out[p][LM_SINK_WORDS] (device; the words of lm_forward_sink, counted per
+ * part: a band goes to the part of its lower node; vertex ids use node ids
+ * local to the part, so a part's words equal those of lm_forward_sink on
+ * the part alone).  tune may be NULL
+ * (limits 4 and 8, groups of 2^23 nodes).  Synchronises the stream. */
+int lm_batched(lm_plan *plan, int64_t n_parts, const int64_t *part_off, const int32_t *part_k,
+               const lm_tuning *tune, uint64_t *d_out);
+
 /* ---- adjoint at fixed topology (gradients of a mesh loss) ------------- */
 
 /* Weights of the loss L = area * Area + volume * Vol + sq_norm * sum |v|^2

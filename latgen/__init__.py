@@ -31,6 +31,7 @@ __all__ = [
     "two_strut",
     "star",
     "knn",
+    "union",
     "config",
     "parts",
 ]
@@ -235,6 +236,19 @@ def parts(n_parts=512, seed=1, n_max=64, n_min=4):
             lat = knn(n, kn, radius=rad, seed=s)
         out.append((lat, res))
     return out
+
+
+def union(lattices):
+    """Disjoint union of lattices (node ids offset part by part); returns the
+    union and the node offsets of the parts [n_parts + 1]."""
+    off = np.zeros(len(lattices) + 1, np.int64)
+    for i, lat in enumerate(lattices):
+        off[i + 1] = off[i] + lat.n_nodes
+    cat = lambda f: np.concatenate([getattr(l, f) for l in lattices])  # noqa: E731
+    sa = np.concatenate([l.strut_a.astype(np.int64) + off[i] for i, l in enumerate(lattices)])
+    sb = np.concatenate([l.strut_b.astype(np.int64) + off[i] for i, l in enumerate(lattices)])
+    return Lattice(x=cat("x"), y=cat("y"), z=cat("z"), radius=cat("radius"), strut_a=sa.astype(np.int32),
+                   strut_b=sb.astype(np.int32), name=f"union{len(lattices)}"), off
 
 
 def two_strut(angle_deg=90.0, length=1.0, radius=0.1, radii=None) -> Lattice:

@@ -382,86 +382,171 @@ int sink_alloc(lm_plan *P)
 
 }  // namespace
 
+namespace {
+
+// One node range in sink mode: its node list (range + higher-id halo) in
+// valence classes (limits t16 / t32), the node pass, and the hashed
+// outputs: to out_chunk through the slots, or per part (node_part set).
+// k_avg sizes the first guess of the record space.
+int sink_range(lm_plan *P, int k, int k_avg, int64_t n0, int64_t n1, int t16, int t32, uint64_t *out_chunk,
+               const int32_t *node_part, uint64_t *out_parts, const int64_t *part_base)
+{
+    const int64_t N = P->in.n_nodes, S = P->in.n_struts;
+    lm::Work &w = P->w;
+    int rc = LM_OK;
+    HIPCHK(hipMemsetAsync(P->sk_cnt, 0, sizeof(int32_t) * 8, P->st));
+    if (++P->sk_epoch <= 0) {  // epochs wrapped: clear the marks
+        HIPCHK(hipMemsetAsync(P->sk_mark, 0, sizeof(int32_t) * (N + 1), P->st));
+        P->sk_epoch = 1;
+    }
+    {
+        PhaseTimer t(P, PH_SIZES);
+        HIPCHK(lm::launch_chunk_list(w, n0, n1, P->sk_mark, P->sk_epoch, P->sk_lists, N + 1, P->sk_cnt, P->sk_info,
+                                     t16, t32, P->st));
+    }
+    int32_t cnt[4];
+    int64_t r01[2];
+    HIPCHK(hipMemcpyAsync(cnt, P->sk_cnt, sizeof(cnt), hipMemcpyDeviceToHost, P->st));
+    HIPCHK(hipMemcpyAsync(&r01[0], w.row + n0, sizeof(int64_t), hipMemcpyDeviceToHost, P->st));
+    HIPCHK(hipMemcpyAsync(&r01[1], w.row + n1, sizeof(int64_t), hipMemcpyDeviceToHost, P->st));
+    HIPCHK(hipStreamSynchronize(P->st));
+    const int64_t listed = (int64_t)cnt[0] + cnt[1] + cnt[2];
+    const int64_t hcnt = r01[1] - r01[0];
+    if (hcnt > P->sk_struts_cap) {
+        if (P->sk_struts) HIPCHK(hipFree(P->sk_struts));
+        P->sk_struts = nullptr;
+        HIPCHK(hipMalloc((void **)&P->sk_struts, sizeof(int32_t) * (hcnt + 1)));
+        P->sk_struts_cap = hcnt;
+    }
+    // record space for the listed nodes (first guess, then what they used)
+    const double avg_deg = N > 0 ? 2.0 * (double)S / (double)N : 0.0;
+    const int64_t per_node =
+        lm::kRecHead + 4 + (int64_t)(avg_deg * (8 + 3 * lm::kRecArcFields + 3 + 2 * (k_avg + 4)) + 1);
+    if ((rc = ensure_rec(P, listed * per_node + listed * per_node / 8 + 4096))) return rc;
+    lm::Work wc = w;
+    wc.queue = P->sk_lists;
+    wc.cls_info = P->sk_info;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        HIPCHK(hipMemsetAsync(w.flags, 0, sizeof(int32_t), P->st));
+        HIPCHK(hipMemsetAsync(w.flags + 2, 0, sizeof(int32_t), P->st));
+        HIPCHK(hipMemsetAsync(w.rec_top, 0, sizeof(unsigned long long) * lm::kRecRegions, P->st));
+        HIPCHK(hipMemsetAsync(w.work_ctr, 0, sizeof(int32_t) * 4, P->st));
+        wc.rec = w.rec;
+        wc.rec_words = w.rec_words;
+        {
+            PhaseTimer t(P, PH_NODE32);
+            HIPCHK(lm::launch_node(P->in, wc, k, P->kappa_max, 0, P->st));
+        }
+        {
+            PhaseTimer t(P, PH_NODE64);
+            HIPCHK(lm::launch_node(P->in, wc, k, P->kappa_max, 1, P->st));
+        }
+        int32_t fl = 0;
+        unsigned long long top[lm::kRecRegions];
+        HIPCHK(hipMemcpyAsync(&fl, w.flags, sizeof(int32_t), hipMemcpyDeviceToHost, P->st));
+        HIPCHK(hipMemcpyAsync(top, w.rec_top, sizeof(top), hipMemcpyDeviceToHost, P->st));
+        HIPCHK(hipStreamSynchronize(P->st));
+        if (!(fl & lm::DF_RECCAP)) break;
+        if (attempt == 1) return LM_ERR_INTERNAL;
+        unsigned long long mx = 0;
+        for (int g = 0; g < lm::kRecRegions; ++g) mx = top[g] > mx ? top[g] : mx;
+        if ((rc = ensure_rec(P, (int64_t)mx * lm::kRecRegions + (int64_t)mx))) return rc;
+    }
+    HIPCHK(hipMemsetAsync(P->sk_cnt + 4, 0, sizeof(int32_t), P->st));
+    {
+        PhaseTimer t(P, PH_EXPAND);
+        HIPCHK(lm::launch_sink(P->in, w, n0, n1, hcnt, P->sk_struts, P->sk_cnt + 4, P->sk_slots, out_chunk,
+                               node_part, out_parts, part_base, P->st));
+    }
+    return LM_OK;
+}
+
+}  // namespace
+
 int lm_forward_sink(lm_plan *P, int k, int64_t chunk_nodes, uint64_t *d_out, int64_t n_chunks_cap)
 {
     if (!P || !d_out || k < 3 || k > 4096 || chunk_nodes < 1) return LM_ERR_INVALID_ARG;
-    const int64_t N = P->in.n_nodes, S = P->in.n_struts;
+    const int64_t N = P->in.n_nodes;
     const int64_t nch = (N + chunk_nodes - 1) / chunk_nodes;
     if (nch > n_chunks_cap) return LM_ERR_CAPACITY;
     int rc = sink_alloc(P);
     if (rc) return rc;
-    lm::Work &w = P->w;
-    const double avg_deg = N > 0 ? 2.0 * (double)S / (double)N : 0.0;
+    P->w.node_k = nullptr;
     for (int64_t c = 0; c < nch; ++c) {
         const int64_t n0 = c * chunk_nodes, n1 = n0 + chunk_nodes < N ? n0 + chunk_nodes : N;
-        // node list of the chunk: the range and its higher-id halo
-        HIPCHK(hipMemsetAsync(P->sk_cnt, 0, sizeof(int32_t) * 8, P->st));
-        if (++P->sk_epoch <= 0) {  // epochs wrapped: clear the marks
-            HIPCHK(hipMemsetAsync(P->sk_mark, 0, sizeof(int32_t) * (N + 1), P->st));
-            P->sk_epoch = 1;
-        }
-        {
-            PhaseTimer t(P, PH_SIZES);
-            HIPCHK(lm::launch_chunk_list(w, n0, n1, P->sk_mark, P->sk_epoch, P->sk_lists, N + 1, P->sk_cnt,
-                                         P->sk_info, P->st));
-        }
-        int32_t cnt[4];
-        int64_t r01[2];
-        HIPCHK(hipMemcpyAsync(cnt, P->sk_cnt, sizeof(cnt), hipMemcpyDeviceToHost, P->st));
-        HIPCHK(hipMemcpyAsync(&r01[0], w.row + n0, sizeof(int64_t), hipMemcpyDeviceToHost, P->st));
-        HIPCHK(hipMemcpyAsync(&r01[1], w.row + n1, sizeof(int64_t), hipMemcpyDeviceToHost, P->st));
-        HIPCHK(hipStreamSynchronize(P->st));
-        const int64_t listed = (int64_t)cnt[0] + cnt[1] + cnt[2];
-        const int64_t hcnt = r01[1] - r01[0];
-        if (hcnt > P->sk_struts_cap) {
-            if (P->sk_struts) HIPCHK(hipFree(P->sk_struts));
-            P->sk_struts = nullptr;
-            HIPCHK(hipMalloc((void **)&P->sk_struts, sizeof(int32_t) * (hcnt + 1)));
-            P->sk_struts_cap = hcnt;
-        }
-        // record space for the listed nodes (first guess, then what they used)
-        const int64_t per_node =
-            lm::kRecHead + 4 + (int64_t)(avg_deg * (8 + 3 * lm::kRecArcFields + 3 + 2 * (k + 4)) + 1);
-        if ((rc = ensure_rec(P, listed * per_node + listed * per_node / 8 + 4096))) return rc;
-        lm::Work wc = w;
-        wc.queue = P->sk_lists;
-        wc.cls_info = P->sk_info;
-        for (int attempt = 0; attempt < 2; ++attempt) {
-            HIPCHK(hipMemsetAsync(w.flags, 0, sizeof(int32_t), P->st));
-            HIPCHK(hipMemsetAsync(w.flags + 2, 0, sizeof(int32_t), P->st));
-            HIPCHK(hipMemsetAsync(w.rec_top, 0, sizeof(unsigned long long) * lm::kRecRegions, P->st));
-            HIPCHK(hipMemsetAsync(w.work_ctr, 0, sizeof(int32_t) * 4, P->st));
-            wc.rec = w.rec;
-            wc.rec_words = w.rec_words;
-            {
-                PhaseTimer t(P, PH_NODE32);
-                HIPCHK(lm::launch_node(P->in, wc, k, P->kappa_max, 0, P->st));
-            }
-            {
-                PhaseTimer t(P, PH_NODE64);
-                HIPCHK(lm::launch_node(P->in, wc, k, P->kappa_max, 1, P->st));
-            }
-            int32_t fl = 0;
-            unsigned long long top[lm::kRecRegions];
-            HIPCHK(hipMemcpyAsync(&fl, w.flags, sizeof(int32_t), hipMemcpyDeviceToHost, P->st));
-            HIPCHK(hipMemcpyAsync(top, w.rec_top, sizeof(top), hipMemcpyDeviceToHost, P->st));
-            HIPCHK(hipStreamSynchronize(P->st));
-            if (!(fl & lm::DF_RECCAP)) break;
-            if (attempt == 1) return LM_ERR_INTERNAL;
-            unsigned long long mx = 0;
-            for (int g = 0; g < lm::kRecRegions; ++g) mx = top[g] > mx ? top[g] : mx;
-            if ((rc = ensure_rec(P, (int64_t)mx * lm::kRecRegions + (int64_t)mx))) return rc;
-        }
-        HIPCHK(hipMemsetAsync(P->sk_cnt + 4, 0, sizeof(int32_t), P->st));
-        {
-            PhaseTimer t(P, PH_EXPAND);
-            HIPCHK(lm::launch_sink(P->in, w, n0, n1, hcnt, P->sk_struts, P->sk_cnt + 4, P->sk_slots,
-                                   d_out + c * LM_SINK_WORDS, P->st));
-        }
+        if ((rc = sink_range(P, k, k, n0, n1, 4, 8, d_out + c * LM_SINK_WORDS, nullptr, nullptr, nullptr)))
+            return rc;
     }
     // the node records now hold chunks: lm_fill / lm_backward need a new count
     P->k = 0;
     return LM_OK;
+}
+
+int lm_batched(lm_plan *P, int64_t n_parts, const int64_t *part_off, const int32_t *part_k, const lm_tuning *tune,
+               uint64_t *d_out)
+{
+    if (!P || n_parts < 1 || !part_off || !part_k || !d_out) return LM_ERR_INVALID_ARG;
+    const int64_t N = P->in.n_nodes;
+    if (part_off[0] != 0 || part_off[n_parts] != N) return LM_ERR_INVALID_ARG;
+    for (int64_t p = 0; p < n_parts; ++p)
+        if (part_off[p + 1] < part_off[p] || part_k[p] < 3 || part_k[p] > 4096) return LM_ERR_INVALID_ARG;
+    int t16 = 4, t32 = 8;
+    int64_t group = (int64_t)1 << 23;
+    if (tune) {
+        if (tune->v_four_per_wave < 0 || tune->v_four_per_wave > 4 || tune->v_two_per_wave < tune->v_four_per_wave ||
+            tune->v_two_per_wave > 8)
+            return LM_ERR_INVALID_ARG;
+        t16 = tune->v_four_per_wave;
+        t32 = tune->v_two_per_wave;
+        if (tune->group_nodes > 0) group = tune->group_nodes;
+    }
+    int rc = sink_alloc(P);
+    if (rc) return rc;
+    // per-node resolution and part (host-built once per call)
+    std::vector<int16_t> nk((size_t)N + 1);
+    std::vector<int32_t> np((size_t)N + 1);
+    int kmax = 3;
+    for (int64_t p = 0; p < n_parts; ++p) {
+        for (int64_t i = part_off[p]; i < part_off[p + 1]; ++i) {
+            nk[i] = (int16_t)part_k[p];
+            np[i] = (int32_t)p;
+        }
+        if (part_off[p + 1] > part_off[p] && part_k[p] > kmax) kmax = part_k[p];
+    }
+    int16_t *d_nk = nullptr;
+    int32_t *d_np = nullptr;
+    int64_t *d_pb = nullptr;
+    HIPCHK(hipMalloc((void **)&d_nk, sizeof(int16_t) * (N + 1)));
+    if (hipMalloc((void **)&d_np, sizeof(int32_t) * (N + 1)) != hipSuccess ||
+        hipMalloc((void **)&d_pb, sizeof(int64_t) * (n_parts + 1)) != hipSuccess) {
+        (void)hipFree(d_nk);
+        if (d_np) (void)hipFree(d_np);
+        return LM_ERR_HIP;
+    }
+    rc = LM_OK;
+    if (hipMemcpyAsync(d_nk, nk.data(), sizeof(int16_t) * (N + 1), hipMemcpyHostToDevice, P->st) != hipSuccess ||
+        hipMemcpyAsync(d_np, np.data(), sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, P->st) != hipSuccess ||
+        hipMemcpyAsync(d_pb, part_off, sizeof(int64_t) * (n_parts + 1), hipMemcpyHostToDevice, P->st) !=
+            hipSuccess ||
+        hipMemsetAsync(d_out, 0, sizeof(uint64_t) * LM_SINK_WORDS * n_parts, P->st) != hipSuccess)
+        rc = LM_ERR_HIP;
+    P->w.node_k = d_nk;
+    // groups of whole parts of about `group` nodes: one node pass each
+    for (int64_t p0 = 0; p0 < n_parts && rc == LM_OK;) {
+        int64_t p1 = p0 + 1;
+        while (p1 < n_parts && part_off[p1 + 1] - part_off[p0] <= group) ++p1;
+        int kg = 3;
+        for (int64_t p = p0; p < p1; ++p) kg = part_k[p] > kg ? part_k[p] : kg;
+        rc = sink_range(P, kg, kg, part_off[p0], part_off[p1], t16, t32, nullptr, d_np, d_out, d_pb);
+        p0 = p1;
+    }
+    (void)hipStreamSynchronize(P->st);
+    P->w.node_k = nullptr;
+    (void)hipFree(d_nk);
+    (void)hipFree(d_np);
+    (void)hipFree(d_pb);
+    P->k = 0;
+    return rc;
 }
 
 int lm_read_totals(lm_plan *P, lm_totals *totals)

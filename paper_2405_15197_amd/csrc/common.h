@@ -105,10 +105,16 @@ struct Work {
     int32_t *queue;         // [N] node ids grouped by valence class
     int64_t *cls_info;      // [8] nodes per class (0..2), queue start per class (4..6)
     int32_t *work_ctr;      // [4] per-class work counters of the node kernel
+    const int16_t *node_k;  // [N] per-node resolution (batched parts) or null
 };
 
 // Valence classes of the node kernel: v <= 4, 5..8, otherwise.
-__host__ __device__ inline int valence_class(int64_t v) { return v <= 4 ? 0 : (v <= 8 ? 1 : 2); }
+// (the batched entry point may lower the two limits: 4 and 8 are the class
+// capacities)
+__host__ __device__ inline int valence_class(int64_t v, int t16 = 4, int t32 = 8)
+{
+    return v <= t16 ? 0 : (v <= t32 ? 1 : 2);
+}
 constexpr int kClasses = 3;
 
 struct FillOut {
@@ -145,10 +151,13 @@ hipError_t launch_backward(const Inputs &in, const Work &w, const float *dldx, f
 // and the hashed triangles of a range.
 int64_t sink_slots_words();
 hipError_t launch_chunk_list(const Work &w, int64_t n0, int64_t n1, int32_t *mark, int32_t epoch, int32_t *lists,
-                             int64_t cap, int32_t *cnt, int64_t *info, hipStream_t st);
+                             int64_t cap, int32_t *cnt, int64_t *info, int t16, int t32, hipStream_t st);
+// Outputs go to `out` (one chunk) through the slots, or with node_part set
+// to out_parts[part of the node][LM_SINK_WORDS] with vertex ids local to the
+// part (node - part_base[part]).
 hipError_t launch_sink(const Inputs &in, const Work &w, int64_t n0, int64_t n1, int64_t max_struts,
                        int32_t *strut_list, int32_t *strut_cnt, unsigned long long *slots, uint64_t *out,
-                       hipStream_t st);
+                       const int32_t *node_part, uint64_t *out_parts, const int64_t *part_base, hipStream_t st);
 
 int64_t scan_tmp_needed(int64_t n, int ncols);
 

@@ -439,7 +439,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
     const int lane = threadIdx.x & (WL - 1);
     const Work &W = P.w;
     const int64_t N = P.in.n_nodes;
-    const int k = P.k;
+    const int k = W.node_k ? (int)W.node_k[n] : P.k;
     const int64_t row = W.row[n];
     const int v = (int)(W.row[n + 1] - row);
     const float4 c4 = W.node4[n];

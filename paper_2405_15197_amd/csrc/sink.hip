@@ -77,7 +77,7 @@ __device__ inline void append(bool active, int k, int32_t value, int32_t *lists,
 // with the chunk's epoch so that each halo node is listed once).
 __global__ void __launch_bounds__(256) k_chunk_list(int64_t n0, int64_t n1, const int64_t *row, const int2 *he,
                                                     int32_t *mark, int32_t epoch, int32_t *lists, int64_t cap,
-                                                    int32_t *cnt)
+                                                    int32_t *cnt, int t16, int t32)
 {
     const int64_t n = n0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = n < n1;
@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256) k_chunk_list(int64_t n0, int64_t n1, cons
         r0 = row[n];
         r1 = row[n + 1];
     }
-    append(in, valence_class(r1 - r0), (int32_t)n, lists, cap, cnt);
+    append(in, valence_class(r1 - r0, t16, t32), (int32_t)n, lists, cap, cnt);
     int deg = (int)(r1 - r0);
     int maxdeg = deg;
     for (int o = 32; o > 0; o >>= 1) maxdeg = max(maxdeg, __shfl_xor(maxdeg, o, 64));
@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(256) k_chunk_list(int64_t n0, int64_t n1, cons
             far = he[r0 + i].x;
             if ((int64_t)far > n && (int64_t)far >= n1) {
                 add = atomicExch(&mark[far], epoch) != epoch;
-                if (add) k = valence_class(row[far + 1] - row[far]);
+                if (add) k = valence_class(row[far + 1] - row[far], t16, t32);
             }
         }
         append(add, k, far, lists, cap, cnt);
@@ -117,11 +117,21 @@ struct SinkParams {
     Work w;
     int64_t N, n0, n1;
     unsigned long long *slots;  // [kSlots][kWords]
+    const int32_t *node_part;   // per-part outputs when set
+    unsigned long long *out_parts;
+    const int64_t *part_base;   // first node of each part: vertex ids are part-local
 };
 
-__device__ inline void add_slot(unsigned long long *slots, int word, uint64_t v)
+__device__ inline int64_t local_node(const SinkParams &P, int64_t n)
 {
-    atomicAdd(&slots[(blockIdx.x & (kSlots - 1)) * kWords + word], (unsigned long long)v);
+    return P.node_part ? n - P.part_base[P.node_part[n]] : n;
+}
+
+// adds v to word `word` of the output of `part` (slot mode: part is ignored)
+__device__ inline void add_out(const SinkParams &P, int32_t part, int word, uint64_t v)
+{
+    if (P.node_part) atomicAdd(&P.out_parts[(int64_t)part * kWords + word], (unsigned long long)v);
+    else atomicAdd(&P.slots[(blockIdx.x & (kSlots - 1)) * kWords + word], (unsigned long long)v);
 }
 
 // Mesh vertices and hole fans of the range's nodes, from their records.
@@ -132,8 +142,9 @@ __global__ void __launch_bounds__(64) k_sink_nodes(SinkParams P)
     const int lane = threadIdx.x;
     if (n >= P.n1) return;
     const int64_t rb = W.node_rec[n];
+    const int32_t part = P.node_part ? P.node_part[n] : 0;
     if (rb < 0) {
-        if (lane == 0) add_slot(P.slots, 7, 1);
+        if (lane == 0) add_out(P, part, 7, 1);
         return;
     }
     const uint32_t *R = W.rec + rb;
@@ -143,6 +154,7 @@ __global__ void __launch_bounds__(64) k_sink_nodes(SinkParams P)
     const uint32_t *RA = RV + 4 * V;
     const uint32_t *RH = RA + kRecArcFields * E;
     const float4 c4 = W.node4[n];
+    const int64_t ln = local_node(P, n);
     auto af = [&](int f, int j) { return __uint_as_float(RA[f * E + j]); };
     uint64_t hv = 0, sx = 0, sy = 0, sz = 0, ht = 0;
     for (int i = lane; i < M; i += 64) {
@@ -176,7 +188,7 @@ __global__ void __launch_bounds__(64) k_sink_nodes(SinkParams P)
             w2 = __uint_as_float(RH[2 * NC + c]);
         }
         const float x = c4.x + w0, y = c4.y + w1, z = c4.z + w2;
-        hv += vert_key(vid_of(n, i), x, y, z);
+        hv += vert_key(vid_of(ln, i), x, y, z);
         sx += (uint64_t)llrint((double)x * 1048576.0);
         sy += (uint64_t)llrint((double)y * 1048576.0);
         sz += (uint64_t)llrint((double)z * 1048576.0);
@@ -199,7 +211,7 @@ __global__ void __launch_bounds__(64) k_sink_nodes(SinkParams P)
         const int lo_i = i0 < i1 ? i0 : i1, hi_i = i0 < i1 ? i1 : i0;
         const int u = lo_i == 0 ? vs : mbase + (fwd ? lo_i - 1 : nseg - 1 - lo_i);
         const int u2i = hi_i == nseg ? ve : mbase + (fwd ? hi_i - 1 : nseg - 1 - hi_i);
-        ht += tri_key(vid_of(n, wsum + contour), vid_of(n, lower ? u2i : u), vid_of(n, lower ? u : u2i));
+        ht += tri_key(vid_of(ln, wsum + contour), vid_of(ln, lower ? u2i : u), vid_of(ln, lower ? u : u2i));
     }
     hv = wave_sum_u64(hv);
     sx = wave_sum_u64(sx);
@@ -207,13 +219,13 @@ __global__ void __launch_bounds__(64) k_sink_nodes(SinkParams P)
     sz = wave_sum_u64(sz);
     ht = wave_sum_u64(ht);
     if (lane == 0) {
-        add_slot(P.slots, 0, (uint64_t)F);
-        add_slot(P.slots, 1, ht);
-        add_slot(P.slots, 2, (uint64_t)M);
-        add_slot(P.slots, 3, hv);
-        add_slot(P.slots, 4, sx);
-        add_slot(P.slots, 5, sy);
-        add_slot(P.slots, 6, sz);
+        add_out(P, part, 0, (uint64_t)F);
+        add_out(P, part, 1, ht);
+        add_out(P, part, 2, (uint64_t)M);
+        add_out(P, part, 3, hv);
+        add_out(P, part, 4, sx);
+        add_out(P, part, 5, sy);
+        add_out(P, part, 6, sz);
     }
 }
 
@@ -256,6 +268,7 @@ __global__ void __launch_bounds__(64) k_sink_zip(SinkParams P, const int32_t *li
     __shared__ int g_na[kZipGroup], g_nb[kZipGroup], g_ra[kZipGroup], g_rb[kZipGroup];
     __shared__ int64_t g_la[kZipGroup], g_lb[kZipGroup], g_a[kZipGroup], g_b[kZipGroup];
     __shared__ int g_t[kZipGroup + 1];
+    __shared__ unsigned long long g_h[kZipGroup];  // triangle-key sum per strut
     const Work &W = P.w;
     const int lane = threadIdx.x;
     const int64_t ns_all = *cnt;
@@ -276,6 +289,7 @@ __global__ void __launch_bounds__(64) k_sink_zip(SinkParams P, const int32_t *li
         g_a[lane] = a < b ? a : b;
         g_b[lane] = a < b ? b : a;
         c = g_na[lane] + g_nb[lane];
+        g_h[lane] = 0ull;
     }
     int ct = c;
 #pragma unroll
@@ -307,8 +321,8 @@ __global__ void __launch_bounds__(64) k_sink_zip(SinkParams P, const int32_t *li
         }
         __syncthreads();
     }
-    uint64_t ht = 0;
     for (int x = lane; x < ntri; x += 64) {
+        uint64_t ht = 0;
         int i = 0;
         while (g_t[i + 1] <= x) ++i;
         const int j = x - g_t[i];
@@ -335,7 +349,7 @@ __global__ void __launch_bounds__(64) k_sink_zip(SinkParams P, const int32_t *li
             }
             return lo == 0 ? n - 1 : lo - 1;
         };
-        const int64_t na_node = g_a[i], nb_node = g_b[i];
+        const int64_t na_node = local_node(P, g_a[i]), nb_node = local_node(P, g_b[i]);
         if (j < na) {
             int k0 = j - ra;
             if (k0 < 0) k0 += na;
@@ -351,11 +365,26 @@ __global__ void __launch_bounds__(64) k_sink_zip(SinkParams P, const int32_t *li
             const int ap = pred(false, __int_as_float(w2.y), true);
             ht += tri_key(vid_of(nb_node, w2.x), vid_of(nb_node, w.x), vid_of(na_node, A(ap).x));
         }
+        atomicAdd(&g_h[i], (unsigned long long)ht);
     }
-    ht = wave_sum_u64(ht);
+    __syncthreads();
+    // per part of the struts' lower nodes (runs of equal parts flushed once)
     if (lane == 0) {
-        add_slot(P.slots, 0, (uint64_t)ntri);
-        add_slot(P.slots, 1, ht);
+        int32_t cur = P.node_part ? P.node_part[g_a[0]] : 0;
+        uint64_t cnt_s = 0, h_s = 0;
+        for (int i = 0; i < ns; ++i) {
+            const int32_t pt = P.node_part ? P.node_part[g_a[i]] : 0;
+            if (pt != cur) {
+                add_out(P, cur, 0, cnt_s);
+                add_out(P, cur, 1, h_s);
+                cur = pt;
+                cnt_s = h_s = 0;
+            }
+            cnt_s += (uint64_t)(g_t[i + 1] - g_t[i]);
+            h_s += g_h[i];
+        }
+        add_out(P, cur, 0, cnt_s);
+        add_out(P, cur, 1, h_s);
     }
 }
 
@@ -379,16 +408,18 @@ inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b);
 int64_t sink_slots_words() { return (int64_t)kSlots * kWords; }
 
 hipError_t launch_chunk_list(const Work &w, int64_t n0, int64_t n1, int32_t *mark, int32_t epoch, int32_t *lists,
-                             int64_t cap, int32_t *cnt, int64_t *info, hipStream_t st)
+                             int64_t cap, int32_t *cnt, int64_t *info, int t16, int t32, hipStream_t st)
 {
-    if (n1 > n0) k_chunk_list<<<grid_for(n1 - n0, 256), 256, 0, st>>>(n0, n1, w.row, w.he, mark, epoch, lists, cap, cnt);
+    if (n1 > n0)
+        k_chunk_list<<<grid_for(n1 - n0, 256), 256, 0, st>>>(n0, n1, w.row, w.he, mark, epoch, lists, cap, cnt, t16,
+                                                             t32);
     k_chunk_info<<<1, 64, 0, st>>>(cnt, cap, info);
     return hipGetLastError();
 }
 
 hipError_t launch_sink(const Inputs &in, const Work &w, int64_t n0, int64_t n1, int64_t max_struts,
                        int32_t *strut_list, int32_t *strut_cnt, unsigned long long *slots, uint64_t *out,
-                       hipStream_t st)
+                       const int32_t *node_part, uint64_t *out_parts, const int64_t *part_base, hipStream_t st)
 {
     SinkParams P;
     P.w = w;
@@ -396,6 +427,9 @@ hipError_t launch_sink(const Inputs &in, const Work &w, int64_t n0, int64_t n1, 
     P.n0 = n0;
     P.n1 = n1;
     P.slots = slots;
+    P.node_part = node_part;
+    P.out_parts = (unsigned long long *)out_parts;
+    P.part_base = part_base;
     if (n1 > n0) {
         k_sink_nodes<<<(unsigned)(n1 - n0), 64, 0, st>>>(P);
         k_chunk_struts<<<grid_for(n1 - n0, 256), 256, 0, st>>>(n0, n1, w.row, w.he, w.node_rec, strut_list,
@@ -404,7 +438,7 @@ hipError_t launch_sink(const Inputs &in, const Work &w, int64_t n0, int64_t n1, 
         if (max_struts > 0)
             k_sink_zip<<<grid_for(max_struts, kZipGroup), 64, 0, st>>>(P, strut_list, strut_cnt, in.sa, in.sb);
     }
-    k_sink_reduce<<<1, 64, 0, st>>>(slots, out);
+    if (!node_part) k_sink_reduce<<<1, 64, 0, st>>>(slots, out);
     return hipGetLastError();
 }
 

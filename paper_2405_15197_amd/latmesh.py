@@ -44,6 +44,7 @@ EXPORTS = (
     "lm_set_profiling",
     "lm_get_profile",
     "lm_forward_sink",
+    "lm_batched",
     "lm_loss",
     "lm_backward",
     "lm_plan_destroy",
@@ -113,6 +114,14 @@ class lm_loss_weights(ctypes.Structure):
     ]
 
 
+class lm_tuning(ctypes.Structure):
+    _fields_ = [
+        ("v_four_per_wave", ctypes.c_int32),
+        ("v_two_per_wave", ctypes.c_int32),
+        ("group_nodes", ctypes.c_int64),
+    ]
+
+
 class LatmeshError(RuntimeError):
     def __init__(self, code: int, where: str):
         super().__init__(f"{where}: {lm_status_string(code)} ({code})")
@@ -151,6 +160,8 @@ def load() -> ctypes.CDLL:
     lib.lm_set_precision.restype = ctypes.c_int
     lib.lm_forward_sink.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, ctypes.c_int64]
     lib.lm_forward_sink.restype = ctypes.c_int
+    lib.lm_batched.argtypes = [P, ctypes.c_int64, P, P, ctypes.POINTER(lm_tuning), P]
+    lib.lm_batched.restype = ctypes.c_int
     lib.lm_loss.argtypes = [P, ctypes.POINTER(lm_outputs), ctypes.POINTER(lm_loss_weights), P, P]
     lib.lm_loss.restype = ctypes.c_int
     lib.lm_backward.argtypes = [P, P, P, P]
@@ -223,6 +234,16 @@ def lm_forward_sink(plan, k: int, chunk_nodes: int, d_out: int, n_chunks_cap: in
     rc = load().lm_forward_sink(plan, int(k), int(chunk_nodes), ctypes.c_void_p(d_out), int(n_chunks_cap))
     if rc != LM_OK:
         raise LatmeshError(rc, "lm_forward_sink")
+
+
+def lm_batched(plan, part_off, part_k, tune, d_out: int) -> None:
+    """part_off: int64 numpy [n_parts + 1], part_k: int32 numpy [n_parts]."""
+    po = np.ascontiguousarray(part_off, np.int64)
+    pk = np.ascontiguousarray(part_k, np.int32)
+    rc = load().lm_batched(plan, len(pk), po.ctypes.data_as(ctypes.c_void_p), pk.ctypes.data_as(ctypes.c_void_p),
+                           ctypes.byref(tune) if tune is not None else None, ctypes.c_void_p(d_out))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_batched")
 
 
 def lm_backward(plan, d_dl_dx: int, d_grad_xyz: int, d_grad_radius: int) -> None:
@@ -420,6 +441,15 @@ class Mesher:
         out = torch.zeros((nch, LM_SINK_WORDS), dtype=torch.int64, device=self.device)
         lm_forward_sink(self.plan, k, chunk_nodes, out.data_ptr(), nch)
         self.torch.cuda.synchronize(self.device)
+        return out.cpu().numpy().view(np.uint64)
+
+    def batched(self, part_off, part_k, tune=None):
+        """Per-part sink words (uint64 numpy [parts, LM_SINK_WORDS]) of the
+        parts [part_off[p], part_off[p+1]) at resolutions part_k."""
+        torch = self.torch
+        out = torch.zeros((len(part_k), LM_SINK_WORDS), dtype=torch.int64, device=self.device)
+        lm_batched(self.plan, part_off, part_k, tune, out.data_ptr())
+        torch.cuda.synchronize(self.device)
         return out.cpu().numpy().view(np.uint64)
 
     def set_inputs(self, xyz, radius) -> None:
