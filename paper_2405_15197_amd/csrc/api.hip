@@ -502,33 +502,27 @@ int lm_batched(lm_plan *P, int64_t n_parts, const int64_t *part_off, const int32
     }
     int rc = sink_alloc(P);
     if (rc) return rc;
-    // per-node resolution and part (host-built once per call)
-    std::vector<int16_t> nk((size_t)N + 1);
-    std::vector<int32_t> np((size_t)N + 1);
-    int kmax = 3;
-    for (int64_t p = 0; p < n_parts; ++p) {
-        for (int64_t i = part_off[p]; i < part_off[p + 1]; ++i) {
-            nk[i] = (int16_t)part_k[p];
-            np[i] = (int32_t)p;
-        }
-        if (part_off[p + 1] > part_off[p] && part_k[p] > kmax) kmax = part_k[p];
-    }
+    // per-node resolution and part, on the device
     int16_t *d_nk = nullptr;
-    int32_t *d_np = nullptr;
+    int32_t *d_np = nullptr, *d_pk = nullptr;
     int64_t *d_pb = nullptr;
-    HIPCHK(hipMalloc((void **)&d_nk, sizeof(int16_t) * (N + 1)));
-    if (hipMalloc((void **)&d_np, sizeof(int32_t) * (N + 1)) != hipSuccess ||
-        hipMalloc((void **)&d_pb, sizeof(int64_t) * (n_parts + 1)) != hipSuccess) {
-        (void)hipFree(d_nk);
-        if (d_np) (void)hipFree(d_np);
+    uint64_t *d_slots = nullptr;  // [n_parts][sink_slots_words()]
+    const int64_t slot_words = n_parts * lm::sink_slots_words();
+    if (hipMalloc((void **)&d_nk, sizeof(int16_t) * (N + 1)) != hipSuccess ||
+        hipMalloc((void **)&d_np, sizeof(int32_t) * (N + 1)) != hipSuccess ||
+        hipMalloc((void **)&d_pk, sizeof(int32_t) * (n_parts + 1)) != hipSuccess ||
+        hipMalloc((void **)&d_pb, sizeof(int64_t) * (n_parts + 1)) != hipSuccess ||
+        hipMalloc((void **)&d_slots, sizeof(uint64_t) * slot_words) != hipSuccess) {
+        for (void *p : {(void *)d_nk, (void *)d_np, (void *)d_pk, (void *)d_pb, (void *)d_slots})
+            if (p) (void)hipFree(p);
         return LM_ERR_HIP;
     }
     rc = LM_OK;
-    if (hipMemcpyAsync(d_nk, nk.data(), sizeof(int16_t) * (N + 1), hipMemcpyHostToDevice, P->st) != hipSuccess ||
-        hipMemcpyAsync(d_np, np.data(), sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, P->st) != hipSuccess ||
-        hipMemcpyAsync(d_pb, part_off, sizeof(int64_t) * (n_parts + 1), hipMemcpyHostToDevice, P->st) !=
+    if (hipMemcpyAsync(d_pb, part_off, sizeof(int64_t) * (n_parts + 1), hipMemcpyHostToDevice, P->st) !=
             hipSuccess ||
-        hipMemsetAsync(d_out, 0, sizeof(uint64_t) * LM_SINK_WORDS * n_parts, P->st) != hipSuccess)
+        hipMemcpyAsync(d_pk, part_k, sizeof(int32_t) * n_parts, hipMemcpyHostToDevice, P->st) != hipSuccess ||
+        lm::launch_part_map(N, d_pb, d_pk, n_parts, d_np, d_nk, P->st) != hipSuccess ||
+        hipMemsetAsync(d_slots, 0, sizeof(uint64_t) * slot_words, P->st) != hipSuccess)
         rc = LM_ERR_HIP;
     P->w.node_k = d_nk;
     // groups of whole parts of about `group` nodes: one node pass each
@@ -537,14 +531,19 @@ int lm_batched(lm_plan *P, int64_t n_parts, const int64_t *part_off, const int32
         while (p1 < n_parts && part_off[p1 + 1] - part_off[p0] <= group) ++p1;
         int kg = 3;
         for (int64_t p = p0; p < p1; ++p) kg = part_k[p] > kg ? part_k[p] : kg;
-        rc = sink_range(P, kg, kg, part_off[p0], part_off[p1], t16, t32, nullptr, d_np, d_out, d_pb);
+        rc = sink_range(P, kg, kg, part_off[p0], part_off[p1], t16, t32, nullptr, d_np, d_slots, d_pb);
         p0 = p1;
     }
+    if (rc == LM_OK && lm::launch_parts_reduce((const unsigned long long *)d_slots, n_parts, d_out, P->st) !=
+                           hipSuccess)
+        rc = LM_ERR_HIP;
     (void)hipStreamSynchronize(P->st);
     P->w.node_k = nullptr;
     (void)hipFree(d_nk);
     (void)hipFree(d_np);
     (void)hipFree(d_pb);
+    (void)hipFree(d_pk);
+    (void)hipFree(d_slots);
     P->k = 0;
     return rc;
 }

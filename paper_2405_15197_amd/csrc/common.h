@@ -149,12 +149,16 @@ hipError_t launch_backward(const Inputs &in, const Work &w, const float *dldx, f
                            hipStream_t st);
 // Sink mode: chunk node lists (range + higher-id halo, in valence classes)
 // and the hashed triangles of a range.
-int64_t sink_slots_words();
+int64_t sink_slots_words();  // per chunk or per part
+hipError_t launch_parts_reduce(const unsigned long long *slots, int64_t n_parts, uint64_t *out, hipStream_t st);
+hipError_t launch_part_map(int64_t N, const int64_t *part_off, const int32_t *part_k, int64_t n_parts,
+                           int32_t *node_part, int16_t *node_k, hipStream_t st);
 hipError_t launch_chunk_list(const Work &w, int64_t n0, int64_t n1, int32_t *mark, int32_t epoch, int32_t *lists,
                              int64_t cap, int32_t *cnt, int64_t *info, int t16, int t32, hipStream_t st);
 // Outputs go to `out` (one chunk) through the slots, or with node_part set
-// to out_parts[part of the node][LM_SINK_WORDS] with vertex ids local to the
-// part (node - part_base[part]).
+// to the per-part slots out_parts[part][sink_slots_words()] (reduced by
+// launch_parts_reduce) with vertex ids local to the part (node -
+// part_base[part]).
 hipError_t launch_sink(const Inputs &in, const Work &w, int64_t n0, int64_t n1, int64_t max_struts,
                        int32_t *strut_list, int32_t *strut_cnt, unsigned long long *slots, uint64_t *out,
                        const int32_t *node_part, uint64_t *out_parts, const int64_t *part_base, hipStream_t st);

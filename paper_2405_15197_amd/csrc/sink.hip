@@ -127,11 +127,13 @@ __device__ inline int64_t local_node(const SinkParams &P, int64_t n)
     return P.node_part ? n - P.part_base[P.node_part[n]] : n;
 }
 
-// adds v to word `word` of the output of `part` (slot mode: part is ignored)
+// adds v to word `word` of the output of `part` (chunk mode: part is
+// ignored); spread over kSlots slots by block to keep atomics apart
 __device__ inline void add_out(const SinkParams &P, int32_t part, int word, uint64_t v)
 {
-    if (P.node_part) atomicAdd(&P.out_parts[(int64_t)part * kWords + word], (unsigned long long)v);
-    else atomicAdd(&P.slots[(blockIdx.x & (kSlots - 1)) * kWords + word], (unsigned long long)v);
+    const int64_t slot = blockIdx.x & (kSlots - 1);
+    if (P.node_part) atomicAdd(&P.out_parts[((int64_t)part * kSlots + slot) * kWords + word], (unsigned long long)v);
+    else atomicAdd(&P.slots[slot * kWords + word], (unsigned long long)v);
 }
 
 // Mesh vertices and hole fans of the range's nodes, from their records.
@@ -401,11 +403,51 @@ __global__ void k_sink_reduce(unsigned long long *slots, uint64_t *out)
     out[w] = s;
 }
 
+// part (binary search in the part offsets) and resolution of every node
+__global__ void k_part_map(int64_t N, const int64_t *part_off, const int32_t *part_k, int64_t n_parts,
+                           int32_t *node_part, int16_t *node_k)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    int64_t lo = 0, hi = n_parts - 1;  // last part with part_off <= n
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (part_off[mid] <= n) lo = mid;
+        else hi = mid - 1;
+    }
+    node_part[n] = (int32_t)lo;
+    node_k[n] = (int16_t)part_k[lo];
+}
+
+// per-part slots -> out[part][kWords]
+__global__ void k_parts_reduce(const unsigned long long *slots, int64_t n_parts, uint64_t *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_parts * kWords) return;
+    const int64_t p = i / kWords, w = i % kWords;
+    uint64_t s = 0;
+    for (int j = 0; j < kSlots; ++j) s += slots[(p * kSlots + j) * kWords + w];
+    out[i] = s;
+}
+
 inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
 int64_t sink_slots_words() { return (int64_t)kSlots * kWords; }
+
+hipError_t launch_part_map(int64_t N, const int64_t *part_off, const int32_t *part_k, int64_t n_parts,
+                           int32_t *node_part, int16_t *node_k, hipStream_t st)
+{
+    if (N > 0) k_part_map<<<grid_for(N, 256), 256, 0, st>>>(N, part_off, part_k, n_parts, node_part, node_k);
+    return hipGetLastError();
+}
+
+hipError_t launch_parts_reduce(const unsigned long long *slots, int64_t n_parts, uint64_t *out, hipStream_t st)
+{
+    if (n_parts > 0) k_parts_reduce<<<grid_for(n_parts * kWords, 256), 256, 0, st>>>(slots, n_parts, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_chunk_list(const Work &w, int64_t n0, int64_t n1, int32_t *mark, int32_t epoch, int32_t *lists,
                              int64_t cap, int32_t *cnt, int64_t *info, int t16, int t32, hipStream_t st)
