@@ -117,6 +117,8 @@ size_t carve(lm::Work &w, char *base, int64_t N, int64_t S)
     w.queue = (int32_t *)take(sizeof(int32_t) * (N + 1));
     w.cls_info = (int64_t *)take(sizeof(int64_t) * 8);
     w.work_ctr = (int32_t *)take(sizeof(int32_t) * 4);
+    w.loss_slots = (double *)take(sizeof(double) * 3 * lm::kLossSlots);
+    w.node_k = nullptr;
     return off;
 }
 

@@ -67,7 +67,7 @@ enum DevFlag : int {
 // lower: the arc's strut q runs to a higher node id.
 constexpr int kRecHead = 8;
 constexpr int kRecArcFields = 16;
-constexpr int kRecRegions = 16;
+constexpr int kRecRegions = 128;
 __host__ __device__ inline int64_t rec_loop_word(int V, int E, int H)
 {
     return ((int64_t)kRecHead + 4 * V + kRecArcFields * E + 3 * H + 3) & ~(int64_t)3;
@@ -106,7 +106,9 @@ struct Work {
     int64_t *cls_info;      // [8] nodes per class (0..2), queue start per class (4..6)
     int32_t *work_ctr;      // [4] per-class work counters of the node kernel
     const int16_t *node_k;  // [N] per-node resolution (batched parts) or null
+    double *loss_slots;     // [kLossSlots][3] partial loss terms
 };
+constexpr int kLossSlots = 256;
 
 // Valence classes of the node kernel: v <= 4, 5..8, otherwise.
 // (the batched entry point may lower the two limits: 4 and 8 are the class

@@ -186,11 +186,24 @@ __global__ void __launch_bounds__(64) k_loss_node(LParams P)
             atomicAdd(d + 2, 2.f * P.w_sq * x.z);
         }
     }
-    if (lane == 0) {
-        atomicAdd(&P.terms[0], area);
-        atomicAdd(&P.terms[1], vol);
-        atomicAdd(&P.terms[2], sq);
+    if (lane == 0) {  // partial sums spread over slots (same-address atomics serialise)
+        double *sl = W.loss_slots + 3 * (blockIdx.x & (kLossSlots - 1));
+        atomicAdd(&sl[0], area);
+        atomicAdd(&sl[1], vol);
+        atomicAdd(&sl[2], sq);
     }
+}
+
+// slots -> terms (and clears the slots)
+__global__ void k_loss_reduce(double *slots, double *terms)
+{
+    if (threadIdx.x >= 3) return;
+    double s = 0.0;
+    for (int i = 0; i < kLossSlots; ++i) {
+        s += slots[3 * i + threadIdx.x];
+        slots[3 * i + threadIdx.x] = 0.0;
+    }
+    terms[threadIdx.x] = s;
 }
 
 __global__ void k_zero_f(float *p, int64_t n)
@@ -201,7 +214,7 @@ __global__ void k_zero_f(float *p, int64_t n)
 
 __global__ void k_zero_d(double *p, int n)
 {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -621,8 +634,11 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 hipError_t launch_loss(const Inputs &in, const Work &w, const FillOut &o, float3 p0, float w_area, float w_vol,
                        float w_sq, float *dldx, double *terms, hipStream_t st)
 {
-    k_zero_d<<<1, 64, 0, st>>>(terms, 3);
-    if (in.n_nodes == 0) return hipGetLastError();
+    k_zero_d<<<1, 256, 0, st>>>(w.loss_slots, 3 * kLossSlots);
+    if (in.n_nodes == 0) {
+        k_zero_d<<<1, 64, 0, st>>>(terms, 3);
+        return hipGetLastError();
+    }
     // nodes whose vertices do not fit the LDS add with atomics: start from 0
     if (o.cap_mesh > 0) k_zero_f<<<grid_for(3 * o.cap_mesh), kBlock, 0, st>>>(dldx, 3 * o.cap_mesh);
     LParams P;
@@ -637,6 +653,7 @@ hipError_t launch_loss(const Inputs &in, const Work &w, const FillOut &o, float3
     P.dldx = dldx;
     P.terms = terms;
     k_loss_node<<<(unsigned)in.n_nodes, 64, 0, st>>>(P);
+    k_loss_reduce<<<1, 64, 0, st>>>(w.loss_slots, terms);
     return hipGetLastError();
 }
 
