@@ -823,21 +823,38 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
     // ---- mesh-vertex layout, hole centres, loop phi check -------------------
     {
         const int E = sh.n_arc, V = sh.n_vert, NC = sh.n_contour;
-        if (lane == 0) {
+        // prefix sums over the arcs (lanes in chunks, carried): interior
+        // points of each arc, and fan triangles of the circular arcs (which
+        // sort first; one fan triangle per segment)
+        {
             int mb = V, fb = 0, nc = 0;
-            for (int j = 0; j < E; ++j) {
-                ArcL<T> &A = sh.A[j];
-                A.mbase = mb;
-                mb += A.nseg - 1;
-                A.fbase = fb;
-                if (A.p == 0) {  // circular arcs sort first; one fan triangle per segment
-                    fb += A.nseg;
-                    ++nc;
+            for (int j0 = 0; j0 < E; j0 += WL) {
+                const int j = j0 + lane;
+                int ni = 0, nf = 0, ic = 0;
+                if (j < E) {
+                    const ArcL<T> &A = sh.A[j];
+                    ni = A.nseg - 1;
+                    if (A.p == 0) {
+                        nf = A.nseg;
+                        ic = 1;
+                    }
                 }
+                int ti, tf, tc;
+                const int ei = group_excl_scan<WL>(ni, &ti), ef = group_excl_scan<WL>(nf, &tf);
+                group_excl_scan<WL>(ic, &tc);
+                if (j < E) {
+                    sh.A[j].mbase = mb + ei;
+                    sh.A[j].fbase = fb + ef;
+                }
+                mb += ti;
+                fb += tf;
+                nc += tc;
             }
-            sh.wsum = mb;  // first hole-centre index
-            sh.fsum = fb;
-            sh.ncirc = nc;
+            if (lane == 0) {
+                sh.wsum = mb;  // first hole-centre index
+                sh.fsum = fb;
+                sh.ncirc = nc;
+            }
         }
         __syncthreads();
         // Eq. 13: barycentre of each contour's vertices (each once: half of
@@ -886,19 +903,33 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
         // strut end loops must be graphs over phi: every step (mod 2 pi)
         // positive and exactly one descent, i.e. one turn.  Lanes run over
         // all loop samples of the node and store them in the node record.
-        if (lane == 0) {
+        // loop entries (arcs of every loop, loops in label order): first
+        // sample of each entry by a carried prefix sum over the lanes
+        {
+            const int nent = sh.loop_base[v + 1];
             int off = 0;
-            for (int m = 1; m <= v; ++m) {
-                const int b0 = sh.loop_base[m], cnt = sh.loop_base[m + 1] - b0;
-                sh.lbase[m] = off;
-                for (int t = 0; t < cnt; ++t) {
-                    sh.entry_off[b0 + t] = off;
-                    sh.entry_m[b0 + t] = (uint8_t)m;
-                    off += sh.A[sh.loop_arc[b0 + sh.loop_ord[b0 + t]]].nseg;
+            for (int e0 = 0; e0 < nent; e0 += WL) {
+                const int e = e0 + lane;
+                int ns = 0, m = 1;
+                if (e < nent) {
+                    while (sh.loop_base[m + 1] <= e) ++m;
+                    const int b0 = sh.loop_base[m];
+                    ns = sh.A[sh.loop_arc[b0 + sh.loop_ord[e]]].nseg;
                 }
+                int tot;
+                const int ex = group_excl_scan<WL>(ns, &tot);
+                if (e < nent) {
+                    sh.entry_off[e] = off + ex;
+                    sh.entry_m[e] = (uint8_t)m;
+                }
+                off += tot;
             }
-            sh.lbase[v + 1] = off;
-            sh.entry_off[sh.loop_base[v + 1]] = off;
+            if (lane == 0) sh.entry_off[nent] = off;
+        }
+        __syncthreads();
+        if (lane <= v) sh.lbase[lane + 1] = sh.entry_off[sh.loop_base[lane + 1]];  // lane v: the total
+        if (lane == 0) {
+            const int off = sh.entry_off[sh.loop_base[v + 1]];
             // record space: bump allocation in the node's region
             const int64_t words = rec_loop_word(V, E, NC) + (((int64_t)2 * off + 3) & ~(int64_t)3);
             const int g = (int)(n & (kRecRegions - 1));
