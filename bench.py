@@ -152,6 +152,39 @@ def adjoint_bench(steps: int, warmup: int, k: int = 16):
     }
 
 
+def retri_bench(M, k0: int, ks, steps: int, warmup: int):
+    """Re-subdivision of the k0 meta-mesh at other resolutions against a
+    forward pass at those resolutions, on the plan's lattice."""
+    import torch
+
+    from paper_2405_15197_amd.latmesh import lm_forward, lm_read_totals, lm_retriangulate
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    out = {"k0": k0}
+    for k in ks:
+        M.count(k0)
+        r = M.retriangulate(k, meta=True)  # sizes the buffers
+        o = M.outputs(r)
+        f_ms = timed(lambda: lm_forward(M.plan, k, o))
+        lm_forward(M.plan, k0, M.outputs(M.alloc(M.count(k0), meta=True)))
+        r_ms = timed(lambda: lm_retriangulate(M.plan, k, o))
+        lm_read_totals(M.plan)
+        out[f"k{k}"] = {"forward_ms": f_ms, "retriangulate_ms": r_ms, "speedup": f_ms / r_ms,
+                        "triangles": r.totals["n_triangles"]}
+    return out
+
+
 def billion_bench(k: int = 12, chunk_nodes: int = 1 << 23, scale: int = 512):
     """The BCC 512^3 lattice (269,223,425 nodes, 1,073,741,824 struts; radii
     0.08 (1 + U[-0.1, 0.1]), no jitter), generated on the device, meshed in
@@ -279,6 +312,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-scale", type=int, default=64, help="BCC cells per side of the oracle's lattice")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint leg (octet 32^3)")
+    ap.add_argument("--no-retri", action="store_true", help="skip the re-subdivision leg")
     ap.add_argument("--billion", action="store_true",
                     help="only the BCC 512^3 lattice in sink mode (generated on the device), one pass")
     ap.add_argument("--billion-scale", type=int, default=512)
@@ -391,6 +425,9 @@ def main():
             "ms_per_launch": kern_ms,
         },
     }
+    if not args.no_retri:
+        print("[bench] re-subdivision of the k=16 meta-mesh", file=sys.stderr, flush=True)
+        res["retriangulate"] = retri_bench(M, args.k, (8, 32), args.steps, args.warmup)
     M.close()
     if not args.no_adjoint:
         print("[bench] forward + adjoint on octet 32^3", file=sys.stderr, flush=True)

@@ -175,8 +175,29 @@ int lm_fill(lm_plan *plan, const lm_outputs *out);
  * lm_count at the same or a larger k. */
 int lm_forward(lm_plan *plan, int k, const lm_outputs *out);
 
-/* Synchronise the stream and return the totals of the last lm_forward or
- * lm_count; LM_ERR_CAPACITY if that lm_forward skipped writes. */
+/* Multi-resolution re-triangulation (Alg. 1 keeps the meta-mesh apart from
+ * its subdivision; Eqs. 11-13).  Subdivide the meta-mesh of the last
+ * lm_count or lm_forward again at k segments per full turn (3 <= k <= 4096)
+ * and write the triangle mesh, without re-solving any node: vertices, arcs
+ * and holes are read from the stored node records and only the arc
+ * subdivision, the end loops, the fans and the strut bands are redone.  The
+ * result equals lm_forward at k on the same lattice except for nodes whose
+ * status depends on k (a loop or subdivision failure at one of the two
+ * resolutions).  The meta-mesh stays in the plan: any number of calls may
+ * follow, each from the same meta-mesh.  The new records go to a second
+ * record space held by the plan (allocated at the first call; about the
+ * size of the first at the same k); lm_loss and lm_backward then act on the
+ * re-triangulated mesh.  lm_fill returns LM_ERR_STATE until the next
+ * lm_count.  Asynchronous; read the totals with lm_read_totals, which
+ * returns LM_ERR_CAPACITY if a buffer was too small (then nothing usable
+ * was written).  Returns LM_ERR_STATE if no meta-mesh is held (lm_count or
+ * lm_forward has not run, or lm_forward_sink, lm_batched or
+ * lm_set_precision ran after it). */
+int lm_retriangulate(lm_plan *plan, int k, const lm_outputs *out);
+
+/* Synchronise the stream and return the totals of the last lm_forward,
+ * lm_retriangulate or lm_count; LM_ERR_CAPACITY if that call skipped
+ * writes. */
 int lm_read_totals(lm_plan *plan, lm_totals *totals);
 
 /* Mixed precision.  Nodes are meshed in FP32; a node is meshed again in

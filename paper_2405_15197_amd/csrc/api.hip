@@ -1,5 +1,6 @@
 // Host side of the C ABI declared in include/latmesh.h.
 #include <new>
+#include <utility>
 #include <string.h>
 #include <vector>
 
@@ -24,6 +25,16 @@ struct lm_plan {
     int64_t sk_struts_cap = 0;
     unsigned long long *sk_slots = nullptr;
     int32_t sk_epoch = 0;
+    // second record slot (re-subdivision): records, node record index, bump
+    // counters; base_slot says where the meta-mesh of the last count is
+    uint32_t *alt_rec = nullptr;
+    int64_t alt_rec_words = 0;
+    int64_t *alt_node_rec = nullptr;
+    unsigned long long *alt_rec_top = nullptr;
+    int base_slot = 0;
+    // the allocations behind the second node record index and counters (the
+    // pointers above swap with the workspace's own at every switch)
+    void *alt_index_mem = nullptr;
     int k;          // resolution of the last count (0: none)
     float kappa_max;// FP32 -> FP64 hand-over threshold
     lm_totals last; // totals of the last lm_count
@@ -148,10 +159,13 @@ lm::FillOut to_fill(const lm_outputs *o)
 
 // Count pass: per-node meta-meshing and counts, band counts, prefix sums,
 // device totals (and capacity flags when out != nullptr).
-int run_count(lm_plan *P, int k, const lm::FillOut *out)
+// Node pass (meta-meshing at k, or with src_rec set the re-subdivision of
+// the meta-mesh in those records) into the records of w, then band counts,
+// prefix sums and device totals.
+int run_count(lm_plan *P, int k, const lm::FillOut *out, const lm::Work &w, const uint32_t *src_rec = nullptr,
+              const int64_t *src_node_rec = nullptr)
 {
     const int64_t N = P->in.n_nodes, S = P->in.n_struts;
-    lm::Work &w = P->w;
     // flags[0] (count / fill) and flags[2] (FP64 hand-over count)
     HIPCHK(hipMemsetAsync(w.flags, 0, sizeof(int32_t), P->st));
     HIPCHK(hipMemsetAsync(w.flags + 2, 0, sizeof(int32_t), P->st));
@@ -160,11 +174,11 @@ int run_count(lm_plan *P, int k, const lm::FillOut *out)
     HIPCHK(hipMemsetAsync(w.work_ctr, 0, sizeof(int32_t) * 4, P->st));
     {
         PhaseTimer t(P, PH_NODE32);
-        HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, 0, P->st));
+        HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, 0, P->st, src_rec, src_node_rec));
     }
     {
         PhaseTimer t(P, PH_NODE64);
-        HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, 1, P->st));
+        HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, 1, P->st, src_rec, src_node_rec));
     }
     PhaseTimer t(P, PH_SIZES);
     HIPCHK(lm::launch_band_count(P->in, w, P->st));
@@ -223,27 +237,27 @@ int64_t rec_estimate(const lm_plan *P, int k)
     return words + words / 8 + 4096;
 }
 
-int fill_common(lm_plan *P, const lm::FillOut &f, const lm_outputs *out)
+int fill_common(lm_plan *P, const lm::FillOut &f, const lm_outputs *out, const lm::Work &w)
 {
     const int64_t N = P->in.n_nodes;
     {
         PhaseTimer t(P, PH_EXPAND);
-        HIPCHK(lm::launch_expand(P->in, P->w, f, P->st));
+        HIPCHK(lm::launch_expand(P->in, w, f, P->st));
     }
     {
         PhaseTimer t(P, PH_ZIP);
-        HIPCHK(lm::launch_zip(P->in, P->w, f, P->st));
+        HIPCHK(lm::launch_zip(P->in, w, f, P->st));
     }
     if (out->d_node_off)
-        HIPCHK(hipMemcpyAsync(out->d_node_off, P->w.node_off, sizeof(int64_t) * lm::kNodeScanCols * (N + 1),
+        HIPCHK(hipMemcpyAsync(out->d_node_off, w.node_off, sizeof(int64_t) * lm::kNodeScanCols * (N + 1),
                               hipMemcpyDeviceToDevice, P->st));
     if (out->d_strut_off)
-        HIPCHK(hipMemcpyAsync(out->d_strut_off, P->w.band_off, sizeof(int64_t) * (P->in.n_struts + 1),
+        HIPCHK(hipMemcpyAsync(out->d_strut_off, w.band_off, sizeof(int64_t) * (P->in.n_struts + 1),
                               hipMemcpyDeviceToDevice, P->st));
     if (out->d_node_status && N > 0) {
         // int32 status column -> uint8 (values fit in 8 bits)
         lm_k_status_u8<<<(unsigned)((N + 255) / 256), 256, 0, P->st>>>(
-            P->w.node_cnt + (int64_t)lm::NC_STATUS * N, out->d_node_status, N);
+            w.node_cnt + (int64_t)lm::NC_STATUS * N, out->d_node_status, N);
         HIPCHK(hipGetLastError());
     }
     return LM_OK;
@@ -286,6 +300,7 @@ int lm_plan_create(lm_plan **plan, const lm_lattice *lat, void *stream)
     int rc = LM_OK;
     int32_t fl = 0;
     if (hipMemsetAsync(P->w.flags, 0, sizeof(int32_t) * 4, P->st) != hipSuccess ||
+        hipMemsetAsync(P->w.totals, 0, sizeof(int64_t) * 16, P->st) != hipSuccess ||
         lm::launch_prepare(P->in, P->w, P->st) != hipSuccess ||
         hipMemcpyAsync(&fl, P->w.flags + 1, sizeof(int32_t), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
         hipStreamSynchronize(P->st) != hipSuccess) {
@@ -309,7 +324,7 @@ int lm_count(lm_plan *P, int k, lm_totals *totals)
     if (P->w.rec_words == 0 && (rc = ensure_rec(P, rec_estimate(P, k)))) return rc;
     int32_t fl = 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
-        if ((rc = run_count(P, k, nullptr))) return rc;
+        if ((rc = run_count(P, k, nullptr, P->w))) return rc;
         if ((rc = read_totals(P, totals, &fl))) return rc;
         if (totals->n_mesh_vertices > 0x7fffffffLL) return LM_ERR_UNSUPPORTED;
         if (!(fl & lm::DF_RECCAP)) break;
@@ -318,6 +333,7 @@ int lm_count(lm_plan *P, int k, lm_totals *totals)
     }
     if (fl & lm::DF_RECCAP) return LM_ERR_INTERNAL;
     P->k = k;
+    P->base_slot = 0;
     P->last = *totals;
     return LM_OK;
 }
@@ -331,7 +347,8 @@ int lm_fill(lm_plan *P, const lm_outputs *out)
     lm::FillOut f = to_fill(out);
     if (f.vert_name && out->cap_vertices < t.n_vertices) return LM_ERR_CAPACITY;
     if (f.arc_f32 && out->cap_arcs < t.n_arcs) return LM_ERR_CAPACITY;
-    return fill_common(P, f, out);
+    if (P->base_slot != 0) return LM_ERR_STATE;  // re-subdivided since lm_count
+    return fill_common(P, f, out, P->w);
 }
 
 int lm_forward(lm_plan *P, int k, const lm_outputs *out)
@@ -340,10 +357,11 @@ int lm_forward(lm_plan *P, int k, const lm_outputs *out)
     lm::FillOut f = to_fill(out);
     int rc = LM_OK;
     if (P->w.rec_words == 0 && (rc = ensure_rec(P, rec_estimate(P, k)))) return rc;
-    rc = run_count(P, k, &f);
+    rc = run_count(P, k, &f, P->w);
     if (rc) return rc;
     P->k = k;
-    return fill_common(P, f, out);
+    P->base_slot = 0;
+    return fill_common(P, f, out, P->w);
 }
 
 int lm_loss(lm_plan *P, const lm_outputs *out, const lm_loss_weights *w, double *d_terms, float *d_dl_dx)
@@ -550,6 +568,66 @@ int lm_batched(lm_plan *P, int64_t n_parts, const int64_t *part_off, const int32
     return rc;
 }
 
+int lm_retriangulate(lm_plan *P, int k, const lm_outputs *out)
+{
+    if (!P || !out || !out->d_mesh_xyz || !out->d_tri || k < 3 || k > 4096) return LM_ERR_INVALID_ARG;
+    if (P->k == 0) return LM_ERR_STATE;  // no meta-mesh from lm_count / lm_forward
+    const int64_t N = P->in.n_nodes;
+    if (!P->alt_index_mem) {
+        const size_t bytes = sizeof(int64_t) * (N + 1) + sizeof(unsigned long long) * lm::kRecRegions;
+        HIPCHK(hipMalloc(&P->alt_index_mem, bytes));
+        P->alt_rec_top = (unsigned long long *)P->alt_index_mem;
+        P->alt_node_rec = (int64_t *)((char *)P->alt_index_mem + sizeof(unsigned long long) * lm::kRecRegions);
+    }
+    // the slot that does not hold the meta-mesh receives the new records
+    const bool base_in_w = P->base_slot == 0;
+    const uint32_t *src_rec = base_in_w ? P->w.rec : P->alt_rec;
+    const int64_t *src_node_rec = base_in_w ? P->w.node_rec : P->alt_node_rec;
+    // records differ from the source's only in their loop samples, whose
+    // count grows at most like k: scale the source slot's size
+    const int64_t src_words = base_in_w ? P->w.rec_words : P->alt_rec_words;
+    int64_t need = rec_estimate(P, k);
+    if (k > P->k) {
+        const int64_t scaled = (int64_t)((double)src_words * k / P->k);
+        need = scaled > need ? scaled : need;
+    } else if (src_words > need) {
+        need = src_words;
+    }
+    const int64_t unit = 4 * lm::kRecRegions;
+    need = (need + unit - 1) / unit * unit;
+    lm::Work wd = P->w;
+    if (base_in_w) {
+        if (need > P->alt_rec_words) {
+            HIPCHK(hipStreamSynchronize(P->st));
+            if (P->alt_rec) HIPCHK(hipFree(P->alt_rec));
+            P->alt_rec = nullptr;
+            HIPCHK(hipMalloc((void **)&P->alt_rec, sizeof(uint32_t) * need));
+            P->alt_rec_words = need;
+        }
+        wd.rec = P->alt_rec;
+        wd.rec_words = P->alt_rec_words;
+        wd.node_rec = P->alt_node_rec;
+        wd.rec_top = P->alt_rec_top;
+    } else if ((P->w.rec_words < need)) {
+        int rc = ensure_rec(P, need);  // the current slot holds an earlier re-subdivision only
+        if (rc) return rc;
+        wd = P->w;
+    }
+    lm::FillOut f = to_fill(out);
+    int rc = run_count(P, k, &f, wd, src_rec, src_node_rec);
+    if (rc) return rc;
+    rc = fill_common(P, f, out, wd);
+    if (rc) return rc;
+    if (base_in_w) {  // the new records become current; the meta-mesh moves to the other slot
+        std::swap(P->w.rec, P->alt_rec);
+        std::swap(P->w.rec_words, P->alt_rec_words);
+        std::swap(P->w.node_rec, P->alt_node_rec);
+        std::swap(P->w.rec_top, P->alt_rec_top);
+        P->base_slot = 1;
+    }
+    return LM_OK;
+}
+
 int lm_read_totals(lm_plan *P, lm_totals *totals)
 {
     if (!P || !totals) return LM_ERR_INVALID_ARG;
@@ -615,7 +693,7 @@ void lm_plan_destroy(lm_plan *P)
     for (auto e : P->pool) (void)hipEventDestroy(e);
     if (P->w.rec) (void)hipFree(P->w.rec);
     for (void *p : {(void *)P->sk_mark, (void *)P->sk_lists, (void *)P->sk_cnt, (void *)P->sk_info,
-                    (void *)P->sk_struts, (void *)P->sk_slots})
+                    (void *)P->sk_struts, (void *)P->sk_slots, (void *)P->alt_rec, P->alt_index_mem})
         if (p) (void)hipFree(p);
     (void)hipFree(P->ws);
     delete P;

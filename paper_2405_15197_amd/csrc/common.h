@@ -60,6 +60,11 @@ enum DevFlag : int {
 //                       p | q<<8 | whole<<16 | fwd<<17 | lower<<18,
 //                       vs | ve<<16, nseg | contour<<16, mbase, fbase
 //   holes   [3][H]      hole centres (node-local)
+//   loop table          bytes: loop start of each strut label 1..v+1 (v+1
+//                       bytes), then for every loop entry in loop order its
+//                       arc | 0x80 if the arc runs along the loop (header
+//                       word 7 = v | entries << 8 | fp64 << 24, fp64
+//                       set when the node was meshed in FP64)
 //   loops               from a multiple of 4 words: for each incident strut
 //                       in label order, its end loop as int2 (node-local mesh
 //                       vertex, phi bits), in loop order
@@ -68,9 +73,13 @@ enum DevFlag : int {
 constexpr int kRecHead = 8;
 constexpr int kRecArcFields = 16;
 constexpr int kRecRegions = 128;
-__host__ __device__ inline int64_t rec_loop_word(int V, int E, int H)
+__host__ __device__ inline int64_t rec_table_word(int V, int E, int H)
 {
-    return ((int64_t)kRecHead + 4 * V + kRecArcFields * E + 3 * H + 3) & ~(int64_t)3;
+    return (int64_t)kRecHead + 4 * V + kRecArcFields * E + 3 * H;
+}
+__host__ __device__ inline int64_t rec_loop_word(int V, int E, int H, int table_bytes)
+{
+    return (rec_table_word(V, E, H) + (table_bytes + 3) / 4 + 3) & ~(int64_t)3;
 }
 
 struct Inputs {
@@ -137,7 +146,10 @@ hipError_t launch_scan(const int32_t *src, int64_t *dst, int64_t n, int ncols, i
                        int64_t dst_stride, int64_t *tmp, int64_t tmp_len, hipStream_t st);
 // Per-node meta-meshing (counts and node records), FP32 over all nodes or
 // FP64 over the hand-over list.
-hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, int fp64, hipStream_t st);
+// With src_rec set, the meta-mesh of each node is read from its record in
+// src_rec (src_node_rec) and only re-subdivided at resolution k.
+hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, int fp64, hipStream_t st,
+                       const uint32_t *src_rec = nullptr, const int64_t *src_node_rec = nullptr);
 // Node records -> meta-mesh, mesh vertices and hole fans.
 hipError_t launch_expand(const Inputs &in, const Work &w, const FillOut &o, hipStream_t st);
 hipError_t launch_band_count(const Inputs &in, const Work &w, hipStream_t st);

@@ -422,6 +422,9 @@ struct Params {
     Work w;
     int k;
     float kappa_max;  // FP32 nodes with a vertex above this go to FP64
+    // re-subdivision: the meta-mesh comes from these records instead
+    const uint32_t *src_rec;
+    const int64_t *src_node_rec;
 };
 
 // statuses that FP64 may resolve
@@ -429,6 +432,322 @@ constexpr int kRetry = NS_NON_ELLIPTIC | NS_LOOP | NS_TOPOLOGY | NS_PREC | NS_CA
 
 // The whole per-node computation: counts, and the node record for the
 // expansion pass.
+// Subdivision at resolution k and the node record, for a node whose
+// meta-mesh (arcs, vertices, end loops, contours) is in LDS with its status.
+template <typename T, typename CF>
+__device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, const int k, const int v,
+                          const int64_t row, const T rho, const V3<T> cen)
+{
+    constexpr int WL = CF::W;
+    constexpr bool F32 = sizeof(T) == 4;
+    const T tp = Cst<T>::two_pi;
+    const int lane = threadIdx.x & (WL - 1);
+    const Work &W = P.w;
+    const int64_t N = P.in.n_nodes;
+    (void)tp;
+    (void)cen;
+    (void)k;
+    if (sh.status) goto finish;
+
+    // ---- mesh-vertex layout, hole centres, loop phi check -------------------
+    {
+        const int E = sh.n_arc, V = sh.n_vert, NC = sh.n_contour;
+        // prefix sums over the arcs (lanes in chunks, carried): interior
+        // points of each arc, and fan triangles of the circular arcs (which
+        // sort first; one fan triangle per segment)
+        {
+            int mb = V, fb = 0, nc = 0;
+            for (int j0 = 0; j0 < E; j0 += WL) {
+                const int j = j0 + lane;
+                int ni = 0, nf = 0, ic = 0;
+                if (j < E) {
+                    const ArcL<T> &A = sh.A[j];
+                    ni = A.nseg - 1;
+                    if (A.p == 0) {
+                        nf = A.nseg;
+                        ic = 1;
+                    }
+                }
+                int ti, tf, tc;
+                const int ei = group_excl_scan<WL>(ni, &ti), ef = group_excl_scan<WL>(nf, &tf);
+                group_excl_scan<WL>(ic, &tc);
+                if (j < E) {
+                    sh.A[j].mbase = mb + ei;
+                    sh.A[j].fbase = fb + ef;
+                }
+                mb += ti;
+                fb += tf;
+                nc += tc;
+            }
+            if (lane == 0) {
+                sh.wsum = mb;  // first hole-centre index
+                sh.fsum = fb;
+                sh.ncirc = nc;
+            }
+        }
+        __syncthreads();
+        // Eq. 13: barycentre of each contour's vertices (each once: half of
+        // both ends of every arc plus its interior points), projected on the
+        // nodal sphere; the point opposite is used when the projection falls
+        // under a strut, and -sum(e_m) when the barycentre is within 1e-3 rho
+        // of the centre.
+        for (int c = lane; c < NC; c += WL) {
+            V3<T> sum = zero3<T>();
+            int cntv = 0;
+            for (int j = 0; j < E && sh.A[j].p == 0; ++j) {
+                const ArcL<T> &A = sh.A[j];
+                if (A.contour != c) continue;
+                sum = sum + (vert_pos(sh, A.vs) + vert_pos(sh, A.ve)) * (T)0.5;
+                for (int ii = 1; ii < A.nseg; ++ii) sum = sum + interior_pt(A, ii);
+                cntv += A.nseg;
+            }
+            V3<T> b = sum * ((T)1 / (T)cntv);
+            T bl = m_sqrt(dot(b, b));
+            // the apex direction b/|b| amplifies rounding by rho/|b|; the
+            // fallback decision near |b| = 1e-3 rho is fragile as well
+            if (F32 && bl * (T)P.kappa_max < rho) atomicOr(&sh.status, NS_PREC);
+            V3<T> dir;
+            if (bl >= (T)1e-3 * rho) {
+                dir = b * ((T)1 / bl);
+            } else {
+                V3<T> se = zero3<T>();
+                for (int m = 1; m <= v; ++m) se = se + v3(sh.S[m].ex, sh.S[m].ey, sh.S[m].ez);
+                T sl = m_sqrt(dot(se, se));
+                if (sl < (T)1e-3) { atomicOr(&sh.status, NS_TOPOLOGY); sl = (T)1; }
+                dir = se * ((T)-1 / sl);
+            }
+            for (int flip = 0; flip < 2; ++flip) {
+                T pm = (T)-1e30;
+                for (int m = 1; m <= v; ++m) pm = m_max(pm, dot(gvec(sh.S[m]), dir * rho) - sh.S[m].h);
+                if (pm <= (T)0) break;
+                if (flip) atomicOr(&sh.status, NS_TOPOLOGY);
+                dir = dir * (T)-1;
+            }
+            sh.hc[c][0] = dir.x * rho;
+            sh.hc[c][1] = dir.y * rho;
+            sh.hc[c][2] = dir.z * rho;
+        }
+        __syncthreads();
+        if (sh.status) goto finish;
+        // strut end loops must be graphs over phi: every step (mod 2 pi)
+        // positive and exactly one descent, i.e. one turn.  Lanes run over
+        // all loop samples of the node and store them in the node record.
+        // loop entries (arcs of every loop, loops in label order): first
+        // sample of each entry by a carried prefix sum over the lanes
+        {
+            const int nent = sh.loop_base[v + 1];
+            int off = 0;
+            for (int e0 = 0; e0 < nent; e0 += WL) {
+                const int e = e0 + lane;
+                int ns = 0, m = 1;
+                if (e < nent) {
+                    while (sh.loop_base[m + 1] <= e) ++m;
+                    const int b0 = sh.loop_base[m];
+                    ns = sh.A[sh.loop_arc[b0 + sh.loop_ord[e]]].nseg;
+                }
+                int tot;
+                const int ex = group_excl_scan<WL>(ns, &tot);
+                if (e < nent) {
+                    sh.entry_off[e] = off + ex;
+                    sh.entry_m[e] = (uint8_t)m;
+                }
+                off += tot;
+            }
+            if (lane == 0) sh.entry_off[nent] = off;
+        }
+        __syncthreads();
+        if (lane <= v) sh.lbase[lane + 1] = sh.entry_off[sh.loop_base[lane + 1]];  // lane v: the total
+        if (lane == 0) {
+            const int off = sh.entry_off[sh.loop_base[v + 1]];
+            // record space: bump allocation in the node's region
+            const int64_t words =
+                rec_loop_word(V, E, NC, v + 1 + sh.loop_base[v + 1]) + (((int64_t)2 * off + 3) & ~(int64_t)3);
+            const int g = (int)(n & (kRecRegions - 1));
+            const int64_t region = W.rec_words / kRecRegions;
+            const unsigned long long old = atomicAdd(&W.rec_top[g], (unsigned long long)words);
+            if ((int64_t)old + words <= region) {
+                sh.rec = (int64_t)g * region + (int64_t)old;
+            } else {
+                sh.rec = -1;
+                atomicOr(&W.flags[0], DF_RECCAP);
+            }
+        }
+        if (lane < v) {
+            sh.loop_desc[lane + 1] = 0;
+            sh.loop_rot[lane + 1] = 0;
+        }
+        __syncthreads();
+        {
+            const int nent = sh.loop_base[v + 1];
+            const int ns_tot = sh.entry_off[nent];
+            int2 *rl = sh.rec >= 0 ? (int2 *)(W.rec + sh.rec + rec_loop_word(V, E, NC, v + 1 + sh.loop_base[v + 1]))
+                                   : nullptr;
+            // phi key and local mesh index of sample j of loop entry e
+            auto sample = [&](int e, int j, int &li) -> T {
+                const int m = sh.entry_m[e];
+                const int pp = sh.loop_base[m] + sh.loop_ord[e];
+                const ArcL<T> &A = sh.A[sh.loop_arc[pp]];
+                const int d = sh.loop_dir[pp];
+                const int ii = d > 0 ? j : A.nseg - j;
+                li = j == 0 ? (d > 0 ? A.vs : A.ve) : interior_idx(A, ii);
+                T st, ct;
+                m_sincos(sub_param(A, ii), &st, &ct);
+                // tangency circles are parametrised in the strut frame: phi
+                // is the parameter itself
+                if (A.p == 0) return phi_key(st, ct);
+                V3<T> w = j == 0 ? vert_pos(sh, li) : arc_con(A).o + arc_con(A).a * st + arc_con(A).b * ct;
+                const SL<T> &sm = sh.S[m];
+                return phi_key(dot(w, v3(sm.qx, sm.qy, sm.qz)), dot(w, v3(sm.rx, sm.ry, sm.rz)));
+            };
+            // each lane checks the step from the previous sample of its loop
+            // (the previous lane's, or the last of the previous chunk); the
+            // step that closes a loop is checked afterwards.  A valid loop
+            // has exactly one descent, just before its smallest phi.
+            T carry = (T)0;
+            for (int base = 0; base < ns_tot; base += WL) {
+                const int sidx = base + lane;
+                const bool act = sidx < ns_tot;
+                int m = 1, idx = 0, nloop = 1, li = 0;
+                T ph = (T)0;
+                if (act) {
+                    int lo = 0, hi = nent - 1;  // last entry with entry_off <= sidx
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) >> 1;
+                        if (sh.entry_off[mid] <= sidx) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    const int e = lo;
+                    m = sh.entry_m[e];
+                    idx = sidx - sh.entry_off[sh.loop_base[m]];
+                    nloop = sh.loop_len[m];
+                    ph = sample(e, sidx - sh.entry_off[e], li);
+                }
+                T prev = __shfl_up(ph, 1, WL);
+                if (lane == 0) prev = carry;
+                carry = __shfl(ph, WL - 1, WL);
+                if (act) {
+                    if (idx == 0) {
+                        sh.ph_first[m] = ph;
+                    } else {
+                        T dp = ph - prev;  // in key units: a full turn is 4
+                        if (dp <= (T)-2) dp += (T)4;
+                        if (dp > (T)2) dp -= (T)4;
+                        if (!(dp > (T)0)) atomicOr(&sh.status, NS_LOOP);
+                        if (ph < prev) {
+                            atomicAdd(&sh.loop_desc[m], 1);
+                            sh.loop_rot[m] = idx;
+                        }
+                    }
+                    if (idx == nloop - 1) sh.ph_last[m] = ph;
+                    if (rl) rl[sidx] = make_int2(li, __float_as_int((float)ph));
+                }
+            }
+        }
+        __syncthreads();
+        if (lane < v) {
+            const int m = lane + 1;
+            const T a = sh.ph_last[m], b = sh.ph_first[m];
+            T dp = b - a;
+            if (dp <= (T)-2) dp += (T)4;
+            if (dp > (T)2) dp -= (T)4;
+            if (!(dp > (T)0)) atomicOr(&sh.status, NS_LOOP);
+            if (b < a) {
+                atomicAdd(&sh.loop_desc[m], 1);
+                sh.loop_rot[m] = 0;
+            }
+        }
+        __syncthreads();
+        if (lane < v) {
+            if (sh.loop_desc[lane + 1] != 1) atomicOr(&sh.status, NS_LOOP);
+            W.he_rot[row + lane] = sh.loop_rot[lane + 1];
+        }
+        __syncthreads();
+    }
+
+finish:
+    __syncthreads();
+    {
+        const int status = sh.status;
+        const int E = sh.n_arc, V = sh.n_vert, NC = sh.n_contour;
+        if (status) {
+            if (lane == 0) {
+                for (int c = 0; c < kNodeCols; ++c) W.node_cnt[c * N + n] = 0;
+                W.node_cnt[NC_STATUS * N + n] = status & ~NS_PREC;
+                W.node_rec[n] = -1;
+                // hand the node to the FP64 pass when precision may be at fault
+                if (F32 && (status & kRetry)) W.fb_list[atomicAdd(&W.flags[2], 1)] = (int32_t)n;
+            }
+            if (lane < v) W.he_len[row + lane] = 0;
+            return;
+        }
+        const int Msum = sh.wsum + NC, Fsum = sh.fsum;
+        const int64_t rb = sh.rec;
+        const int nent = sh.loop_base[v + 1];
+        const int64_t lw = rec_loop_word(V, E, NC, v + 1 + nent);
+        if (lane == 0) {
+            W.node_cnt[NC_VERT * N + n] = V;
+            W.node_cnt[NC_ARC * N + n] = E;
+            W.node_cnt[NC_HOLE * N + n] = NC;
+            W.node_cnt[NC_MESH * N + n] = Msum;
+            W.node_cnt[NC_FAN * N + n] = Fsum;
+            W.node_cnt[NC_STATUS * N + n] = 0;
+            W.node_rec[n] = rb;
+        }
+        if (lane < v) {
+            W.he_len[row + lane] = sh.loop_len[lane + 1];
+            W.he_loop[row + lane] = rb >= 0 ? (rb + lw) / 2 + sh.lbase[lane + 1] : 0;
+        }
+        if (rb < 0) return;
+        uint32_t *R = W.rec + rb;
+        if (lane == 0) {
+            R[0] = (uint32_t)V;
+            R[1] = (uint32_t)E;
+            R[2] = (uint32_t)NC;
+            R[3] = (uint32_t)sh.ncirc;
+            R[4] = (uint32_t)sh.wsum;
+            R[5] = (uint32_t)Msum;
+            R[6] = (uint32_t)Fsum;
+            R[7] = (uint32_t)v | ((uint32_t)nent << 8) | (F32 ? 0u : 1u << 24);
+        }
+        uint32_t *RV = R + kRecHead;
+        for (int i = lane; i < V; i += WL) {
+            RV[i] = sh.vname[i];
+            RV[V + i] = __float_as_uint((float)sh.vx[i]);
+            RV[2 * V + i] = __float_as_uint((float)sh.vy[i]);
+            RV[3 * V + i] = __float_as_uint((float)sh.vz[i]);
+        }
+        uint32_t *RA = RV + 4 * V;
+        for (int j = lane; j < E; j += WL) {
+            const ArcL<T> &A = sh.A[j];
+            const T f[11] = {A.o[0], A.o[1], A.o[2], A.a[0], A.a[1], A.a[2], A.b[0], A.b[1], A.b[2], A.t1, A.t2};
+#pragma unroll
+            for (int t = 0; t < 11; ++t) RA[t * E + j] = __float_as_uint((float)f[t]);
+            const uint32_t fwd = (A.full || A.ns <= A.ne) ? 1u : 0u;
+            const uint32_t lower = sh.S[A.q].lower ? 1u : 0u;
+            RA[11 * E + j] = (uint32_t)A.p | ((uint32_t)A.q << 8) | ((uint32_t)A.full << 16) | (fwd << 17) |
+                             (lower << 18);
+            RA[12 * E + j] = (uint32_t)A.vs | ((uint32_t)A.ve << 16);
+            RA[13 * E + j] = (uint32_t)A.nseg | (((uint32_t)A.contour & 0xffffu) << 16);
+            RA[14 * E + j] = (uint32_t)A.mbase;
+            RA[15 * E + j] = (uint32_t)A.fbase;
+        }
+        uint32_t *RH = RA + kRecArcFields * E;
+        for (int c = lane; c < NC; c += WL) {
+            RH[c] = __float_as_uint((float)sh.hc[c][0]);
+            RH[NC + c] = __float_as_uint((float)sh.hc[c][1]);
+            RH[2 * NC + c] = __float_as_uint((float)sh.hc[c][2]);
+        }
+        // loop table (for re-subdivision at another resolution)
+        uint8_t *RT = (uint8_t *)(R + rec_table_word(V, E, NC));
+        if (lane <= v) RT[lane] = (uint8_t)sh.loop_base[lane + 1];
+        for (int e = lane; e < nent; e += WL) {
+            const int m = sh.entry_m[e];
+            const int pp = sh.loop_base[m] + sh.loop_ord[e];
+            RT[v + 1 + e] = (uint8_t)(sh.loop_arc[pp] | (sh.loop_dir[pp] > 0 ? 0x80 : 0));
+        }
+    }
+}
+
 template <typename T, typename CF>
 __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
 {
@@ -485,7 +804,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
     }
     if (F32 && lane == 0 && !(P.kappa_max > 0.f)) atomicOr(&sh.status, NS_PREC);  // all FP64
     __syncthreads();
-    if (sh.status) goto finish;
+    if (sh.status) goto tail;
 
     // ---- conics, trimming, arcs and owned vertices ------------------------
     {
@@ -621,7 +940,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
             __syncthreads();
         }
     }
-    if (sh.status) goto finish;
+    if (sh.status) goto tail;
 
     // ---- arc ends -> vertex indices, vertex degrees, segment counts -------
     {
@@ -652,7 +971,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
         for (int i = lane; i < V; i += WL)
             if ((sh.vname[i] & 0xff00u) != 0xff00u && sh.vdeg[i] != 3) atomicOr(&sh.status, NS_TOPOLOGY);
         __syncthreads();
-        if (sh.status) goto finish;
+        if (sh.status) goto tail;
     }
 
     // ---- end loops per strut ----------------------------------------------
@@ -739,7 +1058,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
             if (c == 0 || (sh.loop_full[lane] && c != 1)) atomicOr(&sh.status, NS_LOOP);
         }
         __syncthreads();
-        if (sh.status) goto finish;
+        if (sh.status) goto tail;
         // position of each arc in its loop; the first arc also checks that
         // the successor chain closes after exactly the loop's arc count
         for (int pp = lane; pp < tot; pp += WL) {
@@ -766,7 +1085,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
         }
         if (tot > 2 * CF::AC && lane == 0) atomicOr(&sh.status, NS_CAPACITY);
         __syncthreads();
-        if (sh.status) goto finish;
+        if (sh.status) goto tail;
     }
 
     // ---- hole contours ------------------------------------------------------
@@ -817,301 +1136,132 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
         __syncthreads();
         if (lane == 0 && sh.n_vert - sh.n_arc + sh.n_contour != 2 - v) atomicOr(&sh.status, NS_TOPOLOGY);
         __syncthreads();
-        if (sh.status) goto finish;
+        if (sh.status) goto tail;
     }
 
-    // ---- mesh-vertex layout, hole centres, loop phi check -------------------
-    {
-        const int E = sh.n_arc, V = sh.n_vert, NC = sh.n_contour;
-        // prefix sums over the arcs (lanes in chunks, carried): interior
-        // points of each arc, and fan triangles of the circular arcs (which
-        // sort first; one fan triangle per segment)
-        {
-            int mb = V, fb = 0, nc = 0;
-            for (int j0 = 0; j0 < E; j0 += WL) {
-                const int j = j0 + lane;
-                int ni = 0, nf = 0, ic = 0;
-                if (j < E) {
-                    const ArcL<T> &A = sh.A[j];
-                    ni = A.nseg - 1;
-                    if (A.p == 0) {
-                        nf = A.nseg;
-                        ic = 1;
-                    }
-                }
-                int ti, tf, tc;
-                const int ei = group_excl_scan<WL>(ni, &ti), ef = group_excl_scan<WL>(nf, &tf);
-                group_excl_scan<WL>(ic, &tc);
-                if (j < E) {
-                    sh.A[j].mbase = mb + ei;
-                    sh.A[j].fbase = fb + ef;
-                }
-                mb += ti;
-                fb += tf;
-                nc += tc;
-            }
-            if (lane == 0) {
-                sh.wsum = mb;  // first hole-centre index
-                sh.fsum = fb;
-                sh.ncirc = nc;
-            }
-        }
-        __syncthreads();
-        // Eq. 13: barycentre of each contour's vertices (each once: half of
-        // both ends of every arc plus its interior points), projected on the
-        // nodal sphere; the point opposite is used when the projection falls
-        // under a strut, and -sum(e_m) when the barycentre is within 1e-3 rho
-        // of the centre.
-        for (int c = lane; c < NC; c += WL) {
-            V3<T> sum = zero3<T>();
-            int cntv = 0;
-            for (int j = 0; j < E && sh.A[j].p == 0; ++j) {
-                const ArcL<T> &A = sh.A[j];
-                if (A.contour != c) continue;
-                sum = sum + (vert_pos(sh, A.vs) + vert_pos(sh, A.ve)) * (T)0.5;
-                for (int ii = 1; ii < A.nseg; ++ii) sum = sum + interior_pt(A, ii);
-                cntv += A.nseg;
-            }
-            V3<T> b = sum * ((T)1 / (T)cntv);
-            T bl = m_sqrt(dot(b, b));
-            // the apex direction b/|b| amplifies rounding by rho/|b|; the
-            // fallback decision near |b| = 1e-3 rho is fragile as well
-            if (F32 && bl * (T)P.kappa_max < rho) atomicOr(&sh.status, NS_PREC);
-            V3<T> dir;
-            if (bl >= (T)1e-3 * rho) {
-                dir = b * ((T)1 / bl);
-            } else {
-                V3<T> se = zero3<T>();
-                for (int m = 1; m <= v; ++m) se = se + v3(sh.S[m].ex, sh.S[m].ey, sh.S[m].ez);
-                T sl = m_sqrt(dot(se, se));
-                if (sl < (T)1e-3) { atomicOr(&sh.status, NS_TOPOLOGY); sl = (T)1; }
-                dir = se * ((T)-1 / sl);
-            }
-            for (int flip = 0; flip < 2; ++flip) {
-                T pm = (T)-1e30;
-                for (int m = 1; m <= v; ++m) pm = m_max(pm, dot(gvec(sh.S[m]), dir * rho) - sh.S[m].h);
-                if (pm <= (T)0) break;
-                if (flip) atomicOr(&sh.status, NS_TOPOLOGY);
-                dir = dir * (T)-1;
-            }
-            sh.hc[c][0] = dir.x * rho;
-            sh.hc[c][1] = dir.y * rho;
-            sh.hc[c][2] = dir.z * rho;
-        }
-        __syncthreads();
-        if (sh.status) goto finish;
-        // strut end loops must be graphs over phi: every step (mod 2 pi)
-        // positive and exactly one descent, i.e. one turn.  Lanes run over
-        // all loop samples of the node and store them in the node record.
-        // loop entries (arcs of every loop, loops in label order): first
-        // sample of each entry by a carried prefix sum over the lanes
-        {
-            const int nent = sh.loop_base[v + 1];
-            int off = 0;
-            for (int e0 = 0; e0 < nent; e0 += WL) {
-                const int e = e0 + lane;
-                int ns = 0, m = 1;
-                if (e < nent) {
-                    while (sh.loop_base[m + 1] <= e) ++m;
-                    const int b0 = sh.loop_base[m];
-                    ns = sh.A[sh.loop_arc[b0 + sh.loop_ord[e]]].nseg;
-                }
-                int tot;
-                const int ex = group_excl_scan<WL>(ns, &tot);
-                if (e < nent) {
-                    sh.entry_off[e] = off + ex;
-                    sh.entry_m[e] = (uint8_t)m;
-                }
-                off += tot;
-            }
-            if (lane == 0) sh.entry_off[nent] = off;
-        }
-        __syncthreads();
-        if (lane <= v) sh.lbase[lane + 1] = sh.entry_off[sh.loop_base[lane + 1]];  // lane v: the total
-        if (lane == 0) {
-            const int off = sh.entry_off[sh.loop_base[v + 1]];
-            // record space: bump allocation in the node's region
-            const int64_t words = rec_loop_word(V, E, NC) + (((int64_t)2 * off + 3) & ~(int64_t)3);
-            const int g = (int)(n & (kRecRegions - 1));
-            const int64_t region = W.rec_words / kRecRegions;
-            const unsigned long long old = atomicAdd(&W.rec_top[g], (unsigned long long)words);
-            if ((int64_t)old + words <= region) {
-                sh.rec = (int64_t)g * region + (int64_t)old;
-            } else {
-                sh.rec = -1;
-                atomicOr(&W.flags[0], DF_RECCAP);
-            }
-        }
-        if (lane < v) {
-            sh.loop_desc[lane + 1] = 0;
-            sh.loop_rot[lane + 1] = 0;
-        }
-        __syncthreads();
-        {
-            const int nent = sh.loop_base[v + 1];
-            const int ns_tot = sh.entry_off[nent];
-            int2 *rl = sh.rec >= 0 ? (int2 *)(W.rec + sh.rec + rec_loop_word(V, E, NC)) : nullptr;
-            // phi key and local mesh index of sample j of loop entry e
-            auto sample = [&](int e, int j, int &li) -> T {
-                const int m = sh.entry_m[e];
-                const int pp = sh.loop_base[m] + sh.loop_ord[e];
-                const ArcL<T> &A = sh.A[sh.loop_arc[pp]];
-                const int d = sh.loop_dir[pp];
-                const int ii = d > 0 ? j : A.nseg - j;
-                li = j == 0 ? (d > 0 ? A.vs : A.ve) : interior_idx(A, ii);
-                T st, ct;
-                m_sincos(sub_param(A, ii), &st, &ct);
-                // tangency circles are parametrised in the strut frame: phi
-                // is the parameter itself
-                if (A.p == 0) return phi_key(st, ct);
-                V3<T> w = j == 0 ? vert_pos(sh, li) : arc_con(A).o + arc_con(A).a * st + arc_con(A).b * ct;
-                const SL<T> &sm = sh.S[m];
-                return phi_key(dot(w, v3(sm.qx, sm.qy, sm.qz)), dot(w, v3(sm.rx, sm.ry, sm.rz)));
-            };
-            // each lane checks the step from the previous sample of its loop
-            // (the previous lane's, or the last of the previous chunk); the
-            // step that closes a loop is checked afterwards.  A valid loop
-            // has exactly one descent, just before its smallest phi.
-            T carry = (T)0;
-            for (int base = 0; base < ns_tot; base += WL) {
-                const int sidx = base + lane;
-                const bool act = sidx < ns_tot;
-                int m = 1, idx = 0, nloop = 1, li = 0;
-                T ph = (T)0;
-                if (act) {
-                    int lo = 0, hi = nent - 1;  // last entry with entry_off <= sidx
-                    while (lo < hi) {
-                        int mid = (lo + hi + 1) >> 1;
-                        if (sh.entry_off[mid] <= sidx) lo = mid;
-                        else hi = mid - 1;
-                    }
-                    const int e = lo;
-                    m = sh.entry_m[e];
-                    idx = sidx - sh.entry_off[sh.loop_base[m]];
-                    nloop = sh.loop_len[m];
-                    ph = sample(e, sidx - sh.entry_off[e], li);
-                }
-                T prev = __shfl_up(ph, 1, WL);
-                if (lane == 0) prev = carry;
-                carry = __shfl(ph, WL - 1, WL);
-                if (act) {
-                    if (idx == 0) {
-                        sh.ph_first[m] = ph;
-                    } else {
-                        T dp = ph - prev;  // in key units: a full turn is 4
-                        if (dp <= (T)-2) dp += (T)4;
-                        if (dp > (T)2) dp -= (T)4;
-                        if (!(dp > (T)0)) atomicOr(&sh.status, NS_LOOP);
-                        if (ph < prev) {
-                            atomicAdd(&sh.loop_desc[m], 1);
-                            sh.loop_rot[m] = idx;
-                        }
-                    }
-                    if (idx == nloop - 1) sh.ph_last[m] = ph;
-                    if (rl) rl[sidx] = make_int2(li, __float_as_int((float)ph));
-                }
-            }
-        }
-        __syncthreads();
-        if (lane < v) {
-            const int m = lane + 1;
-            const T a = sh.ph_last[m], b = sh.ph_first[m];
-            T dp = b - a;
-            if (dp <= (T)-2) dp += (T)4;
-            if (dp > (T)2) dp -= (T)4;
-            if (!(dp > (T)0)) atomicOr(&sh.status, NS_LOOP);
-            if (b < a) {
-                atomicAdd(&sh.loop_desc[m], 1);
-                sh.loop_rot[m] = 0;
-            }
-        }
-        __syncthreads();
-        if (lane < v) {
-            if (sh.loop_desc[lane + 1] != 1) atomicOr(&sh.status, NS_LOOP);
-            W.he_rot[row + lane] = sh.loop_rot[lane + 1];
-        }
-        __syncthreads();
-    }
+tail:
+    node_tail<T, CF>(P, sh, n, k, v, row, rho, cen);
+}
 
-finish:
+// Re-subdivision at resolution k of a node whose meta-mesh is in a record
+// written at another resolution (the paper's reusable meta-mesh, Alg. 1):
+// arcs, vertices, end-loop order and hole contours are read back; segment
+// counts (Eq. 11), points (Eq. 12), hole centres (Eq. 13) and end-loop
+// samples are redone by the tail.  Only FP32 meta-meshes are reused: a node
+// the FP32 path did not settle at the source resolution (meshed in FP64, or
+// not meshed) is solved again from the lattice, so that every node takes
+// the path, and gives the result, of a forward pass at k.
+template <typename T, typename CF>
+__device__ void node_retri(const Params &P, Shared<T, CF> &sh, const int64_t n)
+{
+    static_assert(sizeof(T) == 4, "FP64 nodes are solved again in full");
+    constexpr int WL = CF::W;
+    const int lane = threadIdx.x & (WL - 1);
+    const Work &W = P.w;
+    const int64_t N = P.in.n_nodes;
+    const int k = W.node_k ? (int)W.node_k[n] : P.k;
+    const int64_t row = W.row[n];
+    const int v = (int)(W.row[n + 1] - row);
+    const float4 c4 = W.node4[n];
+    const T rho = (T)c4.w;
+    const V3<T> cen = v3((T)c4.x, (T)c4.y, (T)c4.z);
+    const int64_t sb = P.src_node_rec[n];
+    const uint32_t *R = sb >= 0 ? P.src_rec + sb : nullptr;
+    const int V = R ? (int)R[0] : 0, E = R ? (int)R[1] : 0, NC = R ? (int)R[2] : 0;
+    const int nent = R ? (int)((R[7] >> 8) & 0xffffu) : 0;
+    if (!R || (R[7] >> 24) || v == 0 || v > CF::VM || E > CF::AC || V > CF::VC || nent > 2 * CF::AC ||
+        NC > CF::AC) {
+        node_body<T, CF>(P, sh, n);
+        return;
+    }
+    if (lane == 0) {
+        sh.status = 0;
+        sh.wsum = 0;
+        sh.fsum = 0;
+        sh.ncirc = 0;
+        sh.rec = -1;
+    }
     __syncthreads();
     {
-        const int status = sh.status;
-        const int E = sh.n_arc, V = sh.n_vert, NC = sh.n_contour;
-        if (status) {
-            if (lane == 0) {
-                for (int c = 0; c < kNodeCols; ++c) W.node_cnt[c * N + n] = 0;
-                W.node_cnt[NC_STATUS * N + n] = status & ~NS_PREC;
-                W.node_rec[n] = -1;
-                // hand the node to the FP64 pass when precision may be at fault
-                if (F32 && (status & kRetry)) W.fb_list[atomicAdd(&W.flags[2], 1)] = (int32_t)n;
-            }
-            if (lane < v) W.he_len[row + lane] = 0;
-            return;
-        }
-        const int Msum = sh.wsum + NC, Fsum = sh.fsum;
-        const int64_t rb = sh.rec;
-        const int64_t lw = rec_loop_word(V, E, NC);
-        if (lane == 0) {
-            W.node_cnt[NC_VERT * N + n] = V;
-            W.node_cnt[NC_ARC * N + n] = E;
-            W.node_cnt[NC_HOLE * N + n] = NC;
-            W.node_cnt[NC_MESH * N + n] = Msum;
-            W.node_cnt[NC_FAN * N + n] = Fsum;
-            W.node_cnt[NC_STATUS * N + n] = 0;
-            W.node_rec[n] = rb;
-        }
+        // strut table
         if (lane < v) {
-            W.he_len[row + lane] = sh.loop_len[lane + 1];
-            W.he_loop[row + lane] = rb >= 0 ? (rb + lw) / 2 + sh.lbase[lane + 1] : 0;
+            const int2 he = W.he[row + lane];
+            const float4 f4 = W.node4[he.x];
+            bool bad;
+            SL<T> s = strut_entry(cen, rho, v3((T)f4.x, (T)f4.y, (T)f4.z), (T)f4.w, (int)((int64_t)he.x > n), bad);
+            s.sid = he.y;
+            s.far = he.x;
+            sh.S[lane + 1] = s;
         }
-        if (rb < 0) return;
-        uint32_t *R = W.rec + rb;
-        if (lane == 0) {
-            R[0] = (uint32_t)V;
-            R[1] = (uint32_t)E;
-            R[2] = (uint32_t)NC;
-            R[3] = (uint32_t)sh.ncirc;
-            R[4] = (uint32_t)sh.wsum;
-            R[5] = (uint32_t)Msum;
-            R[6] = (uint32_t)Fsum;
-            R[7] = 0u;
-        }
-        uint32_t *RV = R + kRecHead;
+        // vertices, arcs, loop table
+        const uint32_t *RV = R + kRecHead;
+        const uint32_t *RA = RV + 4 * V;
+        const uint8_t *RT = (const uint8_t *)(R + rec_table_word(V, E, NC));
         for (int i = lane; i < V; i += WL) {
-            RV[i] = sh.vname[i];
-            RV[V + i] = __float_as_uint((float)sh.vx[i]);
-            RV[2 * V + i] = __float_as_uint((float)sh.vy[i]);
-            RV[3 * V + i] = __float_as_uint((float)sh.vz[i]);
+            sh.vname[i] = RV[i];
+            sh.vx[i] = (T)__uint_as_float(RV[V + i]);
+            sh.vy[i] = (T)__uint_as_float(RV[2 * V + i]);
+            sh.vz[i] = (T)__uint_as_float(RV[3 * V + i]);
         }
-        uint32_t *RA = RV + 4 * V;
+        if (lane <= v) sh.loop_base[lane + 1] = RT[lane];
+        if (lane == 0) {
+            sh.loop_base[0] = 0;
+            sh.n_arc = E;
+            sh.n_vert = V;
+            sh.n_contour = NC;
+        }
+        __syncthreads();
         for (int j = lane; j < E; j += WL) {
-            const ArcL<T> &A = sh.A[j];
-            const T f[11] = {A.o[0], A.o[1], A.o[2], A.a[0], A.a[1], A.a[2], A.b[0], A.b[1], A.b[2], A.t1, A.t2};
-#pragma unroll
-            for (int t = 0; t < 11; ++t) RA[t * E + j] = __float_as_uint((float)f[t]);
-            const uint32_t fwd = (A.full || A.ns <= A.ne) ? 1u : 0u;
-            const uint32_t lower = sh.S[A.q].lower ? 1u : 0u;
-            RA[11 * E + j] = (uint32_t)A.p | ((uint32_t)A.q << 8) | ((uint32_t)A.full << 16) | (fwd << 17) |
-                             (lower << 18);
-            RA[12 * E + j] = (uint32_t)A.vs | ((uint32_t)A.ve << 16);
-            RA[13 * E + j] = (uint32_t)A.nseg | (((uint32_t)A.contour & 0xffffu) << 16);
-            RA[14 * E + j] = (uint32_t)A.mbase;
-            RA[15 * E + j] = (uint32_t)A.fbase;
+            ArcL<T> &A = sh.A[j];
+            for (int d = 0; d < 3; ++d) {
+                A.o[d] = (T)__uint_as_float(RA[d * E + j]);
+                A.a[d] = (T)__uint_as_float(RA[(3 + d) * E + j]);
+                A.b[d] = (T)__uint_as_float(RA[(6 + d) * E + j]);
+            }
+            A.t1 = (T)__uint_as_float(RA[9 * E + j]);
+            A.t2 = (T)__uint_as_float(RA[10 * E + j]);
+            const uint32_t u0 = RA[11 * E + j], u1 = RA[12 * E + j], u2 = RA[13 * E + j];
+            A.p = (int)(u0 & 0xffu);
+            A.q = (int)((u0 >> 8) & 0xffu);
+            A.full = (int)((u0 >> 16) & 1u);
+            A.vs = (int)(u1 & 0xffffu);
+            A.ve = (int)(u1 >> 16);
+            A.ns = sh.vname[A.vs];
+            A.ne = sh.vname[A.ve];
+            A.contour = (u2 >> 16) == 0xffffu ? -1 : (int)(u2 >> 16);
+            // Eq. 11 at the new resolution
+            if (A.full) {
+                A.nseg = k;
+            } else {
+                T u = (A.t2 - A.t1) * ((T)k * Cst<T>::inv_two_pi);
+                int ns = (int)m_floor(u) + 1;
+                A.nseg = ns < k ? ns : k;
+            }
         }
-        uint32_t *RH = RA + kRecArcFields * E;
-        for (int c = lane; c < NC; c += WL) {
-            RH[c] = __float_as_uint((float)sh.hc[c][0]);
-            RH[NC + c] = __float_as_uint((float)sh.hc[c][1]);
-            RH[2 * NC + c] = __float_as_uint((float)sh.hc[c][2]);
+        // entries in loop order: membership b0 + t is the t-th arc of loop m
+        for (int e = lane; e < nent; e += WL) {
+            const uint8_t b = RT[v + 1 + e];
+            int m = 1;
+            while (sh.loop_base[m + 1] <= e) ++m;
+            sh.loop_arc[e] = (uint8_t)(b & 0x7f);
+            sh.loop_dir[e] = (b & 0x80) ? 1 : -1;
+            sh.loop_ord[e] = (uint8_t)(e - sh.loop_base[m]);
         }
+        __syncthreads();
+        if (lane >= 1 && lane <= v) {
+            int len = 0;
+            for (int e = sh.loop_base[lane]; e < sh.loop_base[lane + 1]; ++e) len += sh.A[sh.loop_arc[e]].nseg;
+            sh.loop_len[lane] = len;
+        }
+        __syncthreads();
     }
+    node_tail<T, CF>(P, sh, n, k, v, row, rho, cen);
 }
 
 // FP32, one valence class: a persistent grid takes items of 64 / W queued
 // nodes from a work counter; every wave leaves once the counter has passed
 // the class's last item.
-template <typename C>
+template <typename C, bool RETRI>
 __global__ void __launch_bounds__(64) k_node32(Params P, int cls)
 {
     constexpr int NPW = 64 / C::W;
@@ -1127,18 +1277,24 @@ __global__ void __launch_bounds__(64) k_node32(Params P, int cls)
         __syncthreads();
         if (item >= items) break;
         const int64_t qi = item * NPW + slot;
-        if (qi < cnt) node_body<float, C>(P, sh[slot], (int64_t)P.w.queue[base + qi]);
+        if (qi < cnt) {
+            const int64_t node = P.w.queue[base + qi];
+            if (RETRI) node_retri<float, C>(P, sh[slot], node);
+            else node_body<float, C>(P, sh[slot], node);
+        }
         __syncthreads();
     }
 }
 
 // FP64: the nodes the FP32 pass handed over, looped over by a fixed grid
+// (also after a re-subdivision: these nodes are solved in full)
 __global__ void __launch_bounds__(64) k_node64(Params P)
 {
     __shared__ Shared<double, CfgV16> sh;
     const int cnt = P.w.flags[2];
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
-        node_body<double, CfgV16>(P, sh, (int64_t)P.w.fb_list[i]);
+        const int64_t node = P.w.fb_list[i];
+        node_body<double, CfgV16>(P, sh, node);
         __syncthreads();
     }
 }
@@ -1148,7 +1304,8 @@ constexpr int64_t kNodeGrid = 256 * 32;  // waves per class launch
 
 }  // namespace
 
-hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, int fp64, hipStream_t st)
+hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, int fp64, hipStream_t st,
+                       const uint32_t *src_rec, const int64_t *src_node_rec)
 {
     if (in.n_nodes == 0) return hipSuccess;
     Params P;
@@ -1156,6 +1313,9 @@ hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, 
     P.w = w;
     P.k = k;
     P.kappa_max = kappa_max;
+    P.src_rec = src_rec;
+    P.src_node_rec = src_node_rec;
+    const bool retri = src_rec != nullptr;
     if (fp64) {
         k_node64<<<kFp64Grid, 64, 0, st>>>(P);
         return hipGetLastError();
@@ -1165,9 +1325,15 @@ hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, 
         int64_t items = (in.n_nodes + npw - 1) / npw;
         return (unsigned)(items < kNodeGrid ? items : kNodeGrid);
     };
-    k_node32<CfgV4><<<grid(4), 64, 0, st>>>(P, 0);
-    k_node32<CfgV8><<<grid(2), 64, 0, st>>>(P, 1);
-    k_node32<CfgV16><<<grid(1), 64, 0, st>>>(P, 2);
+    if (retri) {
+        k_node32<CfgV4, true><<<grid(4), 64, 0, st>>>(P, 0);
+        k_node32<CfgV8, true><<<grid(2), 64, 0, st>>>(P, 1);
+        k_node32<CfgV16, true><<<grid(1), 64, 0, st>>>(P, 2);
+    } else {
+        k_node32<CfgV4, false><<<grid(4), 64, 0, st>>>(P, 0);
+        k_node32<CfgV8, false><<<grid(2), 64, 0, st>>>(P, 1);
+        k_node32<CfgV16, false><<<grid(1), 64, 0, st>>>(P, 2);
+    }
     return hipGetLastError();
 }
 

@@ -39,6 +39,7 @@ EXPORTS = (
     "lm_count",
     "lm_fill",
     "lm_forward",
+    "lm_retriangulate",
     "lm_read_totals",
     "lm_set_precision",
     "lm_set_profiling",
@@ -148,6 +149,8 @@ def load() -> ctypes.CDLL:
     lib.lm_fill.restype = ctypes.c_int
     lib.lm_forward.argtypes = [P, ctypes.c_int, ctypes.POINTER(lm_outputs)]
     lib.lm_forward.restype = ctypes.c_int
+    lib.lm_retriangulate.argtypes = [P, ctypes.c_int, ctypes.POINTER(lm_outputs)]
+    lib.lm_retriangulate.restype = ctypes.c_int
     lib.lm_read_totals.argtypes = [P, ctypes.POINTER(lm_totals)]
     lib.lm_read_totals.restype = ctypes.c_int
     lib.lm_prepare.argtypes = [P]
@@ -209,12 +212,25 @@ def lm_forward(plan, k: int, out: lm_outputs) -> None:
         raise LatmeshError(rc, "lm_forward")
 
 
+def lm_retriangulate(plan, k: int, out: lm_outputs) -> None:
+    rc = load().lm_retriangulate(plan, int(k), ctypes.byref(out))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_retriangulate")
+
+
 def lm_read_totals(plan) -> lm_totals:
-    t = lm_totals()
-    rc = load().lm_read_totals(plan, ctypes.byref(t))
+    rc, t = lm_read_totals_rc(plan)
     if rc != LM_OK:
         raise LatmeshError(rc, "lm_read_totals")
     return t
+
+
+def lm_read_totals_rc(plan):
+    """(status, totals): the totals are filled also when the status is
+    LM_ERR_CAPACITY, and then give the sizes the skipped writes needed."""
+    t = lm_totals()
+    rc = load().lm_read_totals(plan, ctypes.byref(t))
+    return rc, t
 
 
 PHASES = ("prepare", "node_fp32", "node_fp64", "sizes", "expand", "bands", "loss", "backward")
@@ -344,6 +360,7 @@ class Mesher:
         if kappa_max is not None:
             lm_set_precision(self.plan, kappa_max)
         self.totals = None
+        self.k = 0
 
     def count(self, k: int) -> dict:
         self.totals = lm_count(self.plan, k).as_dict()
@@ -397,7 +414,31 @@ class Mesher:
         r = self.fill(self.alloc(t, meta=meta))
         self.torch.cuda.synchronize(self.device)
         err = lm_read_totals(self.plan)  # raises on device-side errors
-        r.totals = err.as_dict()
+        return self._trim(r, err.as_dict(), meta)
+
+    def retriangulate(self, k: int, meta: bool = True, r: MeshResult | None = None) -> MeshResult:
+        """Subdivide the meta-mesh of the last count / run / forward again at
+        k without re-solving the nodes.  Writes into ``r`` when given and
+        large enough, else into buffers sized from the totals (a second call
+        when the first guess was too small); returns trimmed tensors."""
+        if r is None:
+            # the last call's totals (none yet: lm_retriangulate refuses)
+            base = lm_read_totals_rc(self.plan)[1].as_dict() if self.k else dict.fromkeys(_TOTAL_FIELDS, 0)
+            f = max(1.0, k / max(self.k, 1)) * 1.05
+            t = {key: int(v * f) + 64 for key, v in base.items()}
+            r = self.alloc(t, meta=meta)
+        for attempt in range(2):
+            lm_retriangulate(self.plan, k, self.outputs(r))
+            rc, tt = lm_read_totals_rc(self.plan)
+            if rc == LM_OK:
+                break
+            if rc != LM_ERR_CAPACITY or attempt == 1:
+                raise LatmeshError(rc, "lm_retriangulate")
+            r = self.alloc(tt.as_dict(), meta=meta)
+        return self._trim(r, tt.as_dict(), meta)
+
+    def _trim(self, r: MeshResult, t: dict, meta: bool) -> MeshResult:
+        r.totals = t
         r.mesh_xyz = r.mesh_xyz[: t["n_mesh_vertices"]]
         r.tri = r.tri[: t["n_triangles"]]
         if meta:
@@ -410,6 +451,7 @@ class Mesher:
 
     def forward(self, k: int, r: MeshResult) -> None:
         lm_forward(self.plan, k, self.outputs(r))
+        self.k = k
 
     def loss(self, r: MeshResult, weights=(1.0, 0.0, 0.0), p0=(0.0, 0.0, 0.0)):
         """Loss terms (area, volume about p0, sum |v|^2) of the mesh in ``r``

@@ -25,23 +25,30 @@ def gpu_result(lat, k, meta=True, kappa_max=None):
 
     M = Mesher(lat, kappa_max=kappa_max)
     try:
-        r = M.run(k, meta=meta)
-        torch.cuda.synchronize()
-        out = {
-            "totals": r.totals,
-            "mesh": r.mesh_xyz.cpu().numpy().astype(np.float64),
-            "tri": r.tri.cpu().numpy().astype(np.int64),
-            "node_off": r.node_off.cpu().numpy(),
-            "status": r.node_status.cpu().numpy().astype(np.int64),
-            "strut_off": r.strut_off.cpu().numpy(),
-        }
-        if meta:
-            out["vert_name"] = r.vert_name.cpu().numpy().view(np.uint32)
-            out["vert_xyz"] = r.vert_xyz.cpu().numpy().T.astype(np.float64)
-            out["arc_f32"] = r.arc_f32.cpu().numpy().T.astype(np.float64)
-            out["arc_u32"] = r.arc_u32.cpu().numpy().view(np.uint32).T.copy()
+        out = result_np(M.run(k, meta=meta), meta)
     finally:
         M.close()
+    return out
+
+
+def result_np(r, meta=True):
+    """Host copies of a trimmed MeshResult."""
+    import torch
+
+    torch.cuda.synchronize()
+    out = {
+        "totals": r.totals,
+        "mesh": r.mesh_xyz.cpu().numpy().astype(np.float64),
+        "tri": r.tri.cpu().numpy().astype(np.int64),
+        "node_off": r.node_off.cpu().numpy(),
+        "status": r.node_status.cpu().numpy().astype(np.int64),
+        "strut_off": r.strut_off.cpu().numpy(),
+    }
+    if meta:
+        out["vert_name"] = r.vert_name.cpu().numpy().view(np.uint32)
+        out["vert_xyz"] = r.vert_xyz.cpu().numpy().T.astype(np.float64)
+        out["arc_f32"] = r.arc_f32.cpu().numpy().T.astype(np.float64)
+        out["arc_u32"] = r.arc_u32.cpu().numpy().view(np.uint32).T.copy()
     return out
 
 

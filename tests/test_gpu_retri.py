@@ -1,0 +1,139 @@
+"""Multi-resolution re-triangulation: the meta-mesh of one count subdivided
+again at other resolutions (lm_retriangulate) against a fresh forward pass
+at those resolutions and against the oracle."""
+
+import numpy as np
+import pytest
+
+import latgen
+from parity import compare, result_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _line(msg):
+    print(msg, flush=True)
+
+
+# record space depends on the order of the bump allocations, not the mesh
+_PATH_TOTALS = ("n_record_bytes",)
+
+
+def _same_mesh(a, b, what):
+    """Identical outputs: a re-subdivided node runs the tail of the forward
+    pass on the FP32 meta-mesh it stored, and every other node is solved
+    again in full, so nothing may differ, not even in the last bit."""
+    ta = {k: v for k, v in a["totals"].items() if k not in _PATH_TOTALS}
+    tb = {k: v for k, v in b["totals"].items() if k not in _PATH_TOTALS}
+    assert ta == tb, what
+    for key in ("status", "node_off", "strut_off", "vert_name", "vert_xyz", "arc_u32", "arc_f32", "tri", "mesh"):
+        assert np.array_equal(a[key], b[key]), f"{what}: {key}"
+
+
+CASES = [
+    ("cfg2_bcc5", lambda: latgen.config(2, scale=5), 16, (7, 24, 5), None),
+    ("cfg4_octet3", lambda: latgen.config(4, scale=3), 12, (16, 9), None),
+    ("cubic_cones", lambda: latgen.cubic(5, radius=("uniform", 0.05, 0.15), jitter=0.04, seed=5), 8, (13, 32), None),
+    ("cfg3_bcc6_unjittered", lambda: latgen.config(3, scale=6), 12, (20, 6), None),
+    # every node in FP64: nothing is reused, all is solved again
+    ("cfg2_bcc4_fp64", lambda: latgen.config(2, scale=4, seed=3), 16, (10,), 0.0),
+    # a low threshold hands many nodes to FP64
+    ("cfg2_bcc5_kappa2", lambda: latgen.config(2, scale=5, seed=8), 12, (17, 4), 2.0),
+]
+
+
+@pytest.mark.parametrize("name,make,k0,ks,kappa", CASES, ids=[c[0] for c in CASES])
+def test_retriangulate_matches_forward(name, make, k0, ks, kappa):
+    from paper_2405_15197_amd import Mesher
+
+    lat = make()
+    _line(f"retri {name}: {lat.n_nodes} nodes, k0={k0} -> {ks}")
+    M = Mesher(lat, kappa_max=kappa)
+    try:
+        base = result_np(M.run(k0))
+        _line(f"  base: {base['totals']['n_fp64_nodes']} FP64 nodes")
+        for k in ks + (k0,):
+            G = result_np(M.retriangulate(k))
+            F = Mesher(lat, kappa_max=kappa)
+            try:
+                ref = result_np(F.run(k))
+            finally:
+                F.close()
+            _line(f"  k={k}: {G['totals']['n_triangles']} triangles")
+            _same_mesh(G, ref, f"{name} k={k}")
+        # back at k0: the source resolution again
+        _same_mesh(G, base, f"{name} k0")
+    finally:
+        M.close()
+
+
+@pytest.mark.parametrize("k", [7, 20])
+def test_retriangulate_vs_oracle(k):
+    """The re-subdivided mesh against the FP64 oracle run at the new k."""
+    from paper_2405_15197_amd import Mesher
+
+    lat = latgen.config(2, scale=6, seed=4)
+    _line(f"retri vs oracle: k 16 -> {k}")
+    M = Mesher(lat)
+    try:
+        M.run(16)
+        G = result_np(M.retriangulate(k))
+    finally:
+        M.close()
+    st = compare(lat, k, G=G)
+    _line(f"  {st}")
+    assert st["stable"] >= 0.95 * lat.n_nodes
+
+
+def test_retriangulate_state_and_fill():
+    """Needs a meta-mesh; lm_fill refuses after it until the next count;
+    lm_forward and lm_count start over."""
+    from paper_2405_15197_amd import Mesher
+    from paper_2405_15197_amd.latmesh import LM_ERR_STATE, LatmeshError
+
+    lat = latgen.config(2, scale=3)
+    M = Mesher(lat)
+    try:
+        with pytest.raises(LatmeshError) as e:
+            M.retriangulate(8)
+        assert e.value.code == LM_ERR_STATE
+        t = M.count(10)
+        r = M.alloc(t)
+        M.retriangulate(14)
+        with pytest.raises(LatmeshError) as e:
+            M.fill(r)
+        assert e.value.code == LM_ERR_STATE
+        a = result_np(M.run(10))
+        b = result_np(M.retriangulate(10))
+        _same_mesh(a, b, "count again")
+    finally:
+        M.close()
+
+
+def test_retriangulate_then_adjoint():
+    """lm_loss / lm_backward act on the re-subdivided mesh: the same values
+    as after a fresh forward pass at that k."""
+    import torch
+
+    from paper_2405_15197_amd import Mesher
+
+    lat = latgen.config(4, scale=2, seed=2)
+    out = []
+    for path in ("retri", "fresh"):
+        M = Mesher(lat)
+        try:
+            if path == "retri":
+                M.run(8)
+                r = M.retriangulate(14)
+            else:
+                r = M.run(14)
+            terms, dl = M.loss(r, (1.0, 0.5, 0.1))
+            gx, gr = M.backward(dl)
+            torch.cuda.synchronize()
+            out.append((terms.cpu().numpy(), gx.cpu().numpy(), gr.cpu().numpy()))
+        finally:
+            M.close()
+    (t0, x0, r0), (t1, x1, r1) = out
+    np.testing.assert_allclose(t0, t1, rtol=1e-6)
+    np.testing.assert_allclose(x0, x1, rtol=1e-4, atol=1e-5)
+    np.testing.assert_allclose(r0, r1, rtol=1e-4, atol=1e-5)
