@@ -157,7 +157,8 @@ def retri_bench(M, k0: int, ks, steps: int, warmup: int):
     forward pass at those resolutions, on the plan's lattice."""
     import torch
 
-    from paper_2405_15197_amd.latmesh import lm_forward, lm_read_totals, lm_retriangulate
+    from paper_2405_15197_amd.latmesh import (lm_forward, lm_get_profile, lm_read_totals, lm_retriangulate,
+                                              lm_set_profiling)
 
     def timed(fn):
         for _ in range(warmup):
@@ -171,17 +172,28 @@ def retri_bench(M, k0: int, ks, steps: int, warmup: int):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / steps
 
+    def phases(fn):
+        lm_get_profile(M.plan)
+        lm_set_profiling(M.plan, True)
+        fn()
+        prof = lm_get_profile(M.plan)
+        lm_set_profiling(M.plan, False)
+        return {p: round(v[0], 4) for p, v in prof.items() if v[1]}
+
     out = {"k0": k0}
     for k in ks:
         M.count(k0)
         r = M.retriangulate(k, meta=True)  # sizes the buffers
         o = M.outputs(r)
         f_ms = timed(lambda: lm_forward(M.plan, k, o))
+        f_ph = phases(lambda: lm_forward(M.plan, k, o))
         lm_forward(M.plan, k0, M.outputs(M.alloc(M.count(k0), meta=True)))
         r_ms = timed(lambda: lm_retriangulate(M.plan, k, o))
+        r_ph = phases(lambda: lm_retriangulate(M.plan, k, o))
         lm_read_totals(M.plan)
         out[f"k{k}"] = {"forward_ms": f_ms, "retriangulate_ms": r_ms, "speedup": f_ms / r_ms,
-                        "triangles": r.totals["n_triangles"]}
+                        "triangles": r.totals["n_triangles"], "forward_phase_ms": f_ph,
+                        "retriangulate_phase_ms": r_ph}
     return out
 
 

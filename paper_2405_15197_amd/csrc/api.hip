@@ -33,8 +33,11 @@ struct lm_plan {
     unsigned long long *alt_rec_top = nullptr;
     int base_slot = 0;
     // the allocations behind the second node record index and counters (the
-    // pointers above swap with the workspace's own at every switch)
+    // pointers above swap with the workspace's own at every switch), and the
+    // redo lists [N] and their counters [8]
     void *alt_index_mem = nullptr;
+    int32_t *redo = nullptr;
+    int32_t *redo_cnt = nullptr;
     int k;          // resolution of the last count (0: none)
     float kappa_max;// FP32 -> FP64 hand-over threshold
     lm_totals last; // totals of the last lm_count
@@ -163,7 +166,7 @@ lm::FillOut to_fill(const lm_outputs *o)
 // the meta-mesh in those records) into the records of w, then band counts,
 // prefix sums and device totals.
 int run_count(lm_plan *P, int k, const lm::FillOut *out, const lm::Work &w, const uint32_t *src_rec = nullptr,
-              const int64_t *src_node_rec = nullptr)
+              const int64_t *src_node_rec = nullptr, int32_t *redo = nullptr, int32_t *redo_cnt = nullptr)
 {
     const int64_t N = P->in.n_nodes, S = P->in.n_struts;
     // flags[0] (count / fill) and flags[2] (FP64 hand-over count)
@@ -174,7 +177,8 @@ int run_count(lm_plan *P, int k, const lm::FillOut *out, const lm::Work &w, cons
     HIPCHK(hipMemsetAsync(w.work_ctr, 0, sizeof(int32_t) * 4, P->st));
     {
         PhaseTimer t(P, PH_NODE32);
-        HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, 0, P->st, src_rec, src_node_rec));
+        if (redo_cnt) HIPCHK(hipMemsetAsync(redo_cnt, 0, sizeof(int32_t) * 8, P->st));
+        HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, 0, P->st, src_rec, src_node_rec, redo, redo_cnt));
     }
     {
         PhaseTimer t(P, PH_NODE64);
@@ -574,10 +578,14 @@ int lm_retriangulate(lm_plan *P, int k, const lm_outputs *out)
     if (P->k == 0) return LM_ERR_STATE;  // no meta-mesh from lm_count / lm_forward
     const int64_t N = P->in.n_nodes;
     if (!P->alt_index_mem) {
-        const size_t bytes = sizeof(int64_t) * (N + 1) + sizeof(unsigned long long) * lm::kRecRegions;
+        const size_t top = sizeof(unsigned long long) * lm::kRecRegions, idx = sizeof(int64_t) * (N + 1);
+        const size_t bytes = top + idx + sizeof(int32_t) * 8 + sizeof(int32_t) * (N + 1);
         HIPCHK(hipMalloc(&P->alt_index_mem, bytes));
-        P->alt_rec_top = (unsigned long long *)P->alt_index_mem;
-        P->alt_node_rec = (int64_t *)((char *)P->alt_index_mem + sizeof(unsigned long long) * lm::kRecRegions);
+        char *m = (char *)P->alt_index_mem;
+        P->alt_rec_top = (unsigned long long *)m;
+        P->alt_node_rec = (int64_t *)(m + top);
+        P->redo_cnt = (int32_t *)(m + top + idx);
+        P->redo = P->redo_cnt + 8;
     }
     // the slot that does not hold the meta-mesh receives the new records
     const bool base_in_w = P->base_slot == 0;
@@ -614,7 +622,7 @@ int lm_retriangulate(lm_plan *P, int k, const lm_outputs *out)
         wd = P->w;
     }
     lm::FillOut f = to_fill(out);
-    int rc = run_count(P, k, &f, wd, src_rec, src_node_rec);
+    int rc = run_count(P, k, &f, wd, src_rec, src_node_rec, P->redo, P->redo_cnt);
     if (rc) return rc;
     rc = fill_common(P, f, out, wd);
     if (rc) return rc;

@@ -148,8 +148,13 @@ hipError_t launch_scan(const int32_t *src, int64_t *dst, int64_t n, int ncols, i
 // FP64 over the hand-over list.
 // With src_rec set, the meta-mesh of each node is read from its record in
 // src_rec (src_node_rec) and only re-subdivided at resolution k.
+// src_rec / src_node_rec set: re-subdivision of the meta-mesh in those
+// records; nodes that must be solved in full go to redo ([N], partitioned
+// like the queue) with counts and work counters in redo_cnt [8], zeroed by
+// the caller.
 hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, int fp64, hipStream_t st,
-                       const uint32_t *src_rec = nullptr, const int64_t *src_node_rec = nullptr);
+                       const uint32_t *src_rec = nullptr, const int64_t *src_node_rec = nullptr,
+                       int32_t *redo = nullptr, int32_t *redo_cnt = nullptr);
 // Node records -> meta-mesh, mesh vertices and hole fans.
 hipError_t launch_expand(const Inputs &in, const Work &w, const FillOut &o, hipStream_t st);
 hipError_t launch_band_count(const Inputs &in, const Work &w, hipStream_t st);

@@ -425,6 +425,11 @@ struct Params {
     // re-subdivision: the meta-mesh comes from these records instead
     const uint32_t *src_rec;
     const int64_t *src_node_rec;
+    // nodes to solve in full after a re-subdivision pass: per class a list
+    // at the class's queue offset, its length and a work counter
+    int32_t *redo;
+    int32_t *redo_cnt;  // [4]
+    int32_t *redo_ctr;  // [4]
 };
 
 // statuses that FP64 may resolve
@@ -1149,137 +1154,160 @@ tail:
 // counts (Eq. 11), points (Eq. 12), hole centres (Eq. 13) and end-loop
 // samples are redone by the tail.  Only FP32 meta-meshes are reused: a node
 // the FP32 path did not settle at the source resolution (meshed in FP64, or
-// not meshed) is solved again from the lattice, so that every node takes
-// the path, and gives the result, of a forward pass at k.
-template <typename T, typename CF>
-__device__ void node_retri(const Params &P, Shared<T, CF> &sh, const int64_t n)
+// not meshed) goes to the class's redo list and is solved again from the
+// lattice, so that every node takes the path, and gives the result, of a
+// forward pass at k.  All record words are loaded in one round (one arc,
+// one vertex and one table word per lane: E <= AC = W, V <= VC <= W) before
+// anything is written to LDS.
+template <typename CF>
+__device__ void node_retri(const Params &P, Shared<float, CF> &sh, const int64_t n, const int cls)
 {
-    static_assert(sizeof(T) == 4, "FP64 nodes are solved again in full");
+    using T = float;
     constexpr int WL = CF::W;
+    static_assert(CF::AC == WL && CF::VC <= WL && (1 + CF::VM + 2 * CF::AC + 3) / 4 <= 2 * CF::AC + 1,
+                  "one arc, vertex and table word per lane; the table is staged in entry_off");
     const int lane = threadIdx.x & (WL - 1);
     const Work &W = P.w;
-    const int64_t N = P.in.n_nodes;
     const int k = W.node_k ? (int)W.node_k[n] : P.k;
     const int64_t row = W.row[n];
     const int v = (int)(W.row[n + 1] - row);
     const float4 c4 = W.node4[n];
-    const T rho = (T)c4.w;
-    const V3<T> cen = v3((T)c4.x, (T)c4.y, (T)c4.z);
     const int64_t sb = P.src_node_rec[n];
+    int2 he = make_int2(0, 0);
+    if (lane < v) he = W.he[row + lane];
     const uint32_t *R = sb >= 0 ? P.src_rec + sb : nullptr;
-    const int V = R ? (int)R[0] : 0, E = R ? (int)R[1] : 0, NC = R ? (int)R[2] : 0;
-    const int nent = R ? (int)((R[7] >> 8) & 0xffffu) : 0;
-    if (!R || (R[7] >> 24) || v == 0 || v > CF::VM || E > CF::AC || V > CF::VC || nent > 2 * CF::AC ||
+    uint32_t h0 = 0, h1 = 0, h2 = 0, h7 = 0;
+    if (R) {
+        h0 = R[0];
+        h1 = R[1];
+        h2 = R[2];
+        h7 = R[7];
+    }
+    const int V = (int)h0, E = (int)h1, NC = (int)h2, nent = (int)((h7 >> 8) & 0xffffu);
+    if (!R || (h7 >> 24) || v == 0 || v > CF::VM || E > CF::AC || V > CF::VC || nent > 2 * CF::AC ||
         NC > CF::AC) {
-        node_body<T, CF>(P, sh, n);
+        if (lane == 0) P.redo[W.cls_info[4 + cls] + atomicAdd(&P.redo_cnt[cls], 1)] = (int32_t)n;
         return;
     }
+    // the record: vertices, arcs, loop table (all independent loads)
+    const uint32_t *RV = R + kRecHead;
+    const uint32_t *RA = RV + 4 * V;
+    const uint32_t *RT = R + rec_table_word(V, E, NC);
+    const int twords = (v + 1 + nent + 3) >> 2;
+    float4 f4 = c4;
+    if (lane < v) f4 = W.node4[he.x];
+    uint32_t vw[4] = {0, 0, 0, 0};
+    if (lane < V)
+        for (int d = 0; d < 4; ++d) vw[d] = RV[d * V + lane];
+    uint32_t aw[14];
+    for (int f = 0; f < 14; ++f) aw[f] = lane < E ? RA[f * E + lane] : 0u;
+    const uint32_t tw = lane < twords ? RT[lane] : 0u;
+
+    const T rho = (T)c4.w;
+    const V3<T> cen = v3((T)c4.x, (T)c4.y, (T)c4.z);
+    if (lane < v) {
+        bool bad;
+        SL<T> st = strut_entry(cen, rho, v3((T)f4.x, (T)f4.y, (T)f4.z), (T)f4.w, (int)((int64_t)he.x > n), bad);
+        st.sid = he.y;
+        st.far = he.x;
+        sh.S[lane + 1] = st;
+    }
+    if (lane < V) {
+        sh.vname[lane] = vw[0];
+        sh.vx[lane] = __uint_as_float(vw[1]);
+        sh.vy[lane] = __uint_as_float(vw[2]);
+        sh.vz[lane] = __uint_as_float(vw[3]);
+    }
+    if (lane < twords) sh.entry_off[lane] = (int)tw;  // staging; the tail rewrites entry_off
     if (lane == 0) {
         sh.status = 0;
         sh.wsum = 0;
         sh.fsum = 0;
         sh.ncirc = 0;
         sh.rec = -1;
+        sh.loop_base[0] = 0;
+        sh.n_arc = E;
+        sh.n_vert = V;
+        sh.n_contour = NC;
     }
     __syncthreads();
-    {
-        // strut table
-        if (lane < v) {
-            const int2 he = W.he[row + lane];
-            const float4 f4 = W.node4[he.x];
-            bool bad;
-            SL<T> s = strut_entry(cen, rho, v3((T)f4.x, (T)f4.y, (T)f4.z), (T)f4.w, (int)((int64_t)he.x > n), bad);
-            s.sid = he.y;
-            s.far = he.x;
-            sh.S[lane + 1] = s;
+    if (lane < E) {
+        ArcL<T> &A = sh.A[lane];
+        for (int d = 0; d < 3; ++d) {
+            A.o[d] = __uint_as_float(aw[d]);
+            A.a[d] = __uint_as_float(aw[3 + d]);
+            A.b[d] = __uint_as_float(aw[6 + d]);
         }
-        // vertices, arcs, loop table
-        const uint32_t *RV = R + kRecHead;
-        const uint32_t *RA = RV + 4 * V;
-        const uint8_t *RT = (const uint8_t *)(R + rec_table_word(V, E, NC));
-        for (int i = lane; i < V; i += WL) {
-            sh.vname[i] = RV[i];
-            sh.vx[i] = (T)__uint_as_float(RV[V + i]);
-            sh.vy[i] = (T)__uint_as_float(RV[2 * V + i]);
-            sh.vz[i] = (T)__uint_as_float(RV[3 * V + i]);
+        A.t1 = __uint_as_float(aw[9]);
+        A.t2 = __uint_as_float(aw[10]);
+        const uint32_t u0 = aw[11], u1 = aw[12], u2 = aw[13];
+        A.p = (int)(u0 & 0xffu);
+        A.q = (int)((u0 >> 8) & 0xffu);
+        A.full = (int)((u0 >> 16) & 1u);
+        A.vs = (int)(u1 & 0xffffu);
+        A.ve = (int)(u1 >> 16);
+        A.ns = sh.vname[A.vs];
+        A.ne = sh.vname[A.ve];
+        A.contour = (u2 >> 16) == 0xffffu ? -1 : (int)(u2 >> 16);
+        // Eq. 11 at the new resolution
+        if (A.full) {
+            A.nseg = k;
+        } else {
+            T u = (A.t2 - A.t1) * ((T)k * Cst<T>::inv_two_pi);
+            int ns = (int)m_floor(u) + 1;
+            A.nseg = ns < k ? ns : k;
         }
-        if (lane <= v) sh.loop_base[lane + 1] = RT[lane];
-        if (lane == 0) {
-            sh.loop_base[0] = 0;
-            sh.n_arc = E;
-            sh.n_vert = V;
-            sh.n_contour = NC;
-        }
-        __syncthreads();
-        for (int j = lane; j < E; j += WL) {
-            ArcL<T> &A = sh.A[j];
-            for (int d = 0; d < 3; ++d) {
-                A.o[d] = (T)__uint_as_float(RA[d * E + j]);
-                A.a[d] = (T)__uint_as_float(RA[(3 + d) * E + j]);
-                A.b[d] = (T)__uint_as_float(RA[(6 + d) * E + j]);
-            }
-            A.t1 = (T)__uint_as_float(RA[9 * E + j]);
-            A.t2 = (T)__uint_as_float(RA[10 * E + j]);
-            const uint32_t u0 = RA[11 * E + j], u1 = RA[12 * E + j], u2 = RA[13 * E + j];
-            A.p = (int)(u0 & 0xffu);
-            A.q = (int)((u0 >> 8) & 0xffu);
-            A.full = (int)((u0 >> 16) & 1u);
-            A.vs = (int)(u1 & 0xffffu);
-            A.ve = (int)(u1 >> 16);
-            A.ns = sh.vname[A.vs];
-            A.ne = sh.vname[A.ve];
-            A.contour = (u2 >> 16) == 0xffffu ? -1 : (int)(u2 >> 16);
-            // Eq. 11 at the new resolution
-            if (A.full) {
-                A.nseg = k;
-            } else {
-                T u = (A.t2 - A.t1) * ((T)k * Cst<T>::inv_two_pi);
-                int ns = (int)m_floor(u) + 1;
-                A.nseg = ns < k ? ns : k;
-            }
-        }
-        // entries in loop order: membership b0 + t is the t-th arc of loop m
-        for (int e = lane; e < nent; e += WL) {
-            const uint8_t b = RT[v + 1 + e];
-            int m = 1;
-            while (sh.loop_base[m + 1] <= e) ++m;
-            sh.loop_arc[e] = (uint8_t)(b & 0x7f);
-            sh.loop_dir[e] = (b & 0x80) ? 1 : -1;
-            sh.loop_ord[e] = (uint8_t)(e - sh.loop_base[m]);
-        }
-        __syncthreads();
-        if (lane >= 1 && lane <= v) {
-            int len = 0;
-            for (int e = sh.loop_base[lane]; e < sh.loop_base[lane + 1]; ++e) len += sh.A[sh.loop_arc[e]].nseg;
-            sh.loop_len[lane] = len;
-        }
-        __syncthreads();
     }
+    // loop table bytes: loop start of labels 1..v+1, then the entries
+    auto tbyte = [&](int i) -> int { return (int)(((uint32_t)sh.entry_off[i >> 2] >> (8 * (i & 3))) & 0xffu); };
+    if (lane <= v) sh.loop_base[lane + 1] = tbyte(lane);
+    // entries in loop order: entry e is the (e - start)-th arc of its loop
+    for (int e = lane; e < nent; e += WL) {
+        const int b = tbyte(v + 1 + e);
+        int m = 1;
+        while (tbyte(m) <= e) ++m;  // loop_base[m + 1] = tbyte(m)
+        sh.loop_arc[e] = (uint8_t)(b & 0x7f);
+        sh.loop_dir[e] = (b & 0x80) ? 1 : -1;
+        sh.loop_ord[e] = (uint8_t)(e - tbyte(m - 1));  // loop_base[m] = tbyte(m - 1)
+    }
+    __syncthreads();
+    if (lane >= 1 && lane <= v) {
+        int len = 0;
+        for (int e = sh.loop_base[lane]; e < sh.loop_base[lane + 1]; ++e) len += sh.A[sh.loop_arc[e]].nseg;
+        sh.loop_len[lane] = len;
+    }
+    __syncthreads();
     node_tail<T, CF>(P, sh, n, k, v, row, rho, cen);
 }
 
 // FP32, one valence class: a persistent grid takes items of 64 / W queued
 // nodes from a work counter; every wave leaves once the counter has passed
-// the class's last item.
-template <typename C, bool RETRI>
+// the class's last item.  MODE 0: meta-meshing of the queue; 1:
+// re-subdivision of the queue; 2: meta-meshing of the redo list that mode 1
+// left (its length is read on the device).
+enum { kModeMesh = 0, kModeRetri = 1, kModeRedo = 2 };
+template <typename C, int MODE>
 __global__ void __launch_bounds__(64) k_node32(Params P, int cls)
 {
     constexpr int NPW = 64 / C::W;
     __shared__ Shared<float, C> sh[NPW];
     __shared__ int s_item;
     const int slot = threadIdx.x / C::W;
-    const int64_t cnt = P.w.cls_info[cls], base = P.w.cls_info[4 + cls];
+    const int64_t cnt = MODE == kModeRedo ? (int64_t)P.redo_cnt[cls] : P.w.cls_info[cls];
+    const int64_t base = P.w.cls_info[4 + cls];
+    const int32_t *list = MODE == kModeRedo ? P.redo : P.w.queue;
+    int32_t *ctr = MODE == kModeRedo ? P.redo_ctr : P.w.work_ctr;
     const int64_t items = (cnt + NPW - 1) / NPW;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(&P.w.work_ctr[cls], 1);
+        if (threadIdx.x == 0) s_item = atomicAdd(&ctr[cls], 1);
         __syncthreads();
         const int64_t item = s_item;
         __syncthreads();
         if (item >= items) break;
         const int64_t qi = item * NPW + slot;
         if (qi < cnt) {
-            const int64_t node = P.w.queue[base + qi];
-            if (RETRI) node_retri<float, C>(P, sh[slot], node);
+            const int64_t node = list[base + qi];
+            if (MODE == kModeRetri) node_retri<C>(P, sh[slot], node, cls);
             else node_body<float, C>(P, sh[slot], node);
         }
         __syncthreads();
@@ -1301,11 +1329,12 @@ __global__ void __launch_bounds__(64) k_node64(Params P)
 
 constexpr unsigned kFp64Grid = 2048;
 constexpr int64_t kNodeGrid = 256 * 32;  // waves per class launch
+constexpr int64_t kRedoGrid = 512;       // waves per class launch over a redo list
 
 }  // namespace
 
 hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, int fp64, hipStream_t st,
-                       const uint32_t *src_rec, const int64_t *src_node_rec)
+                       const uint32_t *src_rec, const int64_t *src_node_rec, int32_t *redo, int32_t *redo_cnt)
 {
     if (in.n_nodes == 0) return hipSuccess;
     Params P;
@@ -1315,24 +1344,31 @@ hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, 
     P.kappa_max = kappa_max;
     P.src_rec = src_rec;
     P.src_node_rec = src_node_rec;
-    const bool retri = src_rec != nullptr;
+    P.redo = redo;
+    P.redo_cnt = redo_cnt;
+    P.redo_ctr = redo_cnt ? redo_cnt + 4 : nullptr;
     if (fp64) {
         k_node64<<<kFp64Grid, 64, 0, st>>>(P);
         return hipGetLastError();
     }
     // persistent grids: enough waves to fill the chip, never more than items
-    auto grid = [&](int npw) {
+    auto grid = [&](int npw, int64_t cap) {
         int64_t items = (in.n_nodes + npw - 1) / npw;
-        return (unsigned)(items < kNodeGrid ? items : kNodeGrid);
+        return (unsigned)(items < cap ? items : cap);
     };
-    if (retri) {
-        k_node32<CfgV4, true><<<grid(4), 64, 0, st>>>(P, 0);
-        k_node32<CfgV8, true><<<grid(2), 64, 0, st>>>(P, 1);
-        k_node32<CfgV16, true><<<grid(1), 64, 0, st>>>(P, 2);
+    if (src_rec) {
+        if (!redo || !redo_cnt) return hipErrorInvalidValue;
+        k_node32<CfgV4, kModeRetri><<<grid(4, kNodeGrid), 64, 0, st>>>(P, 0);
+        k_node32<CfgV8, kModeRetri><<<grid(2, kNodeGrid), 64, 0, st>>>(P, 1);
+        k_node32<CfgV16, kModeRetri><<<grid(1, kNodeGrid), 64, 0, st>>>(P, 2);
+        // the redo lists are short unless most nodes needed FP64 at the source
+        k_node32<CfgV4, kModeRedo><<<grid(4, kRedoGrid), 64, 0, st>>>(P, 0);
+        k_node32<CfgV8, kModeRedo><<<grid(2, kRedoGrid), 64, 0, st>>>(P, 1);
+        k_node32<CfgV16, kModeRedo><<<grid(1, kRedoGrid), 64, 0, st>>>(P, 2);
     } else {
-        k_node32<CfgV4, false><<<grid(4), 64, 0, st>>>(P, 0);
-        k_node32<CfgV8, false><<<grid(2), 64, 0, st>>>(P, 1);
-        k_node32<CfgV16, false><<<grid(1), 64, 0, st>>>(P, 2);
+        k_node32<CfgV4, kModeMesh><<<grid(4, kNodeGrid), 64, 0, st>>>(P, 0);
+        k_node32<CfgV8, kModeMesh><<<grid(2, kNodeGrid), 64, 0, st>>>(P, 1);
+        k_node32<CfgV16, kModeMesh><<<grid(1, kNodeGrid), 64, 0, st>>>(P, 2);
     }
     return hipGetLastError();
 }

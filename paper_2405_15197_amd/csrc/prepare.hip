@@ -6,6 +6,7 @@ namespace lm {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kSortReg = 16;  // rows up to this length are sorted in registers
 
 __global__ void k_pack(Inputs in, float4 *node4, int32_t *deg)
 {
@@ -15,18 +16,54 @@ __global__ void k_pack(Inputs in, float4 *node4, int32_t *deg)
     deg[i] = 0;
 }
 
+// Runs of equal keys among neighbouring lanes of a wave (struts listed cell
+// by cell share endpoints with their neighbours): the first lane of a run
+// does one atomic for the whole run.  Keys of lanes without work must differ
+// from every node id (negative, unique per lane).
+struct Run {
+    int leader, rank, len;
+};
+__device__ inline Run wave_run(int32_t key)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t prev = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || key != prev;
+    const unsigned long long hm = __ballot(head);
+    const unsigned long long upto = (2ull << lane) - 1;  // lanes 0..lane (all for lane 63)
+    const int leader = 63 - __clzll(hm & upto);
+    const unsigned long long above = hm & ~upto;
+    const int next = above ? __ffsll(above) - 1 : 64;
+    return Run{leader, lane - leader, next - leader};
+}
+
+// the two endpoint keys of strut s for the run aggregation (negative: none)
+__device__ inline void strut_keys(const Inputs &in, int64_t s, int32_t &ka, int32_t &kb, bool &bad)
+{
+    const int lane = threadIdx.x & 63;
+    ka = -1 - lane;
+    kb = -1 - lane;
+    bad = false;
+    if (s >= in.n_struts) return;
+    const int32_t a = in.sa[s], b = in.sb[s];
+    if (a < 0 || b < 0 || (int64_t)a >= in.n_nodes || (int64_t)b >= in.n_nodes) {
+        bad = true;
+        return;
+    }
+    ka = a;
+    if (b != a) kb = b;
+}
+
 // Degree histogram; out-of-range endpoints raise DF_BADLAT.
 __global__ void k_degree(Inputs in, int32_t *deg, int32_t *flags)
 {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= in.n_struts) return;
-    int32_t a = in.sa[s], b = in.sb[s];
-    if (a < 0 || b < 0 || (int64_t)a >= in.n_nodes || (int64_t)b >= in.n_nodes) {
-        atomicOr(&flags[1], DF_BADLAT);
-        return;
-    }
-    atomicAdd(&deg[a], 1);
-    if (b != a) atomicAdd(&deg[b], 1);
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t ka, kb;
+    bool bad;
+    strut_keys(in, s, ka, kb, bad);
+    if (bad) atomicOr(&flags[1], DF_BADLAT);
+    const Run ra = wave_run(ka), rb = wave_run(kb);
+    if (ka >= 0 && ra.rank == 0) atomicAdd(&deg[ka], ra.len);
+    if (kb >= 0 && rb.rank == 0) atomicAdd(&deg[kb], rb.len);
 }
 
 __global__ void k_zero(int32_t *p, int64_t n)
@@ -37,16 +74,19 @@ __global__ void k_zero(int32_t *p, int64_t n)
 
 __global__ void k_scatter(Inputs in, const int64_t *row, int32_t *cursor, int2 *he)
 {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= in.n_struts) return;
-    int32_t a = in.sa[s], b = in.sb[s];
-    if (a < 0 || b < 0 || (int64_t)a >= in.n_nodes || (int64_t)b >= in.n_nodes) return;
-    int64_t pa = row[a] + atomicAdd(&cursor[a], 1);
-    he[pa] = make_int2(b, (int32_t)s);
-    if (b != a) {
-        int64_t pb = row[b] + atomicAdd(&cursor[b], 1);
-        he[pb] = make_int2(a, (int32_t)s);
-    }
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t ka, kb;
+    bool bad;
+    strut_keys(in, s, ka, kb, bad);
+    const Run ra = wave_run(ka), rb = wave_run(kb);
+    int32_t ba = 0, bb = 0;
+    if (ka >= 0 && ra.rank == 0) ba = atomicAdd(&cursor[ka], ra.len);
+    if (kb >= 0 && rb.rank == 0) bb = atomicAdd(&cursor[kb], rb.len);
+    ba = __shfl(ba, ra.leader, 64);
+    bb = __shfl(bb, rb.leader, 64);
+    // the order inside a row is arbitrary here; k_sort_rows fixes it
+    if (ka >= 0) he[row[ka] + ba + ra.rank] = make_int2(kb >= 0 ? kb : ka, (int32_t)s);
+    if (kb >= 0) he[row[kb] + bb + rb.rank] = make_int2(ka, (int32_t)s);
 }
 
 // Incident struts of each node in increasing strut id (canonical labels
@@ -58,14 +98,42 @@ __global__ void k_sort_rows(int64_t n_nodes, const int64_t *row, int2 *he, int64
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= n_nodes) return;
     int64_t b = row[n], e = row[n + 1];
-    for (int64_t i = b + 1; i < e; ++i) {
-        int2 x = he[i];
-        int64_t j = i - 1;
-        while (j >= b && he[j].y > x.y) {
-            he[j + 1] = he[j];
-            --j;
+    if (e - b <= kSortReg) {
+        // in registers: bitonic network over kSortReg slots, empty slots last
+        const int v = (int)(e - b);
+        int2 x[kSortReg];
+#pragma unroll
+        for (int i = 0; i < kSortReg; ++i) x[i] = i < v ? he[b + i] : make_int2(0, 0x7fffffff);
+#pragma unroll
+        for (int k = 2; k <= kSortReg; k <<= 1) {
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+                for (int i = 0; i < kSortReg; ++i) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const bool up = (i & k) == 0;
+                        const bool sw = up ? x[i].y > x[l].y : x[i].y < x[l].y;
+                        const int2 lo = sw ? x[l] : x[i], hi = sw ? x[i] : x[l];
+                        x[i] = lo;
+                        x[l] = hi;
+                    }
+                }
+            }
         }
-        he[j + 1] = x;
+#pragma unroll
+        for (int i = 0; i < kSortReg; ++i)
+            if (i < v) he[b + i] = x[i];
+    } else {
+        for (int64_t i = b + 1; i < e; ++i) {
+            int2 x = he[i];
+            int64_t j = i - 1;
+            while (j >= b && he[j].y > x.y) {
+                he[j + 1] = he[j];
+                --j;
+            }
+            he[j + 1] = x;
+        }
     }
     for (int64_t i = b; i < e; ++i) {
         int32_t s = he[i].y;
