@@ -122,6 +122,16 @@ constexpr int kLossSlots = 256;
 // Valence classes of the node kernel: v <= 4, 5..8, otherwise.
 // (the batched entry point may lower the two limits: 4 and 8 are the class
 // capacities)
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) in turn:
+// block b runs on XCD b % 8.  This maps the blocks of one XCD to one
+// contiguous range of [0, nb), so that each L2 sees whole output lines.
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb)
+{
+    const int64_t x = b % kXcds, q = nb / kXcds, r = nb % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 __host__ __device__ inline int valence_class(int64_t v, int t16 = 4, int t32 = 8)
 {
     return v <= t16 ? 0 : (v <= t32 ? 1 : 2);

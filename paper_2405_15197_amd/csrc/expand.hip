@@ -23,22 +23,28 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
     const Work &W = P.w;
     const FillOut &O = P.o;
     const int64_t N = P.in.n_nodes;
-    const int64_t n = blockIdx.x;
+    const int64_t n = xcd_block(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
     if (n >= N) return;
     if (W.flags[0] & (DF_CAPACITY | DF_BADLAT | DF_RECCAP)) return;
+    // the record's sizes are the node's counts: no wait for its header
     const int64_t rb = W.node_rec[n];
+    const int64_t Np1 = N + 1;
+    const int64_t voff = W.node_off[NC_VERT * Np1 + n], aoff = W.node_off[NC_ARC * Np1 + n];
+    const int64_t hoff = W.node_off[NC_HOLE * Np1 + n];
+    const int64_t moff = W.node_off[NC_MESH * Np1 + n], foff = W.node_off[NC_FAN * Np1 + n];
+    const int V = (int)(W.node_off[NC_VERT * Np1 + n + 1] - voff);
+    const int E = (int)(W.node_off[NC_ARC * Np1 + n + 1] - aoff);
+    const int NC = (int)(W.node_off[NC_HOLE * Np1 + n + 1] - hoff);
+    const int M = (int)(W.node_off[NC_MESH * Np1 + n + 1] - moff);
+    const int F = (int)(W.node_off[NC_FAN * Np1 + n + 1] - foff);
+    const float4 c4 = W.node4[n];
     if (rb < 0) return;
+    const int wsum = M - NC;  // hole centres come last
     const uint32_t *R = W.rec + rb;
-    const int V = (int)R[0], E = (int)R[1], NC = (int)R[2], ncirc = (int)R[3];
-    const int wsum = (int)R[4], M = (int)R[5], F = (int)R[6];
     const uint32_t *RV = R + kRecHead;
     const uint32_t *RA = RV + 4 * V;
     const uint32_t *RH = RA + kRecArcFields * E;
-    const int64_t Np1 = N + 1;
-    const int64_t voff = W.node_off[0 * Np1 + n], aoff = W.node_off[1 * Np1 + n];
-    const int64_t moff = W.node_off[3 * Np1 + n], foff = W.node_off[4 * Np1 + n];
-    const float4 c4 = W.node4[n];
 
     for (int j = lane; j < E; j += 64) {
         s_mbase[j] = (int)RA[14 * E + j];
@@ -105,7 +111,9 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
     // hole centre, oriented outward
     const int64_t fan0 = W.band_off[P.in.n_struts] + foff;
     for (int i = lane; i < F; i += 64) {
-        int lo = 0, hi = ncirc - 1;  // last circular arc with fbase <= i
+        // last arc with fbase <= i: a circular arc (the others, after them,
+        // have fbase = F)
+        int lo = 0, hi = E - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (s_fbase[mid] <= i) lo = mid;

@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(64) k_zip(int64_t S, const int64_t *band_off, 
     __shared__ int g_ma[kZipGroup], g_mb[kZipGroup], g_t[kZipGroup + 1], g_q[kZipGroup + 1];
     if (flags[0] & (DF_CAPACITY | DF_BADLAT | DF_RECCAP)) return;
     const int lane = threadIdx.x;
-    const int64_t s0 = (int64_t)blockIdx.x * kZipGroup;
+    const int64_t s0 = xcd_block(blockIdx.x, gridDim.x) * kZipGroup;
     if (s0 >= S) return;
     const int ns = S - s0 < kZipGroup ? (int)(S - s0) : kZipGroup;
     const int64_t t0 = band_off[s0];
