@@ -124,6 +124,29 @@ __global__ void k_sort_rows(int64_t n_nodes, const int64_t *row, int2 *he, int64
 #pragma unroll
         for (int i = 0; i < kSortReg; ++i)
             if (i < v) he[b + i] = x[i];
+        // half-edge ids per strut end, all endpoint loads issued at once
+        int32_t lo[kSortReg];
+#pragma unroll
+        for (int i = 0; i < kSortReg; ++i) {
+            lo[i] = 0;
+            if (i < v) {
+                const int32_t a = sa[x[i].y], c = sb[x[i].y];
+                lo[i] = a == c ? -1 : (a < c ? a : c);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kSortReg; ++i) {
+            if (i < v) {
+                const int64_t s2 = 2 * (int64_t)x[i].y;
+                if (lo[i] < 0) {
+                    strut_he[s2] = b + i;
+                    strut_he[s2 + 1] = b + i;
+                } else {
+                    strut_he[s2 + (n == lo[i] ? 0 : 1)] = b + i;
+                }
+            }
+        }
+        return;
     } else {
         for (int64_t i = b + 1; i < e; ++i) {
             int2 x = he[i];
