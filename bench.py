@@ -197,6 +197,75 @@ def retri_bench(M, k0: int, ks, steps: int, warmup: int):
     return out
 
 
+def stl_bench(scale: int = 64, k: int = 16, path_dir: str | None = None):
+    """Binary STL of the BCC mesh through the pipelined writer: without a
+    file (encode + PCIe copy only), to a file with fsync at several chunk
+    sizes, and the disk and the PCIe copy alone for the same bytes."""
+    import tempfile
+
+    import torch
+
+    import latgen
+    from paper_2405_15197_amd.latmesh import Mesher
+
+    lat = latgen.config(2, scale=scale, seed=1)
+    M = Mesher(lat)
+    r = M.run(k, meta=False)
+    t = r.totals
+    nbytes = 84 + 50 * t["n_triangles"]
+    d = path_dir or os.environ.get("TMPDIR") or tempfile.gettempdir()
+    path = os.path.join(d, f"latmesh_bench_{os.getpid()}.stl")
+    out = {"workload": f"BCC {scale}^3 cells, k={k}: {t['n_triangles']} triangles, {nbytes} bytes", "bytes": nbytes,
+           "dir": d}
+    try:
+        M.write_stl(r, None)  # warm-up: allocations, first launches
+        st = M.write_stl(r, None)
+        out["no_file"] = {"GB_per_s": nbytes / st["seconds"] / 1e9, **st}
+        for mib in (16, 64, 256):
+            st = M.write_stl(r, path, chunk_bytes=mib << 20, fsync=True)
+            out[f"file_fsync_{mib}MiB"] = {"GB_per_s": nbytes / st["seconds"] / 1e9, **st}
+            os.remove(path)
+        # the disk alone: the same bytes from one host buffer, fsync at the end
+        buf = np.zeros(64 << 20, np.uint8)
+        t0 = time.perf_counter()
+        fd = os.open(path, os.O_WRONLY | os.O_CREAT | os.O_TRUNC, 0o644)
+        left = nbytes
+        while left > 0:
+            left -= os.write(fd, memoryview(buf)[: min(left, buf.size)])
+        os.fsync(fd)
+        os.close(fd)
+        out["disk_only_GB_per_s"] = nbytes / (time.perf_counter() - t0) / 1e9
+        os.remove(path)
+        # the same from pinned host memory (what the pipeline writes from)
+        pbuf = torch.zeros(64 << 20, dtype=torch.uint8, pin_memory=True).numpy()
+        t0 = time.perf_counter()
+        fd = os.open(path, os.O_WRONLY | os.O_CREAT | os.O_TRUNC, 0o644)
+        left = nbytes
+        while left > 0:
+            left -= os.write(fd, memoryview(pbuf)[: min(left, pbuf.size)])
+        os.fsync(fd)
+        os.close(fd)
+        out["disk_only_pinned_GB_per_s"] = nbytes / (time.perf_counter() - t0) / 1e9
+        os.remove(path)
+        # the PCIe copy alone: device to pinned host, 64 MiB pieces
+        dev = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+        host = torch.empty(64 << 20, dtype=torch.uint8, pin_memory=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        left = nbytes
+        while left > 0:
+            n = min(left, dev.numel())
+            host[:n].copy_(dev[:n], non_blocking=True)
+            left -= n
+        torch.cuda.synchronize()
+        out["d2h_only_GB_per_s"] = nbytes / (time.perf_counter() - t0) / 1e9
+    finally:
+        if os.path.exists(path):
+            os.remove(path)
+        M.close()
+    return out
+
+
 def billion_bench(k: int = 12, chunk_nodes: int = 1 << 23, scale: int = 512):
     """The BCC 512^3 lattice (269,223,425 nodes, 1,073,741,824 struts; radii
     0.08 (1 + U[-0.1, 0.1]), no jitter), generated on the device, meshed in
@@ -325,6 +394,7 @@ def main():
     ap.add_argument("--cpu-scale", type=int, default=64, help="BCC cells per side of the oracle's lattice")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint leg (octet 32^3)")
     ap.add_argument("--no-retri", action="store_true", help="skip the re-subdivision leg")
+    ap.add_argument("--stl", action="store_true", help="only the binary STL writer on the benchmark mesh")
     ap.add_argument("--billion", action="store_true",
                     help="only the BCC 512^3 lattice in sink mode (generated on the device), one pass")
     ap.add_argument("--billion-scale", type=int, default=512)
@@ -342,6 +412,9 @@ def main():
         return
     if args.batched:
         print(json.dumps(batched_bench(args.batched_parts, args.batched_nmax)), flush=True)
+        return
+    if args.stl:
+        print(json.dumps(stl_bench(args.scale, args.k)), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is in the "

@@ -45,6 +45,7 @@ extern "C" {
 #define LM_ERR_HIP (-5)            /* a HIP runtime call failed */
 #define LM_ERR_STATE (-6)          /* call out of order (e.g. fill before count) */
 #define LM_ERR_INTERNAL (-7)       /* the workspace could not be sized */
+#define LM_ERR_IO (-8)             /* a file could not be opened or written */
 
 /* ---- per-node status bits (node_status output) ------------------------- */
 #define LM_NODE_INVALID_STRUT 1u   /* |r_a - r_b| >= length, zero length or self loop */
@@ -305,6 +306,44 @@ void lm_plan_destroy(lm_plan *plan);
 
 /* Text for an LM_OK / LM_ERR_* code (static storage). */
 const char *lm_status_string(int code);
+
+/* ---- STL output ---------------------------------------------------------- */
+
+/* lm_write_stl flags */
+#define LM_STL_FSYNC 1  /* fsync the file before returning (time includes the disk) */
+
+/* What one lm_write_stl call moved and where its time went. */
+typedef struct lm_stl_stats {
+    int64_t n_triangles;
+    int64_t n_bytes;          /* file size: 84 + 50 n_triangles */
+    int64_t n_chunks;
+    int64_t chunk_triangles;  /* triangles per chunk (whole blocks of 256) */
+    double seconds;           /* wall time of the call */
+    double encode_ms;         /* device time of the encode kernels, summed */
+    double copy_ms;           /* device-to-host copy time, summed */
+    double write_s;           /* host time in write() (and fsync) */
+} lm_stl_stats;
+
+/* Binary STL of an indexed triangle mesh on the device (the output stage of
+ * the paper's asynchronous pipeline, Sec. 4.2.2, with 50-byte triangle
+ * records and the batch sized by the I/O buffer as in Eq. 6).
+ * d_mesh_xyz [n_mesh_vertices][3] FP32 and d_tri [n_triangles][3] int32 are
+ * device pointers (e.g. an lm_outputs after lm_forward; the call is ordered
+ * after earlier work on `stream`).  The file gets an 80-byte header, the
+ * count, and per triangle the unit normal of (v1 - v0) x (v2 - v0) (zero if
+ * degenerate), the three vertices and a zero attribute word.  The mesh goes
+ * out in chunks of about chunk_bytes (at least 12,800): the device encodes
+ * chunk i on `stream` while chunk i-1 is copied on a second stream into
+ * pinned host memory and written to the file by the calling thread, so
+ * encoding, the PCIe copy and the disk overlap.  path NULL runs the pipeline without a
+ * file (to time the device and PCIe part).  The call allocates two device
+ * and two pinned host buffers of chunk_bytes, frees them before returning,
+ * and synchronises the stream.  Returns LM_ERR_INVALID_ARG if a triangle
+ * index is outside [0, n_mesh_vertices) (the file is then incomplete),
+ * LM_ERR_UNSUPPORTED for 2^32 or more triangles, LM_ERR_IO if the file
+ * cannot be written.  stats may be NULL. */
+int lm_write_stl(const float *d_mesh_xyz, int64_t n_mesh_vertices, const int32_t *d_tri, int64_t n_triangles,
+                 const char *path, int64_t chunk_bytes, int flags, void *stream, lm_stl_stats *stats);
 
 #ifdef __cplusplus
 }

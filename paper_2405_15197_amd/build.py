@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblatmesh.so")
-SOURCES = ["prepare.hip", "node.hip", "expand.hip", "zip.hip", "grad.hip", "sink.hip", "api.hip"]
+SOURCES = ["prepare.hip", "node.hip", "expand.hip", "zip.hip", "grad.hip", "sink.hip", "stl.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3",

@@ -718,6 +718,7 @@ const char *lm_status_string(int code)
     case LM_ERR_HIP: return "HIP runtime error";
     case LM_ERR_STATE: return "call out of order";
     case LM_ERR_INTERNAL: return "workspace could not be sized";
+    case LM_ERR_IO: return "file could not be written";
     default: return "unknown status";
     }
 }

@@ -48,6 +48,7 @@ EXPORTS = (
     "lm_batched",
     "lm_loss",
     "lm_backward",
+    "lm_write_stl",
     "lm_plan_destroy",
     "lm_status_string",
 )
@@ -64,6 +65,25 @@ class lm_lattice(ctypes.Structure):
         ("d_strut_a", ctypes.c_void_p),
         ("d_strut_b", ctypes.c_void_p),
     ]
+
+
+class lm_stl_stats(ctypes.Structure):
+    _fields_ = [
+        ("n_triangles", ctypes.c_int64),
+        ("n_bytes", ctypes.c_int64),
+        ("n_chunks", ctypes.c_int64),
+        ("chunk_triangles", ctypes.c_int64),
+        ("seconds", ctypes.c_double),
+        ("encode_ms", ctypes.c_double),
+        ("copy_ms", ctypes.c_double),
+        ("write_s", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+LM_STL_FSYNC = 1
 
 
 _TOTAL_FIELDS = [
@@ -169,6 +189,9 @@ def load() -> ctypes.CDLL:
     lib.lm_loss.restype = ctypes.c_int
     lib.lm_backward.argtypes = [P, P, P, P]
     lib.lm_backward.restype = ctypes.c_int
+    lib.lm_write_stl.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_char_p, ctypes.c_int64, ctypes.c_int, P,
+                                 ctypes.POINTER(lm_stl_stats)]
+    lib.lm_write_stl.restype = ctypes.c_int
     lib.lm_plan_destroy.argtypes = [P]
     lib.lm_plan_destroy.restype = None
     lib.lm_status_string.argtypes = [ctypes.c_int]
@@ -216,6 +239,33 @@ def lm_retriangulate(plan, k: int, out: lm_outputs) -> None:
     rc = load().lm_retriangulate(plan, int(k), ctypes.byref(out))
     if rc != LM_OK:
         raise LatmeshError(rc, "lm_retriangulate")
+
+
+def lm_write_stl(d_mesh_xyz: int, n_mesh_vertices: int, d_tri: int, n_triangles: int, path, chunk_bytes: int,
+                 flags: int, stream: int | None) -> lm_stl_stats:
+    st = lm_stl_stats()
+    p = None if path is None else os.fsencode(path)
+    rc = load().lm_write_stl(ctypes.c_void_p(d_mesh_xyz), int(n_mesh_vertices), ctypes.c_void_p(d_tri),
+                             int(n_triangles), p, int(chunk_bytes), int(flags), ctypes.c_void_p(stream or 0),
+                             ctypes.byref(st))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_write_stl")
+    return st
+
+
+def write_stl(mesh_xyz, tri, path, chunk_bytes: int = 64 << 20, fsync: bool = False) -> dict:
+    """Binary STL of a device mesh (torch tensors [M, 3] float32 and [T, 3]
+    int32 on one GPU) through the library's pipelined writer; path None
+    runs the pipeline without a file.  Returns the call's statistics."""
+    import torch
+
+    mesh_xyz = mesh_xyz.contiguous()
+    tri = tri.contiguous()
+    with torch.cuda.device(mesh_xyz.device):
+        stream = torch.cuda.current_stream().cuda_stream
+        st = lm_write_stl(mesh_xyz.data_ptr(), mesh_xyz.shape[0], tri.data_ptr(), tri.shape[0], path, chunk_bytes,
+                          LM_STL_FSYNC if fsync else 0, stream)
+    return st.as_dict()
 
 
 def lm_read_totals(plan) -> lm_totals:
@@ -436,6 +486,11 @@ class Mesher:
                 raise LatmeshError(rc, "lm_retriangulate")
             r = self.alloc(tt.as_dict(), meta=meta)
         return self._trim(r, tt.as_dict(), meta)
+
+    def write_stl(self, r: MeshResult, path, chunk_bytes: int = 64 << 20, fsync: bool = False) -> dict:
+        """Binary STL of the mesh in ``r`` (trimmed to its totals)."""
+        t = r.totals
+        return write_stl(r.mesh_xyz[: t["n_mesh_vertices"]], r.tri[: t["n_triangles"]], path, chunk_bytes, fsync)
 
     def _trim(self, r: MeshResult, t: dict, meta: bool) -> MeshResult:
         r.totals = t
