@@ -266,6 +266,65 @@ def stl_bench(scale: int = 64, k: int = 16, path_dir: str | None = None):
     return out
 
 
+def codec_bench(scale: int = 64, k: int = 16, steps: int = 10):
+    """Arc codec on the benchmark meta-mesh: encode and decode times, bytes
+    against the FP32 arcs (44 B) and the node records' arc fields (64 B),
+    fallback share, and the Eq. 5 error on a sample of arcs."""
+    import torch
+
+    import latgen
+    from paper_2405_15197_amd.latmesh import Mesher
+
+    lat = latgen.config(2, scale=scale, seed=1)
+    M = Mesher(lat)
+    try:
+        r = M.run(k, meta=True)
+        E = r.arc_f32.shape[1]
+        enc = M.encode_arcs(r)
+        dec = M.decode_arcs(enc, r)
+
+        def timed(fn):
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(steps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / steps
+
+        enc_ms = timed(lambda: M.encode_arcs(r))  # includes its synchronisation
+        dec_ms = timed(lambda: M.decode_arcs(enc, r))
+        rng = np.random.default_rng(0)
+        sel = np.sort(rng.choice(E, size=min(E, 200000), replace=False))
+        arcs = r.arc_f32.cpu().numpy().T[sel].astype(np.float64)
+        dd = dec.cpu().numpy().T[sel].astype(np.float64)
+        mask = enc["mask"].cpu().numpy().view(np.uint32)
+        fb = ((mask[sel >> 5] >> (sel & 31)) & 1).astype(bool)
+        from oracle import codec as ref  # error bound only (test infrastructure)
+
+        err = ref.arc_error(arcs[~fb], dd[~fb])
+        nf = enc["n_fallback"]
+        code_bytes = 16 * E + 44 * nf + 4 * ((E + 31) // 32)
+        return {
+            "workload": f"BCC {scale}^3 cells, k={k}: {E} meta-mesh arcs",
+            "arcs": E,
+            "fallback": nf,
+            "fallback_share": nf / E,
+            "bytes_fp32_arcs": 44 * E,
+            "bytes_codes": code_bytes,
+            "ratio_vs_fp32_arcs": 44 * E / code_bytes,
+            "encode_ms": enc_ms,
+            "decode_ms": dec_ms,
+            "encode_arcs_per_s": E / (enc_ms * 1e-3),
+            "decode_arcs_per_s": E / (dec_ms * 1e-3),
+            "max_error_over_r_max_sampled": float(err.max() / enc["r_max"]),
+            "eq5_bound": ref.eq5_bound(),
+        }
+    finally:
+        M.close()
+
+
 def billion_bench(k: int = 12, chunk_nodes: int = 1 << 23, scale: int = 512):
     """The BCC 512^3 lattice (269,223,425 nodes, 1,073,741,824 struts; radii
     0.08 (1 + U[-0.1, 0.1]), no jitter), generated on the device, meshed in
@@ -395,6 +454,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint leg (octet 32^3)")
     ap.add_argument("--no-retri", action="store_true", help="skip the re-subdivision leg")
     ap.add_argument("--stl", action="store_true", help="only the binary STL writer on the benchmark mesh")
+    ap.add_argument("--codec", action="store_true", help="only the arc codec on the benchmark meta-mesh")
     ap.add_argument("--billion", action="store_true",
                     help="only the BCC 512^3 lattice in sink mode (generated on the device), one pass")
     ap.add_argument("--billion-scale", type=int, default=512)
@@ -415,6 +475,9 @@ def main():
         return
     if args.stl:
         print(json.dumps(stl_bench(args.scale, args.k)), flush=True)
+        return
+    if args.codec:
+        print(json.dumps(codec_bench(args.scale, args.k)), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is in the "

@@ -307,6 +307,43 @@ void lm_plan_destroy(lm_plan *plan);
 /* Text for an LM_OK / LM_ERR_* code (static storage). */
 const char *lm_status_string(int code);
 
+/* ---- lossy arc codec ---------------------------------------------------- */
+
+/* Compressed meta-mesh arcs (Sec. 4.2.1): 128 bits per arc, or the arc kept
+ * whole when it falls outside the format's ranges.  All device memory,
+ * caller-owned. */
+typedef struct lm_arc_codes {
+    uint32_t *d_codes;         /* [cap_arcs][4]; a fallback arc's code holds its slot */
+    uint32_t *d_fallback_mask; /* [(cap_arcs + 31) / 32], bit j: arc j kept whole */
+    float *d_fallback;         /* [cap_fallback][11] arcs kept whole (any order) */
+    int64_t cap_arcs;
+    int64_t cap_fallback;
+} lm_arc_codes;
+
+/* Encode n_arcs meta-mesh arcs given as lm_outputs arrays (d_arc_f32
+ * [11][ld] o, a, b, t1, t2 node-local; d_arc_u32 [3][ld] with p | q << 8 in
+ * row 0 and the node in row 2) of the plan's lattice, whose adjacency must
+ * be the one the arcs were made with (lm_prepare state).  The semi-major
+ * axis a and the centre o are kept as spherical coordinates (12-bit radius,
+ * 15-bit polar angle, 16-bit azimuth; a in [r_min, 4 r_max], o within
+ * r_max), the semi-minor axis b as its 12-bit length in [0.1 r_min, r_max]
+ * (its direction is a x d / |a x d|, d the strut direction for a tangency
+ * circle or the normal of the seam plane (g_p - g_q) / |g_p - g_q| for an
+ * ellipse), t1 on 15 bits over [0, 2 pi) and t2 - t1 on 15 bits over
+ * [0, 2 pi].  r_min, r_max: the smallest and largest node radius.  Decoded
+ * points lie within Eq. 5's 8.69e-4 r_max of the arc's points at the same t.
+ * Synchronises the stream; *n_fallback (host) receives the number of arcs
+ * kept whole.  Returns LM_ERR_CAPACITY if that number exceeds cap_fallback
+ * (then the codes of the excess arcs are unusable). */
+int lm_arc_encode(lm_plan *plan, const float *d_arc_f32, const uint32_t *d_arc_u32, int64_t n_arcs, int64_t ld,
+                  float r_min, float r_max, const lm_arc_codes *codes, int64_t *n_fallback);
+
+/* Decode the first n_arcs codes into d_arc_f32_out [11][ld_out] (same
+ * fields as lm_outputs.d_arc_f32), with d_arc_u32 and r_min, r_max as given
+ * to lm_arc_encode.  Asynchronous. */
+int lm_arc_decode(lm_plan *plan, const lm_arc_codes *codes, const uint32_t *d_arc_u32, int64_t n_arcs, int64_t ld,
+                  float r_min, float r_max, float *d_arc_f32_out, int64_t ld_out);
+
 /* ---- STL output ---------------------------------------------------------- */
 
 /* lm_write_stl flags */

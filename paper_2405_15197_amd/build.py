@@ -11,7 +11,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblatmesh.so")
-SOURCES = ["prepare.hip", "node.hip", "expand.hip", "zip.hip", "grad.hip", "sink.hip", "stl.hip", "api.hip"]
+SOURCES = ["prepare.hip", "node.hip", "expand.hip", "zip.hip", "grad.hip", "sink.hip", "stl.hip", "codec.hip",
+           "api.hip"]
+# quantisation decisions must not depend on fused multiply-adds
+EXTRA = {"codec.hip": ["-ffp-contract=off"]}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3",
@@ -26,7 +29,7 @@ FLAGS = [
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")

@@ -38,6 +38,7 @@ struct lm_plan {
     void *alt_index_mem = nullptr;
     int32_t *redo = nullptr;
     int32_t *redo_cnt = nullptr;
+    unsigned long long *codec_ctr = nullptr;  // fallback counter of lm_arc_encode
     int k;          // resolution of the last count (0: none)
     float kappa_max;// FP32 -> FP64 hand-over threshold
     lm_totals last; // totals of the last lm_count
@@ -636,6 +637,43 @@ int lm_retriangulate(lm_plan *P, int k, const lm_outputs *out)
     return LM_OK;
 }
 
+int lm_arc_encode(lm_plan *P, const float *d_arc_f32, const uint32_t *d_arc_u32, int64_t n_arcs, int64_t ld,
+                  float r_min, float r_max, const lm_arc_codes *c, int64_t *n_fallback)
+{
+    if (!P || !c || !n_fallback || n_arcs < 0 || ld < n_arcs || !(r_min > 0.f) || !(r_max >= r_min))
+        return LM_ERR_INVALID_ARG;
+    if (n_arcs > 0 && (!d_arc_f32 || !d_arc_u32 || !c->d_codes || !c->d_fallback_mask)) return LM_ERR_INVALID_ARG;
+    if (c->cap_arcs < n_arcs || c->cap_fallback < 0 || (c->cap_fallback > 0 && !c->d_fallback))
+        return LM_ERR_CAPACITY;
+    *n_fallback = 0;
+    if (n_arcs == 0) return LM_OK;
+    if (!P->codec_ctr) HIPCHK(hipMalloc((void **)&P->codec_ctr, sizeof(unsigned long long)));
+    HIPCHK(hipMemsetAsync(P->codec_ctr, 0, sizeof(unsigned long long), P->st));
+    HIPCHK(hipMemsetAsync(c->d_fallback_mask, 0, sizeof(uint32_t) * ((n_arcs + 31) / 32), P->st));
+    HIPCHK(lm::launch_arc_codec(P->in, P->w, true, d_arc_f32, d_arc_u32, n_arcs, ld, (double)r_min, (double)r_max,
+                                c->d_codes, c->d_fallback_mask, c->d_fallback, c->cap_fallback, P->codec_ctr,
+                                nullptr, 0, P->st));
+    unsigned long long nf = 0;
+    HIPCHK(hipMemcpyAsync(&nf, P->codec_ctr, sizeof(nf), hipMemcpyDeviceToHost, P->st));
+    HIPCHK(hipStreamSynchronize(P->st));
+    *n_fallback = (int64_t)nf;
+    return (int64_t)nf > c->cap_fallback ? LM_ERR_CAPACITY : LM_OK;
+}
+
+int lm_arc_decode(lm_plan *P, const lm_arc_codes *c, const uint32_t *d_arc_u32, int64_t n_arcs, int64_t ld,
+                  float r_min, float r_max, float *d_arc_f32_out, int64_t ld_out)
+{
+    if (!P || !c || n_arcs < 0 || ld < n_arcs || ld_out < n_arcs || !(r_min > 0.f) || !(r_max >= r_min))
+        return LM_ERR_INVALID_ARG;
+    if (n_arcs == 0) return LM_OK;
+    if (!d_arc_u32 || !d_arc_f32_out || !c->d_codes || !c->d_fallback_mask) return LM_ERR_INVALID_ARG;
+    if (c->cap_arcs < n_arcs) return LM_ERR_CAPACITY;
+    HIPCHK(lm::launch_arc_codec(P->in, P->w, false, nullptr, d_arc_u32, n_arcs, ld, (double)r_min, (double)r_max,
+                                c->d_codes, c->d_fallback_mask, c->d_fallback, c->cap_fallback, nullptr,
+                                d_arc_f32_out, ld_out, P->st));
+    return LM_OK;
+}
+
 int lm_read_totals(lm_plan *P, lm_totals *totals)
 {
     if (!P || !totals) return LM_ERR_INVALID_ARG;
@@ -701,7 +739,7 @@ void lm_plan_destroy(lm_plan *P)
     for (auto e : P->pool) (void)hipEventDestroy(e);
     if (P->w.rec) (void)hipFree(P->w.rec);
     for (void *p : {(void *)P->sk_mark, (void *)P->sk_lists, (void *)P->sk_cnt, (void *)P->sk_info,
-                    (void *)P->sk_struts, (void *)P->sk_slots, (void *)P->alt_rec, P->alt_index_mem})
+                    (void *)P->sk_struts, (void *)P->sk_slots, (void *)P->alt_rec, P->alt_index_mem, (void *)P->codec_ctr})
         if (p) (void)hipFree(p);
     (void)hipFree(P->ws);
     delete P;

@@ -162,6 +162,12 @@ hipError_t launch_scan(const int32_t *src, int64_t *dst, int64_t n, int ncols, i
 // records; nodes that must be solved in full go to redo ([N], partitioned
 // like the queue) with counts and work counters in redo_cnt [8], zeroed by
 // the caller.
+// Arc codec (encode: arc + u32 -> codes, mask, fallback; decode: codes ->
+// out), one thread per arc.
+hipError_t launch_arc_codec(const Inputs &in, const Work &w, bool encode, const float *arc, const uint32_t *u32,
+                            int64_t E, int64_t ld, double rmin, double rmax, uint32_t *codes, uint32_t *mask,
+                            float *fb, int64_t fb_cap, unsigned long long *fb_n, float *out, int64_t ld_out,
+                            hipStream_t st);
 hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, int fp64, hipStream_t st,
                        const uint32_t *src_rec = nullptr, const int64_t *src_node_rec = nullptr,
                        int32_t *redo = nullptr, int32_t *redo_cnt = nullptr);

@@ -49,6 +49,8 @@ EXPORTS = (
     "lm_loss",
     "lm_backward",
     "lm_write_stl",
+    "lm_arc_encode",
+    "lm_arc_decode",
     "lm_plan_destroy",
     "lm_status_string",
 )
@@ -64,6 +66,16 @@ class lm_lattice(ctypes.Structure):
         ("d_radius", ctypes.c_void_p),
         ("d_strut_a", ctypes.c_void_p),
         ("d_strut_b", ctypes.c_void_p),
+    ]
+
+
+class lm_arc_codes(ctypes.Structure):
+    _fields_ = [
+        ("d_codes", ctypes.c_void_p),
+        ("d_fallback_mask", ctypes.c_void_p),
+        ("d_fallback", ctypes.c_void_p),
+        ("cap_arcs", ctypes.c_int64),
+        ("cap_fallback", ctypes.c_int64),
     ]
 
 
@@ -192,6 +204,12 @@ def load() -> ctypes.CDLL:
     lib.lm_write_stl.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_char_p, ctypes.c_int64, ctypes.c_int, P,
                                  ctypes.POINTER(lm_stl_stats)]
     lib.lm_write_stl.restype = ctypes.c_int
+    lib.lm_arc_encode.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
+                                  ctypes.POINTER(lm_arc_codes), ctypes.POINTER(ctypes.c_int64)]
+    lib.lm_arc_encode.restype = ctypes.c_int
+    lib.lm_arc_decode.argtypes = [P, ctypes.POINTER(lm_arc_codes), P, ctypes.c_int64, ctypes.c_int64, ctypes.c_float,
+                                  ctypes.c_float, P, ctypes.c_int64]
+    lib.lm_arc_decode.restype = ctypes.c_int
     lib.lm_plan_destroy.argtypes = [P]
     lib.lm_plan_destroy.restype = None
     lib.lm_status_string.argtypes = [ctypes.c_int]
@@ -491,6 +509,50 @@ class Mesher:
         """Binary STL of the mesh in ``r`` (trimmed to its totals)."""
         t = r.totals
         return write_stl(r.mesh_xyz[: t["n_mesh_vertices"]], r.tri[: t["n_triangles"]], path, chunk_bytes, fsync)
+
+    def radius_range(self):
+        """(smallest, largest) node radius of the lattice."""
+        return float(self.r.min().item()), float(self.r.max().item())
+
+    def encode_arcs(self, r: MeshResult, r_min=None, r_max=None, cap_fallback=None) -> dict:
+        """128-bit codes of the meta-mesh arcs in ``r`` (a MeshResult with
+        meta-mesh arrays); returns device tensors ``codes`` [E, 4] int32
+        (bit patterns), ``mask`` [(E + 31) // 32], ``fallback`` [F, 11] and
+        the host int ``n_fallback``."""
+        torch = self.torch
+        lo, hi = self.radius_range()
+        r_min = lo if r_min is None else r_min
+        r_max = hi if r_max is None else r_max
+        E = r.arc_f32.shape[1]
+        cap_fb = max(E // 16, 64) if cap_fallback is None else cap_fallback
+        dev = self.device
+        codes = torch.empty((max(E, 1), 4), dtype=torch.int32, device=dev)
+        mask = torch.empty(max((E + 31) // 32, 1), dtype=torch.int32, device=dev)
+        fb = torch.empty((max(cap_fb, 1), 11), dtype=torch.float32, device=dev)
+        c = lm_arc_codes(codes.data_ptr(), mask.data_ptr(), fb.data_ptr(), codes.shape[0], cap_fb)
+        nf = ctypes.c_int64(0)
+        ld = r.arc_f32.stride(0)
+        rc = load().lm_arc_encode(self.plan, ctypes.c_void_p(r.arc_f32.data_ptr()),
+                                  ctypes.c_void_p(r.arc_u32.data_ptr()), E, ld, r_min, r_max, ctypes.byref(c),
+                                  ctypes.byref(nf))
+        if rc != LM_OK:
+            raise LatmeshError(rc, "lm_arc_encode")
+        return {"codes": codes[:E], "mask": mask, "fallback": fb[: nf.value], "n_fallback": nf.value,
+                "cap_fallback": cap_fb, "r_min": r_min, "r_max": r_max, "_fb_full": fb}
+
+    def decode_arcs(self, enc: dict, r: MeshResult):
+        """Arcs [11, E] float32 (the fields of arc_f32) from encode_arcs' output."""
+        torch = self.torch
+        E = enc["codes"].shape[0]
+        out = torch.empty((11, max(E, 1)), dtype=torch.float32, device=self.device)
+        c = lm_arc_codes(enc["codes"].data_ptr(), enc["mask"].data_ptr(), enc["_fb_full"].data_ptr(),
+                         max(E, 1), enc["cap_fallback"])
+        rc = load().lm_arc_decode(self.plan, ctypes.byref(c), ctypes.c_void_p(r.arc_u32.data_ptr()), E,
+                                  r.arc_u32.stride(0), enc["r_min"], enc["r_max"], ctypes.c_void_p(out.data_ptr()),
+                                  out.stride(0))
+        if rc != LM_OK:
+            raise LatmeshError(rc, "lm_arc_decode")
+        return out[:, :E]
 
     def _trim(self, r: MeshResult, t: dict, meta: bool) -> MeshResult:
         r.totals = t
