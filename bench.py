@@ -332,6 +332,36 @@ def codec_bench(scale: int = 64, k: int = 16, steps: int = 10):
         M.close()
 
 
+def ablation_bench(scale: int = 64, k: int = 16, steps: int = 3):
+    """The FP32 node pass (lm_count's meta-meshing) wave-centric against the
+    thread-centric ablation (one lane per node, scratch in global memory),
+    device time from the library's events."""
+    import torch
+
+    import latgen
+    from paper_2405_15197_amd.latmesh import Mesher, lm_get_profile, lm_set_profiling
+
+    lat = latgen.config(2, scale=scale, seed=1)
+    M = Mesher(lat)
+    out = {"workload": f"BCC {scale}^3 cells, {lat.n_nodes} nodes, k={k}: FP32 node pass"}
+    try:
+        for name, thread in (("wave_centric", False), ("thread_centric", True)):
+            M.set_schedule(thread)
+            M.count(k)  # warm-up (and the thread pass's scratch)
+            torch.cuda.synchronize()
+            lm_get_profile(M.plan)
+            lm_set_profiling(M.plan, True)
+            for _ in range(steps):
+                M.count(k)
+            prof = lm_get_profile(M.plan)
+            lm_set_profiling(M.plan, False)
+            out[name + "_ms"] = prof["node_fp32"][0] / max(prof["node_fp32"][1], 1)
+        out["speedup_wave_over_thread"] = out["thread_centric_ms"] / out["wave_centric_ms"]
+    finally:
+        M.close()
+    return out
+
+
 def billion_bench(k: int = 12, chunk_nodes: int = 1 << 23, scale: int = 512):
     """The BCC 512^3 lattice (269,223,425 nodes, 1,073,741,824 struts; radii
     0.08 (1 + U[-0.1, 0.1]), no jitter), generated on the device, meshed in
@@ -462,6 +492,8 @@ def main():
     ap.add_argument("--no-retri", action="store_true", help="skip the re-subdivision leg")
     ap.add_argument("--stl", action="store_true", help="only the binary STL writer on the benchmark mesh")
     ap.add_argument("--codec", action="store_true", help="only the arc codec on the benchmark meta-mesh")
+    ap.add_argument("--ablation", action="store_true",
+                    help="only the node pass, wave-centric against the thread-centric ablation")
     ap.add_argument("--billion", action="store_true",
                     help="only the BCC 512^3 lattice in sink mode (generated on the device), one pass")
     ap.add_argument("--billion-scale", type=int, default=512)
@@ -485,6 +517,9 @@ def main():
         return
     if args.codec:
         print(json.dumps(codec_bench(args.scale, args.k)), flush=True)
+        return
+    if args.ablation:
+        print(json.dumps(ablation_bench(args.scale, args.k)), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is in the "

@@ -209,6 +209,19 @@ int lm_read_totals(lm_plan *plan, lm_totals *totals);
  * every node in FP64.  Invalidates the last lm_count. */
 int lm_set_precision(lm_plan *plan, float kappa_max);
 
+/* Scheduling of the FP32 node pass of lm_count and lm_forward.
+ * LM_SCHEDULE_WAVE (default): a node per group of lanes of a wave, lanes
+ * over its conics and samples, nodes bucketed by valence, per-node scratch in
+ * LDS (the paper's warp-centric design, Sec. 4.3, on 64-lane waves).
+ * LM_SCHEDULE_THREAD: an ablation of it — one lane per node, nodes in id
+ * order without buckets, per-node scratch in global memory (allocated at the
+ * first use, about 3 GB) — the thread-centric design the paper measures
+ * against.  Both give identical results.  Re-triangulation, sink mode and
+ * batched parts always use the wave schedule. */
+#define LM_SCHEDULE_WAVE 0
+#define LM_SCHEDULE_THREAD 1
+int lm_set_schedule(lm_plan *plan, int schedule);
+
 /* Profiling: when on, every library call records HIP events on the plan's
  * stream around its phases; lm_get_profile synchronises the stream and
  * returns, per phase, the summed milliseconds and the number of timed calls

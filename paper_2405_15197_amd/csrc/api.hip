@@ -39,6 +39,8 @@ struct lm_plan {
     int32_t *redo = nullptr;
     int32_t *redo_cnt = nullptr;
     unsigned long long *codec_ctr = nullptr;  // fallback counter of lm_arc_encode
+    int schedule = LM_SCHEDULE_WAVE;          // FP32 node pass of lm_count / lm_forward
+    void *thread_scratch = nullptr;           // per-node scratch of the thread-centric pass
     int k;          // resolution of the last count (0: none)
     float kappa_max;// FP32 -> FP64 hand-over threshold
     lm_totals last; // totals of the last lm_count
@@ -179,7 +181,12 @@ int run_count(lm_plan *P, int k, const lm::FillOut *out, const lm::Work &w, cons
     {
         PhaseTimer t(P, PH_NODE32);
         if (redo_cnt) HIPCHK(hipMemsetAsync(redo_cnt, 0, sizeof(int32_t) * 8, P->st));
-        HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, 0, P->st, src_rec, src_node_rec, redo, redo_cnt));
+        if (P->schedule == LM_SCHEDULE_THREAD && !src_rec) {
+            if (!P->thread_scratch) HIPCHK(hipMalloc(&P->thread_scratch, lm::node_thread_scratch_bytes()));
+            HIPCHK(lm::launch_node_thread(P->in, w, k, P->kappa_max, P->thread_scratch, P->st));
+        } else {
+            HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, 0, P->st, src_rec, src_node_rec, redo, redo_cnt));
+        }
     }
     {
         PhaseTimer t(P, PH_NODE64);
@@ -720,6 +727,13 @@ int lm_get_profile(lm_plan *P, double *ms, int64_t *calls, int n)
     return LM_OK;
 }
 
+int lm_set_schedule(lm_plan *P, int schedule)
+{
+    if (!P || (schedule != LM_SCHEDULE_WAVE && schedule != LM_SCHEDULE_THREAD)) return LM_ERR_INVALID_ARG;
+    P->schedule = schedule;
+    return LM_OK;
+}
+
 int lm_set_precision(lm_plan *P, float kappa_max)
 {
     if (!P || !(kappa_max >= 0.0f)) return LM_ERR_INVALID_ARG;
@@ -739,7 +753,7 @@ void lm_plan_destroy(lm_plan *P)
     for (auto e : P->pool) (void)hipEventDestroy(e);
     if (P->w.rec) (void)hipFree(P->w.rec);
     for (void *p : {(void *)P->sk_mark, (void *)P->sk_lists, (void *)P->sk_cnt, (void *)P->sk_info,
-                    (void *)P->sk_struts, (void *)P->sk_slots, (void *)P->alt_rec, P->alt_index_mem, (void *)P->codec_ctr})
+                    (void *)P->sk_struts, (void *)P->sk_slots, (void *)P->alt_rec, P->alt_index_mem, (void *)P->codec_ctr, P->thread_scratch})
         if (p) (void)hipFree(p);
     (void)hipFree(P->ws);
     delete P;

@@ -162,6 +162,12 @@ hipError_t launch_scan(const int32_t *src, int64_t *dst, int64_t n, int ncols, i
 // records; nodes that must be solved in full go to redo ([N], partitioned
 // like the queue) with counts and work counters in redo_cnt [8], zeroed by
 // the caller.
+// Thread-centric ablation of the FP32 node pass (one lane per node, node id
+// order, per-node scratch of node_thread_scratch_bytes() in global memory).
+size_t node_thread_scratch_bytes();
+hipError_t launch_node_thread(const Inputs &in, const Work &w, int k, float kappa_max, void *scratch,
+                              hipStream_t st);
+
 // Arc codec (encode: arc + u32 -> codes, mask, fallback; decode: codes ->
 // out), one thread per arc.
 hipError_t launch_arc_codec(const Inputs &in, const Work &w, bool encode, const float *arc, const uint32_t *u32,

@@ -130,6 +130,19 @@ __device__ inline int group_excl_scan(int x, int *total)
     return inc - x;
 }
 
+// f(i) for i = lo + lane, lo + lane + W, ... up to hi (inclusive; hi is at
+// most the valence + 1): one test when a node has more lanes than that, a
+// loop otherwise (one lane per node)
+template <int W, int VM, typename F>
+__device__ inline void over_lanes(int lane, int lo, int hi, F &&f)
+{
+    if constexpr (W > VM + 1) {
+        if (lo + lane <= hi) f(lo + lane);
+    } else {
+        for (int i = lo + lane; i <= hi; i += W) f(i);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // trimming of one conic: intersection of circular intervals
 
@@ -561,7 +574,8 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
             if (lane == 0) sh.entry_off[nent] = off;
         }
         __syncthreads();
-        if (lane <= v) sh.lbase[lane + 1] = sh.entry_off[sh.loop_base[lane + 1]];  // lane v: the total
+        // index v: the total
+        over_lanes<WL, CF::VM>(lane, 0, v, [&](int l) { sh.lbase[l + 1] = sh.entry_off[sh.loop_base[l + 1]]; });
         if (lane == 0) {
             const int off = sh.entry_off[sh.loop_base[v + 1]];
             // record space: bump allocation in the node's region
@@ -577,10 +591,10 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
                 atomicOr(&W.flags[0], DF_RECCAP);
             }
         }
-        if (lane < v) {
-            sh.loop_desc[lane + 1] = 0;
-            sh.loop_rot[lane + 1] = 0;
-        }
+        over_lanes<WL, CF::VM>(lane, 0, v - 1, [&](int l) {
+            sh.loop_desc[l + 1] = 0;
+            sh.loop_rot[l + 1] = 0;
+        });
         __syncthreads();
         {
             const int nent = sh.loop_base[v + 1];
@@ -649,8 +663,8 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
             }
         }
         __syncthreads();
-        if (lane < v) {
-            const int m = lane + 1;
+        over_lanes<WL, CF::VM>(lane, 0, v - 1, [&](int l) {
+            const int m = l + 1;
             const T a = sh.ph_last[m], b = sh.ph_first[m];
             T dp = b - a;
             if (dp <= (T)-2) dp += (T)4;
@@ -660,12 +674,12 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
                 atomicAdd(&sh.loop_desc[m], 1);
                 sh.loop_rot[m] = 0;
             }
-        }
+        });
         __syncthreads();
-        if (lane < v) {
-            if (sh.loop_desc[lane + 1] != 1) atomicOr(&sh.status, NS_LOOP);
-            W.he_rot[row + lane] = sh.loop_rot[lane + 1];
-        }
+        over_lanes<WL, CF::VM>(lane, 0, v - 1, [&](int l) {
+            if (sh.loop_desc[l + 1] != 1) atomicOr(&sh.status, NS_LOOP);
+            W.he_rot[row + l] = sh.loop_rot[l + 1];
+        });
         __syncthreads();
     }
 
@@ -682,7 +696,7 @@ finish:
                 // hand the node to the FP64 pass when precision may be at fault
                 if (F32 && (status & kRetry)) W.fb_list[atomicAdd(&W.flags[2], 1)] = (int32_t)n;
             }
-            if (lane < v) W.he_len[row + lane] = 0;
+            over_lanes<WL, CF::VM>(lane, 0, v - 1, [&](int l) { W.he_len[row + l] = 0; });
             return;
         }
         const int Msum = sh.wsum + NC, Fsum = sh.fsum;
@@ -698,10 +712,10 @@ finish:
             W.node_cnt[NC_STATUS * N + n] = 0;
             W.node_rec[n] = rb;
         }
-        if (lane < v) {
-            W.he_len[row + lane] = sh.loop_len[lane + 1];
-            W.he_loop[row + lane] = rb >= 0 ? (rb + lw) / 2 + sh.lbase[lane + 1] : 0;
-        }
+        over_lanes<WL, CF::VM>(lane, 0, v - 1, [&](int l) {
+            W.he_len[row + l] = sh.loop_len[l + 1];
+            W.he_loop[row + l] = rb >= 0 ? (rb + lw) / 2 + sh.lbase[l + 1] : 0;
+        });
         if (rb < 0) return;
         uint32_t *R = W.rec + rb;
         if (lane == 0) {
@@ -744,7 +758,7 @@ finish:
         }
         // loop table (for re-subdivision at another resolution)
         uint8_t *RT = (uint8_t *)(R + rec_table_word(V, E, NC));
-        if (lane <= v) RT[lane] = (uint8_t)sh.loop_base[lane + 1];
+        over_lanes<WL, CF::VM>(lane, 0, v, [&](int l) { RT[l] = (uint8_t)sh.loop_base[l + 1]; });
         for (int e = lane; e < nent; e += WL) {
             const int m = sh.entry_m[e];
             const int pp = sh.loop_base[m] + sh.loop_ord[e];
@@ -791,8 +805,8 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
     }
 
     // ---- strut table -----------------------------------------------------
-    if (lane < v) {
-        int2 he = W.he[row + lane];
+    over_lanes<WL, CF::VM>(lane, 0, v - 1, [&](int l) {
+        int2 he = W.he[row + l];
         int far = he.x;
         float4 f4 = W.node4[far];
         bool bad;
@@ -800,13 +814,13 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
         s.sid = he.y;
         s.far = far;
         if (bad || far == n) atomicOr(&sh.status, NS_INVALID_STRUT);
-        sh.S[lane + 1] = s;
-    }
+        sh.S[l + 1] = s;
+    });
     __syncthreads();
-    if (lane < v) {
+    over_lanes<WL, CF::VM>(lane, 0, v - 1, [&](int l) {
         for (int j = 0; j < v; ++j)
-            if (j != lane && sh.S[j + 1].far == sh.S[lane + 1].far) atomicOr(&sh.status, NS_DUPLICATE);
-    }
+            if (j != l && sh.S[j + 1].far == sh.S[l + 1].far) atomicOr(&sh.status, NS_DUPLICATE);
+    });
     if (F32 && lane == 0 && !(P.kappa_max > 0.f)) atomicOr(&sh.status, NS_PREC);  // all FP64
     __syncthreads();
     if (sh.status) goto tail;
@@ -987,11 +1001,11 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
     // smallest name.
     {
         const int E = sh.n_arc;
-        if (lane <= v) {
-            sh.loop_cnt[lane] = 0;
-            sh.loop_len[lane] = 0;
-            sh.loop_full[lane] = 0;
-        }
+        over_lanes<WL, CF::VM>(lane, 0, v, [&](int l) {
+            sh.loop_cnt[l] = 0;
+            sh.loop_len[l] = 0;
+            sh.loop_full[l] = 0;
+        });
         __syncthreads();
         for (int j = lane; j < E; j += WL) {
             const ArcL<T> &A = sh.A[j];
@@ -999,14 +1013,21 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
             atomicAdd(&sh.loop_cnt[A.q], 1);
         }
         __syncthreads();
-        {
+        if constexpr (WL > CF::VM + 1) {
             int c = (lane >= 1 && lane <= v) ? sh.loop_cnt[lane] : 0, tot;
             int base = group_excl_scan<WL>(c, &tot);
             if (lane >= 1 && lane <= v) sh.loop_base[lane] = base;
             if (lane == 0) sh.loop_base[v + 1] = tot;
+        } else if (lane == 0) {
+            int acc = 0;
+            for (int m = 1; m <= v; ++m) {
+                sh.loop_base[m] = acc;
+                acc += sh.loop_cnt[m];
+            }
+            sh.loop_base[v + 1] = acc;
         }
         __syncthreads();
-        if (lane <= v) sh.loop_cnt[lane] = 0;  // reused as fill cursor
+        over_lanes<WL, CF::VM>(lane, 0, v, [&](int l) { sh.loop_cnt[l] = 0; });  // reused as fill cursor
         __syncthreads();
         for (int j = lane; j < E; j += WL) {
             const ArcL<T> &A = sh.A[j];
@@ -1058,10 +1079,10 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
             sh.loop_next[pp] = (uint8_t)(nxt < 0 ? pp : nxt);
             if (first) sh.loop_first[m] = pp;
         }
-        if (lane >= 1 && lane <= v) {
-            const int c = sh.loop_base[lane + 1] - sh.loop_base[lane];
-            if (c == 0 || (sh.loop_full[lane] && c != 1)) atomicOr(&sh.status, NS_LOOP);
-        }
+        over_lanes<WL, CF::VM>(lane, 1, v, [&](int l) {
+            const int c = sh.loop_base[l + 1] - sh.loop_base[l];
+            if (c == 0 || (sh.loop_full[l] && c != 1)) atomicOr(&sh.status, NS_LOOP);
+        });
         __syncthreads();
         if (sh.status) goto tail;
         // position of each arc in its loop; the first arc also checks that
@@ -1314,6 +1335,20 @@ __global__ void __launch_bounds__(64) k_node32(Params P, int cls)
     }
 }
 
+// Thread-centric ablation: every lane meshes a node of its own (64 nodes per
+// wave in node id order, no valence classes, the full capacities), with the
+// per-node scratch that the kernel above keeps in LDS in global memory —
+// the design the paper compares its warp-centric one against.  Same code,
+// one lane per node: the results are those of the wave-centric pass.
+using CfgT1 = Cfg<kVmax, kAcap, kVcap, 1>;
+__global__ void __launch_bounds__(64) k_node32_thread(Params P, Shared<float, CfgT1> *scratch)
+{
+    const int64_t N = P.in.n_nodes;
+    Shared<float, CfgT1> &sh = scratch[(int64_t)blockIdx.x * 64 + threadIdx.x];
+    for (int64_t n = (int64_t)blockIdx.x * 64 + threadIdx.x; n < N; n += (int64_t)gridDim.x * 64)
+        node_body<float, CfgT1>(P, sh, n);
+}
+
 // FP64: the nodes the FP32 pass handed over, looped over by a fixed grid
 // (also after a re-subdivision: these nodes are solved in full)
 __global__ void __launch_bounds__(64) k_node64(Params P)
@@ -1332,6 +1367,30 @@ constexpr int64_t kNodeGrid = 256 * 32;  // waves per class launch
 constexpr int64_t kRedoGrid = 512;       // waves per class launch over a redo list
 
 }  // namespace
+
+constexpr int64_t kThreadGrid = 4096;  // blocks of the thread-centric pass
+
+size_t node_thread_scratch_bytes() { return sizeof(Shared<float, CfgT1>) * (size_t)kThreadGrid * 64; }
+
+hipError_t launch_node_thread(const Inputs &in, const Work &w, int k, float kappa_max, void *scratch,
+                              hipStream_t st)
+{
+    if (in.n_nodes == 0) return hipSuccess;
+    Params P;
+    P.in = in;
+    P.w = w;
+    P.k = k;
+    P.kappa_max = kappa_max;
+    P.src_rec = nullptr;
+    P.src_node_rec = nullptr;
+    P.redo = nullptr;
+    P.redo_cnt = nullptr;
+    P.redo_ctr = nullptr;
+    const int64_t blocks = (in.n_nodes + 63) / 64;
+    k_node32_thread<<<(unsigned)(blocks < kThreadGrid ? blocks : kThreadGrid), 64, 0, st>>>(
+        P, (Shared<float, CfgT1> *)scratch);
+    return hipGetLastError();
+}
 
 hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, int fp64, hipStream_t st,
                        const uint32_t *src_rec, const int64_t *src_node_rec, int32_t *redo, int32_t *redo_cnt)

@@ -42,6 +42,7 @@ EXPORTS = (
     "lm_retriangulate",
     "lm_read_totals",
     "lm_set_precision",
+    "lm_set_schedule",
     "lm_set_profiling",
     "lm_get_profile",
     "lm_forward_sink",
@@ -191,6 +192,8 @@ def load() -> ctypes.CDLL:
     lib.lm_set_profiling.restype = ctypes.c_int
     lib.lm_get_profile.argtypes = [P, P, P, ctypes.c_int]
     lib.lm_get_profile.restype = ctypes.c_int
+    lib.lm_set_schedule.argtypes = [P, ctypes.c_int]
+    lib.lm_set_schedule.restype = ctypes.c_int
     lib.lm_set_precision.argtypes = [P, ctypes.c_float]
     lib.lm_set_precision.restype = ctypes.c_int
     lib.lm_forward_sink.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, ctypes.c_int64]
@@ -509,6 +512,13 @@ class Mesher:
         """Binary STL of the mesh in ``r`` (trimmed to its totals)."""
         t = r.totals
         return write_stl(r.mesh_xyz[: t["n_mesh_vertices"]], r.tri[: t["n_triangles"]], path, chunk_bytes, fsync)
+
+    def set_schedule(self, thread_centric: bool) -> None:
+        """FP32 node pass: wave-centric (default) or the thread-centric
+        ablation (one lane per node, scratch in global memory)."""
+        rc = load().lm_set_schedule(self.plan, 1 if thread_centric else 0)
+        if rc != LM_OK:
+            raise LatmeshError(rc, "lm_set_schedule")
 
     def radius_range(self):
         """(smallest, largest) node radius of the lattice."""
