@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # counter runs scaled by a plain copy's readings (factors 2.0 / 1.0), keyed
 # by the source they were taken on; a changed kernel reports null.
 MEASURED_TRAFFIC = {
-    "b7e284ed101dd920": {"bytes": 1_732_200_000, "summary": "profiles/k_node32_bcc64_k16_hbm_counters.md"},
+    "7e9ac95689c84abf": {"bytes": 1_733_700_000, "summary": "profiles/k_node32_bcc64_k16_hbm_counters.md"},
 }
 
 
