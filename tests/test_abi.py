@@ -33,7 +33,7 @@ def test_status_strings_and_invalid_args():
     from paper_2405_15197_amd import latmesh
 
     lib = latmesh.load()
-    for code in range(-7, 1):
+    for code in range(-8, 1):
         assert latmesh.lm_status_string(code) != "unknown status"
     # null plan pointer is rejected without touching the GPU
     assert lib.lm_count(None, 8, ctypes.byref(latmesh.lm_totals())) == latmesh.LM_ERR_INVALID_ARG
@@ -46,12 +46,36 @@ def test_status_strings_and_invalid_args():
     assert lib.lm_plan_create(ctypes.byref(h), ctypes.byref(lat), None) == latmesh.LM_ERR_UNSUPPORTED
 
 
+def test_new_entry_points_reject_bad_arguments():
+    """Argument checks that return before any HIP call."""
+    from paper_2405_15197_amd import latmesh
+
+    lib = latmesh.load()
+    outs = latmesh.lm_outputs()
+    assert lib.lm_retriangulate(None, 8, ctypes.byref(outs)) == latmesh.LM_ERR_INVALID_ARG
+    assert lib.lm_set_schedule(None, 0) == latmesh.LM_ERR_INVALID_ARG
+    codes = latmesh.lm_arc_codes()
+    nf = ctypes.c_int64()
+    assert lib.lm_arc_encode(None, None, None, 0, 0, 0.05, 0.1, ctypes.byref(codes), ctypes.byref(nf)) == \
+        latmesh.LM_ERR_INVALID_ARG
+    assert lib.lm_arc_decode(None, ctypes.byref(codes), None, 0, 0, 0.05, 0.1, None, 0) == latmesh.LM_ERR_INVALID_ARG
+    st = latmesh.lm_stl_stats()
+    # negative sizes, a chunk below one block of triangles, missing pointers,
+    # and more triangles than the 32-bit count field holds
+    assert lib.lm_write_stl(None, -1, None, 0, None, 1 << 20, 0, None, ctypes.byref(st)) == latmesh.LM_ERR_INVALID_ARG
+    assert lib.lm_write_stl(None, 0, None, 0, None, 100, 0, None, ctypes.byref(st)) == latmesh.LM_ERR_INVALID_ARG
+    assert lib.lm_write_stl(None, 3, None, 1, None, 1 << 20, 0, None, ctypes.byref(st)) == latmesh.LM_ERR_INVALID_ARG
+    assert lib.lm_write_stl(1, 3, 1, 1 << 32, None, 1 << 20, 0, None, ctypes.byref(st)) == latmesh.LM_ERR_UNSUPPORTED
+
+
 def test_structs_match_header_layout():
     from paper_2405_15197_amd import latmesh
 
     assert ctypes.sizeof(latmesh.lm_lattice) == 8 * 8
     assert ctypes.sizeof(latmesh.lm_totals) == 8 * len(latmesh._TOTAL_FIELDS)
     assert ctypes.sizeof(latmesh.lm_outputs) == 8 * 13
+    assert ctypes.sizeof(latmesh.lm_arc_codes) == 8 * 5
+    assert ctypes.sizeof(latmesh.lm_stl_stats) == 8 * 8
 
 
 def test_generators_are_seeded_and_counted():
