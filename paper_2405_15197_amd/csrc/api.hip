@@ -249,7 +249,7 @@ int64_t rec_estimate(const lm_plan *P, int k)
     return words + words / 8 + 4096;
 }
 
-int fill_common(lm_plan *P, const lm::FillOut &f, const lm_outputs *out, const lm::Work &w)
+int fill_common(lm_plan *P, int k, const lm::FillOut &f, const lm_outputs *out, const lm::Work &w)
 {
     const int64_t N = P->in.n_nodes;
     {
@@ -258,7 +258,7 @@ int fill_common(lm_plan *P, const lm::FillOut &f, const lm_outputs *out, const l
     }
     {
         PhaseTimer t(P, PH_ZIP);
-        HIPCHK(lm::launch_zip(P->in, w, f, P->st));
+        HIPCHK(lm::launch_zip(P->in, w, f, k, P->st));
     }
     if (out->d_node_off)
         HIPCHK(hipMemcpyAsync(out->d_node_off, w.node_off, sizeof(int64_t) * lm::kNodeScanCols * (N + 1),
@@ -360,7 +360,7 @@ int lm_fill(lm_plan *P, const lm_outputs *out)
     if (f.vert_name && out->cap_vertices < t.n_vertices) return LM_ERR_CAPACITY;
     if (f.arc_f32 && out->cap_arcs < t.n_arcs) return LM_ERR_CAPACITY;
     if (P->base_slot != 0) return LM_ERR_STATE;  // re-subdivided since lm_count
-    return fill_common(P, f, out, P->w);
+    return fill_common(P, P->k, f, out, P->w);
 }
 
 int lm_forward(lm_plan *P, int k, const lm_outputs *out)
@@ -373,7 +373,7 @@ int lm_forward(lm_plan *P, int k, const lm_outputs *out)
     if (rc) return rc;
     P->k = k;
     P->base_slot = 0;
-    return fill_common(P, f, out, P->w);
+    return fill_common(P, k, f, out, P->w);
 }
 
 int lm_loss(lm_plan *P, const lm_outputs *out, const lm_loss_weights *w, double *d_terms, float *d_dl_dx)
@@ -632,7 +632,7 @@ int lm_retriangulate(lm_plan *P, int k, const lm_outputs *out)
     lm::FillOut f = to_fill(out);
     int rc = run_count(P, k, &f, wd, src_rec, src_node_rec, P->redo, P->redo_cnt);
     if (rc) return rc;
-    rc = fill_common(P, f, out, wd);
+    rc = fill_common(P, k, f, out, wd);
     if (rc) return rc;
     if (base_in_w) {  // the new records become current; the meta-mesh moves to the other slot
         std::swap(P->w.rec, P->alt_rec);

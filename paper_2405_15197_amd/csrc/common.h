@@ -180,7 +180,8 @@ hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, 
 // Node records -> meta-mesh, mesh vertices and hole fans.
 hipError_t launch_expand(const Inputs &in, const Work &w, const FillOut &o, hipStream_t st);
 hipError_t launch_band_count(const Inputs &in, const Work &w, hipStream_t st);
-hipError_t launch_zip(const Inputs &in, const Work &w, const FillOut &o, hipStream_t st);
+// bands; k (the resolution) sizes the groups of struts per wave
+hipError_t launch_zip(const Inputs &in, const Work &w, const FillOut &o, int k, hipStream_t st);
 hipError_t launch_totals(const Inputs &in, const Work &w, const FillOut *o, hipStream_t st);
 // Loss terms (area, volume about p0, sum of squared norms) of the last mesh
 // and their gradient dldx [cap_mesh][3]; then the adjoint to the inputs.

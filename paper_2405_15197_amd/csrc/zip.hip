@@ -9,6 +9,8 @@
 // with the last sample of the other loop that precedes u' (cyclically).
 // Triangles of loop-A edges come first (in loop order), then those of loop-B
 // edges, all oriented outward.
+#include <type_traits>
+
 #include "common.h"
 
 namespace lm {
@@ -37,14 +39,15 @@ __global__ void k_bad_nodes(int64_t N, const int32_t *node_status, int64_t *tota
     if (n < N && node_status[n] != 0) atomicAdd((unsigned long long *)&totals[8], 1ull);
 }
 
-// One wave per kZipGroup consecutive struts.  Lanes load the struts' loop
+// One wave per G consecutive struts.  Lanes load the struts' loop
 // descriptors, the loops are staged in LDS in sorted (phi) order when they
 // fit, then lanes run over the group's band triangles in output order
 // (coalesced writes).  The apex of a loop-edge triangle is the cyclic
 // predecessor of the edge's end among the other loop's samples in
-// (phi, end) order, found by binary search on the sorted samples.
-constexpr int kZipGroup = 8;
-constexpr int kZipStage = 768;  // staged samples per wave (6 KB of LDS)
+// (phi, end) order, found by binary search on the sorted samples.  The
+// staging buffer is kept at 4 KB so that eight waves fit a SIMD; G shrinks
+// with the resolution so that a group's loops still fit it.
+constexpr int kZipStage = 512;  // staged samples per wave (4 KB of LDS)
 
 // Loop access in sorted order: from LDS (already rotated) or from the node
 // record (rotated on the fly).
@@ -107,20 +110,21 @@ __device__ inline void band_tri(const L &A, const L &B, int ra, int rb, int j, i
     }
 }
 
+template <int G>
 __global__ void __launch_bounds__(64) k_zip(int64_t S, const int64_t *band_off, const int64_t *strut_he,
                                             const int64_t *he_loop, const int32_t *he_len, const int32_t *he_rot,
                                             const int2 *loop, const int32_t *sa, const int32_t *sb,
                                             const int64_t *mesh_off, int32_t *tri, const int32_t *flags)
 {
     __shared__ int2 st[kZipStage];
-    __shared__ int64_t g_la[kZipGroup], g_lb[kZipGroup];
-    __shared__ int g_na[kZipGroup], g_nb[kZipGroup], g_ra[kZipGroup], g_rb[kZipGroup];
-    __shared__ int g_ma[kZipGroup], g_mb[kZipGroup], g_t[kZipGroup + 1], g_q[kZipGroup + 1];
+    __shared__ int64_t g_la[G], g_lb[G];
+    __shared__ int g_na[G], g_nb[G], g_ra[G], g_rb[G];
+    __shared__ int g_ma[G], g_mb[G], g_t[G + 1], g_q[G + 1];
     if (flags[0] & (DF_CAPACITY | DF_BADLAT | DF_RECCAP)) return;
     const int lane = threadIdx.x;
-    const int64_t s0 = xcd_block(blockIdx.x, gridDim.x) * kZipGroup;
+    const int64_t s0 = xcd_block(blockIdx.x, gridDim.x) * G;
     if (s0 >= S) return;
-    const int ns = S - s0 < kZipGroup ? (int)(S - s0) : kZipGroup;
+    const int ns = S - s0 < G ? (int)(S - s0) : G;
     const int64_t t0 = band_off[s0];
     int cnt = 0, q = 0;
     if (lane < ns) {
@@ -146,7 +150,7 @@ __global__ void __launch_bounds__(64) k_zip(int64_t S, const int64_t *band_off, 
     // prefix sums of the triangle and sample counts over the group
     int ct = cnt, cq = q;
 #pragma unroll
-    for (int d = 1; d < kZipGroup; d <<= 1) {
+    for (int d = 1; d < G; d <<= 1) {
         const int yt = __shfl_up(ct, d, 64), yq = __shfl_up(cq, d, 64);
         if (lane >= d) {
             ct += yt;
@@ -249,13 +253,22 @@ hipError_t launch_band_count(const Inputs &in, const Work &w, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_zip(const Inputs &in, const Work &w, const FillOut &o, hipStream_t st)
+hipError_t launch_zip(const Inputs &in, const Work &w, const FillOut &o, int k, hipStream_t st)
 {
     const int64_t S = in.n_struts;
-    if (S > 0)
-        k_zip<<<(unsigned)((S + kZipGroup - 1) / kZipGroup), 64, 0, st>>>(S, w.band_off, w.strut_he, w.he_loop, w.he_len, w.he_rot,
-                                                (const int2 *)w.rec, in.sa, in.sb,
-                                                w.node_off + (int64_t)NC_MESH * (in.n_nodes + 1), o.tri, w.flags);
+    if (S == 0) return hipSuccess;
+    // a band has about 2 (k + 4) samples: groups whose loops fill most of
+    // the staging buffer
+    const int64_t *mo = w.node_off + (int64_t)NC_MESH * (in.n_nodes + 1);
+    const int2 *loop = (const int2 *)w.rec;
+    auto go = [&](auto g) {
+        constexpr int G = decltype(g)::value;
+        k_zip<G><<<(unsigned)((S + G - 1) / G), 64, 0, st>>>(S, w.band_off, w.strut_he, w.he_loop, w.he_len,
+                                                              w.he_rot, loop, in.sa, in.sb, mo, o.tri, w.flags);
+    };
+    if (k <= 24) go(std::integral_constant<int, 8>{});
+    else if (k <= 56) go(std::integral_constant<int, 4>{});
+    else go(std::integral_constant<int, 2>{});
     return hipGetLastError();
 }
 
