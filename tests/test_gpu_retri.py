@@ -137,3 +137,27 @@ def test_retriangulate_then_adjoint():
     np.testing.assert_allclose(t0, t1, rtol=1e-6)
     np.testing.assert_allclose(x0, x1, rtol=1e-4, atol=1e-5)
     np.testing.assert_allclose(r0, r1, rtol=1e-4, atol=1e-5)
+
+
+def test_retriangulate_after_forward_medium():
+    """From lm_forward (no count) on a larger lattice, to a finer and a
+    coarser resolution and back, against fresh forward passes."""
+    from paper_2405_15197_amd import Mesher
+
+    lat = latgen.config(2, scale=14, seed=6)
+    k0 = 12
+    M = Mesher(lat)
+    try:
+        r = M.alloc(M.count(k0))
+        M.forward(k0, r)
+        for k in (20, 7, k0):
+            G = result_np(M.retriangulate(k))
+            F = Mesher(lat)
+            try:
+                ref = result_np(F.run(k))
+            finally:
+                F.close()
+            _line(f"  medium k={k}: {G['totals']['n_triangles']} triangles")
+            _same_mesh(G, ref, f"medium k={k}")
+    finally:
+        M.close()
