@@ -487,7 +487,7 @@ int sink_range(lm_plan *P, int k, int k_avg, int64_t n0, int64_t n1, int t16, in
     HIPCHK(hipMemsetAsync(P->sk_cnt + 4, 0, sizeof(int32_t), P->st));
     {
         PhaseTimer t(P, PH_EXPAND);
-        HIPCHK(lm::launch_sink(P->in, w, n0, n1, hcnt, P->sk_struts, P->sk_cnt + 4, P->sk_slots, out_chunk,
+        HIPCHK(lm::launch_sink(P->in, w, n0, n1, hcnt, k, P->sk_struts, P->sk_cnt + 4, P->sk_slots, out_chunk,
                                node_part, out_parts, part_base, P->st));
     }
     return LM_OK;

@@ -200,8 +200,8 @@ hipError_t launch_chunk_list(const Work &w, int64_t n0, int64_t n1, int32_t *mar
 // Outputs go to `out` (one chunk) through the slots, or with node_part set
 // to the per-part slots out_parts[part][sink_slots_words()] (reduced by
 // launch_parts_reduce) with vertex ids local to the part (node -
-// part_base[part]).
-hipError_t launch_sink(const Inputs &in, const Work &w, int64_t n0, int64_t n1, int64_t max_struts,
+// part_base[part]).  k_max: the largest resolution among the nodes.
+hipError_t launch_sink(const Inputs &in, const Work &w, int64_t n0, int64_t n1, int64_t max_struts, int k_max,
                        int32_t *strut_list, int32_t *strut_cnt, unsigned long long *slots, uint64_t *out,
                        const int32_t *node_part, uint64_t *out_parts, const int64_t *part_base, hipStream_t st);
 

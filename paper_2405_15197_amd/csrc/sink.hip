@@ -259,24 +259,26 @@ __global__ void __launch_bounds__(256) k_chunk_struts(int64_t n0, int64_t n1, co
     }
 }
 
-// Bands of the listed struts (one wave per 8), hashed.
-constexpr int kZipGroup = 8;
-constexpr int kZipStage = 768;
+// Bands of the listed struts (one wave per G), hashed.  A 4 KB staging
+// buffer lets eight waves share a SIMD; G shrinks with the resolution so
+// that a group's loops still fit it.
+constexpr int kZipStage = 512;
 
+template <int G>
 __global__ void __launch_bounds__(64) k_sink_zip(SinkParams P, const int32_t *list, const int32_t *cnt,
                                                  const int32_t *sa, const int32_t *sb)
 {
     __shared__ int2 st[kZipStage];
-    __shared__ int g_na[kZipGroup], g_nb[kZipGroup], g_ra[kZipGroup], g_rb[kZipGroup];
-    __shared__ int64_t g_la[kZipGroup], g_lb[kZipGroup], g_a[kZipGroup], g_b[kZipGroup];
-    __shared__ int g_t[kZipGroup + 1];
-    __shared__ unsigned long long g_h[kZipGroup];  // triangle-key sum per strut
+    __shared__ int g_na[G], g_nb[G], g_ra[G], g_rb[G];
+    __shared__ int64_t g_la[G], g_lb[G], g_a[G], g_b[G];
+    __shared__ int g_t[G + 1];
+    __shared__ unsigned long long g_h[G];  // triangle-key sum per strut
     const Work &W = P.w;
     const int lane = threadIdx.x;
     const int64_t ns_all = *cnt;
-    const int64_t g0 = (int64_t)blockIdx.x * kZipGroup;
+    const int64_t g0 = (int64_t)blockIdx.x * G;
     if (g0 >= ns_all) return;
-    const int ns = ns_all - g0 < kZipGroup ? (int)(ns_all - g0) : kZipGroup;
+    const int ns = ns_all - g0 < G ? (int)(ns_all - g0) : G;
     int c = 0;
     if (lane < ns) {
         const int64_t s = list[g0 + lane];
@@ -295,7 +297,7 @@ __global__ void __launch_bounds__(64) k_sink_zip(SinkParams P, const int32_t *li
     }
     int ct = c;
 #pragma unroll
-    for (int d = 1; d < kZipGroup; d <<= 1) {
+    for (int d = 1; d < G; d <<= 1) {
         const int y = __shfl_up(ct, d, 64);
         if (lane >= d) ct += y;
     }
@@ -459,7 +461,7 @@ hipError_t launch_chunk_list(const Work &w, int64_t n0, int64_t n1, int32_t *mar
     return hipGetLastError();
 }
 
-hipError_t launch_sink(const Inputs &in, const Work &w, int64_t n0, int64_t n1, int64_t max_struts,
+hipError_t launch_sink(const Inputs &in, const Work &w, int64_t n0, int64_t n1, int64_t max_struts, int k_max,
                        int32_t *strut_list, int32_t *strut_cnt, unsigned long long *slots, uint64_t *out,
                        const int32_t *node_part, uint64_t *out_parts, const int64_t *part_base, hipStream_t st)
 {
@@ -477,8 +479,15 @@ hipError_t launch_sink(const Inputs &in, const Work &w, int64_t n0, int64_t n1, 
         k_chunk_struts<<<grid_for(n1 - n0, 256), 256, 0, st>>>(n0, n1, w.row, w.he, w.node_rec, strut_list,
                                                                  strut_cnt);
         // grid for the most struts the range can own (its half-edges)
-        if (max_struts > 0)
-            k_sink_zip<<<grid_for(max_struts, kZipGroup), 64, 0, st>>>(P, strut_list, strut_cnt, in.sa, in.sb);
+        if (max_struts > 0) {
+            // a band has about 2 (k + 4) samples
+            if (k_max <= 24)
+                k_sink_zip<8><<<grid_for(max_struts, 8), 64, 0, st>>>(P, strut_list, strut_cnt, in.sa, in.sb);
+            else if (k_max <= 56)
+                k_sink_zip<4><<<grid_for(max_struts, 4), 64, 0, st>>>(P, strut_list, strut_cnt, in.sa, in.sb);
+            else
+                k_sink_zip<2><<<grid_for(max_struts, 2), 64, 0, st>>>(P, strut_list, strut_cnt, in.sa, in.sb);
+        }
     }
     if (!node_part) k_sink_reduce<<<1, 64, 0, st>>>(slots, out);
     return hipGetLastError();
