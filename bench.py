@@ -28,7 +28,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
 # HBM bytes per launch of the node kernel, from FETCH_SIZE / WRITE_SIZE
 # counter runs scaled by a plain copy's readings (factors 2.0 / 1.0), keyed
-# by the source they were taken on; a changed kernel reports null.
+# by the kernel's sources and build flags they were taken on; a changed
+# kernel reports null.
 MEASURED_TRAFFIC = {
     "7e9ac95689c84abf": {"bytes": 1_733_700_000, "summary": "profiles/k_node32_bcc64_k16_hbm_counters.md"},
 }
@@ -38,8 +39,8 @@ def node_source_key():
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("node.hip", "common.h"):
-        with open(os.path.join(ROOT, "paper_2405_15197_amd", "csrc", f), "rb") as fh:
+    for f in ("csrc/node.hip", "csrc/common.h", "csrc/geom.h", "build.py"):
+        with open(os.path.join(ROOT, "paper_2405_15197_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
