@@ -55,11 +55,12 @@ enum DevFlag : int {
 //   header  [kRecHead]  V, E, H (holes), ncirc (circular arcs, stored first),
 //                       wsum (first hole-centre mesh index), M (mesh
 //                       vertices), F (fan triangles), 0
-//   vertices [4][V]     name, x, y, z (node-local)
-//   arcs    [16][E]     o.xyz, a.xyz, b.xyz, t1, t2 (float bits),
+//   vertices [V][4]     name, x, y, z (node-local), one 16-byte group each
+//   arcs    [E][16]     o.xyz, a.xyz, b.xyz, t1, t2 (float bits),
 //                       p | q<<8 | whole<<16 | fwd<<17 | lower<<18,
-//                       vs | ve<<16, nseg | contour<<16, mbase, fbase
-//   holes   [3][H]      hole centres (node-local)
+//                       vs | ve<<16, nseg | contour<<16, mbase, fbase: four
+//                       16-byte groups each
+//   holes   [H][3]      hole centres (node-local)
 //   loop table          bytes: loop start of each strut label 1..v+1 (v+1
 //                       bytes), then for every loop entry in loop order its
 //                       arc | 0x80 if the arc runs along the loop (header

@@ -47,24 +47,24 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
     const uint32_t *RH = RA + kRecArcFields * E;
 
     for (int j = lane; j < E; j += 64) {
-        s_mbase[j] = (int)RA[14 * E + j];
-        s_fbase[j] = (int)RA[15 * E + j];
+        s_mbase[j] = (int)RA[kRecArcFields * j + 14];
+        s_fbase[j] = (int)RA[kRecArcFields * j + 15];
     }
     if (O.vert_name) {
         for (int i = lane; i < V; i += 64) {
-            O.vert_name[voff + i] = RV[i];
-            O.vert_xyz[0 * O.cap_vert + voff + i] = fbits(RV[V + i]);
-            O.vert_xyz[1 * O.cap_vert + voff + i] = fbits(RV[2 * V + i]);
-            O.vert_xyz[2 * O.cap_vert + voff + i] = fbits(RV[3 * V + i]);
+            O.vert_name[voff + i] = RV[4 * i];
+            O.vert_xyz[0 * O.cap_vert + voff + i] = fbits(RV[4 * i + 1]);
+            O.vert_xyz[1 * O.cap_vert + voff + i] = fbits(RV[4 * i + 2]);
+            O.vert_xyz[2 * O.cap_vert + voff + i] = fbits(RV[4 * i + 3]);
         }
     }
     if (O.arc_f32) {
         const int64_t cA = O.cap_arc;
         for (int j = lane; j < E; j += 64) {
 #pragma unroll
-            for (int t = 0; t < 11; ++t) O.arc_f32[t * cA + aoff + j] = fbits(RA[t * E + j]);
-            O.arc_u32[0 * cA + aoff + j] = RA[11 * E + j] & 0x1ffffu;  // p | q<<8 | whole<<16
-            O.arc_u32[1 * cA + aoff + j] = RA[12 * E + j];
+            for (int t = 0; t < 11; ++t) O.arc_f32[t * cA + aoff + j] = fbits(RA[kRecArcFields * j + t]);
+            O.arc_u32[0 * cA + aoff + j] = RA[kRecArcFields * j + 11] & 0x1ffffu;  // p | q<<8 | whole<<16
+            O.arc_u32[1 * cA + aoff + j] = RA[kRecArcFields * j + 12];
             O.arc_u32[2 * cA + aoff + j] = (uint32_t)n;
         }
     }
@@ -72,21 +72,21 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
 
     // Eq. 12 sub-parameter ii (1..nseg-1) of arc j, and its point
     auto interior = [&](int j, int ii) {
-        const float t1 = fbits(RA[9 * E + j]), t2 = fbits(RA[10 * E + j]);
-        const int nseg = (int)(RA[13 * E + j] & 0xffffu);
+        const float t1 = fbits(RA[kRecArcFields * j + 9]), t2 = fbits(RA[kRecArcFields * j + 10]);
+        const int nseg = (int)(RA[kRecArcFields * j + 13] & 0xffffu);
         const float t = t1 + (t2 - t1) * (float)ii / (float)nseg;
         float s, c;
         sincosf(t, &s, &c);
         float w[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) w[d] = fbits(RA[d * E + j]) + fbits(RA[(3 + d) * E + j]) * s + fbits(RA[(6 + d) * E + j]) * c;
+        for (int d = 0; d < 3; ++d) w[d] = fbits(RA[kRecArcFields * j + d]) + fbits(RA[kRecArcFields * j + (3 + d)]) * s + fbits(RA[kRecArcFields * j + (6 + d)]) * c;
         return make_float3(w[0], w[1], w[2]);
     };
     // mesh vertices: meta-vertices, interior points, hole centres
     for (int i = lane; i < M; i += 64) {
         float3 w;
         if (i < V) {
-            w = make_float3(fbits(RV[V + i]), fbits(RV[2 * V + i]), fbits(RV[3 * V + i]));
+            w = make_float3(fbits(RV[4 * i + 1]), fbits(RV[4 * i + 2]), fbits(RV[4 * i + 3]));
         } else if (i < wsum) {
             int lo = 0, hi = E - 1;  // last arc with mbase <= i
             while (lo < hi) {
@@ -94,13 +94,13 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
                 if (s_mbase[mid] <= i) lo = mid;
                 else hi = mid - 1;
             }
-            const int nseg = (int)(RA[13 * E + lo] & 0xffffu);
-            const bool fwd = (RA[11 * E + lo] >> 17) & 1u;
+            const int nseg = (int)(RA[kRecArcFields * lo + 13] & 0xffffu);
+            const bool fwd = (RA[kRecArcFields * lo + 11] >> 17) & 1u;
             const int jc = i - s_mbase[lo];
             w = interior(lo, fwd ? jc + 1 : nseg - 1 - jc);
         } else {
             const int c = i - wsum;
-            w = make_float3(fbits(RH[c]), fbits(RH[NC + c]), fbits(RH[2 * NC + c]));
+            w = make_float3(fbits(RH[3 * c]), fbits(RH[3 * c + 1]), fbits(RH[3 * c + 2]));
         }
         float *dst = O.mesh_xyz + 3 * (moff + i);
         dst[0] = c4.x + w.x;
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
             else hi = mid - 1;
         }
         const int j = lo;
-        const uint32_t u0 = RA[11 * E + j], u1 = RA[12 * E + j], u2 = RA[13 * E + j];
+        const uint32_t u0 = RA[kRecArcFields * j + 11], u1 = RA[kRecArcFields * j + 12], u2 = RA[kRecArcFields * j + 13];
         const bool fwd = (u0 >> 17) & 1u, lower = (u0 >> 18) & 1u;
         const int nseg = (int)(u2 & 0xffffu), contour = (int)(u2 >> 16);
         const int vs = (int)(u1 & 0xffffu), ve = (int)(u1 >> 16);

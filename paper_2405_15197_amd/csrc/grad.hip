@@ -267,11 +267,11 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
     const float rho = c4.w;
     const V3<float> cen = v3(c4.x, c4.y, c4.z);
     const float *L = P.dldx + 3 * moff;
-    auto af = [&](int f, int j) { return __uint_as_float(RA[f * E + j]); };
+    auto af = [&](int f, int j) { return __uint_as_float(RA[kRecArcFields * j + f]); };
     auto vpos = [&](int i, float *w) {
-        w[0] = __uint_as_float(RV[V + i]);
-        w[1] = __uint_as_float(RV[2 * V + i]);
-        w[2] = __uint_as_float(RV[3 * V + i]);
+        w[0] = __uint_as_float(RV[4 * i + 1]);
+        w[1] = __uint_as_float(RV[4 * i + 2]);
+        w[2] = __uint_as_float(RV[4 * i + 3]);
     };
 
     // ---- strut table, cleared adjoints ------------------------------------
@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
     }
     if (lane < 4) lam_node[lane] = 0.f;
     for (int j = lane; j < E; j += 64) {
-        s_mbase[j] = (int)RA[14 * E + j];
+        s_mbase[j] = (int)RA[kRecArcFields * j + 14];
 #pragma unroll
         for (int f = 0; f < 11; ++f) lam_arc[j][f] = 0.f;
     }
@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
     };
     // adds weight lam (a 3-vector) on interior point ii of arc j
     auto add_interior = [&](int j, int ii, const float *lam) {
-        const int nseg = (int)(RA[13 * E + j] & 0xffffu);
+        const int nseg = (int)(RA[kRecArcFields * j + 13] & 0xffffu);
         const float t1 = af(9, j), t2 = af(10, j);
         const float f = (float)ii / (float)nseg;
         const float t = t1 + (t2 - t1) * (float)ii / (float)nseg;
@@ -358,8 +358,8 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
 
     // ---- interior points ----------------------------------------------------
     for (int j = lane; j < E; j += 64) {
-        const int nseg = (int)(RA[13 * E + j] & 0xffffu);
-        const bool fwd = (RA[11 * E + j] >> 17) & 1u;
+        const int nseg = (int)(RA[kRecArcFields * j + 13] & 0xffffu);
+        const bool fwd = (RA[kRecArcFields * j + 11] >> 17) & 1u;
         for (int ii = 1; ii < nseg; ++ii) {
             const int li = s_mbase[j] + (fwd ? ii - 1 : nseg - 1 - ii);
             const float lam[3] = {L[3 * li], L[3 * li + 1], L[3 * li + 2]};
@@ -376,12 +376,12 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
         float b[3] = {0.f, 0.f, 0.f};
         int cnt = 0;
         for (int j = 0; j < ncirc; ++j) {
-            if ((int)(RA[13 * E + j] >> 16) != c) continue;
-            const int vs = (int)(RA[12 * E + j] & 0xffffu), ve = (int)(RA[12 * E + j] >> 16);
+            if ((int)(RA[kRecArcFields * j + 13] >> 16) != c) continue;
+            const int vs = (int)(RA[kRecArcFields * j + 12] & 0xffffu), ve = (int)(RA[kRecArcFields * j + 12] >> 16);
             float ws[3], we[3];
             vpos(vs, ws);
             vpos(ve, we);
-            const int nseg = (int)(RA[13 * E + j] & 0xffffu);
+            const int nseg = (int)(RA[kRecArcFields * j + 13] & 0xffffu);
             for (int d = 0; d < 3; ++d) b[d] += 0.5f * (ws[d] + we[d]);
             for (int ii = 1; ii < nseg; ++ii) {
                 float x[3], dx[3];
@@ -425,13 +425,13 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
             float mu[3];
             for (int d = 0; d < 3; ++d) mu[d] = sgn * (ld[d] - dir[d] * dl) / bl / (float)cnt;
             for (int j = 0; j < ncirc; ++j) {
-                if ((int)(RA[13 * E + j] >> 16) != c) continue;
-                const int vs = (int)(RA[12 * E + j] & 0xffffu), ve = (int)(RA[12 * E + j] >> 16);
+                if ((int)(RA[kRecArcFields * j + 13] >> 16) != c) continue;
+                const int vs = (int)(RA[kRecArcFields * j + 12] & 0xffffu), ve = (int)(RA[kRecArcFields * j + 12] >> 16);
                 for (int d = 0; d < 3; ++d) {
                     atomicAdd(&lam_v[vs][d], 0.5f * mu[d]);
                     atomicAdd(&lam_v[ve][d], 0.5f * mu[d]);
                 }
-                const int nseg = (int)(RA[13 * E + j] & 0xffffu);
+                const int nseg = (int)(RA[kRecArcFields * j + 13] & 0xffffu);
                 for (int ii = 1; ii < nseg; ++ii) add_interior(j, ii, mu);
             }
         } else {
@@ -447,9 +447,9 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
 
     // ---- arc ends: t1, t2 are the parameters of the end vertices ------------
     for (int j = lane; j < E; j += 64) {
-        const uint32_t u0 = RA[11 * E + j];
+        const uint32_t u0 = RA[kRecArcFields * j + 11];
         const bool full = (u0 >> 16) & 1u;
-        const int vs = (int)(RA[12 * E + j] & 0xffffu), ve = (int)(RA[12 * E + j] >> 16);
+        const int vs = (int)(RA[kRecArcFields * j + 12] & 0xffffu), ve = (int)(RA[kRecArcFields * j + 12] >> 16);
         if (full) {
             // the start vertex is the conic point at t = 0: o + b
             for (int d = 0; d < 3; ++d) {
@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
     // ---- conics: (o, a, b) back to the strut table ----------------------------
     // Tangency circle (0, q): o = rho sigma e, a = rho kappa q^, b = rho kappa r^.
     for (int j = lane; j < ncirc; j += 64) {
-        const int q = (int)((RA[11 * E + j] >> 8) & 0xffu);
+        const int q = (int)((RA[kRecArcFields * j + 11] >> 8) & 0xffu);
         const SL<float> &sq = S[q];
         float Lo[9];
         for (int f = 0; f < 9; ++f) Lo[f] = lam_arc[j][f];
@@ -509,7 +509,7 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
     // over (arc, input) pairs.
     for (int x = lane; x < (E - ncirc) * 9; x += 64) {
         const int j = ncirc + x / 9, dir = x % 9;
-        const uint32_t u0 = RA[11 * E + j];
+        const uint32_t u0 = RA[kRecArcFields * j + 11];
         const int p = (int)(u0 & 0xffu), q = (int)((u0 >> 8) & 0xffu);
         SL<Dual> tab[3];
         for (int e2 = 1; e2 <= 2; ++e2) {
@@ -546,7 +546,7 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
     // J^T mu = (lam_w, 0) gives mu3 = -2 s mu4 and
     // [n1 | n2 | 2 (w - s g_p)] (mu1, mu2, mu4) = lam_w.
     for (int i = lane; i < V; i += 64) {
-        const uint32_t name = RV[i];
+        const uint32_t name = RV[4 * i];
         const int p = (int)(name >> 24), q = (int)((name >> 16) & 0xffu), r = (int)((name >> 8) & 0xffu);
         if (r == 0xff) continue;  // start point of a whole conic (handled with its arc)
         float w[3], gp[3] = {0.f, 0.f, 0.f}, gq[3], gr[3];

@@ -728,33 +728,33 @@ finish:
             R[6] = (uint32_t)Fsum;
             R[7] = (uint32_t)v | ((uint32_t)nent << 8) | (F32 ? 0u : 1u << 24);
         }
+        // vertices and arcs as whole 16-byte groups (the record and both
+        // blocks start on 16-byte boundaries)
         uint32_t *RV = R + kRecHead;
-        for (int i = lane; i < V; i += WL) {
-            RV[i] = sh.vname[i];
-            RV[V + i] = __float_as_uint((float)sh.vx[i]);
-            RV[2 * V + i] = __float_as_uint((float)sh.vy[i]);
-            RV[3 * V + i] = __float_as_uint((float)sh.vz[i]);
-        }
+        for (int i = lane; i < V; i += WL)
+            *(uint4 *)(RV + 4 * i) = make_uint4(sh.vname[i], __float_as_uint((float)sh.vx[i]),
+                                                __float_as_uint((float)sh.vy[i]), __float_as_uint((float)sh.vz[i]));
         uint32_t *RA = RV + 4 * V;
         for (int j = lane; j < E; j += WL) {
             const ArcL<T> &A = sh.A[j];
-            const T f[11] = {A.o[0], A.o[1], A.o[2], A.a[0], A.a[1], A.a[2], A.b[0], A.b[1], A.b[2], A.t1, A.t2};
-#pragma unroll
-            for (int t = 0; t < 11; ++t) RA[t * E + j] = __float_as_uint((float)f[t]);
+            uint4 *dst = (uint4 *)(RA + kRecArcFields * j);
+            auto fb = [](T x) { return __float_as_uint((float)x); };
             const uint32_t fwd = (A.full || A.ns <= A.ne) ? 1u : 0u;
             const uint32_t lower = sh.S[A.q].lower ? 1u : 0u;
-            RA[11 * E + j] = (uint32_t)A.p | ((uint32_t)A.q << 8) | ((uint32_t)A.full << 16) | (fwd << 17) |
-                             (lower << 18);
-            RA[12 * E + j] = (uint32_t)A.vs | ((uint32_t)A.ve << 16);
-            RA[13 * E + j] = (uint32_t)A.nseg | (((uint32_t)A.contour & 0xffffu) << 16);
-            RA[14 * E + j] = (uint32_t)A.mbase;
-            RA[15 * E + j] = (uint32_t)A.fbase;
+            dst[0] = make_uint4(fb(A.o[0]), fb(A.o[1]), fb(A.o[2]), fb(A.a[0]));
+            dst[1] = make_uint4(fb(A.a[1]), fb(A.a[2]), fb(A.b[0]), fb(A.b[1]));
+            dst[2] = make_uint4(fb(A.b[2]), fb(A.t1), fb(A.t2),
+                                (uint32_t)A.p | ((uint32_t)A.q << 8) | ((uint32_t)A.full << 16) | (fwd << 17) |
+                                    (lower << 18));
+            dst[3] = make_uint4((uint32_t)A.vs | ((uint32_t)A.ve << 16),
+                                (uint32_t)A.nseg | (((uint32_t)A.contour & 0xffffu) << 16), (uint32_t)A.mbase,
+                                (uint32_t)A.fbase);
         }
         uint32_t *RH = RA + kRecArcFields * E;
         for (int c = lane; c < NC; c += WL) {
-            RH[c] = __float_as_uint((float)sh.hc[c][0]);
-            RH[NC + c] = __float_as_uint((float)sh.hc[c][1]);
-            RH[2 * NC + c] = __float_as_uint((float)sh.hc[c][2]);
+            RH[3 * c] = __float_as_uint((float)sh.hc[c][0]);
+            RH[3 * c + 1] = __float_as_uint((float)sh.hc[c][1]);
+            RH[3 * c + 2] = __float_as_uint((float)sh.hc[c][2]);
         }
         // loop table (for re-subdivision at another resolution)
         uint8_t *RT = (uint8_t *)(R + rec_table_word(V, E, NC));
@@ -1217,11 +1217,14 @@ __device__ void node_retri(const Params &P, Shared<float, CF> &sh, const int64_t
     const int twords = (v + 1 + nent + 3) >> 2;
     float4 f4 = c4;
     if (lane < v) f4 = W.node4[he.x];
-    uint32_t vw[4] = {0, 0, 0, 0};
-    if (lane < V)
-        for (int d = 0; d < 4; ++d) vw[d] = RV[d * V + lane];
-    uint32_t aw[14];
-    for (int f = 0; f < 14; ++f) aw[f] = lane < E ? RA[f * E + lane] : 0u;
+    uint4 vq = make_uint4(0, 0, 0, 0);
+    if (lane < V) vq = *(const uint4 *)(RV + 4 * lane);
+    const uint32_t vw[4] = {vq.x, vq.y, vq.z, vq.w};
+    uint4 aq[4] = {};
+    if (lane < E)
+        for (int f = 0; f < 4; ++f) aq[f] = ((const uint4 *)(RA + kRecArcFields * lane))[f];
+    const uint32_t aw[14] = {aq[0].x, aq[0].y, aq[0].z, aq[0].w, aq[1].x, aq[1].y, aq[1].z,
+                             aq[1].w, aq[2].x, aq[2].y, aq[2].z, aq[2].w, aq[3].x, aq[3].y};
     const uint32_t tw = lane < twords ? RT[lane] : 0u;
 
     const T rho = (T)c4.w;

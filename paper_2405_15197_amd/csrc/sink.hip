@@ -157,24 +157,24 @@ __global__ void __launch_bounds__(64) k_sink_nodes(SinkParams P)
     const uint32_t *RH = RA + kRecArcFields * E;
     const float4 c4 = W.node4[n];
     const int64_t ln = local_node(P, n);
-    auto af = [&](int f, int j) { return __uint_as_float(RA[f * E + j]); };
+    auto af = [&](int f, int j) { return __uint_as_float(RA[kRecArcFields * j + f]); };
     uint64_t hv = 0, sx = 0, sy = 0, sz = 0, ht = 0;
     for (int i = lane; i < M; i += 64) {
         float w0, w1, w2;
         if (i < V) {
-            w0 = __uint_as_float(RV[V + i]);
-            w1 = __uint_as_float(RV[2 * V + i]);
-            w2 = __uint_as_float(RV[3 * V + i]);
+            w0 = __uint_as_float(RV[4 * i + 1]);
+            w1 = __uint_as_float(RV[4 * i + 2]);
+            w2 = __uint_as_float(RV[4 * i + 3]);
         } else if (i < wsum) {
             int lo = 0, hi = E - 1;  // last arc with mbase <= i
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if ((int)RA[14 * E + mid] <= i) lo = mid;
+                if ((int)RA[kRecArcFields * mid + 14] <= i) lo = mid;
                 else hi = mid - 1;
             }
-            const int nseg = (int)(RA[13 * E + lo] & 0xffffu);
-            const bool fwd = (RA[11 * E + lo] >> 17) & 1u;
-            const int jc = i - (int)RA[14 * E + lo];
+            const int nseg = (int)(RA[kRecArcFields * lo + 13] & 0xffffu);
+            const bool fwd = (RA[kRecArcFields * lo + 11] >> 17) & 1u;
+            const int jc = i - (int)RA[kRecArcFields * lo + 14];
             const int ii = fwd ? jc + 1 : nseg - 1 - jc;
             const float t1 = af(9, lo), t2 = af(10, lo);
             const float t = t1 + (t2 - t1) * (float)ii / (float)nseg;
@@ -185,9 +185,9 @@ __global__ void __launch_bounds__(64) k_sink_nodes(SinkParams P)
             w2 = af(2, lo) + af(5, lo) * s + af(8, lo) * c;
         } else {
             const int c = i - wsum;
-            w0 = __uint_as_float(RH[c]);
-            w1 = __uint_as_float(RH[NC + c]);
-            w2 = __uint_as_float(RH[2 * NC + c]);
+            w0 = __uint_as_float(RH[3 * c]);
+            w1 = __uint_as_float(RH[3 * c + 1]);
+            w2 = __uint_as_float(RH[3 * c + 2]);
         }
         const float x = c4.x + w0, y = c4.y + w1, z = c4.z + w2;
         hv += vert_key(vid_of(ln, i), x, y, z);
@@ -199,16 +199,16 @@ __global__ void __launch_bounds__(64) k_sink_nodes(SinkParams P)
         int lo = 0, hi = ncirc - 1;  // last circular arc with fbase <= i
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if ((int)RA[15 * E + mid] <= i) lo = mid;
+            if ((int)RA[kRecArcFields * mid + 15] <= i) lo = mid;
             else hi = mid - 1;
         }
         const int j = lo;
-        const uint32_t u0 = RA[11 * E + j], u1 = RA[12 * E + j], u2 = RA[13 * E + j];
+        const uint32_t u0 = RA[kRecArcFields * j + 11], u1 = RA[kRecArcFields * j + 12], u2 = RA[kRecArcFields * j + 13];
         const bool fwd = (u0 >> 17) & 1u, lower = (u0 >> 18) & 1u;
         const int nseg = (int)(u2 & 0xffffu), contour = (int)(u2 >> 16);
         const int vs = (int)(u1 & 0xffffu), ve = (int)(u1 >> 16);
-        const int mbase = (int)RA[14 * E + j];
-        const int s = i - (int)RA[15 * E + j];
+        const int mbase = (int)RA[kRecArcFields * j + 14];
+        const int s = i - (int)RA[kRecArcFields * j + 15];
         const int i0 = fwd ? s : nseg - s, i1 = fwd ? s + 1 : nseg - s - 1;
         const int lo_i = i0 < i1 ? i0 : i1, hi_i = i0 < i1 ? i1 : i0;
         const int u = lo_i == 0 ? vs : mbase + (fwd ? lo_i - 1 : nseg - 1 - lo_i);
