@@ -138,16 +138,17 @@ __global__ void __launch_bounds__(64) k_loss_node(LParams P)
             area += 0.5 * (double)nl;
             vol += ((double)a.x * bc.x + (double)a.y * bc.y + (double)a.z * bc.z) / 6.0;
         }
-        if (P.w_area != 0.f && nl > 0.f) {
-            const float3 nh = make_float3(Nn.x / nl, Nn.y / nl, Nn.z / nl);
-            add(i0, crs3(nh, sub3(c, b)), 0.5f * P.w_area);
-            add(i1, crs3(nh, sub3(a, c)), 0.5f * P.w_area);
-            add(i2, crs3(nh, sub3(b, a)), 0.5f * P.w_area);
-        }
-        if (P.w_vol != 0.f) {
-            add(i0, bc, P.w_vol / 6.f);
-            add(i1, ca, P.w_vol / 6.f);
-            add(i2, ab, P.w_vol / 6.f);
+        // both terms' gradients summed per corner first: one add per corner
+        // (same-address LDS atomics of neighbouring lanes serialise)
+        const float wa = (P.w_area != 0.f && nl > 0.f) ? 0.5f * P.w_area / nl : 0.f, wv = P.w_vol / 6.f;
+        auto corner = [&](float3 e, float3 vterm) {
+            const float3 ga = crs3(Nn, e);
+            return make_float3(wa * ga.x + wv * vterm.x, wa * ga.y + wv * vterm.y, wa * ga.z + wv * vterm.z);
+        };
+        if (P.w_area != 0.f || P.w_vol != 0.f) {
+            add(i0, corner(sub3(c, b), bc), 1.f);
+            add(i1, corner(sub3(a, c), ca), 1.f);
+            add(i2, corner(sub3(b, a), ab), 1.f);
         }
     };
     // hole fans of the node
@@ -160,7 +161,10 @@ __global__ void __launch_bounds__(64) k_loss_node(LParams P)
         const int2 he = W.he[h];
         const int64_t b0 = W.band_off[he.y], b1 = W.band_off[he.y + 1];
         const bool lower = (int64_t)he.x > n;
-        for (int64_t t = b0 + lane; t < b1; t += 64) tri_do(t, lower);
+        // even triangles on the first lanes, odd ones after: neighbouring
+        // lanes then share fewer corners
+        const int64_t nb = b1 - b0, half = (nb + 1) / 2;
+        for (int64_t l = lane; l < nb; l += 64) tri_do(b0 + (l < half ? 2 * l : 2 * (l - half) + 1), lower);
     }
     // sum of squared norms over the node's vertices
     for (int i = lane; i < M; i += 64) {
