@@ -13,8 +13,12 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblatmesh.so")
 SOURCES = ["prepare.hip", "node.hip", "expand.hip", "zip.hip", "grad.hip", "sink.hip", "stl.hip", "codec.hip",
            "api.hip"]
-# quantisation decisions must not depend on fused multiply-adds
-EXTRA = {"codec.hip": ["-ffp-contract=off"], "node.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt", "-fapprox-func"]}
+EXTRA = {
+    # quantisation decisions must not depend on fused multiply-adds
+    "codec.hip": ["-ffp-contract=off"],
+    "node.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt", "-fapprox-func"],
+    "grad.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt"],
+}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3",

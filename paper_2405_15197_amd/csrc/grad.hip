@@ -313,6 +313,7 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
     {
         const int M = (int)R[5];
         float sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll 4
         for (int i = lane; i < M; i += 64) {
             sx += L[3 * i];
             sy += L[3 * i + 1];
@@ -361,14 +362,42 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
     };
 
     // ---- interior points ----------------------------------------------------
+    // lane j alone writes arc j's adjoint here: sums in registers, one store
     for (int j = lane; j < E; j += 64) {
         const int nseg = (int)(RA[kRecArcFields * j + 13] & 0xffffu);
         const bool fwd = (RA[kRecArcFields * j + 11] >> 17) & 1u;
-        for (int ii = 1; ii < nseg; ++ii) {
-            const int li = s_mbase[j] + (fwd ? ii - 1 : nseg - 1 - ii);
-            const float lam[3] = {L[3 * li], L[3 * li + 1], L[3 * li + 2]};
-            add_interior(j, ii, lam);
+        const float t1 = af(9, j), t2 = af(10, j);
+        float ca[3], cb[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            ca[d] = af(3 + d, j);
+            cb[d] = af(6 + d, j);
         }
+        float acc[11];
+#pragma unroll
+        for (int f = 0; f < 11; ++f) acc[f] = 0.f;
+        const int mb = s_mbase[j];
+#pragma unroll 2
+        for (int ii = 1; ii < nseg; ++ii) {
+            const int li = mb + (fwd ? ii - 1 : nseg - 1 - ii);
+            const float lam[3] = {L[3 * li], L[3 * li + 1], L[3 * li + 2]};
+            const float f = (float)ii / (float)nseg;
+            const float t = t1 + (t2 - t1) * (float)ii / (float)nseg;
+            float sn, cs;
+            sincosf(t, &sn, &cs);
+            float g = 0.f;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                acc[d] += lam[d];
+                acc[3 + d] += lam[d] * sn;
+                acc[6 + d] += lam[d] * cs;
+                g += lam[d] * (ca[d] * cs - cb[d] * sn);
+            }
+            acc[9] += (1.f - f) * g;
+            acc[10] += f * g;
+        }
+#pragma unroll
+        for (int f = 0; f < 11; ++f) lam_arc[j][f] = acc[f];
     }
     __syncthreads();
 
@@ -450,6 +479,7 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
     __syncthreads();
 
     // ---- arc ends: t1, t2 are the parameters of the end vertices ------------
+    // (lane j alone writes arc j's adjoint; vertices are shared: atomics)
     for (int j = lane; j < E; j += 64) {
         const uint32_t u0 = RA[kRecArcFields * j + 11];
         const bool full = (u0 >> 16) & 1u;
@@ -457,20 +487,24 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
         if (full) {
             // the start vertex is the conic point at t = 0: o + b
             for (int d = 0; d < 3; ++d) {
-                atomicAdd(&lam_arc[j][d], lam_v[vs][d]);
-                atomicAdd(&lam_arc[j][6 + d], lam_v[vs][d]);
+                lam_arc[j][d] += lam_v[vs][d];
+                lam_arc[j][6 + d] += lam_v[vs][d];
             }
             continue;
         }
-        float o[3], a[3], bb[3];
+        float o[3], a[3], bb[3], acc[9];
+#pragma unroll
         for (int d = 0; d < 3; ++d) {
             o[d] = af(d, j);
             a[d] = af(3 + d, j);
             bb[d] = af(6 + d, j);
         }
+#pragma unroll
+        for (int f = 0; f < 9; ++f) acc[f] = 0.f;
         const float aa = dotf(a, a), bb2 = dotf(bb, bb);
+#pragma unroll
         for (int end = 0; end < 2; ++end) {
-            const float Lt = atomicAdd(&lam_arc[j][9 + end], 0.f);
+            const float Lt = lam_arc[j][9 + end];
             const int vi = end ? ve : vs;
             float w[3], r[3];
             vpos(vi, w);
@@ -478,15 +512,18 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
             const float u = dotf(r, a) / aa, vv = dotf(r, bb) / bb2, den = u * u + vv * vv;
             const float lu = Lt * vv / den, lv = -Lt * u / den;
             const float ra = dotf(r, a), rbv = dotf(r, bb);
+#pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const float lw = lu * a[d] / aa + lv * bb[d] / bb2;
                 atomicAdd(&lam_v[vi][d], lw);
-                atomicAdd(&lam_arc[j][d], -lw);
+                acc[d] -= lw;
                 // u = (r . a) / (a . a): du/da = r / aa - 2 a (r . a) / aa^2
-                atomicAdd(&lam_arc[j][3 + d], lu * (r[d] / aa - 2.f * a[d] * ra / (aa * aa)));
-                atomicAdd(&lam_arc[j][6 + d], lv * (r[d] / bb2 - 2.f * bb[d] * rbv / (bb2 * bb2)));
+                acc[3 + d] += lu * (r[d] / aa - 2.f * a[d] * ra / (aa * aa));
+                acc[6 + d] += lv * (r[d] / bb2 - 2.f * bb[d] * rbv / (bb2 * bb2));
             }
         }
+#pragma unroll
+        for (int f = 0; f < 9; ++f) lam_arc[j][f] += acc[f];
     }
     __syncthreads();
 
