@@ -17,7 +17,7 @@ EXTRA = {
     # quantisation decisions must not depend on fused multiply-adds
     "codec.hip": ["-ffp-contract=off"],
     "node.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt", "-fapprox-func"],
-    "grad.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt"],
+    "grad.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt", "-fapprox-func"],
 }
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -240,6 +240,12 @@ __device__ inline void seed(const float4 c4, int k, V3<Dual> &c, Dual &r)
 }
 
 __device__ inline float dotf(const float *a, const float *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+__device__ inline void crs(const float *a, const float *b, float *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
 
 __global__ void __launch_bounds__(64) k_backward(BParams P)
 {
@@ -545,39 +551,124 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
             atomicAdd(&lam_rf[q][d], rho * sq.kap * Lo[6 + d]);
         }
     }
-    // Ellipse (p, q), Eq. 7: forward mode over its 9 inputs g_p, h_p, g_q,
-    // h_q, rho (kappa_p = 1 / |g_p|, sigma_p = h_p kappa_p / rho), lanes
-    // over (arc, input) pairs.
-    for (int x = lane; x < (E - ncirc) * 9; x += 64) {
-        const int j = ncirc + x / 9, dir = x % 9;
+    // Ellipse (p, q), Eq. 7, in reverse mode, one lane per arc: the steps of
+    // the conic's construction (plane p = q, in-plane axis u1, the completed
+    // square) are recomputed, then their adjoints taken in reverse order.
+    // Inputs: g_p, h_p, g_q, h_q and rho (kappa_p and sigma_p follow from
+    // g_p, h_p and rho, so 1 - |in-plane g_p|^2 = (g_p . n)^2 - (h_p / rho)^2).
+    for (int j = ncirc + lane; j < E; j += 64) {
         const uint32_t u0 = RA[kRecArcFields * j + 11];
         const int p = (int)(u0 & 0xffu), q = (int)((u0 >> 8) & 0xffu);
-        SL<Dual> tab[3];
-        for (int e2 = 1; e2 <= 2; ++e2) {
-            const SL<float> &sf = S[e2 == 1 ? p : q];
-            const int b0 = e2 == 1 ? 0 : 4;
-            SL<Dual> &t = tab[e2];
-            t.gx = Dual(sf.gx, dir == b0 ? 1.f : 0.f);
-            t.gy = Dual(sf.gy, dir == b0 + 1 ? 1.f : 0.f);
-            t.gz = Dual(sf.gz, dir == b0 + 2 ? 1.f : 0.f);
-            t.h = Dual(sf.h, dir == b0 + 3 ? 1.f : 0.f);
+        const SL<float> &Sp = S[p], &Sq = S[q];
+        const float gp[3] = {Sp.gx, Sp.gy, Sp.gz}, gq[3] = {Sq.gx, Sq.gy, Sq.gz};
+        const float hp = Sp.h, hq = Sq.h;
+        float nv[3], nh[3];
+        for (int d = 0; d < 3; ++d) nv[d] = gp[d] - gq[d];
+        const float nn = sqrtf(dotf(nv, nv));
+        for (int d = 0; d < 3; ++d) nh[d] = nv[d] * (1.f / nn);
+        const float d0 = (hp - hq) / nn;
+        const float gpn = dotf(gp, nh);
+        const float epn = fabsf(gpn * Sp.kap), as = fabsf(Sp.sig);
+        const float om = (epn - as) * (epn + as) / (Sp.kap * Sp.kap);
+        if (!(om > 0.f)) continue;  // not an ellipse: the forward pass kept no arc of it
+        float gam[3], u1[3], tv[3] = {0.f, 0.f, 0.f};
+        for (int d = 0; d < 3; ++d) gam[d] = gp[d] - nh[d] * gpn;
+        const float gl = sqrtf(dotf(gam, gam));
+        const bool axis_from_g = gl > 1e-4f * sqrtf(dotf(gp, gp));
+        float ml = 1.f;
+        if (axis_from_g) {
+            for (int d = 0; d < 3; ++d) u1[d] = gam[d] / gl;
+            const float un = dotf(u1, nh);
+            for (int d = 0; d < 3; ++d) u1[d] -= nh[d] * un;
+            const float il = 1.f / sqrtf(dotf(u1, u1));
+            for (int d = 0; d < 3; ++d) u1[d] *= il;
+        } else {
+            tv[fabsf(nh[0]) < 0.9f ? 0 : 1] = 1.f;
+            crs(nh, tv, u1);
+            ml = sqrtf(dotf(u1, u1));
+            for (int d = 0; d < 3; ++d) u1[d] /= ml;
         }
-        const Dual rd = Dual(rho, dir == 8 ? 1.f : 0.f);
-        {
-            SL<Dual> &t = tab[1];
-            t.kap = Dual(1.f) / m_sqrt(t.gx * t.gx + t.gy * t.gy + t.gz * t.gz);
-            t.sig = t.h * t.kap / rd;
+        const float k0 = d0 * gpn - hp;
+        const float al0 = gl * k0 / om;
+        const float R2 = rho * rho - d0 * d0 + k0 * k0 / om;
+        const float R = sqrtf(fmaxf(R2, 0.f)), som = sqrtf(om), A = R / som;
+        float cv[3];
+        crs(u1, nh, cv);
+        // o = d0 nh + al0 u1, a = A u1, b = R (u1 x nh)
+        float Lo[3], La[3], Lb[3];
+        for (int d = 0; d < 3; ++d) {
+            Lo[d] = lam_arc[j][d];
+            La[d] = lam_arc[j][3 + d];
+            Lb[d] = lam_arc[j][6 + d];
         }
-        Con<Dual> C;
-        conic_of(tab, rd, 1, 2, C);
-        const float g = lam_arc[j][0] * C.o.x.d + lam_arc[j][1] * C.o.y.d + lam_arc[j][2] * C.o.z.d +
-                        lam_arc[j][3] * C.a.x.d + lam_arc[j][4] * C.a.y.d + lam_arc[j][5] * C.a.z.d +
-                        lam_arc[j][6] * C.b.x.d + lam_arc[j][7] * C.b.y.d + lam_arc[j][8] * C.b.z.d;
-        if (dir < 3) atomicAdd(&lam_g[p][dir], g);
-        else if (dir == 3) atomicAdd(&lam_h[p], g);
-        else if (dir < 7) atomicAdd(&lam_g[q][dir - 4], g);
-        else if (dir == 7) atomicAdd(&lam_h[q], g);
-        else atomicAdd(&lam_node[3], g);
+        float L_nh[3], L_u1[3], L_c[3], tmp[3];
+        for (int d = 0; d < 3; ++d) {
+            L_nh[d] = Lo[d] * d0;
+            L_u1[d] = Lo[d] * al0 + La[d] * A;
+            L_c[d] = Lb[d] * R;
+        }
+        float L_d0 = dotf(Lo, nh), L_al0 = dotf(Lo, u1), L_A = dotf(La, u1), L_R = dotf(Lb, cv);
+        crs(nh, L_c, tmp);
+        for (int d = 0; d < 3; ++d) L_u1[d] += tmp[d];
+        crs(L_c, u1, tmp);
+        for (int d = 0; d < 3; ++d) L_nh[d] += tmp[d];
+        // A = R / sqrt(om), R = sqrt(max(R2, 0))
+        L_R += L_A / som;
+        float L_om = -0.5f * L_A * A / om;
+        const float L_R2 = R > 0.f ? 0.5f * L_R / R : 0.f;
+        // R2 = rho^2 - d0^2 + k0^2 / om, al0 = gl k0 / om, k0 = d0 gpn - hp
+        float L_rho = 2.f * rho * L_R2;
+        L_d0 -= 2.f * d0 * L_R2;
+        float L_k0 = 2.f * k0 / om * L_R2;
+        L_om -= (k0 / om) * (k0 / om) * L_R2;
+        const float L_gl = k0 / om * L_al0;
+        L_k0 += gl / om * L_al0;
+        L_om -= al0 / om * L_al0;
+        L_d0 += gpn * L_k0;
+        float L_gpn = d0 * L_k0, L_hp = -L_k0;
+        // u1: gam / |gam| (the re-projection and renormalisation have zero
+        // derivative: u1 stays a unit vector in the plane), else the unit
+        // vector along nh x t
+        float L_gam[3];
+        for (int d = 0; d < 3; ++d) L_gam[d] = gl > 0.f ? gam[d] * (L_gl / gl) : 0.f;
+        const float uu = dotf(u1, L_u1);
+        if (axis_from_g) {
+            for (int d = 0; d < 3; ++d) L_gam[d] += (L_u1[d] - u1[d] * uu) / gl;
+        } else {
+            float Pm[3];
+            for (int d = 0; d < 3; ++d) Pm[d] = (L_u1[d] - u1[d] * uu) / ml;
+            crs(tv, Pm, tmp);
+            for (int d = 0; d < 3; ++d) L_nh[d] += tmp[d];
+        }
+        // gam = g_p - nh gpn
+        float L_gp[3];
+        const float gn = dotf(L_gam, nh);
+        for (int d = 0; d < 3; ++d) {
+            L_gp[d] = L_gam[d];
+            L_nh[d] -= gpn * L_gam[d];
+        }
+        L_gpn -= gn;
+        // om = gpn^2 - (h_p / rho)^2
+        L_gpn += 2.f * gpn * L_om;
+        L_hp -= 2.f * hp / (rho * rho) * L_om;
+        L_rho += 2.f * hp * hp / (rho * rho * rho) * L_om;
+        // gpn = g_p . nh
+        for (int d = 0; d < 3; ++d) {
+            L_gp[d] += nh[d] * L_gpn;
+            L_nh[d] += gp[d] * L_gpn;
+        }
+        // d0 = (h_p - h_q) / |n|, nh = n / |n|, n = g_p - g_q
+        L_hp += L_d0 / nn;
+        const float L_hq = -L_d0 / nn, L_nn = -d0 / nn * L_d0;
+        const float nl = dotf(nh, L_nh);
+        for (int d = 0; d < 3; ++d) {
+            const float L_n = (L_nh[d] - nh[d] * nl) / nn + nh[d] * L_nn;
+            atomicAdd(&lam_g[p][d], L_gp[d] + L_n);
+            atomicAdd(&lam_g[q][d], -L_n);
+        }
+        atomicAdd(&lam_h[p], L_hp);
+        atomicAdd(&lam_h[q], L_hq);
+        atomicAdd(&lam_node[3], L_rho);
     }
     __syncthreads();
 
