@@ -490,6 +490,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-scale", type=int, default=64, help="BCC cells per side of the oracle's lattice")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint leg (octet 32^3)")
+    ap.add_argument("--adjoint", action="store_true", help="only the forward + adjoint leg (octet 32^3)")
     ap.add_argument("--no-retri", action="store_true", help="skip the re-subdivision leg")
     ap.add_argument("--stl", action="store_true", help="only the binary STL writer on the benchmark mesh")
     ap.add_argument("--codec", action="store_true", help="only the arc codec on the benchmark meta-mesh")
@@ -521,6 +522,9 @@ def main():
         return
     if args.ablation:
         print(json.dumps(ablation_bench(args.scale, args.k)), flush=True)
+        return
+    if args.adjoint:
+        print(json.dumps(adjoint_bench(args.steps, args.warmup)), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is in the "
