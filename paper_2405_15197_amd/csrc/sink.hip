@@ -308,8 +308,8 @@ __global__ void __launch_bounds__(64) k_sink_zip(SinkParams P, const int32_t *li
     const bool staged = ntri <= kZipStage;
     const int2 *loops = (const int2 *)W.rec;
     if (staged) {
+        int i = 0;  // x only grows: the strut index carries over
         for (int x = lane; x < ntri; x += 64) {
-            int i = 0;
             while (g_t[i + 1] <= x) ++i;
             int k = x - g_t[i];
             int64_t base;
@@ -325,9 +325,9 @@ __global__ void __launch_bounds__(64) k_sink_zip(SinkParams P, const int32_t *li
         }
         __syncthreads();
     }
+    int i = 0;
     for (int x = lane; x < ntri; x += 64) {
         uint64_t ht = 0;
-        int i = 0;
         while (g_t[i + 1] <= x) ++i;
         const int j = x - g_t[i];
         const int na = g_na[i], nb = g_nb[i], ra = g_ra[i], rb = g_rb[i];

@@ -170,8 +170,8 @@ __global__ void __launch_bounds__(64) k_zip(int64_t S, const int64_t *band_off, 
     const bool staged = nsamp <= kZipStage;
     if (staged) {
         // samples of strut i: loop A sorted, then loop B sorted
+        int i = 0;  // x only grows: the strut index carries over
         for (int x = lane; x < nsamp; x += 64) {
-            int i = 0;
             while (g_q[i + 1] <= x) ++i;
             int k = x - g_q[i];
             const int na = g_na[i];
@@ -193,8 +193,8 @@ __global__ void __launch_bounds__(64) k_zip(int64_t S, const int64_t *band_off, 
         }
         __syncthreads();
     }
+    int i = 0;
     for (int x = lane; x < ntri; x += 64) {
-        int i = 0;
         while (g_t[i + 1] <= x) ++i;
         const int j = x - g_t[i];
         int32_t *T = tri + 3 * (t0 + x);
