@@ -234,102 +234,135 @@ __device__ inline int hi_root(const SL<T> *S, int p, int q, int r, const Con<T> 
     return dot(C.a * k.B - C.b * k.A, d) > (T)0 ? 1 : 0;
 }
 
+// Kept set of constraint r on conic (p, q): 0 never active, 1 removes the
+// whole conic, 2 the interval [lo, lo + lc] in pseudo-angle.
 template <typename T>
-__device__ void trim_conic(const SL<T> *S, int v, int p, int q, const Con<T> &C, TrimOut<T> &TR)
+__device__ inline int cons_interval(const SL<T> *S, V3<T> gp, T hp, int r, const Con<T> &C, T &lo, T &lc)
+{
+    const T tp = (T)4;  // full turn in pseudo-angle
+    const Cons<T> k = cons_of(S, gp, hp, r, C);
+    if (k.Cc >= k.R) return 0;   // never active
+    if (k.Cc <= -k.R) return 1;  // removes the whole conic
+    T los, loc, his, hic;
+    cons_ends(k, los, loc, his, hic);
+    lo = pang(los, loc);
+    const T hi = pang(his, hic);
+    lc = hi - lo;
+    if (lc < (T)0) lc += tp;
+    // more than a half turn exactly when Cc > 0: a kept interval that
+    // comes out almost empty although Cc > 0 is almost the whole turn
+    // (its gap is below rounding), one that comes out almost whole
+    // although Cc < 0 is almost empty.  Near a half turn (Cc near 0)
+    // the computed length stands.
+    if (k.Cc > (T)0 && lc < (T)1) return 0;
+    if (k.Cc < (T)0 && lc > (T)3) return 1;
+    return 2;
+}
+
+// Running intersection of the kept sets of a conic, taken in constraint
+// order.
+template <typename T>
+struct TrimRun {
+    Pc<T> pc[NPieces<T>::n];
+    int n = 1, full = 1;
+    bool ovf = false, done = false;
+};
+
+template <typename T>
+__device__ inline void trim_step(TrimRun<T> &st, int kind, T lo, T lc, int r)
 {
     constexpr int NP = NPieces<T>::n;
-    const T tp = (T)4;  // full turn in pseudo-angle
-    const V3<T> gp = p ? gvec(S[p]) : zero3<T>();
-    const T hp = p ? S[p].h : (T)0;
-    Pc<T> pc[NP];
-    int n = 1, full = 1;
-    bool ovf = false;
-    for (int r = 0; r <= v; ++r) {
-        if (r == p || r == q) continue;
-        const Cons<T> k = cons_of(S, gp, hp, r, C);
-        if (k.Cc >= k.R) continue;      // never active
-        if (k.Cc <= -k.R) {              // removes the whole conic
-            n = 0;
-            full = 0;
-            break;
-        }
-        T los, loc, his, hic;
-        cons_ends(k, los, loc, his, hic);
-        const T lo = pang(los, loc), hi = pang(his, hic);
-        T lc = hi - lo;
-        if (lc < (T)0) lc += tp;
-        // more than a half turn exactly when Cc > 0: a kept interval that
-        // comes out almost empty although Cc > 0 is almost the whole turn
-        // (its gap is below rounding), one that comes out almost whole
-        // although Cc < 0 is almost empty.  Near a half turn (Cc near 0)
-        // the computed length stands.
-        if (k.Cc > (T)0 && lc < (T)1) continue;
-        if (k.Cc < (T)0 && lc > (T)3) {
-            n = 0;
-            full = 0;
-            break;
-        }
-        if (full) {
-            pc[0] = Pc<T>{lo, lc, r, r};
-            n = 1;
-            full = 0;
-            continue;
-        }
-        // intersect the current pieces with [lo, lo + lc]
-        Pc<T> out[NP];
-        int no = 0;
-        auto push = [&](T s0, T l0, int rs, int re) {
-#pragma unroll
-            for (int j = 0; j < NP; ++j)
-                if (j == no) out[j] = Pc<T>{s0, l0, rs, re};
-            if (no < NP) ++no;
-            else ovf = true;
-        };
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-            if (i < n) {
-                const Pc<T> Pp = pc[i];
-                T c0 = lo - Pp.s;
-                if (c0 < (T)0) c0 += tp;
-                const T c1 = c0 + lc;
-                if (c0 < Pp.len) {
-                    const bool ns = c0 > (T)0, ne = c1 < Pp.len;
-                    push(ns ? lo : Pp.s, (ne ? c1 : Pp.len) - c0, ns ? r : Pp.rs, ne ? r : Pp.re);
-                }
-                if (c1 > tp) {
-                    const T w1 = c1 - tp;
-                    const bool ne = w1 < Pp.len;
-                    push(Pp.s, ne ? w1 : Pp.len, Pp.rs, ne ? r : Pp.re);
-                }
-            }
-        }
-        n = no;
-#pragma unroll
-        for (int j = 0; j < NP; ++j) pc[j] = out[j];
-        if (no == 0) break;
+    const T tp = (T)4;
+    if (st.done || kind == 0) return;
+    if (kind == 1) {
+        st.n = 0;
+        st.full = 0;
+        st.done = true;
+        return;
     }
-    TR.n = n;
-    TR.full = full;
-    TR.ovf = ovf ? 1 : 0;
-    if (full) return;
-    // final form: end directions and tie roots of every piece
+    if (st.full) {
+        st.pc[0] = Pc<T>{lo, lc, r, r};
+        st.n = 1;
+        st.full = 0;
+        return;
+    }
+    // intersect the current pieces with [lo, lo + lc]
+    Pc<T> out[NP];
+    int no = 0;
+    auto push = [&](T s0, T l0, int rs, int re) {
+#pragma unroll
+        for (int j = 0; j < NP; ++j)
+            if (j == no) out[j] = Pc<T>{s0, l0, rs, re};
+        if (no < NP) ++no;
+        else st.ovf = true;
+    };
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-        if (i < n) {
+        if (i < st.n) {
+            const Pc<T> Pp = st.pc[i];
+            T c0 = lo - Pp.s;
+            if (c0 < (T)0) c0 += tp;
+            const T c1 = c0 + lc;
+            if (c0 < Pp.len) {
+                const bool ns = c0 > (T)0, ne = c1 < Pp.len;
+                push(ns ? lo : Pp.s, (ne ? c1 : Pp.len) - c0, ns ? r : Pp.rs, ne ? r : Pp.re);
+            }
+            if (c1 > tp) {
+                const T w1 = c1 - tp;
+                const bool ne = w1 < Pp.len;
+                push(Pp.s, ne ? w1 : Pp.len, Pp.rs, ne ? r : Pp.re);
+            }
+        }
+    }
+    st.n = no;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) st.pc[j] = out[j];
+    if (no == 0) st.done = true;
+}
+
+// final form: end directions and tie roots of every piece
+template <typename T>
+__device__ inline void trim_finish(const SL<T> *S, int p, int q, const Con<T> &C, V3<T> gp, T hp,
+                                   const TrimRun<T> &st, TrimOut<T> &TR)
+{
+    constexpr int NP = NPieces<T>::n;
+    TR.n = st.n;
+    TR.full = st.full;
+    TR.ovf = st.ovf ? 1 : 0;
+    if (st.full) return;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        if (i < st.n) {
             Piece<T> &o = TR.pc[i];
             T a0, a1, a2, a3;
-            const Cons<T> ks = cons_of(S, gp, hp, pc[i].rs, C);
+            const Cons<T> ks = cons_of(S, gp, hp, st.pc[i].rs, C);
             cons_ends(ks, o.ss, o.sc, a2, a3);
-            const int root_s = 1 - hi_root(S, p, q, pc[i].rs, C, ks);
-            const Cons<T> ke = cons_of(S, gp, hp, pc[i].re, C);
+            const int root_s = 1 - hi_root(S, p, q, st.pc[i].rs, C, ks);
+            const Cons<T> ke = cons_of(S, gp, hp, st.pc[i].re, C);
             cons_ends(ke, a0, a1, o.es, o.ec);
-            const int root_e = hi_root(S, p, q, pc[i].re, C, ke);
-            o.len = pc[i].len;
-            o.rs = pc[i].rs;
-            o.re = pc[i].re;
+            const int root_e = hi_root(S, p, q, st.pc[i].re, C, ke);
+            o.len = st.pc[i].len;
+            o.rs = st.pc[i].rs;
+            o.re = st.pc[i].re;
             o.roots = root_s | (root_e << 1);
         }
     }
+}
+
+template <typename T>
+__device__ void trim_conic(const SL<T> *S, int v, int p, int q, const Con<T> &C, TrimOut<T> &TR)
+{
+    const V3<T> gp = p ? gvec(S[p]) : zero3<T>();
+    const T hp = p ? S[p].h : (T)0;
+    TrimRun<T> st;
+    for (int r = 0; r <= v; ++r) {
+        if (r == p || r == q) continue;
+        T lo = (T)0, lc = (T)0;
+        const int kind = cons_interval(S, gp, hp, r, C, lo, lc);
+        trim_step(st, kind, lo, lc, r);
+        if (st.done) break;
+    }
+    trim_finish(S, p, q, C, gp, hp, st, TR);
 }
 
 // Conic point at the direction (sin t, cos t) ~ (s, c)
@@ -828,11 +861,19 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
     // ---- conics, trimming, arcs and owned vertices ------------------------
     {
         const int nconic = v * (v + 1) / 2;
-        for (int c0 = 0; c0 < nconic; c0 += WL) {
-            int ci = c0 + lane;
+        for (int c0 = 0; c0 < nconic;) {
+            // A last round of at most WL / 8 conics (v <= 8: at most 7
+            // constraints each) runs on 8 lanes per conic, one constraint per
+            // lane; the conic's first lane intersects the kept sets in
+            // constraint order.  Otherwise one lane per conic.
+            const bool split = F32 && WL >= 16 && v <= 8 && (nconic - c0) * 8 <= WL;
+            const int ci = split ? c0 + (lane >> 3) : c0 + lane;
+            const int sub = split ? (lane & 7) : 0;
+            const bool grp = ci < nconic;
+            const bool act = grp && sub == 0;
+            c0 += split ? WL / 8 : WL;
             int p = 0, q = 0;
-            bool act = ci < nconic;
-            if (act) {
+            if (grp) {
                 int rem = ci;
                 while (rem >= v - p) { rem -= v - p; ++p; }
                 q = p + 1 + rem;
@@ -842,11 +883,39 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
             TR.n = 0;
             TR.full = 0;
             TR.ovf = 0;
-            if (act) {
-                if (!conic_of(sh.S, rho, p, q, C)) {
-                    atomicOr(&sh.status, NS_NON_ELLIPTIC);
-                } else {
-                    trim_conic(sh.S, v, p, q, C, TR);
+            const bool ell = grp && conic_of(sh.S, rho, p, q, C);
+            if (act && !ell) atomicOr(&sh.status, NS_NON_ELLIPTIC);
+            {
+                const V3<T> gp = p ? gvec(sh.S[p]) : zero3<T>();
+                const T hp = p ? sh.S[p].h : (T)0;
+                // split: this lane's constraint, the sub-th label of 0..v
+                // other than p and q (p < q)
+                int myr = sub, mykind = 0;
+                T mylo = (T)0, mylc = (T)0;
+                if (split) {
+                    if (myr >= p) ++myr;
+                    if (myr >= q) ++myr;
+                    if (ell && sub < v - 1) mykind = cons_interval(sh.S, gp, hp, myr, C, mylo, mylc);
+                }
+                const int src0 = (int)(threadIdx.x & 63) & ~7;
+                const int nsteps = split ? 7 : (act && ell ? v + 1 : 0);
+                TrimRun<T> st;
+                for (int s2 = 0; s2 < nsteps; ++s2) {
+                    int r2 = s2, k2 = 0;
+                    T lo2 = (T)0, lc2 = (T)0;
+                    if (split) {
+                        k2 = __shfl(mykind, src0 + s2, 64);
+                        r2 = __shfl(myr, src0 + s2, 64);
+                        lo2 = __shfl(mylo, src0 + s2, 64);
+                        lc2 = __shfl(mylc, src0 + s2, 64);
+                    } else if (r2 != p && r2 != q) {
+                        k2 = cons_interval(sh.S, gp, hp, r2, C, lo2, lc2);
+                    }
+                    trim_step(st, k2, lo2, lc2, r2);
+                    if (!split && st.done) break;
+                }
+                if (act && ell) {
+                    trim_finish(sh.S, p, q, C, gp, hp, st, TR);
                     if (TR.ovf) atomicOr(&sh.status, F32 ? NS_PREC : NS_CAPACITY);
                 }
             }
