@@ -33,6 +33,14 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 MEASURED_TRAFFIC = {
     "fa8d1a5d023069a7": {"bytes": 1_737_350_000, "summary": "profiles/k_node32_bcc64_k16_hbm_counters.md"},
 }
+# wave64 VALU instructions per node pass (SQ_INSTS_VALU summed over the three
+# valence-class launches) from the same counter runs, keyed the same way
+MEASURED_VALU = {
+    "fa8d1a5d023069a7": {"insts": 1_301_200_000, "summary": "profiles/k_node32_bcc64_k16_hbm_counters.md"},
+}
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per
+# SIMD every 4 cycles (16 lanes wide; packed FP32 is not used)
+VALU_PEAK_GINSTS = 256 * 4 * 2.4 / 4
 
 
 def node_source_key():
@@ -580,6 +588,13 @@ def main():
     achieved = fb / (kern_ms * 1e-3) / 1e9
     mt = MEASURED_TRAFFIC.get(node_source_key())
     traffic = mt["bytes"] if mt else None
+    mv = MEASURED_VALU.get(node_source_key())
+    valu = None
+    if mv:
+        gi = mv["insts"] / (kern_ms * 1e-3) / 1e9
+        valu = {"kernel": "k_node32 (per-node meta-meshing, FP32)", "bound": "alu", "achieved": gi,
+                "peak": VALU_PEAK_GINSTS, "unit": "G wave64 VALU instructions/s", "frac": gi / VALU_PEAK_GINSTS,
+                "insts_per_launch": mv["insts"]}
     res = {
         "metric": "struts meta-meshed/s (and triangles emitted/s) at resolution k",
         "value": struts_s,
@@ -619,6 +634,9 @@ def main():
             "bytes_per_launch": fb,
             "ms_per_launch": kern_ms,
         },
+        # the same kernel against the vector-ALU issue rate, which is what
+        # bounds it (null when its source differs from the one counted)
+        "alu_roofline": valu,
     }
     if not args.no_retri:
         print("[bench] re-subdivision of the k=16 meta-mesh", file=sys.stderr, flush=True)
