@@ -1112,27 +1112,25 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
                 if (m == 0) continue;
                 const SL<T> &s = sh.S[m];
                 int pp = sh.loop_base[m] + atomicAdd(&sh.loop_cnt[m], 1);
+                const int dir = dot(wdw, v3(s.sx, s.sy, s.sz)) > (T)0 ? 1 : -1;
                 sh.loop_arc[pp] = (uint8_t)j;
-                sh.loop_dir[pp] = dot(wdw, v3(s.sx, s.sy, s.sz)) > (T)0 ? 1 : -1;
+                sh.loop_dir[pp] = (int8_t)dir;
+                // start name and loop of the membership, kept in entry_off /
+                // entry_m (free until the tail lays out the loop samples)
+                sh.entry_off[pp] = (int)(dir > 0 ? A.ns : A.ne);
+                sh.entry_m[pp] = (uint8_t)m;
                 atomicAdd(&sh.loop_len[m], A.nseg);
                 if (A.full) atomicAdd(&sh.loop_full[m], 1);
             }
         }
         __syncthreads();
         const int tot = sh.loop_base[v + 1];
-        auto sname = [&](int pp) {
-            const ArcL<T> &A = sh.A[sh.loop_arc[pp]];
-            return sh.loop_dir[pp] > 0 ? A.ns : A.ne;
-        };
+        auto sname = [&](int pp) { return (uint32_t)sh.entry_off[pp]; };
         auto ename = [&](int pp) {
             const ArcL<T> &A = sh.A[sh.loop_arc[pp]];
             return sh.loop_dir[pp] > 0 ? A.ne : A.ns;
         };
-        auto strut_of = [&](int pp) {
-            int m = 1;
-            while (sh.loop_base[m + 1] <= pp) ++m;
-            return m;
-        };
+        auto strut_of = [&](int pp) { return (int)sh.entry_m[pp]; };
         for (int pp = lane; pp < tot; pp += WL) {
             const int m = strut_of(pp);
             const int b0 = sh.loop_base[m], b1 = sh.loop_base[m + 1];
