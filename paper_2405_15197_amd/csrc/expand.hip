@@ -20,6 +20,7 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
 {
     __shared__ int s_mbase[kAcap];
     __shared__ int s_fbase[kAcap];
+    __shared__ uint4 s_arc[kAcap][kRecArcFields / 4];  // the node's arcs, staged once
     const Work &W = P.w;
     const FillOut &O = P.o;
     const int64_t N = P.in.n_nodes;
@@ -46,9 +47,15 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
     const uint32_t *RA = RV + 4 * V;
     const uint32_t *RH = RA + kRecArcFields * E;
 
+    // arcs: whole 16-byte groups into LDS (the arc block starts on a 16-byte
+    // boundary); every later read of an arc field is an LDS read
+    for (int x = lane; x < (kRecArcFields / 4) * E; x += 64)
+        s_arc[x / (kRecArcFields / 4)][x % (kRecArcFields / 4)] = ((const uint4 *)RA)[x];
+    __syncthreads();
+    auto aw = [&](int j, int f) -> uint32_t { return ((const uint32_t *)s_arc[j])[f]; };
     for (int j = lane; j < E; j += 64) {
-        s_mbase[j] = (int)RA[kRecArcFields * j + 14];
-        s_fbase[j] = (int)RA[kRecArcFields * j + 15];
+        s_mbase[j] = (int)aw(j, 14);
+        s_fbase[j] = (int)aw(j, 15);
     }
     if (O.vert_name) {
         for (int i = lane; i < V; i += 64) {
@@ -62,9 +69,9 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
         const int64_t cA = O.cap_arc;
         for (int j = lane; j < E; j += 64) {
 #pragma unroll
-            for (int t = 0; t < 11; ++t) O.arc_f32[t * cA + aoff + j] = fbits(RA[kRecArcFields * j + t]);
-            O.arc_u32[0 * cA + aoff + j] = RA[kRecArcFields * j + 11] & 0x1ffffu;  // p | q<<8 | whole<<16
-            O.arc_u32[1 * cA + aoff + j] = RA[kRecArcFields * j + 12];
+            for (int t = 0; t < 11; ++t) O.arc_f32[t * cA + aoff + j] = fbits(aw(j, t));
+            O.arc_u32[0 * cA + aoff + j] = aw(j, 11) & 0x1ffffu;  // p | q<<8 | whole<<16
+            O.arc_u32[1 * cA + aoff + j] = aw(j, 12);
             O.arc_u32[2 * cA + aoff + j] = (uint32_t)n;
         }
     }
@@ -72,14 +79,14 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
 
     // Eq. 12 sub-parameter ii (1..nseg-1) of arc j, and its point
     auto interior = [&](int j, int ii) {
-        const float t1 = fbits(RA[kRecArcFields * j + 9]), t2 = fbits(RA[kRecArcFields * j + 10]);
-        const int nseg = (int)(RA[kRecArcFields * j + 13] & 0xffffu);
+        const float t1 = fbits(aw(j, 9)), t2 = fbits(aw(j, 10));
+        const int nseg = (int)(aw(j, 13) & 0xffffu);
         const float t = t1 + (t2 - t1) * (float)ii / (float)nseg;
         float s, c;
         sincosf(t, &s, &c);
         float w[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) w[d] = fbits(RA[kRecArcFields * j + d]) + fbits(RA[kRecArcFields * j + (3 + d)]) * s + fbits(RA[kRecArcFields * j + (6 + d)]) * c;
+        for (int d = 0; d < 3; ++d) w[d] = fbits(aw(j, d)) + fbits(aw(j, 3 + d)) * s + fbits(aw(j, 6 + d)) * c;
         return make_float3(w[0], w[1], w[2]);
     };
     // mesh vertices: meta-vertices, interior points, hole centres
@@ -94,8 +101,8 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
                 if (s_mbase[mid] <= i) lo = mid;
                 else hi = mid - 1;
             }
-            const int nseg = (int)(RA[kRecArcFields * lo + 13] & 0xffffu);
-            const bool fwd = (RA[kRecArcFields * lo + 11] >> 17) & 1u;
+            const int nseg = (int)(aw(lo, 13) & 0xffffu);
+            const bool fwd = (aw(lo, 11) >> 17) & 1u;
             const int jc = i - s_mbase[lo];
             w = interior(lo, fwd ? jc + 1 : nseg - 1 - jc);
         } else {
@@ -120,7 +127,7 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
             else hi = mid - 1;
         }
         const int j = lo;
-        const uint32_t u0 = RA[kRecArcFields * j + 11], u1 = RA[kRecArcFields * j + 12], u2 = RA[kRecArcFields * j + 13];
+        const uint32_t u0 = aw(j, 11), u1 = aw(j, 12), u2 = aw(j, 13);
         const bool fwd = (u0 >> 17) & 1u, lower = (u0 >> 18) & 1u;
         const int nseg = (int)(u2 & 0xffffu), contour = (int)(u2 >> 16);
         const int vs = (int)(u1 & 0xffffu), ve = (int)(u1 >> 16);
