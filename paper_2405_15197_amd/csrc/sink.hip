@@ -139,6 +139,7 @@ __device__ inline void add_out(const SinkParams &P, int32_t part, int word, uint
 // Mesh vertices and hole fans of the range's nodes, from their records.
 __global__ void __launch_bounds__(64) k_sink_nodes(SinkParams P)
 {
+    __shared__ uint4 s_arc[kAcap][kRecArcFields / 4];  // the node's arcs, staged once
     const Work &W = P.w;
     const int64_t n = P.n0 + blockIdx.x;
     const int lane = threadIdx.x;
@@ -157,7 +158,12 @@ __global__ void __launch_bounds__(64) k_sink_nodes(SinkParams P)
     const uint32_t *RH = RA + kRecArcFields * E;
     const float4 c4 = W.node4[n];
     const int64_t ln = local_node(P, n);
-    auto af = [&](int f, int j) { return __uint_as_float(RA[kRecArcFields * j + f]); };
+    // arcs: whole 16-byte groups into LDS; every arc field is then read there
+    for (int x = lane; x < (kRecArcFields / 4) * E; x += 64)
+        s_arc[x / (kRecArcFields / 4)][x % (kRecArcFields / 4)] = ((const uint4 *)RA)[x];
+    __syncthreads();
+    auto aw = [&](int j, int f) -> uint32_t { return ((const uint32_t *)s_arc[j])[f]; };
+    auto af = [&](int f, int j) { return __uint_as_float(aw(j, f)); };
     uint64_t hv = 0, sx = 0, sy = 0, sz = 0, ht = 0;
     for (int i = lane; i < M; i += 64) {
         float w0, w1, w2;
@@ -169,12 +175,12 @@ __global__ void __launch_bounds__(64) k_sink_nodes(SinkParams P)
             int lo = 0, hi = E - 1;  // last arc with mbase <= i
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if ((int)RA[kRecArcFields * mid + 14] <= i) lo = mid;
+                if ((int)aw(mid, 14) <= i) lo = mid;
                 else hi = mid - 1;
             }
-            const int nseg = (int)(RA[kRecArcFields * lo + 13] & 0xffffu);
-            const bool fwd = (RA[kRecArcFields * lo + 11] >> 17) & 1u;
-            const int jc = i - (int)RA[kRecArcFields * lo + 14];
+            const int nseg = (int)(aw(lo, 13) & 0xffffu);
+            const bool fwd = (aw(lo, 11) >> 17) & 1u;
+            const int jc = i - (int)aw(lo, 14);
             const int ii = fwd ? jc + 1 : nseg - 1 - jc;
             const float t1 = af(9, lo), t2 = af(10, lo);
             const float t = t1 + (t2 - t1) * (float)ii / (float)nseg;
@@ -199,16 +205,16 @@ __global__ void __launch_bounds__(64) k_sink_nodes(SinkParams P)
         int lo = 0, hi = ncirc - 1;  // last circular arc with fbase <= i
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if ((int)RA[kRecArcFields * mid + 15] <= i) lo = mid;
+            if ((int)aw(mid, 15) <= i) lo = mid;
             else hi = mid - 1;
         }
         const int j = lo;
-        const uint32_t u0 = RA[kRecArcFields * j + 11], u1 = RA[kRecArcFields * j + 12], u2 = RA[kRecArcFields * j + 13];
+        const uint32_t u0 = aw(j, 11), u1 = aw(j, 12), u2 = aw(j, 13);
         const bool fwd = (u0 >> 17) & 1u, lower = (u0 >> 18) & 1u;
         const int nseg = (int)(u2 & 0xffffu), contour = (int)(u2 >> 16);
         const int vs = (int)(u1 & 0xffffu), ve = (int)(u1 >> 16);
-        const int mbase = (int)RA[kRecArcFields * j + 14];
-        const int s = i - (int)RA[kRecArcFields * j + 15];
+        const int mbase = (int)aw(j, 14);
+        const int s = i - (int)aw(j, 15);
         const int i0 = fwd ? s : nseg - s, i1 = fwd ? s + 1 : nseg - s - 1;
         const int lo_i = i0 < i1 ? i0 : i1, hi_i = i0 < i1 ? i1 : i0;
         const int u = lo_i == 0 ? vs : mbase + (fwd ? lo_i - 1 : nseg - 1 - lo_i);
