@@ -41,7 +41,7 @@ extern "C" {
 #define LM_ERR_INVALID_ARG (-1)    /* null pointer, negative size, bad k */
 #define LM_ERR_BAD_LATTICE (-2)    /* strut endpoint index outside [0, n_nodes) */
 #define LM_ERR_CAPACITY (-3)       /* an output buffer is smaller than the totals */
-#define LM_ERR_UNSUPPORTED (-4)    /* size beyond what this build handles */
+#define LM_ERR_UNSUPPORTED (-4)    /* size beyond what this library handles */
 #define LM_ERR_HIP (-5)            /* a HIP runtime call failed */
 #define LM_ERR_STATE (-6)          /* call out of order (e.g. fill before count) */
 #define LM_ERR_INTERNAL (-7)       /* the workspace could not be sized */
@@ -55,7 +55,7 @@ extern "C" {
 #define LM_NODE_TOPOLOGY 8u        /* arc/vertex incidence or Euler check failed
                                       (e.g. an annular hole), or no hole-fan apex */
 #define LM_NODE_ISOLATED 16u       /* no incident strut */
-#define LM_NODE_VALENCE 32u        /* more incident struts than this build handles */
+#define LM_NODE_VALENCE 32u        /* more incident struts than this library handles */
 #define LM_NODE_DUPLICATE 64u      /* two struts join the same pair of nodes */
 #define LM_NODE_CAPACITY 128u      /* per-node arc / vertex / piece capacity exceeded */
 

@@ -766,7 +766,7 @@ const char *lm_status_string(int code)
     case LM_ERR_INVALID_ARG: return "invalid argument";
     case LM_ERR_BAD_LATTICE: return "strut endpoint out of range";
     case LM_ERR_CAPACITY: return "output buffer too small";
-    case LM_ERR_UNSUPPORTED: return "size not supported by this build";
+    case LM_ERR_UNSUPPORTED: return "size not supported by this library";
     case LM_ERR_HIP: return "HIP runtime error";
     case LM_ERR_STATE: return "call out of order";
     case LM_ERR_INTERNAL: return "workspace could not be sized";

@@ -6,7 +6,7 @@
 
 namespace lm {
 
-// Per-node limits of this build.  A node beyond them is flagged (its status
+// Per-node limits of this library.  A node beyond them is flagged (its status
 // bit is set) and emits nothing.
 constexpr int kVmax = 16;       // incident struts per node
 constexpr int kAcap = 64;       // arcs per node
