@@ -56,6 +56,7 @@ def _load():
     lib.orc_free.argtypes = [P]
     lib.orc_sizes.argtypes = [P, P]
     lib.orc_nodes.argtypes = [P, P, P]
+    lib.orc_node_margins.argtypes = [P, P]
     lib.orc_vertices.argtypes = [P, P, P, P]
     lib.orc_arcs.argtypes = [P, P, P]
     lib.orc_loops.argtypes = [P, P, P, P]
@@ -86,6 +87,7 @@ class OracleResult:
     nfan: np.ndarray
     margin: np.ndarray  # float64 [N]
     margin_kind: np.ndarray  # int32 [N] (MK_* codes of oracle.c)
+    kmargin: np.ndarray  # float64 [N, 8]: smallest margin of each kind MK_* = 1..8 (column kind - 1)
     # meta-mesh (node order; per-node offsets from nv / ne)
     vert_off: np.ndarray
     vert_name: np.ndarray  # uint32 [V]
@@ -143,6 +145,8 @@ def run(lat, k: int, threads: int | None = None) -> OracleResult:
         cnt = np.zeros((N, 8), np.int32)
         mg = np.zeros(N, np.float64)
         lib.orc_nodes(h, _p(cnt), _p(mg))
+        kmg = np.zeros((N, 8), np.float64)
+        lib.orc_node_margins(h, _p(kmg))
         vn = np.zeros(nV, np.uint32)
         vw = np.zeros((nV, 3), np.float64)
         vc = np.zeros((nV, 2), np.float64)
@@ -172,7 +176,7 @@ def run(lat, k: int, threads: int | None = None) -> OracleResult:
         k=int(k), n_nodes=N, n_struts=S,
         status=cnt[:, 0].copy(), valence=cnt[:, 1].copy(), nv=cnt[:, 2].copy(), ne=cnt[:, 3].copy(),
         nc=cnt[:, 4].copy(), nmesh=cnt[:, 5].copy(), nfan=cnt[:, 6].copy(), margin=mg,
-        margin_kind=cnt[:, 7].copy(),
+        margin_kind=cnt[:, 7].copy(), kmargin=kmg,
         vert_off=off(cnt[:, 2]), vert_name=vn, vert_w=vw, vert_cond=vc,
         arc_off=off(cnt[:, 3]), arc_int=ai, arc_dbl=ad,
         loop_off=lo, loop_arc=la[:nL], loop_dir=ld[:nL], adj_off=aoff, adj=adj[: 2 * S],

@@ -56,7 +56,14 @@
 #define MK_FLOOR 6    /* k dt / 2 pi close to an integer (Eq. 11 floor) */
 #define MK_HOLE 7     /* hole barycentre close to the node centre */
 #define MK_STEP 8     /* small phi step along a loop */
-#define LOWER(val, kind) do { double v_ = (val); if (v_ < margin) { margin = v_; mkind = (kind); } } while (0)
+#define MK_N 9       /* margin kinds 1..8 */
+/* lowers the node's margin and the margin of its kind */
+#define LOWER(val, kind)                                                      \
+    do {                                                                      \
+        double v_ = (val);                                                    \
+        if (v_ < margin) { margin = v_; mkind = (kind); }                     \
+        if (v_ < kmin[(kind)]) kmin[(kind)] = v_;                             \
+    } while (0)
 
 /* node status bits */
 #define ST_INVALID_STRUT 1u
@@ -114,6 +121,7 @@ typedef struct {
     int status;
     double margin;     /* min normalised margin (topology + geometry) */
     int margin_kind;   /* which test set the margin (MK_* codes) */
+    double kmargin[MK_N]; /* smallest margin of each kind (index MK_*) */
     int v;
     int nv, ne, nc;
     Vert *verts;       /* sorted by name */
@@ -127,6 +135,7 @@ typedef struct {
     int *lv_off;       /* per label: loop vertex sequence offsets (v+1) */
     int *lv_idx;       /* local mesh index */
     double *lv_phi;
+    uint8_t *lv_whole; /* the sample lies on a whole tangency circle */
     double *cont_b;    /* hole centre (local) per contour, 3*nc */
 } NodeRes;
 
@@ -476,6 +485,7 @@ static void node_compute(Ctx *X, int64_t n)
     NodeRes *R = &X->nodes[n];
     memset(R, 0, sizeof(*R));
     R->margin = 1e300;
+    for (int i = 0; i < MK_N; ++i) R->kmargin[i] = 1e300;
     int v = (int)(X->off[n + 1] - X->off[n]);
     R->v = v;
     if (v == 0) { node_fail(R, ST_ISOLATED); return; }
@@ -515,6 +525,8 @@ static void node_compute(Ctx *X, int64_t n)
 
     double margin = 1e300;
     int mkind = 0;
+    double kmin[MK_N];
+    for (int i = 0; i < MK_N; ++i) kmin[i] = 1e300;
     /* Steps 1-2: conics and their kept arcs */
     int cap = 64, ne = 0;
     Arc *arcs = malloc(sizeof(Arc) * cap);
@@ -561,7 +573,12 @@ static void node_compute(Ctx *X, int64_t n)
             verts[nv].w = conic_pt(A->o, A->a, A->b, 0.0);
             verts[nv].sep = verts[nv].gap = 1e300;
             ++nv;
-            if (A->p == 0) { /* dummy position depends on the strut frame */
+            /* the start point of a whole circle depends on the strut frame.
+             * An exact tie of |e_s,j| (gap 0: equal magnitudes of the FP32
+             * coordinate differences, which FP32 arithmetic keeps equal) is
+             * decided by the lowest index on both sides; only a near tie is
+             * a margin. */
+            if (A->p == 0 && L->frame_gap[A->q] > 0.0) {
                 LOWER(L->frame_gap[A->q], MK_FRAME);
             }
             continue;
@@ -746,7 +763,13 @@ static void node_compute(Ctx *X, int64_t n)
     R->nv = nv; R->ne = ne; R->nc = nc;
     R->verts = verts; R->arcs = arcs;
     R->loop_off = loop_off; R->loop_arc = loop_arc; R->loop_dir = loop_dir;
-    if (R->status) { R->margin = margin; R->margin_kind = mkind; free(L); return; }
+    if (R->status) {
+        R->margin = margin;
+        R->margin_kind = mkind;
+        memcpy(R->kmargin, kmin, sizeof(kmin));
+        free(L);
+        return;
+    }
 
     /* Step 5: subdivision at resolution k (Eqs. 11-12) */
     int k = X->k;
@@ -884,6 +907,7 @@ static void node_compute(Ctx *X, int64_t n)
     for (int li = 0; li < nl; ++li) tot += arcs[loop_arc[li]].nseg;
     int *lv_idx = malloc(sizeof(int) * (tot + 1));
     double *lv_phi = malloc(sizeof(double) * (tot + 1));
+    uint8_t *lv_whole = malloc(tot + 1);
     {
         int pos = 0;
         for (int m = 1; m <= v; ++m) {
@@ -900,6 +924,7 @@ static void node_compute(Ctx *X, int64_t n)
                     int ii = d > 0 ? j : A->nseg - j;
                     int mi = j == 0 ? (d > 0 ? A->vs : A->ve) : INTERIOR(A, ii);
                     lv_idx[pos] = mi;
+                    lv_whole[pos] = (uint8_t)(A->p == 0 && A->full);
                     if (A->p == 0) {
                         double t = A->t1 + (A->t2 - A->t1) * ii / A->nseg;
                         if (t >= TWO_PI) t -= TWO_PI;
@@ -927,9 +952,10 @@ static void node_compute(Ctx *X, int64_t n)
     }
 #undef INTERIOR
     R->nmesh = nmesh; R->nfan = nfan; R->mesh_w = mw; R->fan = fan;
-    R->lv_off = lv_off; R->lv_idx = lv_idx; R->lv_phi = lv_phi; R->cont_b = cb;
+    R->lv_off = lv_off; R->lv_idx = lv_idx; R->lv_phi = lv_phi; R->lv_whole = lv_whole; R->cont_b = cb;
     R->margin = margin;
     R->margin_kind = mkind;
+    memcpy(R->kmargin, kmin, sizeof(kmin));
     free(L);
 }
 
@@ -978,9 +1004,16 @@ static void strut_band(Ctx *X, int64_t s)
         T[3 * t] = ob + ib[j2]; T[3 * t + 1] = ob + ib[j]; T[3 * t + 2] = oa + ia[ap];
         ++t;
     }
+    /* margin: the smallest phi gap between the two loops' samples.  Two
+     * samples of whole tangency circles are both at t = 2 pi i / k (phi is
+     * the circle parameter, the same sub-parameters at both ends): they tie
+     * exactly or lie a step apart, and an exact tie is decided by the end
+     * tag on both sides, so such pairs are no margin. */
+    const uint8_t *wa = Ra->lv_whole + Ra->lv_off[ma - 1], *wb = Rb->lv_whole + Rb->lv_off[mb - 1];
     double mg = 1e300;
     for (int i = 0; i < na; ++i)
         for (int j = 0; j < nb; ++j) {
+            if (wa[i] && wb[j]) continue;
             double d = fabs(wrap_pi(pa[i] - pb[j]));
             if (d < mg) mg = d;
         }
@@ -1135,7 +1168,7 @@ void orc_free(Ctx *X)
     for (int64_t i = 0; i < X->N; ++i) {
         NodeRes *R = &X->nodes[i];
         free(R->verts); free(R->arcs); free(R->loop_off); free(R->loop_arc); free(R->loop_dir);
-        free(R->mesh_w); free(R->fan); free(R->lv_off); free(R->lv_idx); free(R->lv_phi);
+        free(R->mesh_w); free(R->fan); free(R->lv_off); free(R->lv_idx); free(R->lv_phi); free(R->lv_whole);
         free(R->cont_b);
     }
     free(X->nodes); free(X->off); free(X->adj); free((void *)X->X); free((void *)X->R);
@@ -1168,6 +1201,14 @@ void orc_nodes(const Ctx *X, int32_t *cnt, double *margin)
         c[5] = R->status ? 0 : R->nmesh; c[6] = R->status ? 0 : R->nfan; c[7] = R->margin_kind;
         margin[i] = R->margin;
     }
+}
+
+/* per node: the smallest margin of each kind MK_* = 1..8 (double x 8; 1e300
+ * where a kind did not occur) */
+void orc_node_margins(const Ctx *X, double *out)
+{
+    for (int64_t i = 0; i < X->N; ++i)
+        for (int kd = 1; kd < MK_N; ++kd) out[8 * i + kd - 1] = X->nodes[i].kmargin[kd];
 }
 
 /* meta-mesh vertices, concatenated in node order: name, local position,

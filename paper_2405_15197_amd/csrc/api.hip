@@ -39,11 +39,13 @@ struct lm_plan {
     int32_t *redo = nullptr;
     int32_t *redo_cnt = nullptr;
     unsigned long long *codec_ctr = nullptr;  // fallback counter of lm_arc_encode
+    void *grad_mem = nullptr;                 // adjoint scratch (loss terms and partials per node / half-edge)
     int schedule = LM_SCHEDULE_WAVE;          // FP32 node pass of lm_count / lm_forward
     void *thread_scratch = nullptr;           // per-node scratch of the thread-centric pass
     int k;          // resolution of the last count (0: none)
     float kappa_max;// FP32 -> FP64 hand-over threshold
     lm_totals last; // totals of the last lm_count
+    bool last_on_host = false;  // `last` describes the current mesh (lm_count ran last)
     bool profiling;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
     std::vector<hipEvent_t> pool;
@@ -134,8 +136,10 @@ size_t carve(lm::Work &w, char *base, int64_t N, int64_t S)
     w.queue = (int32_t *)take(sizeof(int32_t) * (N + 1));
     w.cls_info = (int64_t *)take(sizeof(int64_t) * 8);
     w.work_ctr = (int32_t *)take(sizeof(int32_t) * 4);
-    w.loss_slots = (double *)take(sizeof(double) * 3 * lm::kLossSlots);
     w.node_k = nullptr;
+    w.loss_node = nullptr;
+    w.grad_node = nullptr;
+    w.grad_he = nullptr;
     return off;
 }
 
@@ -347,6 +351,7 @@ int lm_count(lm_plan *P, int k, lm_totals *totals)
     P->k = k;
     P->base_slot = 0;
     P->last = *totals;
+    P->last_on_host = true;
     return LM_OK;
 }
 
@@ -373,13 +378,43 @@ int lm_forward(lm_plan *P, int k, const lm_outputs *out)
     if (rc) return rc;
     P->k = k;
     P->base_slot = 0;
+    P->last_on_host = false;
     return fill_common(P, k, f, out, P->w);
 }
+
+namespace {
+
+// Scratch of lm_loss and lm_backward: per-node loss terms, per-node and
+// per-half-edge adjoint partials (allocated at the first use).
+int grad_alloc(lm_plan *P)
+{
+    if (P->grad_mem) return LM_OK;
+    const int64_t N = P->in.n_nodes, H = 2 * P->in.n_struts;
+    const size_t a = align_up(sizeof(double) * 3 * (N + 1)), b = align_up(sizeof(float) * 4 * (N + 1));
+    const size_t c = align_up(sizeof(float) * 4 * (H + 1));
+    HIPCHK(hipMalloc(&P->grad_mem, a + b + c));
+    char *m = (char *)P->grad_mem;
+    P->w.loss_node = (double *)m;
+    P->w.grad_node = (float *)(m + a);
+    P->w.grad_he = (float *)(m + a + b);
+    return LM_OK;
+}
+
+}  // namespace
 
 int lm_loss(lm_plan *P, const lm_outputs *out, const lm_loss_weights *w, double *d_terms, float *d_dl_dx)
 {
     if (!P || !out || !w || !d_terms || !d_dl_dx || !out->d_mesh_xyz || !out->d_tri) return LM_ERR_INVALID_ARG;
     if (P->k == 0) return LM_ERR_STATE;
+    // sizes known on the host (after lm_count): refuse small buffers before
+    // any launch; otherwise the kernels check the device totals and skip
+    // (lm_read_totals then reports LM_ERR_CAPACITY)
+    if (P->last_on_host &&
+        (out->cap_mesh_vertices < P->last.n_mesh_vertices || out->cap_triangles < P->last.n_triangles))
+        return LM_ERR_CAPACITY;
+    if (out->cap_mesh_vertices < 0 || out->cap_triangles < 0) return LM_ERR_INVALID_ARG;
+    int rc = grad_alloc(P);
+    if (rc) return rc;
     lm::FillOut f = to_fill(out);
     PhaseTimer t(P, PH_LOSS);
     HIPCHK(lm::launch_loss(P->in, P->w, f, make_float3(w->p0[0], w->p0[1], w->p0[2]), w->area, w->volume, w->sq_norm,
@@ -391,6 +426,8 @@ int lm_backward(lm_plan *P, const float *d_dl_dx, float *d_grad_xyz, float *d_gr
 {
     if (!P || !d_dl_dx || !d_grad_xyz || !d_grad_radius) return LM_ERR_INVALID_ARG;
     if (P->k == 0) return LM_ERR_STATE;
+    int rc = grad_alloc(P);
+    if (rc) return rc;
     PhaseTimer t(P, PH_BACKWARD);
     HIPCHK(lm::launch_backward(P->in, P->w, d_dl_dx, d_grad_xyz, d_grad_radius, P->st));
     return LM_OK;
@@ -641,6 +678,7 @@ int lm_retriangulate(lm_plan *P, int k, const lm_outputs *out)
         std::swap(P->w.rec_top, P->alt_rec_top);
         P->base_slot = 1;
     }
+    P->last_on_host = false;
     return LM_OK;
 }
 
@@ -753,7 +791,7 @@ void lm_plan_destroy(lm_plan *P)
     for (auto e : P->pool) (void)hipEventDestroy(e);
     if (P->w.rec) (void)hipFree(P->w.rec);
     for (void *p : {(void *)P->sk_mark, (void *)P->sk_lists, (void *)P->sk_cnt, (void *)P->sk_info,
-                    (void *)P->sk_struts, (void *)P->sk_slots, (void *)P->alt_rec, P->alt_index_mem, (void *)P->codec_ctr, P->thread_scratch})
+                    (void *)P->sk_struts, (void *)P->sk_slots, (void *)P->alt_rec, P->alt_index_mem, (void *)P->codec_ctr, P->thread_scratch, P->grad_mem})
         if (p) (void)hipFree(p);
     (void)hipFree(P->ws);
     delete P;

@@ -6,11 +6,17 @@
 
 namespace lm {
 
-// Per-node limits of this library.  A node beyond them is flagged (its status
-// bit is set) and emits nothing.
-constexpr int kVmax = 16;       // incident struts per node
-constexpr int kAcap = 64;       // arcs per node
-constexpr int kVcap = 64;       // meta-vertices per node
+// Per-node limits of this library.  Nodes of up to kVmax incident struts are
+// meshed by one wave (or a part of one); nodes of kVmax + 1 .. kVmaxBig by a
+// group of kBigWaves waves sharing the node's LDS.  A node beyond the limits
+// is flagged (its status bit is set) and emits nothing.
+constexpr int kVmax = 16;       // incident struts per node, one-wave classes
+constexpr int kAcap = 64;       // arcs per node, one-wave classes
+constexpr int kVcap = 64;       // meta-vertices per node, one-wave classes
+constexpr int kVmaxBig = 48;    // incident struts per node, multi-wave class
+constexpr int kAcapBig = 192;   // arcs per node, multi-wave class
+constexpr int kVcapBig = 128;   // meta-vertices per node, multi-wave class
+constexpr int kBigWaves = 4;    // waves per node of the multi-wave class
 constexpr int kPieces = 4;      // kept arcs per conic
 
 constexpr float kTwoPi = 6.28318530717958647692f;
@@ -64,8 +70,11 @@ enum DevFlag : int {
 //   loop table          bytes: loop start of each strut label 1..v+1 (v+1
 //                       bytes), then for every loop entry in loop order its
 //                       arc | 0x80 if the arc runs along the loop (header
-//                       word 7 = v | entries << 8 | fp64 << 24, fp64
-//                       set when the node was meshed in FP64)
+//                       word 7 = v | entries << 8 | fp64 << 24 | wide << 25,
+//                       fp64 set when the node was meshed in FP64; wide: the
+//                       node has more than 127 arcs or 255 loop entries
+//                       possible (multi-wave class), and the table holds
+//                       16-bit entries, the direction in bit 15)
 //   loops               from a multiple of 4 words: for each incident strut
 //                       in label order, its end loop as int2 (node-local mesh
 //                       vertex, phi bits), in loop order
@@ -82,6 +91,13 @@ __host__ __device__ inline int64_t rec_loop_word(int V, int E, int H, int table_
 {
     return (rec_table_word(V, E, H) + (table_bytes + 3) / 4 + 3) & ~(int64_t)3;
 }
+// bytes of the loop table of a node of valence v with nent loop entries
+__host__ __device__ inline int rec_table_bytes(int v, int nent, bool wide)
+{
+    return (wide ? 2 : 1) * (v + 1 + nent);
+}
+constexpr uint32_t kRecFp64 = 1u << 24;  // header word 7: meshed in FP64
+constexpr uint32_t kRecWide = 1u << 25;  // header word 7: 16-bit loop table
 
 struct Inputs {
     int64_t n_nodes, n_struts;
@@ -113,16 +129,15 @@ struct Work {
     int64_t *totals;        // [16] device copy of totals
     int32_t *fb_list;       // [N] nodes for the FP64 pass
     int32_t *queue;         // [N] node ids grouped by valence class
-    int64_t *cls_info;      // [8] nodes per class (0..2), queue start per class (4..6)
+    int64_t *cls_info;      // [8] nodes per class (0..3), queue start per class (4..7)
     int32_t *work_ctr;      // [4] per-class work counters of the node kernel
     const int16_t *node_k;  // [N] per-node resolution (batched parts) or null
-    double *loss_slots;     // [kLossSlots][3] partial loss terms
+    // adjoint scratch (set before lm_loss / lm_backward run)
+    double *loss_node;      // [N][3] loss terms per node
+    float *grad_node;       // [N][4] adjoint of each node's own x, y, z, radius
+    float *grad_he;         // [2S][4] adjoint of the far node's inputs, per half-edge
 };
-constexpr int kLossSlots = 256;
 
-// Valence classes of the node kernel: v <= 4, 5..8, otherwise.
-// (the batched entry point may lower the two limits: 4 and 8 are the class
-// capacities)
 // Workgroups are dispatched to the 8 XCDs (each with its own L2) in turn:
 // block b runs on XCD b % 8.  This maps the blocks of one XCD to one
 // contiguous range of [0, nb), so that each L2 sees whole output lines.
@@ -133,11 +148,15 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t nb)
     return x * q + (x < r ? x : r) + b / kXcds;
 }
 
+// Valence classes of the node kernel: v <= 4 (four nodes per wave), 5..8
+// (two per wave), 9..kVmax (one per wave), otherwise (kBigWaves waves per
+// node).  The batched entry point may lower the first two limits (4 and 8
+// are the class capacities).
 __host__ __device__ inline int valence_class(int64_t v, int t16 = 4, int t32 = 8)
 {
-    return v <= t16 ? 0 : (v <= t32 ? 1 : 2);
+    return v <= t16 ? 0 : (v <= t32 ? 1 : (v <= kVmax ? 2 : 3));
 }
-constexpr int kClasses = 3;
+constexpr int kClasses = 4;
 
 struct FillOut {
     float *mesh_xyz;

@@ -18,8 +18,6 @@ __device__ inline float fbits(uint32_t u) { return __uint_as_float(u); }
 
 __global__ void __launch_bounds__(64) k_expand(XParams P)
 {
-    __shared__ int s_mbase[kAcap];
-    __shared__ int s_fbase[kAcap];
     __shared__ uint4 s_arc[kAcap][kRecArcFields / 4];  // the node's arcs, staged once
     const Work &W = P.w;
     const FillOut &O = P.o;
@@ -48,15 +46,16 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
     const uint32_t *RH = RA + kRecArcFields * E;
 
     // arcs: whole 16-byte groups into LDS (the arc block starts on a 16-byte
-    // boundary); every later read of an arc field is an LDS read
-    for (int x = lane; x < (kRecArcFields / 4) * E; x += 64)
-        s_arc[x / (kRecArcFields / 4)][x % (kRecArcFields / 4)] = ((const uint4 *)RA)[x];
+    // boundary); every later read of an arc field is an LDS read.  The arcs
+    // of a node of the multi-wave class (more than kAcap) stay in the record.
+    const bool staged = E <= kAcap;
+    if (staged)
+        for (int x = lane; x < (kRecArcFields / 4) * E; x += 64)
+            s_arc[x / (kRecArcFields / 4)][x % (kRecArcFields / 4)] = ((const uint4 *)RA)[x];
     __syncthreads();
-    auto aw = [&](int j, int f) -> uint32_t { return ((const uint32_t *)s_arc[j])[f]; };
-    for (int j = lane; j < E; j += 64) {
-        s_mbase[j] = (int)aw(j, 14);
-        s_fbase[j] = (int)aw(j, 15);
-    }
+    auto aw = [&](int j, int f) -> uint32_t {
+        return staged ? ((const uint32_t *)s_arc[j])[f] : RA[kRecArcFields * j + f];
+    };
     if (O.vert_name) {
         for (int i = lane; i < V; i += 64) {
             O.vert_name[voff + i] = RV[4 * i];
@@ -98,12 +97,12 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
             int lo = 0, hi = E - 1;  // last arc with mbase <= i
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (s_mbase[mid] <= i) lo = mid;
+                if ((int)aw(mid, 14) <= i) lo = mid;
                 else hi = mid - 1;
             }
             const int nseg = (int)(aw(lo, 13) & 0xffffu);
             const bool fwd = (aw(lo, 11) >> 17) & 1u;
-            const int jc = i - s_mbase[lo];
+            const int jc = i - (int)aw(lo, 14);
             w = interior(lo, fwd ? jc + 1 : nseg - 1 - jc);
         } else {
             const int c = i - wsum;
@@ -123,7 +122,7 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
         int lo = 0, hi = E - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (s_fbase[mid] <= i) lo = mid;
+            if ((int)aw(mid, 15) <= i) lo = mid;
             else hi = mid - 1;
         }
         const int j = lo;
@@ -131,8 +130,8 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
         const bool fwd = (u0 >> 17) & 1u, lower = (u0 >> 18) & 1u;
         const int nseg = (int)(u2 & 0xffffu), contour = (int)(u2 >> 16);
         const int vs = (int)(u1 & 0xffffu), ve = (int)(u1 >> 16);
-        const int mbase = s_mbase[j];
-        const int s = i - s_fbase[j];
+        const int mbase = (int)aw(j, 14);
+        const int s = i - (int)aw(j, 15);
         const int i0 = fwd ? s : nseg - s, i1 = fwd ? s + 1 : nseg - s - 1;
         const int lo_i = i0 < i1 ? i0 : i1, hi_i = i0 < i1 ? i1 : i0;
         // interior point ii sits at mbase + (fwd ? ii - 1 : nseg - 1 - ii)

@@ -92,6 +92,7 @@ struct LParams {
     Work w;
     const int32_t *tri;
     const float *xyz;
+    int64_t cap_mesh, cap_tri;  // sizes of tri / xyz (and dldx) in rows
     float3 p0;
     float w_area, w_vol, w_sq;
     float *dldx;
@@ -108,9 +109,24 @@ __global__ void __launch_bounds__(64) k_loss_node(LParams P)
     const int lane = threadIdx.x;
     if (n >= N) return;
     const int64_t Np1 = N + 1;
+    double *nt = W.loss_node + 3 * n;  // this node's share of the loss terms
+    // the mesh of the last pass must be complete and fit the buffers given
+    // here (tri, xyz and dldx): otherwise nothing is read or written
+    const int64_t m_all = W.node_off[(int64_t)NC_MESH * Np1 + N];
+    const int64_t t_all = W.band_off[S] + W.node_off[(int64_t)NC_FAN * Np1 + N];
+    if ((W.flags[0] & (DF_CAPACITY | DF_RECCAP)) || m_all > P.cap_mesh || t_all > P.cap_tri) {
+        if (lane == 0) {
+            atomicOr(&W.flags[0], DF_CAPACITY);
+            nt[0] = nt[1] = nt[2] = 0.0;
+        }
+        return;
+    }
     const int64_t m0 = W.node_off[(int64_t)NC_MESH * Np1 + n], m1 = W.node_off[(int64_t)NC_MESH * Np1 + n + 1];
     const int M = (int)(m1 - m0);
-    if (M == 0) return;
+    if (M == 0) {
+        if (lane == 0) nt[0] = nt[1] = nt[2] = 0.0;
+        return;
+    }
     const bool lds = M <= kLossLds;
     for (int i = lane; i < (lds ? M : 0); i += 64) g[i][0] = g[i][1] = g[i][2] = 0.f;
     if (lane < 3) s_terms[lane] = 0.0;
@@ -190,24 +206,38 @@ __global__ void __launch_bounds__(64) k_loss_node(LParams P)
             atomicAdd(d + 2, 2.f * P.w_sq * x.z);
         }
     }
-    if (lane == 0) {  // partial sums spread over slots (same-address atomics serialise)
-        double *sl = W.loss_slots + 3 * (blockIdx.x & (kLossSlots - 1));
-        atomicAdd(&sl[0], area);
-        atomicAdd(&sl[1], vol);
-        atomicAdd(&sl[2], sq);
+    if (lane == 0) {  // the node's terms; summed in a fixed order by k_loss_reduce
+        nt[0] = area;
+        nt[1] = vol;
+        nt[2] = sq;
     }
 }
 
-// slots -> terms (and clears the slots)
-__global__ void k_loss_reduce(double *slots, double *terms)
+// per-node terms -> terms, in an order that does not depend on scheduling:
+// thread t sums nodes t, t + kBlock, ... in turn, then a fixed tree
+__global__ void __launch_bounds__(256) k_loss_reduce(int64_t N, const double *node_terms, double *terms)
 {
-    if (threadIdx.x >= 3) return;
-    double s = 0.0;
-    for (int i = 0; i < kLossSlots; ++i) {
-        s += slots[3 * i + threadIdx.x];
-        slots[3 * i + threadIdx.x] = 0.0;
+    __shared__ double s[3][kBlock];
+    const int t = threadIdx.x;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t n = t; n < N; n += kBlock) {
+        a += node_terms[3 * n];
+        b += node_terms[3 * n + 1];
+        c += node_terms[3 * n + 2];
     }
-    terms[threadIdx.x] = s;
+    s[0][t] = a;
+    s[1][t] = b;
+    s[2][t] = c;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            s[0][t] += s[0][t + h];
+            s[1][t] += s[1][t + h];
+            s[2][t] += s[2][t + h];
+        }
+        __syncthreads();
+    }
+    if (t < 3) terms[t] = s[t][0];
 }
 
 __global__ void k_zero_f(float *p, int64_t n)
@@ -232,6 +262,21 @@ struct BParams {
     float *grad_r;      // [N]
 };
 
+// The adjoint's per-node scratch in LDS, for nodes of up to VM struts, AC
+// arcs and VC vertices.
+template <int VM, int AC, int VC>
+struct BwdLds {
+    SL<float> S[VM + 1];
+    float lam_v[VC][3];
+    float lam_arc[AC][11];  // o, a, b, t1, t2
+    float lam_g[VM + 1][3], lam_h[VM + 1], lam_e[VM + 1][3];
+    // circle adjoints per strut: sigma, kappa, frame q, frame r
+    float lam_sig[VM + 1], lam_kap[VM + 1], lam_qf[VM + 1][3], lam_rf[VM + 1][3];
+    float lam_node[4];      // this node's x, y, z, radius
+    float own[VM][4];       // strut-table terms of this node's inputs, per strut
+    int s_mbase[AC];
+};
+
 // the 4 inputs (x, y, z, radius) of node `node` as dual seeds: direction k
 __device__ inline void seed(const float4 c4, int k, V3<Dual> &c, Dual &r)
 {
@@ -247,22 +292,33 @@ __device__ inline void crs(const float *a, const float *b, float *c)
     c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-__global__ void __launch_bounds__(64) k_backward(BParams P)
+// The adjoint of node n's mesh vertices, by one wave.  Writes the node's own
+// input adjoint to grad_node[n] and, for every incident strut, the part that
+// belongs to the far node's inputs to grad_he at the strut's half-edge here;
+// k_grad_gather adds them up per node in a fixed order (no atomics between
+// nodes, so the gradient's bits do not depend on scheduling).
+template <int VM, int AC, int VC>
+__device__ void backward_node(const BParams &P, BwdLds<VM, AC, VC> &sm, const int64_t n)
 {
-    __shared__ SL<float> S[kVmax + 1];
-    __shared__ float lam_v[kVcap][3];
-    __shared__ float lam_arc[kAcap][11];  // o, a, b, t1, t2
-    __shared__ float lam_g[kVmax + 1][3], lam_h[kVmax + 1], lam_e[kVmax + 1][3];
-    // circle adjoints per strut: sigma, kappa, frame q, frame r
-    __shared__ float lam_sig[kVmax + 1], lam_kap[kVmax + 1], lam_qf[kVmax + 1][3], lam_rf[kVmax + 1][3];
-    __shared__ float lam_node[4];         // this node's x, y, z, radius
-    __shared__ int s_mbase[kAcap];
+    auto &S = sm.S;
+    auto &lam_v = sm.lam_v;
+    auto &lam_arc = sm.lam_arc;
+    auto &lam_g = sm.lam_g;
+    auto &lam_h = sm.lam_h;
+    auto &lam_e = sm.lam_e;
+    auto &lam_sig = sm.lam_sig;
+    auto &lam_kap = sm.lam_kap;
+    auto &lam_qf = sm.lam_qf;
+    auto &lam_rf = sm.lam_rf;
+    auto &lam_node = sm.lam_node;
+    auto &s_mbase = sm.s_mbase;
     const Work &W = P.w;
     const int64_t N = P.in.n_nodes;
-    const int64_t n = blockIdx.x;
     const int lane = threadIdx.x;
-    if (n >= N) return;
     const int64_t rb = W.node_rec[n];
+    // the forward pass or the loss skipped writes: no usable mesh (the
+    // gather then writes zeros)
+    if (W.flags[0] & (DF_CAPACITY | DF_RECCAP)) return;
     if (rb < 0) return;
     const uint32_t *R = W.rec + rb;
     const int V = (int)R[0], E = (int)R[1], NC = (int)R[2], ncirc = (int)R[3];
@@ -294,7 +350,7 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
         s.far = he.x;
         S[lane + 1] = s;
     }
-    for (int i = lane; i <= kVmax; i += 64) {
+    for (int i = lane; i <= VM; i += 64) {
         lam_g[i][0] = lam_g[i][1] = lam_g[i][2] = 0.f;
         lam_h[i] = 0.f;
         lam_e[i][0] = lam_e[i][1] = lam_e[i][2] = 0.f;
@@ -750,23 +806,75 @@ __global__ void __launch_bounds__(64) k_backward(BParams P)
                         lam_e[m][0] * s.ex.d + lam_e[m][1] * s.ey.d + lam_e[m][2] * s.ez.d + lam_sig[m] * s.sig.d +
                         lam_kap[m] * s.kap.d + lam_qf[m][0] * s.qx.d + lam_qf[m][1] * s.qy.d +
                         lam_qf[m][2] * s.qz.d + lam_rf[m][0] * s.rx.d + lam_rf[m][1] * s.ry.d + lam_rf[m][2] * s.rz.d;
-        if (dir < 4) atomicAdd(&lam_node[dir], g);
-        else if (dir < 7) atomicAdd(&P.grad_xyz[3 * (int64_t)far + dir - 4], g);
-        else atomicAdd(&P.grad_r[far], g);
+        if (dir < 4) sm.own[m - 1][dir] = g;
+        else W.grad_he[4 * (row + m - 1) + dir - 4] = g;
     }
     __syncthreads();
-    if (lane < 3) atomicAdd(&P.grad_xyz[3 * n + lane], lam_node[lane]);
-    if (lane == 3) atomicAdd(&P.grad_r[n], lam_node[3]);
+    if (lane < 4) {
+        float acc = lam_node[lane];
+        for (int m = 0; m < v; ++m) acc += sm.own[m][lane];
+        W.grad_node[4 * n + lane] = acc;
+    }
+}
+
+// nodes of up to kVmax struts, one block (wave) each
+__global__ void __launch_bounds__(64) k_backward(BParams P)
+{
+    __shared__ BwdLds<kVmax, kAcap, kVcap> sm;
+    const int64_t n = blockIdx.x;
+    if (n >= P.in.n_nodes) return;
+    if (P.w.row[n + 1] - P.w.row[n] > kVmax) return;  // k_backward_big
+    backward_node(P, sm, n);
+}
+
+// nodes of the multi-wave class (queue class 3), one wave each with the
+// larger capacities, a fixed grid looping over the class
+__global__ void __launch_bounds__(64) k_backward_big(BParams P)
+{
+    __shared__ BwdLds<kVmaxBig, kAcapBig, kVcapBig> sm;
+    const int64_t cnt = P.w.cls_info[3], base = P.w.cls_info[4 + 3];
+    for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+        backward_node(P, sm, P.w.queue[base + i]);
+        __syncthreads();
+    }
+}
+
+// gradient of node n = its own part + the parts its neighbours wrote for
+// it at the other half-edge of each incident strut, in adjacency order
+__global__ void k_grad_gather(BParams P)
+{
+    const Work &W = P.w;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= P.in.n_nodes) return;
+    float g[4] = {0.f, 0.f, 0.f, 0.f};
+    if (W.flags[0] & (DF_CAPACITY | DF_RECCAP)) {
+        P.grad_xyz[3 * n] = P.grad_xyz[3 * n + 1] = P.grad_xyz[3 * n + 2] = 0.f;
+        P.grad_r[n] = 0.f;
+        return;
+    }
+    if (W.node_rec[n] >= 0)
+        for (int d = 0; d < 4; ++d) g[d] = W.grad_node[4 * n + d];
+    for (int64_t h = W.row[n]; h < W.row[n + 1]; ++h) {
+        const int2 he = W.he[h];
+        if (W.node_rec[he.x] < 0) continue;
+        const int64_t h0 = W.strut_he[2 * (int64_t)he.y], h1 = W.strut_he[2 * (int64_t)he.y + 1];
+        const int64_t tw = h0 == h ? h1 : h0;
+        for (int d = 0; d < 4; ++d) g[d] += W.grad_he[4 * tw + d];
+    }
+    P.grad_xyz[3 * n] = g[0];
+    P.grad_xyz[3 * n + 1] = g[1];
+    P.grad_xyz[3 * n + 2] = g[2];
+    P.grad_r[n] = g[3];
 }
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+constexpr int64_t kBigGridBwd = 1024;  // blocks of k_backward_big
 
 }  // namespace
 
 hipError_t launch_loss(const Inputs &in, const Work &w, const FillOut &o, float3 p0, float w_area, float w_vol,
                        float w_sq, float *dldx, double *terms, hipStream_t st)
 {
-    k_zero_d<<<1, 256, 0, st>>>(w.loss_slots, 3 * kLossSlots);
     if (in.n_nodes == 0) {
         k_zero_d<<<1, 64, 0, st>>>(terms, 3);
         return hipGetLastError();
@@ -778,6 +886,8 @@ hipError_t launch_loss(const Inputs &in, const Work &w, const FillOut &o, float3
     P.w = w;
     P.tri = o.tri;
     P.xyz = o.mesh_xyz;
+    P.cap_mesh = o.cap_mesh;
+    P.cap_tri = o.cap_tri;
     P.p0 = p0;
     P.w_area = w_area;
     P.w_vol = w_vol;
@@ -785,7 +895,7 @@ hipError_t launch_loss(const Inputs &in, const Work &w, const FillOut &o, float3
     P.dldx = dldx;
     P.terms = terms;
     k_loss_node<<<(unsigned)in.n_nodes, 64, 0, st>>>(P);
-    k_loss_reduce<<<1, 64, 0, st>>>(w.loss_slots, terms);
+    k_loss_reduce<<<1, kBlock, 0, st>>>(in.n_nodes, w.loss_node, terms);
     return hipGetLastError();
 }
 
@@ -794,8 +904,6 @@ hipError_t launch_backward(const Inputs &in, const Work &w, const float *dldx, f
 {
     const int64_t N = in.n_nodes;
     if (N == 0) return hipSuccess;
-    k_zero_f<<<grid_for(3 * N), kBlock, 0, st>>>(grad_xyz, 3 * N);
-    k_zero_f<<<grid_for(N), kBlock, 0, st>>>(grad_r, N);
     BParams P;
     P.in = in;
     P.w = w;
@@ -803,6 +911,8 @@ hipError_t launch_backward(const Inputs &in, const Work &w, const float *dldx, f
     P.grad_xyz = grad_xyz;
     P.grad_r = grad_r;
     k_backward<<<(unsigned)N, 64, 0, st>>>(P);
+    k_backward_big<<<(unsigned)(N < kBigGridBwd ? N : kBigGridBwd), 64, 0, st>>>(P);
+    k_grad_gather<<<grid_for(N), kBlock, 0, st>>>(P);
     return hipGetLastError();
 }
 

@@ -34,6 +34,8 @@
 // (the three surfaces meeting there have nearly dependent normals, so FP32
 // rounding is amplified by the condition number kappa = |n1||n2||n3| /
 // |det(n1, n2, n3)|) or when an FP32 consistency check fails.
+#include <type_traits>
+
 #include "geom.h"
 
 namespace lm {
@@ -63,6 +65,10 @@ struct Cfg {
 using CfgV4 = Cfg<4, 16, 16, 16>;   // v <= 4: four nodes per wave
 using CfgV8 = Cfg<8, 32, 24, 32>;   // v <= 8: two nodes per wave
 using CfgV16 = Cfg<kVmax, kAcap, kVcap, 64>;
+// v = kVmax + 1 .. kVmaxBig: one node per block of kBigWaves waves, lanes of
+// all its waves over the node's conics and samples, the node's data in the
+// block's LDS (the paper's several warps per heavy workload, Sec. 4.3.3)
+using CfgBig = Cfg<kVmaxBig, kAcapBig, kVcapBig, 64 * kBigWaves>;
 
 template <typename T, typename C>
 struct Shared {
@@ -78,7 +84,7 @@ struct Shared {
     int loop_cnt[C::VM + 1];  // arcs per loop, then fill cursor
     int loop_first[C::VM + 1];
     int loop_full[C::VM + 1];
-    uint8_t loop_next[2 * C::AC];
+    uint16_t loop_next[2 * C::AC];
     int vdeg[C::VC];
     uint32_t clabel[C::AC];
     T hc[C::AC][3];           // hole centre (local) per contour
@@ -115,19 +121,80 @@ __device__ inline uint32_t tie_name(int p, int q, int r, int root)
     return vname3(t.x, t.y, t.z, root);
 }
 
-// exclusive scan over the W lanes of a node
+// exclusive scan over the W lanes of a node.  A group wider than a wave
+// (the whole block) combines the waves' totals through LDS; every lane of
+// the block must call it.
 template <int W>
 __device__ inline int group_excl_scan(int x, int *total)
 {
-    const int lane = threadIdx.x & (W - 1);
-    int inc = x;
+    if constexpr (W <= 64) {
+        const int lane = threadIdx.x & (W - 1);
+        int inc = x;
 #pragma unroll
-    for (int d = 1; d < W; d <<= 1) {
-        int y = __shfl_up(inc, d, W);
-        if (lane >= d) inc += y;
+        for (int d = 1; d < W; d <<= 1) {
+            int y = __shfl_up(inc, d, W);
+            if (lane >= d) inc += y;
+        }
+        *total = __shfl(inc, W - 1, W);
+        return inc - x;
+    } else {
+        __shared__ int s_part[W / 64];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        int inc = x;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            int y = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += y;
+        }
+        if (lane == 63) s_part[wv] = inc;
+        __syncthreads();
+        int before = 0, tot = 0;
+#pragma unroll
+        for (int i = 0; i < W / 64; ++i) {
+            const int pv = s_part[i];
+            if (i < wv) before += pv;
+            tot += pv;
+        }
+        __syncthreads();  // s_part is reused by the next call
+        *total = tot;
+        return before + inc - x;
     }
-    *total = __shfl(inc, W - 1, W);
-    return inc - x;
+}
+
+// x of the previous lane of the group (lane 0: carry) and of its last lane
+template <int W, typename T>
+__device__ inline void group_prev_last(T x, T carry, T &prev, T &last)
+{
+    const int lane = threadIdx.x & (W - 1);
+    if constexpr (W <= 64) {
+        prev = __shfl_up(x, 1, W);
+        if (lane == 0) prev = carry;
+        last = __shfl(x, W - 1, W);
+    } else {
+        __shared__ T s_x[W];
+        s_x[lane] = x;
+        __syncthreads();
+        prev = lane ? s_x[lane - 1] : carry;
+        last = s_x[W - 1];
+        __syncthreads();
+    }
+}
+
+// The node's status word as every lane of the group sees it at this point.
+// Within a wave the lanes read it together; a group of several waves reads
+// it between two barriers, so that no wave can already be setting bits of
+// the next phase while another still reads (all lanes take the same branch).
+template <int W, typename SH>
+__device__ inline int group_status(SH &sh)
+{
+    if constexpr (W <= 64) {
+        return sh.status;
+    } else {
+        __syncthreads();
+        const int s = sh.status;
+        __syncthreads();
+        return s;
+    }
 }
 
 // f(i) for i = lo + lane, lo + lane + W, ... up to hi (inclusive; hi is at
@@ -491,6 +558,9 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
 {
     constexpr int WL = CF::W;
     constexpr bool F32 = sizeof(T) == 4;
+    // arc indices above 127 or loop positions above 255 need 16-bit entries
+    // in the record's loop table
+    constexpr bool WIDE = CF::AC > 127;
     const T tp = Cst<T>::two_pi;
     const int lane = threadIdx.x & (WL - 1);
     const Work &W = P.w;
@@ -498,7 +568,7 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
     (void)tp;
     (void)cen;
     (void)k;
-    if (sh.status) goto finish;
+    if (group_status<WL>(sh)) goto finish;
 
     // ---- mesh-vertex layout, hole centres, loop phi check -------------------
     {
@@ -579,7 +649,7 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
             sh.hc[c][2] = dir.z * rho;
         }
         __syncthreads();
-        if (sh.status) goto finish;
+        if (group_status<WL>(sh)) goto finish;
         // strut end loops must be graphs over phi: every step (mod 2 pi)
         // positive and exactly one descent, i.e. one turn.  Lanes run over
         // all loop samples of the node and store them in the node record.
@@ -613,7 +683,8 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
             const int off = sh.entry_off[sh.loop_base[v + 1]];
             // record space: bump allocation in the node's region
             const int64_t words =
-                rec_loop_word(V, E, NC, v + 1 + sh.loop_base[v + 1]) + (((int64_t)2 * off + 3) & ~(int64_t)3);
+                rec_loop_word(V, E, NC, rec_table_bytes(v, sh.loop_base[v + 1], WIDE)) +
+                (((int64_t)2 * off + 3) & ~(int64_t)3);
             const int g = (int)(n & (kRecRegions - 1));
             const int64_t region = W.rec_words / kRecRegions;
             const unsigned long long old = atomicAdd(&W.rec_top[g], (unsigned long long)words);
@@ -632,7 +703,8 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
         {
             const int nent = sh.loop_base[v + 1];
             const int ns_tot = sh.entry_off[nent];
-            int2 *rl = sh.rec >= 0 ? (int2 *)(W.rec + sh.rec + rec_loop_word(V, E, NC, v + 1 + sh.loop_base[v + 1]))
+            int2 *rl = sh.rec >= 0 ? (int2 *)(W.rec + sh.rec +
+                                              rec_loop_word(V, E, NC, rec_table_bytes(v, nent, WIDE)))
                                    : nullptr;
             // phi key and local mesh index of sample j of loop entry e
             auto sample = [&](int e, int j, int &li) -> T {
@@ -674,9 +746,9 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
                     nloop = sh.loop_len[m];
                     ph = sample(e, sidx - sh.entry_off[e], li);
                 }
-                T prev = __shfl_up(ph, 1, WL);
-                if (lane == 0) prev = carry;
-                carry = __shfl(ph, WL - 1, WL);
+                T prev, last;
+                group_prev_last<WL>(ph, carry, prev, last);
+                carry = last;
                 if (act) {
                     if (idx == 0) {
                         sh.ph_first[m] = ph;
@@ -735,7 +807,7 @@ finish:
         const int Msum = sh.wsum + NC, Fsum = sh.fsum;
         const int64_t rb = sh.rec;
         const int nent = sh.loop_base[v + 1];
-        const int64_t lw = rec_loop_word(V, E, NC, v + 1 + nent);
+        const int64_t lw = rec_loop_word(V, E, NC, rec_table_bytes(v, nent, WIDE));
         if (lane == 0) {
             W.node_cnt[NC_VERT * N + n] = V;
             W.node_cnt[NC_ARC * N + n] = E;
@@ -759,7 +831,7 @@ finish:
             R[4] = (uint32_t)sh.wsum;
             R[5] = (uint32_t)Msum;
             R[6] = (uint32_t)Fsum;
-            R[7] = (uint32_t)v | ((uint32_t)nent << 8) | (F32 ? 0u : 1u << 24);
+            R[7] = (uint32_t)v | ((uint32_t)nent << 8) | (F32 ? 0u : kRecFp64) | (WIDE ? kRecWide : 0u);
         }
         // vertices and arcs as whole 16-byte groups (the record and both
         // blocks start on 16-byte boundaries)
@@ -790,12 +862,14 @@ finish:
             RH[3 * c + 2] = __float_as_uint((float)sh.hc[c][2]);
         }
         // loop table (for re-subdivision at another resolution)
-        uint8_t *RT = (uint8_t *)(R + rec_table_word(V, E, NC));
-        over_lanes<WL, CF::VM>(lane, 0, v, [&](int l) { RT[l] = (uint8_t)sh.loop_base[l + 1]; });
+        using TabT = typename std::conditional<WIDE, uint16_t, uint8_t>::type;
+        constexpr uint32_t kFwd = WIDE ? 0x8000u : 0x80u;
+        TabT *RT = (TabT *)(R + rec_table_word(V, E, NC));
+        over_lanes<WL, CF::VM>(lane, 0, v, [&](int l) { RT[l] = (TabT)sh.loop_base[l + 1]; });
         for (int e = lane; e < nent; e += WL) {
             const int m = sh.entry_m[e];
             const int pp = sh.loop_base[m] + sh.loop_ord[e];
-            RT[v + 1 + e] = (uint8_t)(sh.loop_arc[pp] | (sh.loop_dir[pp] > 0 ? 0x80 : 0));
+            RT[v + 1 + e] = (TabT)(sh.loop_arc[pp] | (sh.loop_dir[pp] > 0 ? kFwd : 0u));
         }
     }
 }
@@ -856,7 +930,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
     });
     if (F32 && lane == 0 && !(P.kappa_max > 0.f)) atomicOr(&sh.status, NS_PREC);  // all FP64
     __syncthreads();
-    if (sh.status) goto tail;
+    if (group_status<WL>(sh)) goto tail;
 
     // ---- conics, trimming, arcs and owned vertices ------------------------
     {
@@ -1028,7 +1102,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
             __syncthreads();
         }
     }
-    if (sh.status) goto tail;
+    if (group_status<WL>(sh)) goto tail;
 
     // ---- arc ends -> vertex indices, vertex degrees, segment counts -------
     {
@@ -1059,7 +1133,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
         for (int i = lane; i < V; i += WL)
             if ((sh.vname[i] & 0xff00u) != 0xff00u && sh.vdeg[i] != 3) atomicOr(&sh.status, NS_TOPOLOGY);
         __syncthreads();
-        if (sh.status) goto tail;
+        if (group_status<WL>(sh)) goto tail;
     }
 
     // ---- end loops per strut ----------------------------------------------
@@ -1143,7 +1217,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
                 if (s2 < sn || (s2 == sn && q2 < pp)) first = false;
             }
             if (hits != 1) atomicOr(&sh.status, NS_LOOP);
-            sh.loop_next[pp] = (uint8_t)(nxt < 0 ? pp : nxt);
+            sh.loop_next[pp] = (uint16_t)(nxt < 0 ? pp : nxt);
             if (first) sh.loop_first[m] = pp;
         }
         over_lanes<WL, CF::VM>(lane, 1, v, [&](int l) {
@@ -1151,7 +1225,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
             if (c == 0 || (sh.loop_full[l] && c != 1)) atomicOr(&sh.status, NS_LOOP);
         });
         __syncthreads();
-        if (sh.status) goto tail;
+        if (group_status<WL>(sh)) goto tail;
         // position of each arc in its loop; the first arc also checks that
         // the successor chain closes after exactly the loop's arc count
         for (int pp = lane; pp < tot; pp += WL) {
@@ -1178,7 +1252,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
         }
         if (tot > 2 * CF::AC && lane == 0) atomicOr(&sh.status, NS_CAPACITY);
         __syncthreads();
-        if (sh.status) goto tail;
+        if (group_status<WL>(sh)) goto tail;
     }
 
     // ---- hole contours ------------------------------------------------------
@@ -1229,7 +1303,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
         __syncthreads();
         if (lane == 0 && sh.n_vert - sh.n_arc + sh.n_contour != 2 - v) atomicOr(&sh.status, NS_TOPOLOGY);
         __syncthreads();
-        if (sh.status) goto tail;
+        if (group_status<WL>(sh)) goto tail;
     }
 
 tail:
@@ -1405,12 +1479,41 @@ __global__ void __launch_bounds__(64) k_node32(Params P, int cls)
     }
 }
 
+// The multi-wave class: one node per block of kBigWaves waves, items from the
+// class's work counter as above.  Re-subdivision does not read these nodes'
+// records: they are queued for a full solve (MODE 1), which MODE 2 runs.
+template <int MODE>
+__global__ void __launch_bounds__(64 * kBigWaves) k_node32_big(Params P)
+{
+    constexpr int cls = 3;
+    __shared__ Shared<float, CfgBig> sh;
+    __shared__ int s_item;
+    const int64_t cnt = MODE == kModeRedo ? (int64_t)P.redo_cnt[cls] : P.w.cls_info[cls];
+    const int64_t base = P.w.cls_info[4 + cls];
+    const int32_t *list = MODE == kModeRedo ? P.redo : P.w.queue;
+    int32_t *ctr = MODE == kModeRedo ? P.redo_ctr : P.w.work_ctr;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&ctr[cls], 1);
+        __syncthreads();
+        const int64_t item = s_item;
+        __syncthreads();
+        if (item >= cnt) break;
+        const int64_t node = list[base + item];
+        if (MODE == kModeRetri) {
+            if (threadIdx.x == 0) P.redo[base + atomicAdd(&P.redo_cnt[cls], 1)] = (int32_t)node;
+        } else {
+            node_body<float, CfgBig>(P, sh, node);
+        }
+        __syncthreads();
+    }
+}
+
 // Thread-centric ablation: every lane meshes a node of its own (64 nodes per
 // wave in node id order, no valence classes, the full capacities), with the
 // per-node scratch that the kernel above keeps in LDS in global memory —
 // the design the paper compares its warp-centric one against.  Same code,
 // one lane per node: the results are those of the wave-centric pass.
-using CfgT1 = Cfg<kVmax, kAcap, kVcap, 1>;
+using CfgT1 = Cfg<kVmaxBig, kAcapBig, kVcapBig, 1>;
 __global__ void __launch_bounds__(64) k_node32_thread(Params P, Shared<float, CfgT1> *scratch)
 {
     const int64_t N = P.in.n_nodes;
@@ -1420,25 +1523,32 @@ __global__ void __launch_bounds__(64) k_node32_thread(Params P, Shared<float, Cf
 }
 
 // FP64: the nodes the FP32 pass handed over, looped over by a fixed grid
-// (also after a re-subdivision: these nodes are solved in full)
-__global__ void __launch_bounds__(64) k_node64(Params P)
+// (also after a re-subdivision: these nodes are solved in full).  One
+// instantiation takes the nodes of up to kVmax struts (a wave per node), the
+// other the multi-wave class (a block of kBigWaves waves per node).
+template <typename C>
+__global__ void __launch_bounds__(C::W) k_node64(Params P)
 {
-    __shared__ Shared<double, CfgV16> sh;
+    __shared__ Shared<double, C> sh;
+    constexpr bool big = C::VM > kVmax;
     const int cnt = P.w.flags[2];
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
         const int64_t node = P.w.fb_list[i];
-        node_body<double, CfgV16>(P, sh, node);
+        const bool is_big = P.w.row[node + 1] - P.w.row[node] > kVmax;
+        if (is_big == big) node_body<double, C>(P, sh, node);
         __syncthreads();
     }
 }
 
 constexpr unsigned kFp64Grid = 2048;
+constexpr unsigned kFp64BigGrid = 512;
+constexpr int64_t kBigGrid = 2048;  // blocks of a multi-wave class launch
 constexpr int64_t kNodeGrid = 256 * 32;  // waves per class launch
 constexpr int64_t kRedoGrid = 512;       // waves per class launch over a redo list
 
 }  // namespace
 
-constexpr int64_t kThreadGrid = 4096;  // blocks of the thread-centric pass
+constexpr int64_t kThreadGrid = 2048;  // blocks of the thread-centric pass
 
 size_t node_thread_scratch_bytes() { return sizeof(Shared<float, CfgT1>) * (size_t)kThreadGrid * 64; }
 
@@ -1477,9 +1587,11 @@ hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, 
     P.redo_cnt = redo_cnt;
     P.redo_ctr = redo_cnt ? redo_cnt + 4 : nullptr;
     if (fp64) {
-        k_node64<<<kFp64Grid, 64, 0, st>>>(P);
+        k_node64<CfgV16><<<kFp64Grid, 64, 0, st>>>(P);
+        k_node64<CfgBig><<<kFp64BigGrid, CfgBig::W, 0, st>>>(P);
         return hipGetLastError();
     }
+    const unsigned big_grid = (unsigned)(in.n_nodes < kBigGrid ? in.n_nodes : kBigGrid);
     // persistent grids: enough waves to fill the chip, never more than items
     auto grid = [&](int npw, int64_t cap) {
         int64_t items = (in.n_nodes + npw - 1) / npw;
@@ -1490,14 +1602,17 @@ hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, 
         k_node32<CfgV4, kModeRetri><<<grid(4, kNodeGrid), 64, 0, st>>>(P, 0);
         k_node32<CfgV8, kModeRetri><<<grid(2, kNodeGrid), 64, 0, st>>>(P, 1);
         k_node32<CfgV16, kModeRetri><<<grid(1, kNodeGrid), 64, 0, st>>>(P, 2);
+        k_node32_big<kModeRetri><<<big_grid, CfgBig::W, 0, st>>>(P);
         // the redo lists are short unless most nodes needed FP64 at the source
         k_node32<CfgV4, kModeRedo><<<grid(4, kRedoGrid), 64, 0, st>>>(P, 0);
         k_node32<CfgV8, kModeRedo><<<grid(2, kRedoGrid), 64, 0, st>>>(P, 1);
         k_node32<CfgV16, kModeRedo><<<grid(1, kRedoGrid), 64, 0, st>>>(P, 2);
+        k_node32_big<kModeRedo><<<big_grid, CfgBig::W, 0, st>>>(P);
     } else {
         k_node32<CfgV4, kModeMesh><<<grid(4, kNodeGrid), 64, 0, st>>>(P, 0);
         k_node32<CfgV8, kModeMesh><<<grid(2, kNodeGrid), 64, 0, st>>>(P, 1);
         k_node32<CfgV16, kModeMesh><<<grid(1, kNodeGrid), 64, 0, st>>>(P, 2);
+        k_node32_big<kModeMesh><<<big_grid, CfgBig::W, 0, st>>>(P);
     }
     return hipGetLastError();
 }

@@ -159,10 +159,15 @@ __global__ void __launch_bounds__(64) k_sink_nodes(SinkParams P)
     const float4 c4 = W.node4[n];
     const int64_t ln = local_node(P, n);
     // arcs: whole 16-byte groups into LDS; every arc field is then read there
-    for (int x = lane; x < (kRecArcFields / 4) * E; x += 64)
-        s_arc[x / (kRecArcFields / 4)][x % (kRecArcFields / 4)] = ((const uint4 *)RA)[x];
+    // (the arcs of a node of the multi-wave class stay in the record)
+    const bool staged = E <= kAcap;
+    if (staged)
+        for (int x = lane; x < (kRecArcFields / 4) * E; x += 64)
+            s_arc[x / (kRecArcFields / 4)][x % (kRecArcFields / 4)] = ((const uint4 *)RA)[x];
     __syncthreads();
-    auto aw = [&](int j, int f) -> uint32_t { return ((const uint32_t *)s_arc[j])[f]; };
+    auto aw = [&](int j, int f) -> uint32_t {
+        return staged ? ((const uint32_t *)s_arc[j])[f] : RA[kRecArcFields * j + f];
+    };
     auto af = [&](int f, int j) { return __uint_as_float(aw(j, f)); };
     uint64_t hv = 0, sx = 0, sy = 0, sz = 0, ht = 0;
     for (int i = lane; i < M; i += 64) {

@@ -1,0 +1,143 @@
+"""Nodes of more than 16 struts: the multi-wave class (a block of several
+waves per node sharing its LDS, Sec. 4.3.3 "several warps for a heavy
+workload") against the FP64 oracle, through the C ABI.
+
+Random k-NN lattices (the batched workload's fourth family, k up to 20,
+symmetrised: valences up to about 40) have most of their nodes in that class.
+The comparison is the same element-by-element one as for the one-wave
+classes (tests/parity.py): status, counts, names, arcs, mesh vertices and
+triangles of every node whose oracle margins are above the comparison
+thresholds.
+"""
+
+import numpy as np
+import pytest
+
+import latgen
+import oracle
+from parity import above_margin, compare, gpu_result
+
+pytestmark = pytest.mark.gpu
+
+RAD = ("uniform", 0.04, 0.12)
+KNN = [
+    ("knn6_20_k16", lambda: latgen.knn(6, 20, radius=RAD, seed=620), 16),
+    ("knn8_16_k12", lambda: latgen.knn(8, 16, radius=RAD, seed=816), 12),
+    ("knn5_12_k9", lambda: latgen.knn(5, 12, radius=RAD, seed=512), 9),
+    ("knn7_18_k8", lambda: latgen.knn(7, 18, radius=RAD, seed=718), 8),
+    ("knn4_18_k32", lambda: latgen.knn(4, 18, radius=RAD, seed=418), 32),
+]
+
+
+def _line(msg):
+    print(msg, flush=True)
+
+
+def _valence(lat):
+    return np.bincount(np.concatenate([lat.strut_a, lat.strut_b]), minlength=lat.n_nodes)
+
+
+@pytest.mark.parametrize("name,make,k", KNN, ids=[c[0] for c in KNN])
+def test_knn_parity(name, make, k):
+    lat = make()
+    v = _valence(lat)
+    _line(f"knn {name}: {lat.n_nodes} nodes, {lat.n_struts} struts, valence <= {v.max()}, k={k}")
+    R = oracle.run(lat, k)
+    G = gpu_result(lat, k)
+    st = compare(lat, k, R=R, G=G)
+    stable_big = int((((R.status == 0) & above_margin(R, k)) & (v > 16)).sum())
+    _line(f"  {st}, stable nodes above 16 struts: {stable_big}")
+    assert stable_big > 0
+    # every node the oracle meshes is meshed (those below the margin too)
+    meshed = G["status"] == 0
+    assert (meshed[R.status == 0]).mean() >= 0.98
+    assert st["stable"] >= 0.9 * int((R.status == 0).sum())
+
+
+@pytest.mark.parametrize("nstrut", [17, 24, 33, 40, 48])
+def test_star_valence(nstrut):
+    """A centre node with nstrut thin struts in quasi-random directions (a
+    Fibonacci sphere, jittered): meshed by the multi-wave class, equal to
+    the oracle."""
+    i = np.arange(nstrut) + 0.5
+    phi = np.arccos(1 - 2 * i / nstrut)
+    th = np.pi * (1 + 5 ** 0.5) * i + 0.1 * np.sin(7 * i)
+    d = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
+    lat = latgen.star(d, radius=0.05)
+    st = compare(lat, 12, tau=1e-6)
+    _line(f"star {nstrut}: {st}")
+    assert st["stable"] == lat.n_nodes
+
+
+def test_valence_beyond_limit_is_flagged():
+    i = np.arange(60) + 0.5
+    phi = np.arccos(1 - 2 * i / 60)
+    th = np.pi * (1 + 5 ** 0.5) * i
+    d = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
+    lat = latgen.star(d, radius=0.01)
+    G = gpu_result(lat, 8, meta=False)
+    assert G["status"][0] & 32  # LM_NODE_VALENCE
+    assert (G["status"][1:] == 0).all()
+
+
+def test_knn_all_fp64():
+    """kappa_max = 0: every node, the multi-wave class included, meshed by the
+    FP64 pass; combinatorics equal to the oracle above margin 1e-8."""
+    lat = latgen.knn(5, 17, radius=RAD, seed=517)
+    st = compare(lat, 12, tau=1e-8, geom_tol=1e-6, kappa_max=0.0)
+    _line(f"  {st}")
+    assert st["fp64_nodes"] == lat.n_nodes
+
+
+def test_knn_retriangulate_equals_forward():
+    """Re-subdivision solves multi-wave nodes again (their records are not
+    re-read), so it gives the bits of lm_forward at the new k."""
+    import torch
+
+    from paper_2405_15197_amd import Mesher
+    from parity import result_np
+
+    lat = latgen.knn(6, 19, radius=RAD, seed=619)
+    M = Mesher(lat)
+    try:
+        M.run(16)
+        a = result_np(M.retriangulate(9))
+    finally:
+        M.close()
+    b = gpu_result(lat, 9)
+    torch.cuda.synchronize()
+    for key in ("status", "node_off", "strut_off", "vert_name", "vert_xyz", "arc_u32", "arc_f32", "tri", "mesh"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_knn_gradient_matches_oracle():
+    """The adjoint of high-valence nodes (their own kernel instantiation)
+    against the oracle's FP64 central differences, on every parameter of
+    the nodes above 16 struts of a small k-NN lattice."""
+    import torch
+
+    from paper_2405_15197_amd import Mesher
+
+    lat = latgen.knn(4, 17, radius=RAD, seed=417)
+    k = 12
+    R = oracle.run(lat, k)
+    v = _valence(lat)
+    nodes = np.nonzero((v > 16) & (R.status == 0) & (R.margin >= 1e-3))[0][:6]
+    assert len(nodes) > 0
+    params = [(int(n), c) for n in nodes for c in range(4)]
+    M = Mesher(lat)
+    try:
+        r = M.run(k, meta=False)
+        terms, dl = M.loss(r, (1.0, 0.0, 0.0))
+        gx, gr = M.backward(dl)
+        torch.cuda.synchronize()
+        gx, gr = gx.cpu().numpy().astype(np.float64), gr.cpu().numpy().astype(np.float64)
+    finally:
+        M.close()
+    G, ok = oracle.fd_gradient(lat, k, params, weights=(1.0, 0.0, 0.0))
+    g_gpu = np.array([gx[n, c] if c < 3 else gr[n] for n, c in params])
+    assert ok.mean() >= 0.75
+    sel = ok
+    tol = 1e-3 * np.abs(G[sel]) + 1e-4 * np.abs(G[sel]).max()
+    err = np.abs(g_gpu[sel] - G[sel])
+    assert (err <= tol).all(), (err / tol).max()

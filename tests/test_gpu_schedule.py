@@ -1,13 +1,14 @@
 """Thread-centric ablation of the FP32 node pass (one lane per node, scratch
-in global memory): the same code as the wave-centric pass, so identical
-outputs on every lattice, including nodes handed to FP64 and nodes beyond
-the valence limit."""
+in global memory): against the FP64 oracle element by element (the parity
+bar of tests/parity.py), and bit-identical to the wave-centric pass (the
+same node code), including nodes handed to FP64 and nodes of more than 16
+struts."""
 
 import numpy as np
 import pytest
 
 import latgen
-from parity import result_np
+from parity import compare, result_np
 
 pytestmark = pytest.mark.gpu
 
@@ -16,8 +17,9 @@ CASES = [
     ("cfg4_octet3", lambda: latgen.config(4, scale=3), 12),
     ("cubic_cones", lambda: latgen.cubic(5, radius=("uniform", 0.05, 0.15), jitter=0.04, seed=5), 8),
     ("cfg3_bcc5_unjittered", lambda: latgen.config(3, scale=5), 12),
-    # random k-NN: high valences, some beyond the limit, many invalid nodes
+    # random k-NN: valences above 16 (the multi-wave class), many invalid nodes
     ("knn5_12", lambda: latgen.knn(5, 12, radius=0.12, seed=3), 9),
+    ("knn5_18", lambda: latgen.knn(5, 18, radius=("uniform", 0.04, 0.12), seed=518), 12),
 ]
 
 
@@ -41,3 +43,5 @@ def test_thread_schedule_matches_wave(name, make, k):
     assert ta == tb
     for key in ("status", "node_off", "strut_off", "vert_name", "vert_xyz", "arc_u32", "arc_f32", "tri", "mesh"):
         assert np.array_equal(a[key], b[key]), key
+    st = compare(lat, k, G=b)
+    print(f"  thread schedule against the oracle: {st}", flush=True)
