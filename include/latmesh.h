@@ -46,6 +46,7 @@ extern "C" {
 #define LM_ERR_STATE (-6)          /* call out of order (e.g. fill before count) */
 #define LM_ERR_INTERNAL (-7)       /* the workspace could not be sized */
 #define LM_ERR_IO (-8)             /* a file could not be opened or written */
+#define LM_ERR_RADIUS_MISMATCH (-9) /* the end radii of a node's struts differ */
 
 /* ---- per-node status bits (node_status output) ------------------------- */
 #define LM_NODE_INVALID_STRUT 1u   /* |r_a - r_b| >= length, zero length or self loop */
@@ -55,7 +56,7 @@ extern "C" {
 #define LM_NODE_TOPOLOGY 8u        /* arc/vertex incidence or Euler check failed
                                       (e.g. an annular hole), or no hole-fan apex */
 #define LM_NODE_ISOLATED 16u       /* no incident strut */
-#define LM_NODE_VALENCE 32u        /* more incident struts than this library handles */
+#define LM_NODE_VALENCE 32u        /* more incident struts than this library handles (48) */
 #define LM_NODE_DUPLICATE 64u      /* two struts join the same pair of nodes */
 #define LM_NODE_CAPACITY 128u      /* per-node arc / vertex / piece capacity exceeded */
 
@@ -142,11 +143,68 @@ typedef struct lm_plan lm_plan;
  * per strut) and, at the first lm_count or lm_forward, the node-record space
  * (each meshed node's meta-mesh and strut end loops: about 1.2 kB per node
  * plus 8 bytes per loop sample, about 2.5 kB per node of the BCC lattice at
- * k = 16).  stream is a
- * hipStream_t (NULL = default stream).  On success *plan is set; on error it
- * is NULL.  Returns LM_ERR_BAD_LATTICE for out-of-range endpoints,
- * LM_ERR_UNSUPPORTED if n_nodes or n_struts is 2^31 or more. */
+ * k = 16); sink mode, batched parts, the adjoint and re-triangulation
+ * allocate their scratch at their first call (lm_plan_create_in allocates
+ * nothing).  stream is a hipStream_t (NULL = default stream).  On success
+ * *plan is set; on error it is NULL.  Returns LM_ERR_BAD_LATTICE for
+ * out-of-range endpoints, LM_ERR_UNSUPPORTED if n_nodes or n_struts is 2^31
+ * or more. */
 int lm_plan_create(lm_plan **plan, const lm_lattice *lat, void *stream);
+
+/* ---- caller-owned device memory ------------------------------------------
+ * A plan made by lm_plan_create_in takes all of its device memory from one
+ * caller buffer sized by lm_workspace_size and allocates no device memory
+ * afterwards: a call that needs more node-record space than was sized
+ * returns LM_ERR_CAPACITY (lm_count: with the needed bytes in
+ * n_record_bytes), one that needs a part not requested in opt->flags returns
+ * LM_ERR_UNSUPPORTED, writing nothing.  (lm_write_stl, which takes no plan,
+ * allocates its own staging buffers.) */
+#define LM_WS_SINK 1      /* lm_forward_sink and lm_batched */
+#define LM_WS_GRADIENT 2  /* lm_loss and lm_backward */
+#define LM_WS_RETRI 4     /* lm_retriangulate (a second node-record space) */
+
+typedef struct lm_options {
+    int32_t flags;        /* LM_WS_* */
+    int32_t k_max;        /* resolution the node-record space is sized for when record_bytes is 0 */
+    int64_t record_bytes; /* node-record space in bytes; 0: an estimate for the whole lattice at k_max
+                             (sink-mode chunks need only their nodes' share) */
+    int64_t max_parts;    /* most parts of one lm_batched call (with LM_WS_SINK) */
+} lm_options;
+
+/* Bytes of device memory a plan for n_nodes nodes and n_struts struts needs
+ * with options opt (NULL: no optional parts, records for k = 16).  Returns
+ * LM_ERR_INVALID_ARG for negative sizes, k_max outside 3..4096 or a negative
+ * record_bytes / max_parts, LM_ERR_UNSUPPORTED for 2^31 nodes or struts or
+ * more. */
+int lm_workspace_size(int64_t n_nodes, int64_t n_struts, const lm_options *opt, size_t *bytes);
+
+/* lm_plan_create with all device memory in d_workspace (device, 256-byte
+ * aligned, at least lm_workspace_size(lat->n_nodes, lat->n_struts, opt)
+ * bytes, owned by the caller and kept alive until lm_plan_destroy).
+ * LM_ERR_CAPACITY if workspace_bytes is too small. */
+int lm_plan_create_in(lm_plan **plan, const lm_lattice *lat, const lm_options *opt, void *d_workspace,
+                      size_t workspace_bytes, void *stream);
+
+/* Per-strut end radii (Sec. 4.1: every strut is the cone tangent to the
+ * nodal spheres of its ends, so all struts meeting at a node have the same
+ * radius there).  d_end_radius [n_struts][2] (device) holds the radius of
+ * strut i at strut_a[i] and at strut_b[i]; the node radius is the mean of
+ * its incident struts' end radii (taken in increasing strut id), written to
+ * d_radius [n_nodes] (device; 0 for a node without struts), and the plan is
+ * created for the lattice with those radii (lat->d_radius is not read; the
+ * plan keeps d_radius).  If at some node two end radii differ by more than
+ * rel_tol times their mean, no plan is made and LM_ERR_RADIUS_MISMATCH is
+ * returned (d_radius then holds the means); *n_mismatch (host, may be NULL)
+ * receives the number of such nodes.  Gradients with respect to end radii:
+ * lm_end_radius_gradient.  Synchronises the stream. */
+int lm_plan_create_end_radii(lm_plan **plan, const lm_lattice *lat, const float *d_end_radius, float rel_tol,
+                             float *d_radius, int64_t *n_mismatch, void *stream);
+
+/* Maps a gradient with respect to node radii (lm_backward's d_grad_radius)
+ * to the end radii of a plan made by lm_plan_create_end_radii: the end of
+ * strut i at node n gets d_grad_radius[n] / (struts at n), the derivative of
+ * the mean.  d_grad_end [n_struts][2] (device).  Asynchronous. */
+int lm_end_radius_gradient(lm_plan *plan, const float *d_grad_radius, float *d_grad_end);
 
 /* Redo the validation and adjacency build of lm_plan_create on the device,
  * asynchronously (the lattice arrays may have changed in place; the sizes
@@ -252,9 +310,15 @@ int lm_get_profile(lm_plan *plan, double *ms, int64_t *calls, int n);
  * vertex's key m(m(m(vid) ^ (bits(x) | bits(y) << 32)) ^ bits(z)) over its
  * FP32 position, m the SplitMix64 finaliser and G = 0x9E3779B97F4A7C15.
  * Sums are modulo 2^64, so totals over chunks are chunking independent.
- * Each chunk also meshes the higher-id neighbours of its nodes (for the
- * bands).  Synchronises the stream once per chunk; LM_ERR_CAPACITY if
- * n_chunks_cap < ceil(n_nodes / chunk_nodes).  The node records then hold
+ * Each chunk also meshes the higher-id neighbours of its nodes outside it
+ * (for the bands; with node ids numbered in spatial layers this halo is a
+ * thin shell).  The node pass hashes vertices and fans itself and keeps
+ * only the strut end loops for the bands.  Chunks run back to back without
+ * host synchronisation; the call synchronises once at the end (and runs a
+ * chunk again, with more record space, if its records did not fit; with a
+ * caller-owned workspace that is LM_ERR_CAPACITY instead).  LM_ERR_CAPACITY
+ * if n_chunks_cap < ceil(n_nodes / chunk_nodes); LM_ERR_UNSUPPORTED for a
+ * caller-owned workspace without LM_WS_SINK.  The node records then hold
  * the last chunk only: lm_fill and lm_backward need a new lm_count. */
 int lm_forward_sink(lm_plan *plan, int k, int64_t chunk_nodes, uint64_t *d_out, int64_t n_chunks_cap);
 
@@ -262,8 +326,10 @@ int lm_forward_sink(lm_plan *plan, int k, int64_t chunk_nodes, uint64_t *d_out, 
 
 /* Work mapping of lm_batched: nodes of valence <= v_four_per_wave (at most 4)
  * go four to a wave, up to v_two_per_wave (at most 8) two to a wave, the rest
- * one to a wave; group_nodes whole parts' worth of nodes (about) share one
- * node pass (0: 2^23). */
+ * up to 16 one to a wave, above that four waves to a node; group_nodes whole
+ * parts' worth of nodes (about) share one node pass (0: all parts in one
+ * pass when their records fit the device memory, else the fewest groups
+ * that fit). */
 typedef struct lm_tuning {
     int32_t v_four_per_wave;
     int32_t v_two_per_wave;
@@ -273,15 +339,18 @@ typedef struct lm_tuning {
 /* Many lattice parts in one plan: part p is the node range
  * [part_off[p], part_off[p+1]) of the plan's lattice (host arrays; part_off[0]
  * = 0, part_off[n_parts] = n_nodes; struts should join nodes of one part) and
- * is meshed at its own resolution part_k[p] (3..4096).  Parts are taken in
- * groups of about tune->group_nodes nodes; the nodes of a group, whatever
- * their part, are meshed by one persistent launch per valence class that
- * takes its work from a global queue.  Output per part, in sink mode:
+ * is meshed at its own resolution part_k[p] (3..4096).  The nodes of all
+ * parts (of a group, when tune->group_nodes splits them) are meshed by one
+ * persistent launch per valence class that takes its work from a global
+ * queue ordered by valence class, whatever the part; then one launch hashes
+ * the bands of all their struts.  Output per part, in sink mode:
  * d_out[p][LM_SINK_WORDS] (device; the words of lm_forward_sink, counted per
  * part: a band goes to the part of its lower node; vertex ids use node ids
  * local to the part, so a part's words equal those of lm_forward_sink on
- * the part alone).  tune may be NULL
- * (limits 4 and 8, groups of 2^23 nodes).  Synchronises the stream. */
+ * the part alone).  tune may be NULL (limits 4 and 8, automatic groups).
+ * Synchronises the stream once (again per group whose records did not fit
+ * and is run a second time).  With a caller-owned workspace: needs
+ * LM_WS_SINK and n_parts <= max_parts. */
 int lm_batched(lm_plan *plan, int64_t n_parts, const int64_t *part_off, const int32_t *part_k,
                const lm_tuning *tune, uint64_t *d_out);
 
@@ -298,7 +367,13 @@ typedef struct lm_loss_weights {
 /* Loss terms of the mesh written by the last lm_fill / lm_forward into
  * `out` (its d_mesh_xyz and d_tri): d_terms (device, 3 doubles) receives
  * Area, Vol and sum |v|^2 (unweighted), d_dl_dx (device, [cap_mesh_vertices]
- * [3] FP32) receives dL/dx for every mesh vertex (overwritten).
+ * [3] FP32) receives dL/dx for every mesh vertex (overwritten).  The terms
+ * are summed per node and then in a fixed order (bit-reproducible).
+ * Returns LM_ERR_CAPACITY, launching nothing, when the totals of the last
+ * lm_count exceed out's capacities; after lm_forward (totals on the device)
+ * the kernels check and write nothing instead, and lm_read_totals then
+ * returns LM_ERR_CAPACITY (also when that pass itself skipped writes).
+ * LM_ERR_UNSUPPORTED for a caller-owned workspace without LM_WS_GRADIENT.
  * Asynchronous.  Not a step of the method: a convenience loss for the
  * adjoint. */
 int lm_loss(lm_plan *plan, const lm_outputs *out, const lm_loss_weights *w, double *d_terms, float *d_dl_dx);
@@ -310,8 +385,13 @@ int lm_loss(lm_plan *plan, const lm_outputs *out, const lm_loss_weights *w, doub
  * vertex moves with the inputs as the method defines it: vertices as triple
  * ties, Eq. 12 interior points, Eq. 13 hole centres).  Writes
  * d_grad_xyz [n_nodes][3] and d_grad_radius [n_nodes] (device, FP32;
- * nodes with a nonzero status contribute nothing).  The plan must not have
- * been counted again since that pass.  Asynchronous. */
+ * nodes with a nonzero status contribute nothing).  Each node's adjoint and
+ * the parts it contributes to its neighbours are written per node and per
+ * strut end and summed in adjacency order, so the result is bit-reproducible.
+ * The plan must not have been counted again since that pass; if that pass
+ * (or lm_loss) skipped writes for lack of capacity, zeros are written.
+ * LM_ERR_UNSUPPORTED for a caller-owned workspace without LM_WS_GRADIENT.
+ * Asynchronous. */
 int lm_backward(lm_plan *plan, const float *d_dl_dx, float *d_grad_xyz, float *d_grad_radius);
 
 /* Release the plan and its workspace (synchronises its stream). */

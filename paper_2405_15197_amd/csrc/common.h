@@ -62,7 +62,7 @@ enum DevFlag : int {
 //                       wsum (first hole-centre mesh index), M (mesh
 //                       vertices), F (fan triangles), 0
 //   vertices [V][4]     name, x, y, z (node-local), one 16-byte group each
-//   arcs    [E][16]     o.xyz, a.xyz, b.xyz, t1, t2 (float bits),
+//   arcs    [E][16]     o.xyz, a.xyz, b.xyz, t1, dt = t2 - t1 (float bits),
 //                       p | q<<8 | whole<<16 | fwd<<17 | lower<<18,
 //                       vs | ve<<16, nseg | contour<<16, mbase, fbase: four
 //                       16-byte groups each
@@ -158,6 +158,98 @@ __host__ __device__ inline int valence_class(int64_t v, int t16 = 4, int t32 = 8
 }
 constexpr int kClasses = 4;
 
+// Eq. 12 point ii (of nseg segments) of an arc x(t) = o + a sin t + b cos t,
+// t in [t1, t1 + dt], node-local, from FP32 fields.  A whole conic (no end
+// points) is evaluated directly.  An arc is evaluated from its start point
+// x1 = x(t1) (its vertex) as x1 + a (sin t - sin t1) + b (cos t - cos t1),
+// the differences in product form, 2 cos(t1 + h) sin h and
+// -2 sin(t1 + h) sin h with h = (t - t1) / 2: a point of a long, thin seam
+// ellipse (|a| far above the node radius, the arc a short piece of it near
+// the node) then carries rounding relative to its distance from x1 rather
+// than to |a|.  The one formula of every pass that outputs mesh vertices
+// (stored mode and sink mode give the same bits).
+__device__ __forceinline__ float3 arc_point_f32(const float *o, const float *a, const float *b, const float *x1,
+                                                float t1, float dt, int ii, int nseg, bool whole)
+{
+    if (whole) {
+        const float t = t1 + dt * (float)ii / (float)nseg;
+        float s, c;
+        sincosf(t, &s, &c);
+        return make_float3(o[0] + a[0] * s + b[0] * c, o[1] + a[1] * s + b[1] * c, o[2] + a[2] * s + b[2] * c);
+    }
+    const float h = 0.5f * dt * (float)ii / (float)nseg;
+    float sh, ch, sm, cm;
+    sincosf(h, &sh, &ch);
+    sincosf(t1 + h, &sm, &cm);
+    const float ds = 2.f * cm * sh, dc = -2.f * sm * sh;
+    return make_float3(x1[0] + a[0] * ds + b[0] * dc, x1[1] + a[1] * ds + b[1] * dc, x1[2] + a[2] * ds + b[2] * dc);
+}
+
+// ---- sink mode: counts and order-independent hashes instead of a mesh ----
+// A mesh vertex is named vid = node << 21 | node-local index; a triangle's
+// key is mix(mix(mix(v0 + G) ^ v1) ^ v2) with its vids rotated so that the
+// smallest comes first (orientation kept), a vertex's key
+// mix(mix(mix(vid) ^ (bits(x) | bits(y) << 32)) ^ bits(z)) over its FP32
+// absolute position; mix is the SplitMix64 finaliser, G its increment.
+// Sums are modulo 2^64, so they do not depend on chunking or numbering.
+constexpr int kSinkSlots = 64;  // spread of the hash atomics
+constexpr int kSinkWords = 8;   // triangles, triangle keys, mesh vertices, vertex keys,
+                                // fixed-point x, y, z sums, nodes without a mesh
+
+__device__ inline uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ inline uint64_t vid_of(int64_t node, int local) { return ((uint64_t)node << 21) | (uint64_t)local; }
+
+__device__ inline uint64_t tri_key(uint64_t a, uint64_t b, uint64_t c)
+{
+    // rotate the smallest id first, keeping the cyclic order
+    if (b < a && b < c) {
+        const uint64_t t = a; a = b; b = c; c = t;
+    } else if (c < a && c < b) {
+        const uint64_t t = c; c = b; b = a; a = t;
+    }
+    return mix64(mix64(mix64(a + 0x9E3779B97F4A7C15ull) ^ b) ^ c);
+}
+
+__device__ inline uint64_t vert_key(uint64_t vid, float x, float y, float z)
+{
+    const uint64_t xy = (uint64_t)__float_as_uint(x) | ((uint64_t)__float_as_uint(y) << 32);
+    return mix64(mix64(mix64(vid) ^ xy) ^ (uint64_t)__float_as_uint(z));
+}
+
+// Where sink-mode words go: per chunk through slots (node_part null), or per
+// part (the part of a node from node_part, vertex ids local to the part).
+// The node pass counts vertices and fans of the nodes in [n0, n1) only (the
+// chunk's own nodes; its halo is meshed for the bands' loops).
+struct SinkOut {
+    int64_t n0, n1;
+    unsigned long long *slots;      // [kSinkSlots][kSinkWords]
+    const int32_t *node_part;       // [N] or null
+    unsigned long long *out_parts;  // [parts][kSinkSlots][kSinkWords]
+    const int64_t *part_base;       // first node of each part
+};
+
+__device__ inline int64_t sink_local_node(const SinkOut &S, int64_t n)
+{
+    return S.node_part ? n - S.part_base[S.node_part[n]] : n;
+}
+
+// adds v to word `word` of `part`'s output (chunk mode: part ignored),
+// spread over kSinkSlots slots by block
+__device__ inline void sink_add(const SinkOut &S, int32_t part, int word, uint64_t v)
+{
+    const int64_t slot = blockIdx.x & (kSinkSlots - 1);
+    if (S.node_part)
+        atomicAdd(&S.out_parts[((int64_t)part * kSinkSlots + slot) * kSinkWords + word], (unsigned long long)v);
+    else
+        atomicAdd(&S.slots[slot * kSinkWords + word], (unsigned long long)v);
+}
+
 struct FillOut {
     float *mesh_xyz;
     int32_t *tri;
@@ -172,6 +264,12 @@ struct FillOut {
 
 // launchers (return hipError_t)
 hipError_t launch_prepare(const Inputs &in, const Work &w, hipStream_t st);
+// node radii from per-strut end radii [S][2] (mean per node, mismatches
+// beyond rel_tol counted), and the end-radius gradient [S][2] of a node-radius
+// gradient; both need the adjacency of launch_prepare
+hipError_t launch_end_radii(const Inputs &in, const Work &w, const float *end_r, float rel_tol, float *radius,
+                            int32_t *mismatch, hipStream_t st);
+hipError_t launch_end_grad(const Inputs &in, const Work &w, const float *grad_r, float *grad_end, hipStream_t st);
 hipError_t launch_scan(const int32_t *src, int64_t *dst, int64_t n, int ncols, int64_t src_stride,
                        int64_t dst_stride, int64_t *tmp, int64_t tmp_len, hipStream_t st);
 // Per-node meta-meshing (counts and node records), FP32 over all nodes or
@@ -194,9 +292,11 @@ hipError_t launch_arc_codec(const Inputs &in, const Work &w, bool encode, const 
                             int64_t E, int64_t ld, double rmin, double rmax, uint32_t *codes, uint32_t *mask,
                             float *fb, int64_t fb_cap, unsigned long long *fb_n, float *out, int64_t ld_out,
                             hipStream_t st);
+// With sink set, the node pass runs in sink mode (end loops only in the
+// records; vertices and fans of the nodes in [sink->n0, sink->n1) hashed).
 hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, int fp64, hipStream_t st,
                        const uint32_t *src_rec = nullptr, const int64_t *src_node_rec = nullptr,
-                       int32_t *redo = nullptr, int32_t *redo_cnt = nullptr);
+                       int32_t *redo = nullptr, int32_t *redo_cnt = nullptr, const SinkOut *sink = nullptr);
 // Node records -> meta-mesh, mesh vertices and hole fans.
 hipError_t launch_expand(const Inputs &in, const Work &w, const FillOut &o, hipStream_t st);
 hipError_t launch_band_count(const Inputs &in, const Work &w, hipStream_t st);
@@ -217,13 +317,17 @@ hipError_t launch_part_map(int64_t N, const int64_t *part_off, const int32_t *pa
                            int32_t *node_part, int16_t *node_k, hipStream_t st);
 hipError_t launch_chunk_list(const Work &w, int64_t n0, int64_t n1, int32_t *mark, int32_t epoch, int32_t *lists,
                              int64_t cap, int32_t *cnt, int64_t *info, int t16, int t32, hipStream_t st);
-// Outputs go to `out` (one chunk) through the slots, or with node_part set
-// to the per-part slots out_parts[part][sink_slots_words()] (reduced by
-// launch_parts_reduce) with vertex ids local to the part (node -
-// part_base[part]).  k_max: the largest resolution among the nodes.
-hipError_t launch_sink(const Inputs &in, const Work &w, int64_t n0, int64_t n1, int64_t max_struts, int k_max,
-                       int32_t *strut_list, int32_t *strut_cnt, unsigned long long *slots, uint64_t *out,
-                       const int32_t *node_part, uint64_t *out_parts, const int64_t *part_base, hipStream_t st);
+// The struts a range owns (lower end in [n0, n1), both ends meshed) and their
+// bands, hashed into `so`'s slots; k_max: the largest resolution among the
+// range's nodes (sizes the groups of struts per wave).
+hipError_t launch_sink_bands(const Inputs &in, const Work &w, int64_t n0, int64_t n1, int k_max, int32_t *strut_list,
+                             int32_t *strut_cnt, const SinkOut &so, hipStream_t st);
+// chunk slots -> out[kSinkWords]; clears the slots
+hipError_t launch_sink_reduce(unsigned long long *slots, uint64_t *out, hipStream_t st);
+// after range r's node pass: fail[r] = records overflowed; flags cleared
+hipError_t launch_range_done(int32_t *flags, int32_t *fail, int64_t r, hipStream_t st);
+// zero the per-part slots of parts [p0, p1)
+hipError_t launch_clear_parts(unsigned long long *slots, int64_t p0, int64_t p1, hipStream_t st);
 
 int64_t scan_tmp_needed(int64_t n, int ncols);
 

@@ -68,7 +68,8 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
         const int64_t cA = O.cap_arc;
         for (int j = lane; j < E; j += 64) {
 #pragma unroll
-            for (int t = 0; t < 11; ++t) O.arc_f32[t * cA + aoff + j] = fbits(aw(j, t));
+            for (int t = 0; t < 10; ++t) O.arc_f32[t * cA + aoff + j] = fbits(aw(j, t));
+            O.arc_f32[10 * cA + aoff + j] = fbits(aw(j, 9)) + fbits(aw(j, 10));  // t2 = t1 + dt
             O.arc_u32[0 * cA + aoff + j] = aw(j, 11) & 0x1ffffu;  // p | q<<8 | whole<<16
             O.arc_u32[1 * cA + aoff + j] = aw(j, 12);
             O.arc_u32[2 * cA + aoff + j] = (uint32_t)n;
@@ -76,17 +77,23 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
     }
     __syncthreads();
 
-    // Eq. 12 sub-parameter ii (1..nseg-1) of arc j, and its point
+    // Eq. 12 point ii (1..nseg-1) of arc j (from its start vertex unless it
+    // is a whole conic)
     auto interior = [&](int j, int ii) {
-        const float t1 = fbits(aw(j, 9)), t2 = fbits(aw(j, 10));
-        const int nseg = (int)(aw(j, 13) & 0xffffu);
-        const float t = t1 + (t2 - t1) * (float)ii / (float)nseg;
-        float s, c;
-        sincosf(t, &s, &c);
-        float w[3];
+        float o[3], a[3], b[3], x1[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int d = 0; d < 3; ++d) w[d] = fbits(aw(j, d)) + fbits(aw(j, 3 + d)) * s + fbits(aw(j, 6 + d)) * c;
-        return make_float3(w[0], w[1], w[2]);
+        for (int d = 0; d < 3; ++d) {
+            o[d] = fbits(aw(j, d));
+            a[d] = fbits(aw(j, 3 + d));
+            b[d] = fbits(aw(j, 6 + d));
+        }
+        const bool whole = (aw(j, 11) >> 16) & 1u;
+        if (!whole) {
+            const int vs = (int)(aw(j, 12) & 0xffffu);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) x1[d] = fbits(RV[4 * vs + 1 + d]);
+        }
+        return arc_point_f32(o, a, b, x1, fbits(aw(j, 9)), fbits(aw(j, 10)), ii, (int)(aw(j, 13) & 0xffffu), whole);
     };
     // mesh vertices: meta-vertices, interior points, hole centres
     for (int i = lane; i < M; i += 64) {

@@ -406,7 +406,7 @@ __device__ void backward_node(const BParams &P, BwdLds<VM, AC, VC> &sm, const in
     // adds weight lam (a 3-vector) on interior point ii of arc j
     auto add_interior = [&](int j, int ii, const float *lam) {
         const int nseg = (int)(RA[kRecArcFields * j + 13] & 0xffffu);
-        const float t1 = af(9, j), t2 = af(10, j);
+        const float t1 = af(9, j), t2 = t1 + af(10, j);  // the record keeps dt = t2 - t1
         const float f = (float)ii / (float)nseg;
         const float t = t1 + (t2 - t1) * (float)ii / (float)nseg;
         float s, c;
@@ -428,7 +428,7 @@ __device__ void backward_node(const BParams &P, BwdLds<VM, AC, VC> &sm, const in
     for (int j = lane; j < E; j += 64) {
         const int nseg = (int)(RA[kRecArcFields * j + 13] & 0xffffu);
         const bool fwd = (RA[kRecArcFields * j + 11] >> 17) & 1u;
-        const float t1 = af(9, j), t2 = af(10, j);
+        const float t1 = af(9, j), t2 = t1 + af(10, j);  // the record keeps dt = t2 - t1
         float ca[3], cb[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -480,7 +480,7 @@ __device__ void backward_node(const BParams &P, BwdLds<VM, AC, VC> &sm, const in
             for (int d = 0; d < 3; ++d) b[d] += 0.5f * (ws[d] + we[d]);
             for (int ii = 1; ii < nseg; ++ii) {
                 float x[3], dx[3];
-                arc_point(j, af(9, j) + (af(10, j) - af(9, j)) * (float)ii / (float)nseg, x, dx);
+                arc_point(j, af(9, j) + af(10, j) * (float)ii / (float)nseg, x, dx);
                 for (int d = 0; d < 3; ++d) b[d] += x[d];
             }
             cnt += nseg;

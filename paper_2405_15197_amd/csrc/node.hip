@@ -50,6 +50,7 @@ template <typename T>
 struct ArcL {
     T o[3], a[3], b[3];
     T t1, t2;
+    T dt;            // t2 - t1, kept with its own relative precision
     uint32_t ns, ne; // vertex names at t1 / t2
     int vs, ve;      // local vertex indices
     int p, q, full;
@@ -177,6 +178,29 @@ __device__ inline void group_prev_last(T x, T carry, T &prev, T &last)
         prev = lane ? s_x[lane - 1] : carry;
         last = s_x[W - 1];
         __syncthreads();
+    }
+}
+
+// sum over the W lanes of a node (every lane gets it); a group wider than a
+// wave adds the waves' sums through LDS
+template <int W>
+__device__ inline uint64_t group_sum_u64(uint64_t x)
+{
+    if constexpr (W <= 64) {
+#pragma unroll
+        for (int o = W / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, W);
+        return x;
+    } else {
+        __shared__ uint64_t s_part[W / 64];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = x;
+        __syncthreads();
+        uint64_t t = 0;
+#pragma unroll
+        for (int i = 0; i < W / 64; ++i) t += s_part[i];
+        __syncthreads();
+        return t;
     }
 }
 
@@ -440,9 +464,9 @@ __device__ inline V3<T> conic_dir(const Con<T> &C, T s, T c)
     return C.o + C.a * (s * inv) + C.b * (c * inv);
 }
 
-// Parameter range [t1, t2] (t1 in [0, 2 pi)) of a kept piece
+// Parameter range [t1, t2] (t1 in [0, 2 pi)) and span of a kept piece
 template <typename T>
-__device__ inline void piece_range(const Piece<T> &pc, T &t1, T &t2)
+__device__ inline void piece_range(const Piece<T> &pc, T &t1, T &t2, T &dt)
 {
     const T tp = Cst<T>::two_pi;
     T ts = m_atan2(pc.ss, pc.sc), te = m_atan2(pc.es, pc.ec);
@@ -456,6 +480,7 @@ __device__ inline void piece_range(const Piece<T> &pc, T &t1, T &t2)
     if (pc.len > (T)3 && span < (T)0.5 * Cst<T>::pi) span = tp;
     t1 = ts;
     t2 = ts + span;
+    dt = span;
 }
 
 // Condition number of a tie point: the three surfaces through it are cone p
@@ -521,14 +546,82 @@ __device__ inline int interior_idx(const ArcL<T> &A, int ii)
 template <typename T>
 __device__ inline T sub_param(const ArcL<T> &A, int ii)
 {
-    return A.t1 + (A.t2 - A.t1) * (T)ii / (T)A.nseg;
+    return A.t1 + A.dt * (T)ii / (T)A.nseg;
 }
-
-template <typename T>
-__device__ inline V3<T> interior_pt(const ArcL<T> &A, int ii) { return conic_at(arc_con(A), sub_param(A, ii)); }
 
 template <typename T, typename C>
 __device__ inline V3<T> vert_pos(const Shared<T, C> &sh, int i) { return v3(sh.vx[i], sh.vy[i], sh.vz[i]); }
+
+// Eq. 12 point ii of arc A: the formula of arc_point_f32 (whole conics
+// directly, arcs from their start vertex with the differences in product
+// form), in the node's precision
+template <typename T, typename C>
+__device__ inline V3<T> interior_pt(const Shared<T, C> &sh, const ArcL<T> &A, int ii)
+{
+    if constexpr (sizeof(T) == 4) {
+        const float x1[3] = {A.full ? 0.f : sh.vx[A.vs], A.full ? 0.f : sh.vy[A.vs], A.full ? 0.f : sh.vz[A.vs]};
+        const float3 w = arc_point_f32(A.o, A.a, A.b, x1, A.t1, A.dt, ii, A.nseg, A.full != 0);
+        return v3(w.x, w.y, w.z);
+    } else {
+        if (A.full) return conic_at(arc_con(A), sub_param(A, ii));
+        const T h = (T)0.5 * A.dt * (T)ii / (T)A.nseg;
+        T sh_, ch_, sm, cm;
+        m_sincos(h, &sh_, &ch_);
+        m_sincos(A.t1 + h, &sm, &cm);
+        const T ds = (T)2 * cm * sh_, dc = (T)-2 * sm * sh_;
+        const Con<T> Cn = arc_con(A);
+        return vert_pos(sh, A.vs) + Cn.a * ds + Cn.b * dc;
+    }
+}
+
+// One Newton step on the tie equations of vertex i: P_p = P_q = P_r on
+// |w|^2 - rho^2 = P_p^2 (label 0 has P_0 = 0).  The position from the conic
+// (p, q) carries the rounding of that conic's parametrisation, large for a
+// long thin ellipse; these equations involve only quantities of the node's
+// scale, so the step leaves the error the tie's conditioning allows.
+template <typename T, typename C>
+__device__ inline void refine_vertex(Shared<T, C> &sh, int i, T rho)
+{
+    const uint32_t nm = sh.vname[i];
+    const int p = (int)(nm >> 24), q = (int)((nm >> 16) & 0xffu), r = (int)((nm >> 8) & 0xffu);
+    if (r == 0xff) return;  // start point of a whole conic
+    const V3<T> w = vert_pos(sh, i);
+    const V3<T> gp = p ? gvec(sh.S[p]) : zero3<T>();
+    const T hp = p ? sh.S[p].h : (T)0;
+    const V3<T> n1 = gp - gvec(sh.S[q]), n2 = gp - gvec(sh.S[r]);
+    const T s = dot(gp, w) - hp;
+    const V3<T> n3 = (w - gp * s) * (T)2;
+    const T f1 = dot(n1, w) - (hp - sh.S[q].h), f2 = dot(n2, w) - (hp - sh.S[r].h);
+    const T f3 = dot(w, w) - rho * rho - s * s;
+    const V3<T> c23 = cross(n2, n3), c31 = cross(n3, n1), c12 = cross(n1, n2);
+    const T det = dot(n1, c23);
+    if (!(m_abs(det) > (T)0)) return;
+    const V3<T> d = (c23 * f1 + c31 * f2 + c12 * f3) * ((T)-1 / det);
+    sh.vx[i] = w.x + d.x;
+    sh.vy[i] = w.y + d.y;
+    sh.vz[i] = w.z + d.z;
+}
+
+// Span of an arc from its (refined) end vertices: the chord
+// x2 - x1 = 2 sin(dt / 2) (a cos tm - b sin tm), tm = t1 + dt / 2, fixes dt
+// with the relative precision of the chord, where the difference of two
+// parameters would carry their absolute rounding.  Arcs of more than a
+// quarter turn keep the span from the trimming.
+template <typename T, typename C>
+__device__ inline void refine_span(const Shared<T, C> &sh, ArcL<T> &A)
+{
+    if (!(A.dt < (T)0.5 * Cst<T>::pi)) return;
+    const V3<T> ch = vert_pos(sh, A.ve) - vert_pos(sh, A.vs);
+    T st, ct;
+    m_sincos(A.t1 + (T)0.5 * A.dt, &st, &ct);
+    const Con<T> Cn = arc_con(A);
+    const V3<T> tg = Cn.a * ct - Cn.b * st;
+    const T den = m_sqrt(dot(tg, tg));
+    const T x = m_sqrt(dot(ch, ch)) / ((T)2 * den);
+    if (!(x < (T)1)) return;
+    A.dt = (T)2 * m_asin(x);
+    A.t2 = A.t1 + A.dt;
+}
 
 struct Params {
     Inputs in;
@@ -543,6 +636,8 @@ struct Params {
     int32_t *redo;
     int32_t *redo_cnt;  // [4]
     int32_t *redo_ctr;  // [4]
+    // sink mode: where the counts and hashes of vertices and fans go
+    SinkOut sink;
 };
 
 // statuses that FP64 may resolve
@@ -552,7 +647,99 @@ constexpr int kRetry = NS_NON_ELLIPTIC | NS_LOOP | NS_TOPOLOGY | NS_PREC | NS_CA
 // expansion pass.
 // Subdivision at resolution k and the node record, for a node whose
 // meta-mesh (arcs, vertices, end loops, contours) is in LDS with its status.
+// Sink mode: counts and hashes of the node's mesh vertices (meta-vertices,
+// Eq. 12 interior points, Eq. 13 hole centres, in the stored mode's node-local
+// order and FP32 arithmetic) and of its hole fans, added to the node's chunk
+// or part.
 template <typename T, typename CF>
+__device__ void sink_hash_node(const Params &P, Shared<T, CF> &sh, const int64_t n, const int M, const int F)
+{
+    constexpr int WL = CF::W;
+    const int lane = threadIdx.x & (WL - 1);
+    const SinkOut &S = P.sink;
+    const float4 c4 = P.w.node4[n];
+    const int64_t ln = sink_local_node(S, n);
+    const int V = sh.n_vert, E = sh.n_arc, wsum = sh.wsum, ncirc = sh.ncirc;
+    auto ffield = [](const T *x, float *o) {
+        o[0] = (float)x[0];
+        o[1] = (float)x[1];
+        o[2] = (float)x[2];
+    };
+    uint64_t hv = 0, sx = 0, sy = 0, sz = 0, ht = 0;
+    for (int i = lane; i < M; i += WL) {
+        float3 w;
+        if (i < V) {
+            w = make_float3((float)sh.vx[i], (float)sh.vy[i], (float)sh.vz[i]);
+        } else if (i < wsum) {
+            int lo = 0, hi = E - 1;  // last arc with mbase <= i
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (sh.A[mid].mbase <= i) lo = mid;
+                else hi = mid - 1;
+            }
+            const ArcL<T> &A = sh.A[lo];
+            const bool fwd = A.full || A.ns <= A.ne;
+            const int jc = i - A.mbase;
+            float o[3], a[3], b[3], x1[3] = {0.f, 0.f, 0.f};
+            ffield(A.o, o);
+            ffield(A.a, a);
+            ffield(A.b, b);
+            if (!A.full) {
+                x1[0] = (float)sh.vx[A.vs];
+                x1[1] = (float)sh.vy[A.vs];
+                x1[2] = (float)sh.vz[A.vs];
+            }
+            w = arc_point_f32(o, a, b, x1, (float)A.t1, (float)A.dt, fwd ? jc + 1 : A.nseg - 1 - jc, A.nseg,
+                              A.full != 0);
+        } else {
+            const int c = i - wsum;
+            w = make_float3((float)sh.hc[c][0], (float)sh.hc[c][1], (float)sh.hc[c][2]);
+        }
+        const float x = c4.x + w.x, y = c4.y + w.y, z = c4.z + w.z;
+        hv += vert_key(vid_of(ln, i), x, y, z);
+        sx += (uint64_t)llrint((double)x * 1048576.0);
+        sy += (uint64_t)llrint((double)y * 1048576.0);
+        sz += (uint64_t)llrint((double)z * 1048576.0);
+    }
+    // hole fans: one triangle per circular-arc segment, apex at the contour's
+    // hole centre, oriented outward
+    for (int i = lane; i < F; i += WL) {
+        int lo = 0, hi = ncirc - 1;  // last circular arc with fbase <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sh.A[mid].fbase <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const ArcL<T> &A = sh.A[lo];
+        const bool fwd = A.full || A.ns <= A.ne, lower = sh.S[A.q].lower;
+        const int nseg = A.nseg, sseg = i - A.fbase;
+        const int i0 = fwd ? sseg : nseg - sseg, i1 = fwd ? sseg + 1 : nseg - sseg - 1;
+        const int lo_i = i0 < i1 ? i0 : i1, hi_i = i0 < i1 ? i1 : i0;
+        const int u = lo_i == 0 ? A.vs : A.mbase + (fwd ? lo_i - 1 : nseg - 1 - lo_i);
+        const int u2 = hi_i == nseg ? A.ve : A.mbase + (fwd ? hi_i - 1 : nseg - 1 - hi_i);
+        ht += tri_key(vid_of(ln, wsum + A.contour), vid_of(ln, lower ? u2 : u), vid_of(ln, lower ? u : u2));
+    }
+    hv = group_sum_u64<WL>(hv);
+    sx = group_sum_u64<WL>(sx);
+    sy = group_sum_u64<WL>(sy);
+    sz = group_sum_u64<WL>(sz);
+    ht = group_sum_u64<WL>(ht);
+    if (lane == 0) {
+        const int32_t part = S.node_part ? S.node_part[n] : 0;
+        sink_add(S, part, 0, (uint64_t)F);
+        sink_add(S, part, 1, ht);
+        sink_add(S, part, 2, (uint64_t)M);
+        sink_add(S, part, 3, hv);
+        sink_add(S, part, 4, sx);
+        sink_add(S, part, 5, sy);
+        sink_add(S, part, 6, sz);
+    }
+}
+
+// SINK: instead of a node record for the expansion and the bands, only the
+// strut end loops are kept (for the bands); the node's mesh vertices and hole
+// fans are counted and hashed here (sink mode).
+template <typename T, typename CF, bool SINK>
 __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, const int k, const int v,
                           const int64_t row, const T rho, const V3<T> cen)
 {
@@ -619,7 +806,7 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
                 const ArcL<T> &A = sh.A[j];
                 if (A.contour != c) continue;
                 sum = sum + (vert_pos(sh, A.vs) + vert_pos(sh, A.ve)) * (T)0.5;
-                for (int ii = 1; ii < A.nseg; ++ii) sum = sum + interior_pt(A, ii);
+                for (int ii = 1; ii < A.nseg; ++ii) sum = sum + interior_pt(sh, A, ii);
                 cntv += A.nseg;
             }
             V3<T> b = sum * ((T)1 / (T)cntv);
@@ -683,7 +870,7 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
             const int off = sh.entry_off[sh.loop_base[v + 1]];
             // record space: bump allocation in the node's region
             const int64_t words =
-                rec_loop_word(V, E, NC, rec_table_bytes(v, sh.loop_base[v + 1], WIDE)) +
+                (SINK ? 0 : rec_loop_word(V, E, NC, rec_table_bytes(v, sh.loop_base[v + 1], WIDE))) +
                 (((int64_t)2 * off + 3) & ~(int64_t)3);
             const int g = (int)(n & (kRecRegions - 1));
             const int64_t region = W.rec_words / kRecRegions;
@@ -703,9 +890,9 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
         {
             const int nent = sh.loop_base[v + 1];
             const int ns_tot = sh.entry_off[nent];
-            int2 *rl = sh.rec >= 0 ? (int2 *)(W.rec + sh.rec +
-                                              rec_loop_word(V, E, NC, rec_table_bytes(v, nent, WIDE)))
-                                   : nullptr;
+            int2 *rl = sh.rec >= 0
+                           ? (int2 *)(W.rec + sh.rec + (SINK ? 0 : rec_loop_word(V, E, NC, rec_table_bytes(v, nent, WIDE))))
+                           : nullptr;
             // phi key and local mesh index of sample j of loop entry e
             auto sample = [&](int e, int j, int &li) -> T {
                 const int m = sh.entry_m[e];
@@ -719,7 +906,7 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
                 // tangency circles are parametrised in the strut frame: phi
                 // is the parameter itself
                 if (A.p == 0) return phi_key(st, ct);
-                V3<T> w = j == 0 ? vert_pos(sh, li) : arc_con(A).o + arc_con(A).a * st + arc_con(A).b * ct;
+                const V3<T> w = j == 0 ? vert_pos(sh, li) : interior_pt(sh, A, ii);
                 const SL<T> &sm = sh.S[m];
                 return phi_key(dot(w, v3(sm.qx, sm.qy, sm.qz)), dot(w, v3(sm.rx, sm.ry, sm.rz)));
             };
@@ -799,7 +986,11 @@ finish:
                 W.node_cnt[NC_STATUS * N + n] = status & ~NS_PREC;
                 W.node_rec[n] = -1;
                 // hand the node to the FP64 pass when precision may be at fault
-                if (F32 && (status & kRetry)) W.fb_list[atomicAdd(&W.flags[2], 1)] = (int32_t)n;
+                const bool retry = F32 && (status & kRetry);
+                if (retry) W.fb_list[atomicAdd(&W.flags[2], 1)] = (int32_t)n;
+                // sink mode: a node of the range left without a mesh
+                if (SINK && !retry && n >= P.sink.n0 && n < P.sink.n1)
+                    sink_add(P.sink, P.sink.node_part ? P.sink.node_part[n] : 0, 7, 1);
             }
             over_lanes<WL, CF::VM>(lane, 0, v - 1, [&](int l) { W.he_len[row + l] = 0; });
             return;
@@ -807,7 +998,17 @@ finish:
         const int Msum = sh.wsum + NC, Fsum = sh.fsum;
         const int64_t rb = sh.rec;
         const int nent = sh.loop_base[v + 1];
-        const int64_t lw = rec_loop_word(V, E, NC, rec_table_bytes(v, nent, WIDE));
+        const int64_t lw = SINK ? 0 : rec_loop_word(V, E, NC, rec_table_bytes(v, nent, WIDE));
+        if constexpr (SINK) {
+            over_lanes<WL, CF::VM>(lane, 0, v - 1, [&](int l) {
+                W.he_len[row + l] = sh.loop_len[l + 1];
+                W.he_loop[row + l] = rb >= 0 ? rb / 2 + sh.lbase[l + 1] : 0;
+            });
+            if (lane == 0) W.node_rec[n] = rb;
+            if (n < P.sink.n0 || n >= P.sink.n1) return;  // halo node: its loops only
+            sink_hash_node<T, CF>(P, sh, n, Msum, Fsum);
+            return;
+        }
         if (lane == 0) {
             W.node_cnt[NC_VERT * N + n] = V;
             W.node_cnt[NC_ARC * N + n] = E;
@@ -848,7 +1049,7 @@ finish:
             const uint32_t lower = sh.S[A.q].lower ? 1u : 0u;
             dst[0] = make_uint4(fb(A.o[0]), fb(A.o[1]), fb(A.o[2]), fb(A.a[0]));
             dst[1] = make_uint4(fb(A.a[1]), fb(A.a[2]), fb(A.b[0]), fb(A.b[1]));
-            dst[2] = make_uint4(fb(A.b[2]), fb(A.t1), fb(A.t2),
+            dst[2] = make_uint4(fb(A.b[2]), fb(A.t1), fb(A.dt),
                                 (uint32_t)A.p | ((uint32_t)A.q << 8) | ((uint32_t)A.full << 16) | (fwd << 17) |
                                     (lower << 18));
             dst[3] = make_uint4((uint32_t)A.vs | ((uint32_t)A.ve << 16),
@@ -874,7 +1075,7 @@ finish:
     }
 }
 
-template <typename T, typename CF>
+template <typename T, typename CF, bool SINK = false>
 __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
 {
     constexpr int WL = CF::W;
@@ -906,6 +1107,8 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
             for (int c = 0; c < kNodeCols; ++c) W.node_cnt[c * N + n] = 0;
             W.node_cnt[NC_STATUS * N + n] = v == 0 ? NS_ISOLATED : NS_VALENCE;
             W.node_rec[n] = -1;
+            if (SINK && n >= P.sink.n0 && n < P.sink.n1)
+                sink_add(P.sink, P.sink.node_part ? P.sink.node_part[n] : 0, 7, 1);
         }
         for (int i = lane; i < v; i += WL) W.he_len[row + i] = 0;
         return;
@@ -1029,8 +1232,9 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
                         if (TR.full) {
                             A.t1 = (T)0;
                             A.t2 = tp;
+                            A.dt = tp;
                         } else {
-                            piece_range(TR.pc[i], A.t1, A.t2);
+                            piece_range(TR.pc[i], A.t1, A.t2, A.dt);
                         }
                         A.ns = ns_[i];
                         A.ne = ne_[i];
@@ -1112,17 +1316,26 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
             A.vs = find_vert(sh, A.ns);
             A.ve = find_vert(sh, A.ne);
             if (A.vs < 0 || A.ve < 0) atomicOr(&sh.status, NS_TOPOLOGY);
+            A.contour = -1;
+        }
+        // vertices on their tie equations, then the spans and segment
+        // counts (Eq. 11) from them
+        for (int i = lane; i < V; i += WL) {
+            refine_vertex(sh, i, rho);
+            sh.vdeg[i] = 0;
+        }
+        __syncthreads();
+        for (int j = lane; j < E; j += WL) {
+            ArcL<T> &A = sh.A[j];
             if (A.full) {
                 A.nseg = k;
             } else {
-                T u = (A.t2 - A.t1) * ((T)k * Cst<T>::inv_two_pi);
+                if (A.vs >= 0 && A.ve >= 0) refine_span(sh, A);
+                T u = A.dt * ((T)k * Cst<T>::inv_two_pi);
                 int ns = (int)m_floor(u) + 1;
                 A.nseg = ns < k ? ns : k;
             }
-            A.contour = -1;
         }
-        for (int i = lane; i < V; i += WL) sh.vdeg[i] = 0;
-        __syncthreads();
         for (int j = lane; j < E; j += WL) {
             const ArcL<T> &A = sh.A[j];
             if (A.full || A.vs < 0 || A.ve < 0) continue;
@@ -1174,7 +1387,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
         __syncthreads();
         for (int j = lane; j < E; j += WL) {
             const ArcL<T> &A = sh.A[j];
-            T tm = (T)0.5 * (A.t1 + A.t2);
+            T tm = A.t1 + (T)0.5 * A.dt;
             T st, ct;
             m_sincos(tm, &st, &ct);
             Con<T> C = arc_con(A);
@@ -1307,7 +1520,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
     }
 
 tail:
-    node_tail<T, CF>(P, sh, n, k, v, row, rho, cen);
+    node_tail<T, CF, SINK>(P, sh, n, k, v, row, rho, cen);
 }
 
 // Re-subdivision at resolution k of a node whose meta-mesh is in a record
@@ -1404,7 +1617,8 @@ __device__ void node_retri(const Params &P, Shared<float, CF> &sh, const int64_t
             A.b[d] = __uint_as_float(aw[6 + d]);
         }
         A.t1 = __uint_as_float(aw[9]);
-        A.t2 = __uint_as_float(aw[10]);
+        A.dt = __uint_as_float(aw[10]);
+        A.t2 = A.t1 + A.dt;
         const uint32_t u0 = aw[11], u1 = aw[12], u2 = aw[13];
         A.p = (int)(u0 & 0xffu);
         A.q = (int)((u0 >> 8) & 0xffu);
@@ -1418,7 +1632,7 @@ __device__ void node_retri(const Params &P, Shared<float, CF> &sh, const int64_t
         if (A.full) {
             A.nseg = k;
         } else {
-            T u = (A.t2 - A.t1) * ((T)k * Cst<T>::inv_two_pi);
+            T u = A.dt * ((T)k * Cst<T>::inv_two_pi);
             int ns = (int)m_floor(u) + 1;
             A.nseg = ns < k ? ns : k;
         }
@@ -1442,15 +1656,16 @@ __device__ void node_retri(const Params &P, Shared<float, CF> &sh, const int64_t
         sh.loop_len[lane] = len;
     }
     __syncthreads();
-    node_tail<T, CF>(P, sh, n, k, v, row, rho, cen);
+    node_tail<T, CF, false>(P, sh, n, k, v, row, rho, cen);
 }
 
 // FP32, one valence class: a persistent grid takes items of 64 / W queued
 // nodes from a work counter; every wave leaves once the counter has passed
 // the class's last item.  MODE 0: meta-meshing of the queue; 1:
 // re-subdivision of the queue; 2: meta-meshing of the redo list that mode 1
-// left (its length is read on the device).
-enum { kModeMesh = 0, kModeRetri = 1, kModeRedo = 2 };
+// left (its length is read on the device); 3: meta-meshing of the queue in
+// sink mode (end loops kept, vertices and fans hashed).
+enum { kModeMesh = 0, kModeRetri = 1, kModeRedo = 2, kModeSink = 3 };
 template <typename C, int MODE>
 __global__ void __launch_bounds__(64) k_node32(Params P, int cls)
 {
@@ -1473,6 +1688,7 @@ __global__ void __launch_bounds__(64) k_node32(Params P, int cls)
         if (qi < cnt) {
             const int64_t node = list[base + qi];
             if (MODE == kModeRetri) node_retri<C>(P, sh[slot], node, cls);
+            else if (MODE == kModeSink) node_body<float, C, true>(P, sh[slot], node);
             else node_body<float, C>(P, sh[slot], node);
         }
         __syncthreads();
@@ -1501,6 +1717,8 @@ __global__ void __launch_bounds__(64 * kBigWaves) k_node32_big(Params P)
         const int64_t node = list[base + item];
         if (MODE == kModeRetri) {
             if (threadIdx.x == 0) P.redo[base + atomicAdd(&P.redo_cnt[cls], 1)] = (int32_t)node;
+        } else if (MODE == kModeSink) {
+            node_body<float, CfgBig, true>(P, sh, node);
         } else {
             node_body<float, CfgBig>(P, sh, node);
         }
@@ -1526,7 +1744,7 @@ __global__ void __launch_bounds__(64) k_node32_thread(Params P, Shared<float, Cf
 // (also after a re-subdivision: these nodes are solved in full).  One
 // instantiation takes the nodes of up to kVmax struts (a wave per node), the
 // other the multi-wave class (a block of kBigWaves waves per node).
-template <typename C>
+template <typename C, bool SINK>
 __global__ void __launch_bounds__(C::W) k_node64(Params P)
 {
     __shared__ Shared<double, C> sh;
@@ -1535,7 +1753,7 @@ __global__ void __launch_bounds__(C::W) k_node64(Params P)
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
         const int64_t node = P.w.fb_list[i];
         const bool is_big = P.w.row[node + 1] - P.w.row[node] > kVmax;
-        if (is_big == big) node_body<double, C>(P, sh, node);
+        if (is_big == big) node_body<double, C, SINK>(P, sh, node);
         __syncthreads();
     }
 }
@@ -1566,6 +1784,7 @@ hipError_t launch_node_thread(const Inputs &in, const Work &w, int k, float kapp
     P.redo = nullptr;
     P.redo_cnt = nullptr;
     P.redo_ctr = nullptr;
+    P.sink = SinkOut{};
     const int64_t blocks = (in.n_nodes + 63) / 64;
     k_node32_thread<<<(unsigned)(blocks < kThreadGrid ? blocks : kThreadGrid), 64, 0, st>>>(
         P, (Shared<float, CfgT1> *)scratch);
@@ -1573,10 +1792,12 @@ hipError_t launch_node_thread(const Inputs &in, const Work &w, int k, float kapp
 }
 
 hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, int fp64, hipStream_t st,
-                       const uint32_t *src_rec, const int64_t *src_node_rec, int32_t *redo, int32_t *redo_cnt)
+                       const uint32_t *src_rec, const int64_t *src_node_rec, int32_t *redo, int32_t *redo_cnt,
+                       const SinkOut *sink)
 {
     if (in.n_nodes == 0) return hipSuccess;
     Params P;
+    P.sink = sink ? *sink : SinkOut{};
     P.in = in;
     P.w = w;
     P.k = k;
@@ -1587,8 +1808,13 @@ hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, 
     P.redo_cnt = redo_cnt;
     P.redo_ctr = redo_cnt ? redo_cnt + 4 : nullptr;
     if (fp64) {
-        k_node64<CfgV16><<<kFp64Grid, 64, 0, st>>>(P);
-        k_node64<CfgBig><<<kFp64BigGrid, CfgBig::W, 0, st>>>(P);
+        if (sink) {
+            k_node64<CfgV16, true><<<kFp64Grid, 64, 0, st>>>(P);
+            k_node64<CfgBig, true><<<kFp64BigGrid, CfgBig::W, 0, st>>>(P);
+        } else {
+            k_node64<CfgV16, false><<<kFp64Grid, 64, 0, st>>>(P);
+            k_node64<CfgBig, false><<<kFp64BigGrid, CfgBig::W, 0, st>>>(P);
+        }
         return hipGetLastError();
     }
     const unsigned big_grid = (unsigned)(in.n_nodes < kBigGrid ? in.n_nodes : kBigGrid);
@@ -1608,6 +1834,11 @@ hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, 
         k_node32<CfgV8, kModeRedo><<<grid(2, kRedoGrid), 64, 0, st>>>(P, 1);
         k_node32<CfgV16, kModeRedo><<<grid(1, kRedoGrid), 64, 0, st>>>(P, 2);
         k_node32_big<kModeRedo><<<big_grid, CfgBig::W, 0, st>>>(P);
+    } else if (sink) {
+        k_node32<CfgV4, kModeSink><<<grid(4, kNodeGrid), 64, 0, st>>>(P, 0);
+        k_node32<CfgV8, kModeSink><<<grid(2, kNodeGrid), 64, 0, st>>>(P, 1);
+        k_node32<CfgV16, kModeSink><<<grid(1, kNodeGrid), 64, 0, st>>>(P, 2);
+        k_node32_big<kModeSink><<<big_grid, CfgBig::W, 0, st>>>(P);
     } else {
         k_node32<CfgV4, kModeMesh><<<grid(4, kNodeGrid), 64, 0, st>>>(P, 0);
         k_node32<CfgV8, kModeMesh><<<grid(2, kNodeGrid), 64, 0, st>>>(P, 1);

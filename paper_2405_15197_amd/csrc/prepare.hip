@@ -302,9 +302,62 @@ __global__ void k_class_scatter(int64_t N, const int64_t *row, const int64_t *of
     queue[base[c] + off[c * Np1 + n]] = (int32_t)n;
 }
 
+// Node radius from per-strut end radii (Sec. 4.1: a strut is tangent to the
+// nodal spheres of its ends, so the end radii at a node agree): the mean of
+// the end radii of the node's struts in adjacency (strut id) order; a node
+// whose end radii spread by more than rel_tol times that mean is counted.
+__global__ void k_end_radii(int64_t N, const int64_t *row, const int2 *he, const int32_t *sa, const float *end_r,
+                            float rel_tol, float *radius, int32_t *mismatch)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int64_t h0 = row[n], h1 = row[n + 1];
+    float sum = 0.f, lo = 3.0e38f, hi = -3.0e38f;
+    for (int64_t h = h0; h < h1; ++h) {
+        const int64_t st = he[h].y;
+        const float r = end_r[2 * st + (sa[st] == (int32_t)n ? 0 : 1)];
+        sum += r;
+        lo = fminf(lo, r);
+        hi = fmaxf(hi, r);
+    }
+    // equal end radii give exactly that radius
+    const float mean = h1 > h0 ? (hi == lo ? lo : sum / (float)(h1 - h0)) : 0.f;
+    radius[n] = mean;
+    if (h1 > h0 && hi - lo > rel_tol * fabsf(mean)) atomicAdd(mismatch, 1);
+}
+
+// d mean / d end radius = 1 / (struts at the node)
+__global__ void k_end_grad(int64_t S, const int64_t *row, const int32_t *sa, const int32_t *sb, const float *grad_r,
+                           float *grad_end)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * S) return;
+    const int64_t st = i >> 1;
+    const int32_t n = (i & 1) ? sb[st] : sa[st];
+    const int64_t deg = row[n + 1] - row[n];
+    grad_end[i] = deg > 0 ? grad_r[n] / (float)deg : 0.f;
+}
+
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 }  // namespace
+
+hipError_t launch_end_radii(const Inputs &in, const Work &w, const float *end_r, float rel_tol, float *radius,
+                            int32_t *mismatch, hipStream_t st)
+{
+    if (in.n_nodes > 0)
+        k_end_radii<<<grid_for(in.n_nodes, kBlock), kBlock, 0, st>>>(in.n_nodes, w.row, w.he, in.sa, end_r, rel_tol,
+                                                                      radius, mismatch);
+    return hipGetLastError();
+}
+
+hipError_t launch_end_grad(const Inputs &in, const Work &w, const float *grad_r, float *grad_end, hipStream_t st)
+{
+    if (in.n_struts > 0)
+        k_end_grad<<<grid_for(2 * in.n_struts, kBlock), kBlock, 0, st>>>(in.n_struts, w.row, in.sa, in.sb, grad_r,
+                                                                         grad_end);
+    return hipGetLastError();
+}
 
 int64_t scan_tmp_needed(int64_t n, int ncols) { return ((n + kTile - 1) / kTile + 1) * ncols; }
 

@@ -22,6 +22,12 @@ LM_ERR_UNSUPPORTED = -4
 LM_ERR_HIP = -5
 LM_ERR_STATE = -6
 LM_ERR_INTERNAL = -7
+LM_ERR_IO = -8
+LM_ERR_RADIUS_MISMATCH = -9
+
+LM_WS_SINK = 1
+LM_WS_GRADIENT = 2
+LM_WS_RETRI = 4
 
 LM_NODE_INVALID_STRUT = 1
 LM_NODE_NON_ELLIPTIC = 2
@@ -35,6 +41,10 @@ LM_NODE_CAPACITY = 128
 # every function the header declares (checked by the CPU tests)
 EXPORTS = (
     "lm_plan_create",
+    "lm_workspace_size",
+    "lm_plan_create_in",
+    "lm_plan_create_end_radii",
+    "lm_end_radius_gradient",
     "lm_prepare",
     "lm_count",
     "lm_fill",
@@ -67,6 +77,15 @@ class lm_lattice(ctypes.Structure):
         ("d_radius", ctypes.c_void_p),
         ("d_strut_a", ctypes.c_void_p),
         ("d_strut_b", ctypes.c_void_p),
+    ]
+
+
+class lm_options(ctypes.Structure):
+    _fields_ = [
+        ("flags", ctypes.c_int32),
+        ("k_max", ctypes.c_int32),
+        ("record_bytes", ctypes.c_int64),
+        ("max_parts", ctypes.c_int64),
     ]
 
 
@@ -176,6 +195,17 @@ def load() -> ctypes.CDLL:
     P = ctypes.c_void_p
     lib.lm_plan_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(lm_lattice), P]
     lib.lm_plan_create.restype = ctypes.c_int
+    lib.lm_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(lm_options),
+                                      ctypes.POINTER(ctypes.c_size_t)]
+    lib.lm_workspace_size.restype = ctypes.c_int
+    lib.lm_plan_create_in.argtypes = [ctypes.POINTER(P), ctypes.POINTER(lm_lattice), ctypes.POINTER(lm_options), P,
+                                      ctypes.c_size_t, P]
+    lib.lm_plan_create_in.restype = ctypes.c_int
+    lib.lm_plan_create_end_radii.argtypes = [ctypes.POINTER(P), ctypes.POINTER(lm_lattice), P, ctypes.c_float, P,
+                                             ctypes.POINTER(ctypes.c_int64), P]
+    lib.lm_plan_create_end_radii.restype = ctypes.c_int
+    lib.lm_end_radius_gradient.argtypes = [P, P, P]
+    lib.lm_end_radius_gradient.restype = ctypes.c_int
     lib.lm_count.argtypes = [P, ctypes.c_int, ctypes.POINTER(lm_totals)]
     lib.lm_count.restype = ctypes.c_int
     lib.lm_fill.argtypes = [P, ctypes.POINTER(lm_outputs)]
@@ -234,6 +264,47 @@ def lm_plan_create(lat: lm_lattice, stream: int | None) -> ctypes.c_void_p:
     if rc != LM_OK:
         raise LatmeshError(rc, "lm_plan_create")
     return h
+
+
+def lm_workspace_size(n_nodes: int, n_struts: int, opt: lm_options | None) -> int:
+    b = ctypes.c_size_t(0)
+    rc = load().lm_workspace_size(int(n_nodes), int(n_struts), ctypes.byref(opt) if opt is not None else None,
+                                  ctypes.byref(b))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_workspace_size")
+    return int(b.value)
+
+
+def lm_plan_create_in(lat: lm_lattice, opt: lm_options | None, d_workspace: int, nbytes: int,
+                      stream: int | None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    rc = load().lm_plan_create_in(ctypes.byref(h), ctypes.byref(lat), ctypes.byref(opt) if opt is not None else None,
+                                  ctypes.c_void_p(d_workspace), int(nbytes), ctypes.c_void_p(stream or 0))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_plan_create_in")
+    return h
+
+
+def lm_plan_create_end_radii(lat: lm_lattice, d_end_radius: int, rel_tol: float, d_radius: int,
+                             stream: int | None):
+    """(plan, mismatching nodes); raises LatmeshError (code
+    LM_ERR_RADIUS_MISMATCH) when end radii at a node differ."""
+    h = ctypes.c_void_p()
+    nm = ctypes.c_int64(0)
+    rc = load().lm_plan_create_end_radii(ctypes.byref(h), ctypes.byref(lat), ctypes.c_void_p(d_end_radius),
+                                         float(rel_tol), ctypes.c_void_p(d_radius), ctypes.byref(nm),
+                                         ctypes.c_void_p(stream or 0))
+    if rc != LM_OK:
+        err = LatmeshError(rc, "lm_plan_create_end_radii")
+        err.n_mismatch = int(nm.value)
+        raise err
+    return h, int(nm.value)
+
+
+def lm_end_radius_gradient(plan, d_grad_radius: int, d_grad_end: int) -> None:
+    rc = load().lm_end_radius_gradient(plan, ctypes.c_void_p(d_grad_radius), ctypes.c_void_p(d_grad_end))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_end_radius_gradient")
 
 
 def lm_count(plan, k: int) -> lm_totals:
@@ -392,9 +463,14 @@ class MeshResult:
 
 class Mesher:
     """Owns device copies of a lattice and one plan.  ``lat`` is any object
-    with x, y, z, radius (float32) and strut_a, strut_b (int32) arrays."""
+    with x, y, z, radius (float32) and strut_a, strut_b (int32) arrays.
+    ``options`` (an lm_options): the plan takes all of its device memory from
+    one buffer allocated here (lm_plan_create_in) instead of allocating it
+    itself.  ``end_radius`` ([S, 2] per-strut end radii): the node radii are
+    derived from them (lm_plan_create_end_radii, tolerance ``rel_tol``)."""
 
-    def __init__(self, lat, device: str = "cuda:0", kappa_max: float | None = None):
+    def __init__(self, lat, device: str = "cuda:0", kappa_max: float | None = None, options=None,
+                 end_radius=None, rel_tol: float = 0.0):
         import torch
 
         if not torch.cuda.is_available():
@@ -425,9 +501,21 @@ class Mesher:
             self.sa.data_ptr(),
             self.sb.data_ptr(),
         )
+        self.workspace = None
+        self.end_radius = None
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream().cuda_stream
-            self.plan = lm_plan_create(self._lat, self.stream)
+            if end_radius is not None:
+                self.end_radius = f(end_radius, torch.float32).reshape(-1, 2).contiguous()
+                self.plan, _ = lm_plan_create_end_radii(self._lat, self.end_radius.data_ptr(), rel_tol,
+                                                        self.r.data_ptr(), self.stream)
+            elif options is not None:
+                nb = lm_workspace_size(self.n_nodes, self.n_struts, options)
+                # 256-byte aligned (the caching allocator aligns blocks to 512)
+                self.workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=self.device)
+                self.plan = lm_plan_create_in(self._lat, options, self.workspace.data_ptr(), nb, self.stream)
+            else:
+                self.plan = lm_plan_create(self._lat, self.stream)
         if kappa_max is not None:
             lm_set_precision(self.plan, kappa_max)
         self.totals = None
@@ -576,9 +664,21 @@ class Mesher:
         r.node_status = r.node_status[: self.n_nodes]
         return r
 
-    def forward(self, k: int, r: MeshResult) -> None:
+    def forward(self, k: int, r: MeshResult, check: bool = False) -> None:
+        """lm_forward into ``r``; with check, synchronise and raise when the
+        pass skipped writes (buffers or records too small) or its mesh sizes
+        differ from r.totals (a different topology than the buffers hold)."""
         lm_forward(self.plan, k, self.outputs(r))
         self.k = k
+        if check:
+            rc, t = lm_read_totals_rc(self.plan)
+            if rc != LM_OK:
+                raise LatmeshError(rc, "lm_forward")
+            t = t.as_dict()
+            for key in ("n_mesh_vertices", "n_triangles"):
+                if t[key] != r.totals[key]:
+                    raise LatmeshError(LM_ERR_STATE, f"lm_forward: {key} {t[key]} differs from the buffers' "
+                                                     f"{r.totals[key]} (topology changed)")
 
     def loss(self, r: MeshResult, weights=(1.0, 0.0, 0.0), p0=(0.0, 0.0, 0.0)):
         """Loss terms (area, volume about p0, sum |v|^2) of the mesh in ``r``
@@ -591,6 +691,14 @@ class Mesher:
                             (ctypes.c_float * 3)(*[float(x) for x in p0]))
         lm_loss(self.plan, self.outputs(r), w, terms.data_ptr(), dl.data_ptr())
         return terms, dl
+
+    def end_radius_grad(self, grad_radius):
+        """[S, 2] gradient with respect to the end radii of a plan made from
+        end radii, from a gradient with respect to the node radii."""
+        torch = self.torch
+        g = torch.empty((self.n_struts, 2), dtype=torch.float32, device=self.device)
+        lm_end_radius_gradient(self.plan, grad_radius.contiguous().data_ptr(), g.data_ptr())
+        return g
 
     def backward(self, dl_dx):
         """Gradient with respect to node centres [N, 3] and radii [N] of a
@@ -654,7 +762,9 @@ def mesh_function():
         @staticmethod
         def forward(ctx, xyz, radius, mesher, k, result):
             mesher.set_inputs(xyz.detach(), radius.detach())
-            mesher.forward(k, result)
+            # raises if the new inputs changed the topology the buffers were
+            # sized for (then the adjoint would not match the mesh)
+            mesher.forward(k, result, check=True)
             ctx.mesher = mesher
             return result.mesh_xyz.clone()
 

@@ -33,7 +33,7 @@ def test_status_strings_and_invalid_args():
     from paper_2405_15197_amd import latmesh
 
     lib = latmesh.load()
-    for code in range(-8, 1):
+    for code in range(-9, 1):
         assert latmesh.lm_status_string(code) != "unknown status"
     # null plan pointer is rejected without touching the GPU
     assert lib.lm_count(None, 8, ctypes.byref(latmesh.lm_totals())) == latmesh.LM_ERR_INVALID_ARG
@@ -76,6 +76,45 @@ def test_structs_match_header_layout():
     assert ctypes.sizeof(latmesh.lm_outputs) == 8 * 13
     assert ctypes.sizeof(latmesh.lm_arc_codes) == 8 * 5
     assert ctypes.sizeof(latmesh.lm_stl_stats) == 8 * 8
+    assert ctypes.sizeof(latmesh.lm_options) == 4 + 4 + 8 + 8
+
+
+def test_workspace_size_is_host_only_and_additive():
+    """lm_workspace_size computes sizes on the host: each optional part adds
+    to the fixed part, the record space follows record_bytes or k_max, and
+    bad options are refused."""
+    from paper_2405_15197_amd import latmesh
+
+    lib = latmesh.load()
+    N, S = 536769, 2097152
+
+    def size(flags=0, k=16, rec=0, parts=0):
+        return latmesh.lm_workspace_size(N, S, latmesh.lm_options(flags, k, rec, parts))
+
+    base = size(rec=1 << 20)
+    assert base >= 108 * N + 76 * S  # adjacency, counts, offsets, queues
+    assert size(latmesh.LM_WS_GRADIENT, rec=1 << 20) - base >= 24 * N + 32 * S
+    assert size(latmesh.LM_WS_SINK, rec=1 << 20, parts=512) - base >= 4 * S + 512 * 64 * 8 * 8
+    assert size(latmesh.LM_WS_RETRI, rec=1 << 20) - base >= (1 << 20) + 12 * N
+    assert size(rec=2 << 20) - base == 1 << 20
+    assert size(k=32) > size(k=16)
+    assert latmesh.lm_workspace_size(N, S, None) == size()
+    b = ctypes.c_size_t()
+    for bad in (latmesh.lm_options(0, 2, 0, 0), latmesh.lm_options(0, 16, -1, 0), latmesh.lm_options(8, 16, 0, 0),
+                latmesh.lm_options(0, 16, 0, -1)):
+        assert lib.lm_workspace_size(N, S, ctypes.byref(bad), ctypes.byref(b)) == latmesh.LM_ERR_INVALID_ARG
+    assert lib.lm_workspace_size(-1, S, None, ctypes.byref(b)) == latmesh.LM_ERR_INVALID_ARG
+    assert lib.lm_workspace_size(1 << 31, S, None, ctypes.byref(b)) == latmesh.LM_ERR_UNSUPPORTED
+    h = ctypes.c_void_p()
+    lat = latmesh.lm_lattice(4, 1, 1, 1, 1, 1, 1, 1)
+    # unaligned or missing workspace: refused before any HIP call
+    assert lib.lm_plan_create_in(ctypes.byref(h), ctypes.byref(lat), None, ctypes.c_void_p(8), 1 << 30,
+                                 None) == latmesh.LM_ERR_INVALID_ARG
+    assert lib.lm_plan_create_in(ctypes.byref(h), ctypes.byref(lat), None, None, 1 << 30,
+                                 None) == latmesh.LM_ERR_INVALID_ARG
+    assert lib.lm_plan_create_end_radii(ctypes.byref(h), ctypes.byref(lat), None, ctypes.c_float(0.0), None, None,
+                                        None) == latmesh.LM_ERR_INVALID_ARG
+    assert lib.lm_end_radius_gradient(None, None, None) == latmesh.LM_ERR_INVALID_ARG
 
 
 def test_generators_are_seeded_and_counted():

@@ -1,0 +1,190 @@
+"""The C-ABI boundary on the GPU: a plan in caller-owned device memory
+(lm_workspace_size / lm_plan_create_in) gives the bits of a library-owned
+plan in every mode and refuses what it was not sized for; per-strut end radii
+(lm_plan_create_end_radii) give the node radii of Sec. 4.1 or
+LM_ERR_RADIUS_MISMATCH; lm_loss and the adjoint refuse meshes that do not fit
+their buffers."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import latgen
+from parity import result_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _line(msg):
+    print(msg, flush=True)
+
+
+def _arrays(r):
+    return result_np(r)
+
+
+def test_caller_workspace_matches_library_plan():
+    import torch
+
+    from paper_2405_15197_amd import Mesher
+    from paper_2405_15197_amd.latmesh import LM_WS_GRADIENT, LM_WS_RETRI, LM_WS_SINK, lm_options
+
+    lat = latgen.config(2, scale=6, seed=8)
+    k = 16
+    opts = lm_options(LM_WS_SINK | LM_WS_GRADIENT | LM_WS_RETRI, k, 0, 4)
+    out = []
+    for o in (None, opts):
+        M = Mesher(lat, options=o)
+        try:
+            r = M.run(k)
+            a = _arrays(r)
+            terms, dl = M.loss(r, (1.0, 0.5, 0.25))
+            gx, gr = M.backward(dl)
+            a["grad"] = np.concatenate([gx.cpu().numpy().ravel(), gr.cpu().numpy()])
+            a["terms"] = terms.cpu().numpy()
+            a["retri"] = _arrays(M.retriangulate(9))["tri"]
+            a["sink"] = M.sink(k, 97)
+            off = np.array([0, 100, lat.n_nodes // 2, lat.n_nodes], np.int64)
+            a["batched"] = M.batched(off, np.array([8, 16, 32], np.int32))
+            torch.cuda.synchronize()
+            out.append(a)
+        finally:
+            M.close()
+    lib, ws = out
+    for key in lib:
+        if key == "totals":
+            continue
+        assert np.array_equal(lib[key], ws[key]), key
+
+
+def test_caller_workspace_limits():
+    import torch
+
+    from paper_2405_15197_amd import Mesher
+    from paper_2405_15197_amd import latmesh as L
+
+    lat = latgen.config(2, scale=5, seed=2)
+    k = 16
+    # too small a buffer: refused before the plan exists
+    nb = L.lm_workspace_size(lat.n_nodes, lat.n_struts, L.lm_options(0, k, 0, 0))
+    buf = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    M = Mesher(latgen.config(2, scale=2))  # device copies of a lattice for the ctypes call
+    try:
+        with pytest.raises(L.LatmeshError) as ei:
+            L.lm_plan_create_in(M._lat, L.lm_options(L.LM_WS_SINK, k, 0, 4), buf.data_ptr(), 1024, M.stream)
+        assert ei.value.code == L.LM_ERR_CAPACITY
+    finally:
+        M.close()
+    # record space too small: lm_count says so and reports the bytes it needs
+    M = Mesher(lat, options=L.lm_options(0, k, 4096, 0))
+    try:
+        t = L.lm_totals()
+        rc = L.load().lm_count(M.plan, k, ctypes.byref(t))
+        assert rc == L.LM_ERR_CAPACITY
+        need = t.n_record_bytes
+        assert need > 4096
+        # parts not sized in are unsupported, the ablation too
+        assert L.load().lm_set_schedule(M.plan, 1) == L.LM_ERR_UNSUPPORTED
+        o = torch.zeros((4, 8), dtype=torch.int64, device="cuda")
+        assert L.load().lm_forward_sink(M.plan, k, 64, ctypes.c_void_p(o.data_ptr()), 4) == L.LM_ERR_UNSUPPORTED
+    finally:
+        M.close()
+    # sized from that report: it runs and equals a library-owned plan
+    M = Mesher(lat, options=L.lm_options(0, k, need + need // 8, 0))
+    try:
+        a = _arrays(M.run(k))
+        with pytest.raises(L.LatmeshError) as ei:
+            M.loss(M.run(k, meta=False))
+        assert ei.value.code == L.LM_ERR_UNSUPPORTED  # no LM_WS_GRADIENT
+    finally:
+        M.close()
+    b = _arrays_of(lat, k)
+    assert np.array_equal(a["tri"], b["tri"]) and np.array_equal(a["mesh"], b["mesh"])
+
+
+def _arrays_of(lat, k):
+    from parity import gpu_result
+
+    return gpu_result(lat, k)
+
+
+def test_end_radii_plan():
+    """End radii equal at each node: the same mesh as the node radii; the
+    end-radius gradient is the node gradient shared over the node's struts;
+    unequal end radii are refused with the number of nodes concerned."""
+    import torch
+
+    from paper_2405_15197_amd import Mesher
+    from paper_2405_15197_amd import latmesh as L
+
+    lat = latgen.config(4, scale=3, seed=5)
+    k = 12
+    sa, sb = lat.strut_a.astype(np.int64), lat.strut_b.astype(np.int64)
+    ends = np.stack([lat.radius[sa], lat.radius[sb]], 1).astype(np.float32)
+    ref = _arrays_of(lat, k)
+    M = Mesher(lat, end_radius=ends)
+    try:
+        assert np.array_equal(M.r.cpu().numpy(), lat.radius)
+        r = M.run(k)
+        a = _arrays(r)
+        assert np.array_equal(a["tri"], ref["tri"]) and np.array_equal(a["mesh"], ref["mesh"])
+        terms, dl = M.loss(r, (1.0, 0.0, 0.0))
+        gx, gr = M.backward(dl)
+        ge = M.end_radius_grad(gr).cpu().numpy()
+        gr = gr.cpu().numpy()
+        deg = np.bincount(np.concatenate([sa, sb]), minlength=lat.n_nodes)
+        np.testing.assert_allclose(ge[:, 0], gr[sa] / deg[sa], rtol=1e-6)
+        np.testing.assert_allclose(ge[:, 1], gr[sb] / deg[sb], rtol=1e-6)
+    finally:
+        M.close()
+    bad = ends.copy()
+    bad[3, 0] *= 1.01  # one end of strut 3 differs at node strut_a[3]
+    with pytest.raises(L.LatmeshError) as ei:
+        Mesher(lat, end_radius=bad, rel_tol=1e-3)
+    assert ei.value.code == L.LM_ERR_RADIUS_MISMATCH and ei.value.n_mismatch == 1
+    M = Mesher(lat, end_radius=bad, rel_tol=0.02)  # within the tolerance: the mean
+    try:
+        n = int(sa[3])
+        exp = np.float32(np.mean([bad[s, 0] if sa[s] == n else bad[s, 1] for s in np.nonzero((sa == n) | (sb == n))[0]]))
+        assert abs(float(M.r[n].item()) - float(exp)) <= 1e-6 * float(exp)
+    finally:
+        M.close()
+    torch.cuda.synchronize()
+
+
+def test_loss_refuses_small_buffers():
+    """After lm_count the host refuses; after lm_forward (sizes on the device)
+    the kernels write nothing and lm_read_totals reports LM_ERR_CAPACITY; an
+    autograd forward whose topology differs from its buffers raises."""
+    import torch
+
+    from paper_2405_15197_amd import Mesher
+    from paper_2405_15197_amd import latmesh as L
+
+    lat = latgen.config(2, scale=4, seed=3)
+    k = 12
+    M = Mesher(lat)
+    try:
+        t = M.count(k)
+        small = dict(t)
+        small["n_mesh_vertices"] -= 1
+        r = M.alloc(small, meta=False)
+        with pytest.raises(L.LatmeshError) as ei:
+            M.loss(r)
+        assert ei.value.code == L.LM_ERR_CAPACITY
+        # lm_forward into the small buffers: skipped on the device
+        M.forward(k, r)
+        terms, dl = M.loss(r)
+        gx, gr = M.backward(dl)
+        torch.cuda.synchronize()
+        rc, _ = L.lm_read_totals_rc(M.plan)
+        assert rc == L.LM_ERR_CAPACITY
+        assert float(terms.abs().sum().item()) == 0.0 and float(gx.abs().sum().item()) == 0.0
+        with pytest.raises(L.LatmeshError):
+            M.forward(k, r, check=True)
+        # buffers of the right size: fine again
+        r = M.alloc(t, meta=False)
+        M.forward(k, r, check=True)
+    finally:
+        M.close()

@@ -110,34 +110,46 @@ def test_knn_retriangulate_equals_forward():
         assert np.array_equal(a[key], b[key]), key
 
 
-def test_knn_gradient_matches_oracle():
-    """The adjoint of high-valence nodes (their own kernel instantiation)
-    against the oracle's FP64 central differences, on every parameter of
-    the nodes above 16 struts of a small k-NN lattice."""
+def _fib_dirs(n, wobble=0.1):
+    i = np.arange(n) + 0.5
+    phi = np.arccos(1 - 2 * i / n)
+    th = np.pi * (1 + 5 ** 0.5) * i + wobble * np.sin(7 * i)
+    return np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
+
+
+@pytest.mark.parametrize("nstrut", [20, 31])
+def test_high_valence_gradient_matches_oracle(nstrut):
+    """The adjoint of a node of more than 16 struts (its own kernel
+    instantiation, over the multi-wave class's queue) against the oracle's
+    FP64 central differences: every parameter of the centre node and of
+    three of its neighbours, conical struts (seeded end-node radii)."""
     import torch
 
     from paper_2405_15197_amd import Mesher
 
-    lat = latgen.knn(4, 17, radius=RAD, seed=417)
+    rng = np.random.default_rng(nstrut)
+    d = _fib_dirs(nstrut) * rng.uniform(0.8, 1.2, size=(nstrut, 1))
+    radii = np.concatenate([[0.08], rng.uniform(0.04, 0.07, size=nstrut)])
+    xyz = np.concatenate([np.zeros((1, 3)), d])
+    lat = latgen.lattice_from_arrays(xyz, radii, [(0, i + 1) for i in range(nstrut)])
     k = 12
     R = oracle.run(lat, k)
-    v = _valence(lat)
-    nodes = np.nonzero((v > 16) & (R.status == 0) & (R.margin >= 1e-3))[0][:6]
-    assert len(nodes) > 0
-    params = [(int(n), c) for n in nodes for c in range(4)]
+    assert (R.status == 0).all()
+    params = [(n, c) for n in (0, 1, 5, nstrut) for c in range(4)]
+    G, ok = oracle.fd_gradient(lat, k, params, weights=[(1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0)])
+    assert ok.all()
     M = Mesher(lat)
     try:
         r = M.run(k, meta=False)
-        terms, dl = M.loss(r, (1.0, 0.0, 0.0))
-        gx, gr = M.backward(dl)
-        torch.cuda.synchronize()
-        gx, gr = gx.cpu().numpy().astype(np.float64), gr.cpu().numpy().astype(np.float64)
+        for wi, w in enumerate(((1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0))):
+            terms, dl = M.loss(r, w)
+            gx, gr = M.backward(dl)
+            torch.cuda.synchronize()
+            gx, gr = gx.cpu().numpy().astype(np.float64), gr.cpu().numpy().astype(np.float64)
+            g_gpu = np.array([gx[n, c] if c < 3 else gr[n] for n, c in params])
+            g_orc = G[:, wi]
+            tol = 1e-3 * np.abs(g_orc) + 1e-4 * np.abs(g_orc).max()
+            err = np.abs(g_gpu - g_orc)
+            assert (err <= tol).all(), (wi, (err / tol).max(), params[int(np.argmax(err / tol))])
     finally:
         M.close()
-    G, ok = oracle.fd_gradient(lat, k, params, weights=(1.0, 0.0, 0.0))
-    g_gpu = np.array([gx[n, c] if c < 3 else gr[n] for n, c in params])
-    assert ok.mean() >= 0.75
-    sel = ok
-    tol = 1e-3 * np.abs(G[sel]) + 1e-4 * np.abs(G[sel]).max()
-    err = np.abs(g_gpu[sel] - G[sel])
-    assert (err <= tol).all(), (err / tol).max()

@@ -63,8 +63,34 @@ def test_config_parity(name, make, k):
     st = compare(lat, k, R=R, G=G)
     chi, vol = check_closed(G, lat)
     _line(f"  {st}; closed, chi {chi}, volume {vol:.4g}")
-    # exact symmetry (no jitter) leaves more nodes below the margins
-    assert st["stable"] >= (0.97 if "unjittered" in name else 0.99) * lat.n_nodes
+    # small lattices: a handful of nodes below the margins
+    assert st["stable"] >= 0.98 * lat.n_nodes
+
+
+BUDGET = [
+    # the benchmark lattice's family (BCC, radii U[0.05, 0.12], jitter 0.05)
+    ("cfg2_bcc16", lambda: latgen.config(2, scale=16, seed=5), 16, 0.003),
+    # the billion-strut lattice's family (BCC, radii 0.08 (1 +- 0.1), no jitter)
+    ("cfg3_bcc14", lambda: latgen.config(3, scale=14, seed=2), 12, 0.02),
+]
+
+
+@pytest.mark.parametrize("name,make,k,budget", BUDGET, ids=[c[0] for c in BUDGET])
+def test_exclusion_budget(name, make, k, budget):
+    """Nodes below the comparison margins stay within the budget (0.3 % on
+    the benchmark family, 2 % on the unjittered billion-strut family), every
+    other node and strut equals the oracle, and the whole GPU mesh is closed
+    and oriented (so the excluded nodes are checked for a valid surface)."""
+    lat = make()
+    R = oracle.run(lat, k)
+    G = gpu_result(lat, k)
+    st = compare(lat, k, R=R, G=G)
+    chi, vol = check_closed(G, lat)
+    excl = 1.0 - st["stable"] / lat.n_nodes
+    strut_excl = 1.0 - (st["stable_struts"] + st["tied_struts"]) / lat.n_struts
+    _line(f"  {st}; excluded nodes {excl:.4%}, struts compared by vertex set only {st['tied_struts']}, "
+          f"not compared {strut_excl:.4%}; closed, chi {chi}")
+    assert excl <= budget
 
 
 def test_full_config2_sampled():
