@@ -72,6 +72,20 @@ def node_kernel_bytes(lat, t):
     return read + 16 * t["n_vertices"] + 56 * t["n_arcs"]
 
 
+def host_cpu():
+    """CPU model and logical CPU count of the host (from /proc/cpuinfo)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
 def cpu_baseline(scale: int, k: int, threads: int):
     import latgen
     import oracle
@@ -86,6 +100,8 @@ def cpu_baseline(scale: int, k: int, threads: int):
         "unit": "struts/s",
         "cores": threads,
         "kind": "oracle",
+        "cpu_model": host_cpu()[0],
+        "host_logical_cpus": host_cpu()[1],
         "sample": f"BCC {scale}^3 cells ({lat.n_nodes} nodes, {lat.n_struts} struts), k={k}, same seeded "
         f"distributions as the GPU workload, meta-mesh + triangulation, FP64 C oracle, {dt:.1f} s wall",
         "triangles_per_s": len(R.tris) / dt,
@@ -416,7 +432,18 @@ def billion_bench(k: int = 12, chunk_nodes: int = 1 << 23, scale: int = 512):
     }
 
 
-def batched_bench(n_parts: int = 512, n_max: int = 64, seed: int = 1):
+def make_parts(n_parts: int = 512, n_max: int = 64, seed: int = 1):
+    """The batched workload's parts, built on the host in worker processes
+    (before this process touches the GPU); returns (parts, seconds)."""
+    import latgen
+
+    t0 = time.perf_counter()
+    print(f"[bench] generating {n_parts} parts", file=sys.stderr, flush=True)
+    parts = latgen.parts(n_parts, seed=seed, n_max=n_max, workers=min(16, os.cpu_count() or 1))
+    return parts, time.perf_counter() - t0
+
+
+def batched_bench(n_parts: int = 512, n_max: int = 64, seed: int = 1, pre=None):
     """512 lattice parts (cubic, BCC, octet or random k-NN, 4..64 cells per
     side, radii U[0.04, 0.12], resolutions 8/16/32) meshed in sink mode:
     batched (one plan, autotuned wave mapping and group size, one node pass
@@ -429,12 +456,11 @@ def batched_bench(n_parts: int = 512, n_max: int = 64, seed: int = 1):
     from paper_2405_15197_amd.autotune import tune
     from paper_2405_15197_amd.latmesh import Mesher, lm_prepare
 
+    parts, t_gen = pre if pre is not None else make_parts(n_parts, n_max, seed)
     t0 = time.perf_counter()
-    print(f"[bench] generating {n_parts} parts", file=sys.stderr, flush=True)
-    parts = latgen.parts(n_parts, seed=seed, n_max=n_max)
     lat, off = latgen.union([p[0] for p in parts])
     ks = np.array([p[1] for p in parts], np.int32)
-    t_gen = time.perf_counter() - t0
+    t_gen += time.perf_counter() - t0
     print(f"[bench] {lat.n_nodes} nodes, {lat.n_struts} struts ({t_gen:.0f} s); autotuning", file=sys.stderr,
           flush=True)
     best, table = tune(parts, latgen.union, sample=32)
@@ -508,6 +534,8 @@ def main():
                     help="only the BCC 512^3 lattice in sink mode (generated on the device), one pass")
     ap.add_argument("--billion-scale", type=int, default=512)
     ap.add_argument("--batched", action="store_true", help="only the 512-part batch (sink mode), batched vs sequential")
+    ap.add_argument("--no-billion", action="store_true", help="skip the billion-strut sink leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-part batched leg")
     ap.add_argument("--batched-parts", type=int, default=512)
     ap.add_argument("--batched-nmax", type=int, default=64)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -538,6 +566,9 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is in the "
               "design notes and not built", file=sys.stderr)
         sys.exit(2)
+    # the batched leg's parts are built first, in worker processes forked
+    # before anything here initialises the GPU
+    pre_parts = None if args.no_batched else make_parts(args.batched_parts, args.batched_nmax)
 
     import torch
 
@@ -645,7 +676,16 @@ def main():
     if not args.no_adjoint:
         print("[bench] forward + adjoint on octet 32^3", file=sys.stderr, flush=True)
         res["fwd_bwd"] = adjoint_bench(args.steps, args.warmup)
+    if not args.no_billion:
+        print("[bench] billion-strut lattice in sink mode", file=sys.stderr, flush=True)
+        res["billion"] = billion_bench(scale=args.billion_scale)
+    if not args.no_batched:
+        print("[bench] 512-part batch", file=sys.stderr, flush=True)
+        res["batched"] = batched_bench(args.batched_parts, args.batched_nmax, pre=pre_parts)
+        pre_parts = None
     if not args.no_cpu_baseline:
+        # one GPU's share of the host is 16 hardware threads, whatever
+        # os.cpu_count() reports for the whole machine
         threads = min(16, os.cpu_count() or 1)
         print(f"[bench] CPU oracle baseline on {threads} threads", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(args.cpu_scale, args.k, threads)

@@ -142,11 +142,16 @@ def cubic(n, radius=0.1, jitter=0.0, seed=1, cell=1.0) -> Lattice:
     return _finish(pos, seed, radius, jitter, cell, np.concatenate(st), f"cubic{n}")
 
 
-def bcc(n, radius=0.1, jitter=0.0, seed=1, cell=1.0) -> Lattice:
+def bcc(n, radius=0.1, jitter=0.0, seed=1, cell=1.0, order="grid") -> Lattice:
     """Body-centred cubic lattice of n^3 cells.
 
-    Nodes: (n+1)^3 cell corners, then n^3 body centres.  Struts: the 8 half
-    body diagonals of every cell (corner -> centre), 8 n^3 in total.
+    Nodes: (n+1)^3 cell corners and n^3 body centres.  Struts: the 8 half
+    body diagonals of every cell (corner -> centre), 8 n^3 in total, cell by
+    cell.  ``order`` numbers the nodes: "grid" lists all corners (x fastest),
+    then all centres; "layer" lists layer z = 0, 1, ..., n, each as its corners
+    followed by the centres just above it, so that a range of consecutive node
+    ids is a slab whose only higher-id neighbours outside it are the next
+    corner layer.  Random draws are keyed by the node id in either order.
     """
     m = n + 1
     k, j, i = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
@@ -154,14 +159,26 @@ def bcc(n, radius=0.1, jitter=0.0, seed=1, cell=1.0) -> Lattice:
     k, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
     ci, cj, ck = i.ravel(), j.ravel(), k.ravel()
     centres = np.stack([ci, cj, ck], axis=1).astype(np.float64) + 0.5
-    pos = np.concatenate([corners, centres])
-    cid = m**3 + ci + n * (cj + n * ck)
+    if order == "grid":
+        corner_id = lambda a, b, c: a + m * (b + m * c)  # noqa: E731
+        cid = m**3 + ci + n * (cj + n * ck)
+        pos = np.concatenate([corners, centres])
+    elif order == "layer":
+        B = m * m + n * n  # ids per layer below the top one
+        corner_id = lambda a, b, c: c * B + a + m * b  # noqa: E731
+        cid = ck * B + m * m + ci + n * cj
+        pos = np.empty((m**3 + n**3, 3))
+        pos[corner_id(corners[:, 0].astype(np.int64), corners[:, 1].astype(np.int64),
+                      corners[:, 2].astype(np.int64))] = corners
+        pos[cid] = centres
+    else:
+        raise ValueError(f"unknown node order {order!r}")
     st = np.empty((n**3, 8, 2), dtype=np.int64)
     for c in range(8):
         di, dj, dk = c & 1, (c >> 1) & 1, (c >> 2) & 1
-        st[:, c, 0] = (ci + di) + m * ((cj + dj) + m * (ck + dk))
+        st[:, c, 0] = corner_id(ci + di, cj + dj, ck + dk)
         st[:, c, 1] = cid
-    return _finish(pos, seed, radius, jitter, cell, st.reshape(-1, 2), f"bcc{n}")
+    return _finish(pos, seed, radius, jitter, cell, st.reshape(-1, 2), f"bcc{n}" + ("" if order == "grid" else "L"))
 
 
 def octet(n, radius=0.1, jitter=0.0, seed=1, cell=1.0) -> Lattice:
@@ -211,11 +228,8 @@ def knn(n, kn, radius=0.1, seed=1, cell=1.0) -> Lattice:
 FIELD_PART = 16  # fields of the per-part draws
 
 
-def parts(n_parts=512, seed=1, n_max=64, n_min=4):
-    """The batched workload: ``n_parts`` lattice parts, each a cubic, BCC,
-    octet or random k-NN lattice (uniform choice) with cells per side drawn
-    from {n_min..n_max}, k-NN degree from {3..20}, node radii U[0.04, 0.12],
-    and a resolution from {8, 16, 32}.  Returns a list of (Lattice, k)."""
+def _part_specs(n_parts, seed, n_max, n_min):
+    """(kind, cells, resolution, k-NN degree, seed) of every part."""
     pid = np.arange(n_parts, dtype=np.uint64)
     u = [uniform(seed, pid, FIELD_PART + f) for f in range(4)]
     out = []
@@ -223,18 +237,43 @@ def parts(n_parts=512, seed=1, n_max=64, n_min=4):
         kind = min(int(u[0][p] * 4), 3)
         n = n_min + min(int(u[1][p] * (n_max - n_min + 1)), n_max - n_min)
         res = (8, 16, 32)[min(int(u[2][p] * 3), 2)]
-        rad = ("uniform", 0.04, 0.12)
-        s = seed * 1000003 + p
-        if kind == 0:
-            lat = cubic(n, radius=rad, jitter=0.0, seed=s)
-        elif kind == 1:
-            lat = bcc(n, radius=rad, jitter=0.0, seed=s)
-        elif kind == 2:
-            lat = octet(n, radius=rad, jitter=0.0, seed=s)
-        else:
-            kn = 3 + min(int(u[3][p] * 18), 17)
-            lat = knn(n, kn, radius=rad, seed=s)
-        out.append((lat, res))
+        kn = 3 + min(int(u[3][p] * 18), 17)
+        out.append((kind, n, res, kn, seed * 1000003 + p))
+    return out
+
+
+def _make_part(spec):
+    kind, n, res, kn, s = spec
+    rad = ("uniform", 0.04, 0.12)
+    if kind == 0:
+        lat = cubic(n, radius=rad, jitter=0.0, seed=s)
+    elif kind == 1:
+        lat = bcc(n, radius=rad, jitter=0.0, seed=s)
+    elif kind == 2:
+        lat = octet(n, radius=rad, jitter=0.0, seed=s)
+    else:
+        lat = knn(n, kn, radius=rad, seed=s)
+    return lat, res
+
+
+def parts(n_parts=512, seed=1, n_max=64, n_min=4, workers=1):
+    """The batched workload: ``n_parts`` lattice parts, each a cubic, BCC,
+    octet or random k-NN lattice (uniform choice) with cells per side drawn
+    from {n_min..n_max}, k-NN degree from {3..20}, node radii U[0.04, 0.12],
+    and a resolution from {8, 16, 32}.  Returns a list of (Lattice, k).
+    ``workers`` > 1 builds the parts in that many processes (same result)."""
+    specs = _part_specs(n_parts, seed, n_max, n_min)
+    if workers <= 1 or n_parts < 2:
+        return [_make_part(s) for s in specs]
+    import multiprocessing as mp
+
+    # largest parts first, so the pool's tail is short
+    order = sorted(range(n_parts), key=lambda i: -specs[i][1])
+    with mp.get_context("fork").Pool(workers) as pool:
+        made = pool.map(_make_part, [specs[i] for i in order], chunksize=1)
+    out = [None] * n_parts
+    for i, r in zip(order, made):
+        out[i] = r
     return out
 
 
@@ -242,13 +281,20 @@ def union(lattices):
     """Disjoint union of lattices (node ids offset part by part); returns the
     union and the node offsets of the parts [n_parts + 1]."""
     off = np.zeros(len(lattices) + 1, np.int64)
+    soff = np.zeros(len(lattices) + 1, np.int64)
     for i, lat in enumerate(lattices):
         off[i + 1] = off[i] + lat.n_nodes
+        soff[i + 1] = soff[i] + lat.n_struts
+    if off[-1] >= 2**31:
+        raise ValueError("union has 2^31 nodes or more")
     cat = lambda f: np.concatenate([getattr(l, f) for l in lattices])  # noqa: E731
-    sa = np.concatenate([l.strut_a.astype(np.int64) + off[i] for i, l in enumerate(lattices)])
-    sb = np.concatenate([l.strut_b.astype(np.int64) + off[i] for i, l in enumerate(lattices)])
-    return Lattice(x=cat("x"), y=cat("y"), z=cat("z"), radius=cat("radius"), strut_a=sa.astype(np.int32),
-                   strut_b=sb.astype(np.int32), name=f"union{len(lattices)}"), off
+    sa = np.empty(soff[-1], np.int32)
+    sb = np.empty(soff[-1], np.int32)
+    for i, l in enumerate(lattices):
+        np.add(l.strut_a, np.int32(off[i]), out=sa[soff[i]:soff[i + 1]], dtype=np.int32)
+        np.add(l.strut_b, np.int32(off[i]), out=sb[soff[i]:soff[i + 1]], dtype=np.int32)
+    return Lattice(x=cat("x"), y=cat("y"), z=cat("z"), radius=cat("radius"), strut_a=sa, strut_b=sb,
+                   name=f"union{len(lattices)}"), off
 
 
 def two_strut(angle_deg=90.0, length=1.0, radius=0.1, radii=None) -> Lattice:
@@ -278,7 +324,8 @@ def config(i: int, seed: int = 1, scale: int | None = None) -> Lattice:
 
     1: simple cubic 6^3, radius 0.1, jitter 0.02 (resolution k = 8).
     2: BCC 64^3, node radii U[0.05, 0.12], jitter 0.05 (k = 16).
-    3: BCC 512^3, node radii 0.08 (1 + U[-0.1, 0.1]), no jitter (k = 12).
+    3: BCC 512^3, node radii 0.08 (1 + U[-0.1, 0.1]), no jitter (k = 12), nodes
+       numbered layer by layer (sink-mode chunks are slabs).
     4: octet 32^3, node radii U[0.04, 0.10], jitter 0.03 (k = 16).
     ``scale`` replaces the cell count n (same family and distributions).
     """
@@ -287,7 +334,7 @@ def config(i: int, seed: int = 1, scale: int | None = None) -> Lattice:
     if i == 2:
         return bcc(scale or 64, radius=("uniform", 0.05, 0.12), jitter=0.05, seed=seed)
     if i == 3:
-        return bcc(scale or 512, radius=("rel", 0.08, 0.1), jitter=0.0, seed=seed)
+        return bcc(scale or 512, radius=("rel", 0.08, 0.1), jitter=0.0, seed=seed, order="layer")
     if i == 4:
         return octet(scale or 32, radius=("uniform", 0.04, 0.10), jitter=0.03, seed=seed)
     raise ValueError(f"no config {i}")

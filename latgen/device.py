@@ -37,15 +37,15 @@ def _load():
             raise ImportError(f"{_LIB} is missing: run latgen.device.build() (or __graft_entry__.build())")
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
-        lib.lg_bcc.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                               ctypes.c_uint64, ctypes.c_double] + [P] * 7
+        lib.lg_bcc.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_uint64, ctypes.c_double] + [P] * 7
         lib.lg_bcc.restype = ctypes.c_int
         _lib = lib
     return _lib
 
 
-def bcc(n, radius=0.1, jitter=0.0, seed=1, cell=1.0, device="cuda:0"):
-    """latgen.bcc(n, radius, jitter, seed, cell) generated on the GPU; returns
+def bcc(n, radius=0.1, jitter=0.0, seed=1, cell=1.0, order="grid", device="cuda:0"):
+    """latgen.bcc(n, radius, jitter, seed, cell, order) generated on the GPU; returns
     a namespace of device tensors x, y, z, radius (float32), strut_a,
     strut_b (int32)."""
     import torch
@@ -60,18 +60,21 @@ def bcc(n, radius=0.1, jitter=0.0, seed=1, cell=1.0, device="cuda:0"):
         kind, a, b = 2, float(radius[1]), float(radius[2])
     else:
         raise ValueError(f"unknown radius spec {radius!r}")
+    if order not in ("grid", "layer"):
+        raise ValueError(f"unknown node order {order!r}")
     dev = torch.device(device)
     f = lambda k, dt: torch.empty(k, dtype=dt, device=dev)  # noqa: E731
     x, y, z, r = (f(N, torch.float32) for _ in range(4))
     sa, sb = f(S, torch.int32), f(S, torch.int32)
     with torch.cuda.device(dev):
         st = torch.cuda.current_stream().cuda_stream
-        rc = _load().lg_bcc(int(n), kind, a, b, float(jitter), int(seed), float(cell), x.data_ptr(), y.data_ptr(),
-                            z.data_ptr(), r.data_ptr(), sa.data_ptr(), sb.data_ptr(), ctypes.c_void_p(st))
+        rc = _load().lg_bcc(int(n), 0 if order == "grid" else 1, kind, a, b, float(jitter), int(seed), float(cell),
+                            x.data_ptr(), y.data_ptr(), z.data_ptr(), r.data_ptr(), sa.data_ptr(), sb.data_ptr(),
+                            ctypes.c_void_p(st))
     if rc != 0:
         raise RuntimeError(f"lg_bcc failed with HIP error {rc}")
     return types.SimpleNamespace(x=x, y=y, z=z, radius=r, strut_a=sa, strut_b=sb, n_nodes=N, n_struts=S,
-                                 name=f"bcc{n}")
+                                 name=f"bcc{n}" + ("" if order == "grid" else "L"))
 
 
 def config(i: int, seed: int = 1, scale: int | None = None, device="cuda:0"):
@@ -79,5 +82,5 @@ def config(i: int, seed: int = 1, scale: int | None = None, device="cuda:0"):
     if i == 2:
         return bcc(scale or 64, radius=("uniform", 0.05, 0.12), jitter=0.05, seed=seed, device=device)
     if i == 3:
-        return bcc(scale or 512, radius=("rel", 0.08, 0.1), jitter=0.0, seed=seed, device=device)
+        return bcc(scale or 512, radius=("rel", 0.08, 0.1), jitter=0.0, seed=seed, order="layer", device=device)
     raise ValueError(f"no device generator for config {i}")

@@ -10,6 +10,12 @@ namespace lm {
 // meshed by one wave (or a part of one); nodes of kVmax + 1 .. kVmaxBig by a
 // group of kBigWaves waves sharing the node's LDS.  A node beyond the limits
 // is flagged (its status bit is set) and emits nothing.
+// FP32 -> FP64 hand-over beside the condition number (kappa_max): a kept
+// conic whose centre or semi-major axis exceeds kConicMax rho, or a vertex
+// whose FP32 error bound exceeds kVertexErr rho (kFp32Eps: unit roundoff).
+constexpr float kConicMax = 4.0f;
+constexpr float kVertexErr = 4e-6f;
+constexpr float kFp32Eps = 5.9604645e-8f;
 constexpr int kVmax = 16;       // incident struts per node, one-wave classes
 constexpr int kAcap = 64;       // arcs per node, one-wave classes
 constexpr int kVcap = 64;       // meta-vertices per node, one-wave classes
@@ -96,7 +102,8 @@ __host__ __device__ inline int rec_table_bytes(int v, int nent, bool wide)
 {
     return (wide ? 2 : 1) * (v + 1 + nent);
 }
-constexpr uint32_t kRecFp64 = 1u << 24;  // header word 7: meshed in FP64
+constexpr uint32_t kRecFp64 = 1u << 24;  // header word 7: meshed in FP64 (its Eq. 12
+                                         // interior points follow the hole centres)
 constexpr uint32_t kRecWide = 1u << 25;  // header word 7: 16-bit loop table
 
 struct Inputs {

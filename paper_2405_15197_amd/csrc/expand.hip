@@ -44,6 +44,9 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
     const uint32_t *RV = R + kRecHead;
     const uint32_t *RA = RV + 4 * V;
     const uint32_t *RH = RA + kRecArcFields * E;
+    // a node meshed in FP64 stores its interior points after the hole centres
+    const bool fp64 = (R[7] & kRecFp64) != 0;
+    const uint32_t *RI = RH + 3 * NC - 3 * V;
 
     // arcs: whole 16-byte groups into LDS (the arc block starts on a 16-byte
     // boundary); every later read of an arc field is an LDS read.  The arcs
@@ -100,6 +103,8 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
         float3 w;
         if (i < V) {
             w = make_float3(fbits(RV[4 * i + 1]), fbits(RV[4 * i + 2]), fbits(RV[4 * i + 3]));
+        } else if (i < wsum && fp64) {
+            w = make_float3(fbits(RI[3 * i]), fbits(RI[3 * i + 1]), fbits(RI[3 * i + 2]));
         } else if (i < wsum) {
             int lo = 0, hi = E - 1;  // last arc with mbase <= i
             while (lo < hi) {

@@ -579,6 +579,11 @@ __device__ inline V3<T> interior_pt(const Shared<T, C> &sh, const ArcL<T> &A, in
 // (p, q) carries the rounding of that conic's parametrisation, large for a
 // long thin ellipse; these equations involve only quantities of the node's
 // scale, so the step leaves the error the tie's conditioning allows.
+// In FP32 the step's own residuals carry rounding of the size of their terms
+// (|g||w| for the plane equations, |w|^2 for the cone), amplified by the
+// inverse Jacobian; when that bound exceeds kVertexErr rho the node goes to
+// FP64 (a condition number alone misses vertices far from the node centre
+// on the seams of nearly parallel struts).
 template <typename T, typename C>
 __device__ inline void refine_vertex(Shared<T, C> &sh, int i, T rho)
 {
@@ -595,7 +600,18 @@ __device__ inline void refine_vertex(Shared<T, C> &sh, int i, T rho)
     const T f3 = dot(w, w) - rho * rho - s * s;
     const V3<T> c23 = cross(n2, n3), c31 = cross(n3, n1), c12 = cross(n1, n2);
     const T det = dot(n1, c23);
-    if (!(m_abs(det) > (T)0)) return;
+    if (!(m_abs(det) > (T)0)) {
+        if (sizeof(T) == 4) atomicOr(&sh.status, NS_PREC);
+        return;
+    }
+    if constexpr (sizeof(T) == 4) {
+        const T lw = m_sqrt(dot(w, w)), lgp = m_sqrt(dot(gp, gp));
+        const T lq = m_sqrt(dot(gvec(sh.S[q]), gvec(sh.S[q]))), lr = m_sqrt(dot(gvec(sh.S[r]), gvec(sh.S[r])));
+        // |c23| f1 + |c31| f2 + |c12| f3 with each f replaced by its rounding
+        const T bound = m_sqrt(dot(c23, c23)) * (lgp + lq) * lw + m_sqrt(dot(c31, c31)) * (lgp + lr) * lw +
+                        m_sqrt(dot(c12, c12)) * (lw * lw + s * s + rho * rho);
+        if (bound * (T)kFp32Eps > (T)kVertexErr * rho * m_abs(det)) atomicOr(&sh.status, NS_PREC);
+    }
     const V3<T> d = (c23 * f1 + c31 * f2 + c12 * f3) * ((T)-1 / det);
     sh.vx[i] = w.x + d.x;
     sh.vy[i] = w.y + d.y;
@@ -680,6 +696,11 @@ __device__ void sink_hash_node(const Params &P, Shared<T, CF> &sh, const int64_t
             const ArcL<T> &A = sh.A[lo];
             const bool fwd = A.full || A.ns <= A.ne;
             const int jc = i - A.mbase;
+            if constexpr (sizeof(T) == 8) {
+                // as stored for an FP64 node: the FP64 point rounded once
+                const V3<T> wd = interior_pt(sh, A, fwd ? jc + 1 : A.nseg - 1 - jc);
+                w = make_float3((float)wd.x, (float)wd.y, (float)wd.z);
+            } else {
             float o[3], a[3], b[3], x1[3] = {0.f, 0.f, 0.f};
             ffield(A.o, o);
             ffield(A.a, a);
@@ -691,6 +712,7 @@ __device__ void sink_hash_node(const Params &P, Shared<T, CF> &sh, const int64_t
             }
             w = arc_point_f32(o, a, b, x1, (float)A.t1, (float)A.dt, fwd ? jc + 1 : A.nseg - 1 - jc, A.nseg,
                               A.full != 0);
+            }
         } else {
             const int c = i - wsum;
             w = make_float3((float)sh.hc[c][0], (float)sh.hc[c][1], (float)sh.hc[c][2]);
@@ -869,8 +891,10 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
         if (lane == 0) {
             const int off = sh.entry_off[sh.loop_base[v + 1]];
             // record space: bump allocation in the node's region
+            // an FP64 node keeps its interior points after the hole centres
+            const int HX = NC + (F32 ? 0 : sh.wsum - V);
             const int64_t words =
-                (SINK ? 0 : rec_loop_word(V, E, NC, rec_table_bytes(v, sh.loop_base[v + 1], WIDE))) +
+                (SINK ? 0 : rec_loop_word(V, E, HX, rec_table_bytes(v, sh.loop_base[v + 1], WIDE))) +
                 (((int64_t)2 * off + 3) & ~(int64_t)3);
             const int g = (int)(n & (kRecRegions - 1));
             const int64_t region = W.rec_words / kRecRegions;
@@ -890,8 +914,9 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
         {
             const int nent = sh.loop_base[v + 1];
             const int ns_tot = sh.entry_off[nent];
+            const int HX = NC + (F32 ? 0 : sh.wsum - V);
             int2 *rl = sh.rec >= 0
-                           ? (int2 *)(W.rec + sh.rec + (SINK ? 0 : rec_loop_word(V, E, NC, rec_table_bytes(v, nent, WIDE))))
+                           ? (int2 *)(W.rec + sh.rec + (SINK ? 0 : rec_loop_word(V, E, HX, rec_table_bytes(v, nent, WIDE))))
                            : nullptr;
             // phi key and local mesh index of sample j of loop entry e
             auto sample = [&](int e, int j, int &li) -> T {
@@ -998,7 +1023,8 @@ finish:
         const int Msum = sh.wsum + NC, Fsum = sh.fsum;
         const int64_t rb = sh.rec;
         const int nent = sh.loop_base[v + 1];
-        const int64_t lw = SINK ? 0 : rec_loop_word(V, E, NC, rec_table_bytes(v, nent, WIDE));
+        const int HX = NC + (F32 ? 0 : sh.wsum - V);
+        const int64_t lw = SINK ? 0 : rec_loop_word(V, E, HX, rec_table_bytes(v, nent, WIDE));
         if constexpr (SINK) {
             over_lanes<WL, CF::VM>(lane, 0, v - 1, [&](int l) {
                 W.he_len[row + l] = sh.loop_len[l + 1];
@@ -1062,10 +1088,25 @@ finish:
             RH[3 * c + 1] = __float_as_uint((float)sh.hc[c][1]);
             RH[3 * c + 2] = __float_as_uint((float)sh.hc[c][2]);
         }
+        if constexpr (!F32) {
+            // Eq. 12 points evaluated in FP64 and rounded once: the FP32 arc
+            // fields of a large conic cannot reproduce them to 1e-5 rho
+            uint32_t *RI = RH + 3 * NC - 3 * V;  // indexed by node-local mesh index
+            for (int j = lane; j < E; j += WL) {
+                const ArcL<T> &A = sh.A[j];
+                for (int ii = 1; ii < A.nseg; ++ii) {
+                    const V3<T> w = interior_pt(sh, A, ii);
+                    const int idx = interior_idx(A, ii);
+                    RI[3 * idx] = __float_as_uint((float)w.x);
+                    RI[3 * idx + 1] = __float_as_uint((float)w.y);
+                    RI[3 * idx + 2] = __float_as_uint((float)w.z);
+                }
+            }
+        }
         // loop table (for re-subdivision at another resolution)
         using TabT = typename std::conditional<WIDE, uint16_t, uint8_t>::type;
         constexpr uint32_t kFwd = WIDE ? 0x8000u : 0x80u;
-        TabT *RT = (TabT *)(R + rec_table_word(V, E, NC));
+        TabT *RT = (TabT *)(R + rec_table_word(V, E, HX));
         over_lanes<WL, CF::VM>(lane, 0, v, [&](int l) { RT[l] = (TabT)sh.loop_base[l + 1]; });
         for (int e = lane; e < nent; e += WL) {
             const int m = sh.entry_m[e];
@@ -1194,6 +1235,12 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
                 if (act && ell) {
                     trim_finish(sh.S, p, q, C, gp, hp, st, TR);
                     if (TR.ovf) atomicOr(&sh.status, F32 ? NS_PREC : NS_CAPACITY);
+                    // a kept conic far larger than the node: its points (and the
+                    // parameters of its ends) lose its size over rho in relative
+                    // FP32 precision
+                    if (F32 && TR.n > 0 &&
+                        m_max(dot(C.o, C.o), dot(C.a, C.a)) > (T)(kConicMax * kConicMax) * rho * rho)
+                        atomicOr(&sh.status, NS_PREC);
                 }
             }
             // arcs of this conic, sorted by the smaller endpoint name
@@ -1666,8 +1713,10 @@ __device__ void node_retri(const Params &P, Shared<float, CF> &sh, const int64_t
 // left (its length is read on the device); 3: meta-meshing of the queue in
 // sink mode (end loops kept, vertices and fans hashed).
 enum { kModeMesh = 0, kModeRetri = 1, kModeRedo = 2, kModeSink = 3 };
+// At most 168 VGPRs: three waves per SIMD (LDS allows as many), where one
+// register more would leave two.
 template <typename C, int MODE>
-__global__ void __launch_bounds__(64) k_node32(Params P, int cls)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_node32(Params P, int cls)
 {
     constexpr int NPW = 64 / C::W;
     __shared__ Shared<float, C> sh[NPW];

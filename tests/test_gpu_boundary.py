@@ -86,8 +86,9 @@ def test_caller_workspace_limits():
         assert need > 4096
         # parts not sized in are unsupported, the ablation too
         assert L.load().lm_set_schedule(M.plan, 1) == L.LM_ERR_UNSUPPORTED
-        o = torch.zeros((4, 8), dtype=torch.int64, device="cuda")
-        assert L.load().lm_forward_sink(M.plan, k, 64, ctypes.c_void_p(o.data_ptr()), 4) == L.LM_ERR_UNSUPPORTED
+        nch = (lat.n_nodes + 63) // 64
+        o = torch.zeros((nch, 8), dtype=torch.int64, device="cuda")
+        assert L.load().lm_forward_sink(M.plan, k, 64, ctypes.c_void_p(o.data_ptr()), nch) == L.LM_ERR_UNSUPPORTED
     finally:
         M.close()
     # sized from that report: it runs and equals a library-owned plan
