@@ -322,6 +322,35 @@ int lm_get_profile(lm_plan *plan, double *ms, int64_t *calls, int n);
  * the last chunk only: lm_fill and lm_backward need a new lm_count. */
 int lm_forward_sink(lm_plan *plan, int k, int64_t chunk_nodes, uint64_t *d_out, int64_t n_chunks_cap);
 
+/* ---- sink mode without allocation ---------------------------------------
+ * For callers that cannot allocate device memory (tight serving loops, code
+ * that must not call hipMalloc): one lattice meshed in sink mode as a single
+ * chunk, every device buffer (adjacency, node lists, hash slots, node records)
+ * carved from a fixed array that the library holds in device memory,
+ * LM_STATIC_SCRATCH_BYTES on each GPU it runs on, kept until the process ends.
+ * Nothing is allocated, on the device or the host.  The BCC lattice of 24^3
+ * cells (29,449 nodes, 110,592 struts) at k = 16 needs 108 MiB;
+ * lm_static_scratch_size gives the exact need of a lattice. */
+#define LM_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* Bytes of the fixed array that lm_forward_sink_static needs for a lattice of
+ * n_nodes nodes and n_struts struts at resolution k (3..4096).  Host only. */
+int lm_static_scratch_size(int64_t n_nodes, int64_t n_struts, int k, size_t *bytes);
+
+/* The words of lm_forward_sink over the whole lattice as one chunk
+ * (d_words[LM_SINK_WORDS], device; see lm_forward_sink), computed without a
+ * plan and without allocating: the same validation, adjacency, node pass and
+ * band hashing, with the fixed array as workspace.  stream is a hipStream_t
+ * of the current device (whose copy of the array is used).  Returns
+ * LM_ERR_CAPACITY, before any device work, when the lattice needs more than
+ * LM_STATIC_SCRATCH_BYTES (or, after the pass, if its node records did not
+ * fit); LM_ERR_BAD_LATTICE for out-of-range endpoints; the checks of
+ * lm_plan_create otherwise.  A lattice without nodes gives zero words.
+ * Synchronises the stream (so it cannot be captured into a graph).  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU (two
+ * host threads, or two streams) race and must be serialised by the caller. */
+int lm_forward_sink_static(const lm_lattice *lat, int k, uint64_t *d_words, void *stream);
+
 /* ---- batched parts -------------------------------------------------------- */
 
 /* Work mapping of lm_batched: nodes of valence <= v_four_per_wave (at most 4)

@@ -1,4 +1,5 @@
 // Host side of the C ABI declared in include/latmesh.h.
+#include <mutex>
 #include <new>
 #include <utility>
 #include <string.h>
@@ -356,10 +357,8 @@ int check_lattice(const lm_lattice *lat, bool need_radius = true)
     return LM_OK;
 }
 
-lm_plan *new_plan(const lm_lattice *lat, void *stream)
+void init_plan(lm_plan *P, const lm_lattice *lat, void *stream)
 {
-    lm_plan *P = new (std::nothrow) lm_plan();
-    if (!P) return nullptr;
     P->st = (hipStream_t)stream;
     P->in.n_nodes = lat->n_nodes;
     P->in.n_struts = lat->n_struts;
@@ -377,6 +376,13 @@ lm_plan *new_plan(const lm_lattice *lat, void *stream)
     P->k = 0;
     P->kappa_max = 32.0f;
     P->profiling = false;
+}
+
+lm_plan *new_plan(const lm_lattice *lat, void *stream)
+{
+    lm_plan *P = new (std::nothrow) lm_plan();
+    if (!P) return nullptr;
+    init_plan(P, lat, stream);
     return P;
 }
 
@@ -1092,6 +1098,111 @@ const char *lm_status_string(int code)
     case LM_ERR_RADIUS_MISMATCH: return "end radii at a node differ";
     default: return "unknown status";
     }
+}
+
+}  // extern "C"
+
+// ---- sink mode without allocation ------------------------------------------
+// Device memory of lm_forward_sink_static: the whole plan (adjacency, counts,
+// node lists, slots and node records) is carved from this array.  Every GPU
+// the library runs on holds its own copy, at its own address, until the
+// process ends.  In host code `scratch` only stands for the symbol: its device
+// address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[LM_STATIC_SCRATCH_BYTES];
+
+__global__ void lm_k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up at the first
+// call on that device).
+int static_scratch(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return LM_ERR_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return LM_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LM_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LM_OK;
+}
+
+// Clears n 32-bit words with a kernel (no memset node).
+int fill_u32(void *p, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return LM_OK;
+    lm_k_fill_u32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>((uint32_t *)p, 0u, n);
+    return hipGetLastError() == hipSuccess ? LM_OK : LM_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lm_static_scratch_size(int64_t n_nodes, int64_t n_struts, int k, size_t *bytes)
+{
+    if (!bytes || k < 3 || k > 4096) return LM_ERR_INVALID_ARG;
+    lm_options o;
+    o.flags = LM_WS_SINK;
+    o.k_max = k;
+    o.record_bytes = 0;
+    o.max_parts = 0;
+    return lm_workspace_size(n_nodes, n_struts, &o, bytes);
+}
+
+int lm_forward_sink_static(const lm_lattice *lat, int k, uint64_t *d_words, void *stream)
+{
+    if (!d_words || k < 3 || k > 4096) return LM_ERR_INVALID_ARG;
+    int rc = check_lattice(lat);
+    if (rc) return rc;
+    size_t need = 0;
+    if ((rc = lm_static_scratch_size(lat->n_nodes, lat->n_struts, k, &need))) return rc;
+    if (need > (size_t)LM_STATIC_SCRATCH_BYTES) return LM_ERR_CAPACITY;  // before any device call
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = lat->n_nodes;
+    if (N == 0) {
+        if ((rc = fill_u32(d_words, 2 * LM_SINK_WORDS, st))) return rc;
+        return hipStreamSynchronize(st) == hipSuccess ? LM_OK : LM_ERR_HIP;
+    }
+    void *base = nullptr;
+    if ((rc = static_scratch(&base))) return rc;
+    // a plan on the stack, every device buffer carved from the array
+    lm_plan P{};  // value-initialised: every device pointer starts null
+    init_plan(&P, lat, stream);
+    P.caller_ws = true;
+    P.ws_flags = LM_WS_SINK;
+    lm_options o;
+    o.flags = LM_WS_SINK;
+    o.k_max = k;
+    o.record_bytes = 0;
+    o.max_parts = 0;
+    ws_layout(&P, base, lat->n_nodes, lat->n_struts, o);
+    // the array keeps the previous call's contents: clear what the sink
+    // range expects at zero (node marks, slots, the range's failure flag)
+    if ((rc = fill_u32(P.sk_mark, N + 1, st)) ||
+        (rc = fill_u32(P.sk_slots, 2 * lm::sink_slots_words(), st)) || (rc = fill_u32(P.sk_fail, 1, st)))
+        return rc;
+    if ((rc = first_prepare(&P))) return rc;  // synchronises; LM_ERR_BAD_LATTICE
+    if ((rc = fill_u32(P.w.flags, 3, st))) return rc;
+    lm::SinkOut so{0, 0, P.sk_slots, nullptr, nullptr, nullptr};
+    if ((rc = sink_range(&P, k, 0, 0, N, 4, 8, so, d_words))) return rc;
+    int32_t fail = 0;
+    if (hipMemcpyAsync(&fail, P.sk_fail, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return LM_ERR_HIP;
+    return fail ? LM_ERR_CAPACITY : LM_OK;
 }
 
 }  // extern "C"

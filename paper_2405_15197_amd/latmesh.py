@@ -56,6 +56,8 @@ EXPORTS = (
     "lm_set_profiling",
     "lm_get_profile",
     "lm_forward_sink",
+    "lm_static_scratch_size",
+    "lm_forward_sink_static",
     "lm_batched",
     "lm_loss",
     "lm_backward",
@@ -228,6 +230,11 @@ def load() -> ctypes.CDLL:
     lib.lm_set_precision.restype = ctypes.c_int
     lib.lm_forward_sink.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, ctypes.c_int64]
     lib.lm_forward_sink.restype = ctypes.c_int
+    lib.lm_static_scratch_size.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_size_t)]
+    lib.lm_static_scratch_size.restype = ctypes.c_int
+    lib.lm_forward_sink_static.argtypes = [ctypes.POINTER(lm_lattice), ctypes.c_int, P, P]
+    lib.lm_forward_sink_static.restype = ctypes.c_int
     lib.lm_batched.argtypes = [P, ctypes.c_int64, P, P, ctypes.POINTER(lm_tuning), P]
     lib.lm_batched.restype = ctypes.c_int
     lib.lm_loss.argtypes = [P, ctypes.POINTER(lm_outputs), ctypes.POINTER(lm_loss_weights), P, P]
@@ -392,6 +399,23 @@ def lm_forward_sink(plan, k: int, chunk_nodes: int, d_out: int, n_chunks_cap: in
     rc = load().lm_forward_sink(plan, int(k), int(chunk_nodes), ctypes.c_void_p(d_out), int(n_chunks_cap))
     if rc != LM_OK:
         raise LatmeshError(rc, "lm_forward_sink")
+
+
+LM_STATIC_SCRATCH_BYTES = 128 << 20
+
+
+def lm_static_scratch_size(n_nodes: int, n_struts: int, k: int) -> int:
+    b = ctypes.c_size_t()
+    rc = load().lm_static_scratch_size(int(n_nodes), int(n_struts), int(k), ctypes.byref(b))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_static_scratch_size")
+    return int(b.value)
+
+
+def lm_forward_sink_static(lat: lm_lattice, k: int, d_words: int, stream: int) -> None:
+    rc = load().lm_forward_sink_static(ctypes.byref(lat), int(k), ctypes.c_void_p(d_words), ctypes.c_void_p(stream))
+    if rc != LM_OK:
+        raise LatmeshError(rc, "lm_forward_sink_static")
 
 
 def lm_batched(plan, part_off, part_k, tune, d_out: int) -> None:
