@@ -95,6 +95,10 @@ def cpu_baseline(scale: int, k: int, threads: int):
     t0 = time.perf_counter()
     R = oracle.run(lat, k, threads=threads)
     dt = time.perf_counter() - t0
+    excl = excluded_fractions(R, lat, k)
+    # the billion-strut family (no jitter) on a 24^3 sample
+    lat3 = latgen.config(3, scale=24, seed=1)
+    excl3 = excluded_fractions(oracle.run(lat3, 12, threads=threads), lat3, 12)
     return {
         "value": lat.n_struts / dt,
         "unit": "struts/s",
@@ -105,7 +109,23 @@ def cpu_baseline(scale: int, k: int, threads: int):
         "sample": f"BCC {scale}^3 cells ({lat.n_nodes} nodes, {lat.n_struts} struts), k={k}, same seeded "
         f"distributions as the GPU workload, meta-mesh + triangulation, FP64 C oracle, {dt:.1f} s wall",
         "triangles_per_s": len(R.tris) / dt,
+        # nodes and struts the parity tests leave out of the element-wise
+        # comparison (oracle margins below the per-kind thresholds)
+        "excluded": {"bcc64_k16": excl, "billion_family_bcc24_k12": excl3},
     }
+
+
+def excluded_fractions(R, lat, k):
+    """Shares of the nodes and struts below the parity tests' comparison
+    thresholds (the tests' own per-kind margins)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import STRUT_TAU, above_margin
+
+    above = above_margin(R, k)
+    sa, sb = lat.strut_a.astype(np.int64), lat.strut_b.astype(np.int64)
+    ok = (R.strut_status == 0) & above[sa] & above[sb]
+    return {"nodes": float(1.0 - above.mean()),
+            "struts": float(1.0 - (ok & (R.strut_margin >= STRUT_TAU)).mean())}
 
 
 def copy_probe(mib: int):
@@ -454,7 +474,7 @@ def batched_bench(n_parts: int = 512, n_max: int = 64, seed: int = 1, pre=None):
 
     import latgen
     from paper_2405_15197_amd.autotune import tune
-    from paper_2405_15197_amd.latmesh import Mesher, lm_prepare
+    from paper_2405_15197_amd.latmesh import Mesher, lm_get_profile, lm_prepare, lm_set_profiling
 
     parts, t_gen = pre if pre is not None else make_parts(n_parts, n_max, seed)
     t0 = time.perf_counter()
@@ -472,6 +492,13 @@ def batched_bench(n_parts: int = 512, n_max: int = 64, seed: int = 1, pre=None):
     words = M.batched(off, ks, best)
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
+    # the same call again with the library's phase timers on (not the timed run)
+    lm_get_profile(M.plan)
+    lm_set_profiling(M.plan, True)
+    M.batched(off, ks, best)
+    prof = lm_get_profile(M.plan)
+    lm_set_profiling(M.plan, False)
+    phase_ms = {p: round(v[0], 3) for p, v in prof.items() if v[1]}
     M.close()
     print(f"[bench] batched {t_batched:.2f} s; sequential per-part baseline", file=sys.stderr, flush=True)
     t_seq = 0.0
@@ -510,6 +537,7 @@ def batched_bench(n_parts: int = 512, n_max: int = 64, seed: int = 1, pre=None):
         "triangles": int(tot[0]),
         "triangles_per_s": int(tot[0]) / t_batched,
         "nodes_without_mesh": int(tot[7]),
+        "phase_ms": phase_ms,
         "generation_s": t_gen,
     }
 

@@ -19,6 +19,7 @@ __device__ inline float fbits(uint32_t u) { return __uint_as_float(u); }
 __global__ void __launch_bounds__(64) k_expand(XParams P)
 {
     __shared__ uint4 s_arc[kAcap][kRecArcFields / 4];  // the node's arcs, staged once
+    __shared__ uint4 s_vtx[kVcap];                     // its vertices (name, xyz)
     const Work &W = P.w;
     const FillOut &O = P.o;
     const int64_t N = P.in.n_nodes;
@@ -55,16 +56,23 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
     if (staged)
         for (int x = lane; x < (kRecArcFields / 4) * E; x += 64)
             s_arc[x / (kRecArcFields / 4)][x % (kRecArcFields / 4)] = ((const uint4 *)RA)[x];
+    const bool vstaged = V <= kVcap;
+    if (vstaged)
+        for (int i = lane; i < V; i += 64) s_vtx[i] = ((const uint4 *)RV)[i];
     __syncthreads();
     auto aw = [&](int j, int f) -> uint32_t {
         return staged ? ((const uint32_t *)s_arc[j])[f] : RA[kRecArcFields * j + f];
     };
+    // word f (0 name, 1..3 xyz) of vertex i
+    auto vw = [&](int i, int f) -> uint32_t {
+        return vstaged ? ((const uint32_t *)&s_vtx[i])[f] : RV[4 * i + f];
+    };
     if (O.vert_name) {
         for (int i = lane; i < V; i += 64) {
-            O.vert_name[voff + i] = RV[4 * i];
-            O.vert_xyz[0 * O.cap_vert + voff + i] = fbits(RV[4 * i + 1]);
-            O.vert_xyz[1 * O.cap_vert + voff + i] = fbits(RV[4 * i + 2]);
-            O.vert_xyz[2 * O.cap_vert + voff + i] = fbits(RV[4 * i + 3]);
+            O.vert_name[voff + i] = vw(i, 0);
+            O.vert_xyz[0 * O.cap_vert + voff + i] = fbits(vw(i, 1));
+            O.vert_xyz[1 * O.cap_vert + voff + i] = fbits(vw(i, 2));
+            O.vert_xyz[2 * O.cap_vert + voff + i] = fbits(vw(i, 3));
         }
     }
     if (O.arc_f32) {
@@ -94,7 +102,7 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
         if (!whole) {
             const int vs = (int)(aw(j, 12) & 0xffffu);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) x1[d] = fbits(RV[4 * vs + 1 + d]);
+            for (int d = 0; d < 3; ++d) x1[d] = fbits(vw(vs, 1 + d));
         }
         return arc_point_f32(o, a, b, x1, fbits(aw(j, 9)), fbits(aw(j, 10)), ii, (int)(aw(j, 13) & 0xffffu), whole);
     };
@@ -102,7 +110,7 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
     for (int i = lane; i < M; i += 64) {
         float3 w;
         if (i < V) {
-            w = make_float3(fbits(RV[4 * i + 1]), fbits(RV[4 * i + 2]), fbits(RV[4 * i + 3]));
+            w = make_float3(fbits(vw(i, 1)), fbits(vw(i, 2)), fbits(vw(i, 3)));
         } else if (i < wsum && fp64) {
             w = make_float3(fbits(RI[3 * i]), fbits(RI[3 * i + 1]), fbits(RI[3 * i + 2]));
         } else if (i < wsum) {

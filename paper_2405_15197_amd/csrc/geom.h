@@ -25,8 +25,6 @@ __device__ inline float m_floor(float x) { return floorf(x); }
 __device__ inline double m_floor(double x) { return floor(x); }
 __device__ inline float m_max(float a, float b) { return fmaxf(a, b); }
 __device__ inline double m_max(double a, double b) { return fmax(a, b); }
-__device__ inline float m_asin(float x) { return asinf(x); }
-__device__ inline double m_asin(double x) { return asin(x); }
 __device__ inline void m_sincos(float t, float *s, float *c) { sincosf(t, s, c); }
 __device__ inline void m_sincos(double t, double *s, double *c) { sincos(t, s, c); }
 

@@ -91,6 +91,7 @@ struct Shared {
     T hc[C::AC][3];           // hole centre (local) per contour
     int entry_off[2 * C::AC + 1];   // first loop sample of each loop entry
     uint8_t entry_m[2 * C::AC];     // strut label of each loop entry
+    uint16_t entry_arc[2 * C::AC];  // arc of each loop entry | 0x8000 when run forward
     int loop_desc[C::VM + 1];       // descents of phi along each loop
     int loop_rot[C::VM + 1];        // loop position of the smallest phi
     T ph_first[C::VM + 1], ph_last[C::VM + 1];  // phi keys of each loop's ends
@@ -483,20 +484,35 @@ __device__ inline void piece_range(const Piece<T> &pc, T &t1, T &t2, T &dt)
     dt = span;
 }
 
-// Condition number of a tie point: the three surfaces through it are cone p
-// (normal w - P_p g_p, or w for the sphere), and the planes P_p = P_q and
-// P_p = P_r; returns |n1||n2||n3| / |det(n1, n2, n3)|.
+// Whether FP32 can be trusted with the tie point w of labels p < q < r.  The
+// three surfaces through it are cone p (normal n1 = w - P_p g_p, or w for the
+// sphere) and the planes P_p = P_q, P_p = P_r (normals n2 = g_p - g_q,
+// n3 = g_p - g_r).  Not trusted when
+//   - the condition number |n1||n2||n3| / |det(n1, n2, n3)| exceeds
+//     kappa_max (FP32 rounding of the surfaces is amplified that much), or
+//   - the FP32 error of the point as the solution of the tie equations
+//     exceeds kVertexErr rho: the equations' residuals carry rounding of
+//     the size of their terms (|g||w| for the planes, |w|^2 + P_p^2 + rho^2
+//     for the cone), mapped through the inverse Jacobian (cofactors over
+//     the determinant).  The condition number alone misses points far from
+//     the node centre on the seams of nearly parallel struts.
 template <typename T>
-__device__ inline T tie_kappa(const SL<T> *S, int p, int q, int r, V3<T> w)
+__device__ inline bool tie_trusted(const SL<T> *S, int p, int q, int r, V3<T> w, T rho, T kappa_max)
 {
-    V3<T> gp = p ? gvec(S[p]) : zero3<T>();
-    T pp = p ? dot(gp, w) - S[p].h : (T)0;
-    V3<T> n1 = w - gp * pp;
-    V3<T> n2 = gp - gvec(S[q]);
-    V3<T> n3 = gp - (r ? gvec(S[r]) : zero3<T>());
-    T det = m_abs(dot(n1, cross(n2, n3)));
-    T den = m_sqrt(dot(n1, n1) * dot(n2, n2) * dot(n3, n3));
-    return det > (T)0 ? den / det : (T)1e30;
+    const V3<T> gp = p ? gvec(S[p]) : zero3<T>();
+    const T pp = p ? dot(gp, w) - S[p].h : (T)0;
+    const V3<T> gq = gvec(S[q]), gr = r ? gvec(S[r]) : zero3<T>();
+    const V3<T> n1 = w - gp * pp, n2 = gp - gq, n3 = gp - gr;
+    const V3<T> c12 = cross(n1, n2), c23 = cross(n2, n3), c31 = cross(n3, n1);
+    const T det = m_abs(dot(n1, c23));
+    if (!(det > (T)0)) return false;
+    if (m_sqrt(dot(n1, n1) * dot(n2, n2) * dot(n3, n3)) > kappa_max * det) return false;
+    const T lw = m_sqrt(dot(w, w));
+    const T lgp = m_sqrt(dot(gp, gp)), lq = m_sqrt(dot(gq, gq)), lr = m_sqrt(dot(gr, gr));
+    const T bound = m_sqrt(dot(c31, c31)) * ((T)2 * (lgp + lq) * lw) +
+                    m_sqrt(dot(c12, c12)) * ((T)2 * (lgp + lr) * lw) +
+                    m_sqrt(dot(c23, c23)) * (lw * lw + pp * pp + rho * rho);
+    return !(bound * (T)kFp32Eps > (T)(2.0f * kVertexErr) * rho * det);
 }
 
 // ---------------------------------------------------------------------------
@@ -572,71 +588,6 @@ __device__ inline V3<T> interior_pt(const Shared<T, C> &sh, const ArcL<T> &A, in
         const Con<T> Cn = arc_con(A);
         return vert_pos(sh, A.vs) + Cn.a * ds + Cn.b * dc;
     }
-}
-
-// One Newton step on the tie equations of vertex i: P_p = P_q = P_r on
-// |w|^2 - rho^2 = P_p^2 (label 0 has P_0 = 0).  The position from the conic
-// (p, q) carries the rounding of that conic's parametrisation, large for a
-// long thin ellipse; these equations involve only quantities of the node's
-// scale, so the step leaves the error the tie's conditioning allows.
-// In FP32 the step's own residuals carry rounding of the size of their terms
-// (|g||w| for the plane equations, |w|^2 for the cone), amplified by the
-// inverse Jacobian; when that bound exceeds kVertexErr rho the node goes to
-// FP64 (a condition number alone misses vertices far from the node centre
-// on the seams of nearly parallel struts).
-template <typename T, typename C>
-__device__ inline void refine_vertex(Shared<T, C> &sh, int i, T rho)
-{
-    const uint32_t nm = sh.vname[i];
-    const int p = (int)(nm >> 24), q = (int)((nm >> 16) & 0xffu), r = (int)((nm >> 8) & 0xffu);
-    if (r == 0xff) return;  // start point of a whole conic
-    const V3<T> w = vert_pos(sh, i);
-    const V3<T> gp = p ? gvec(sh.S[p]) : zero3<T>();
-    const T hp = p ? sh.S[p].h : (T)0;
-    const V3<T> n1 = gp - gvec(sh.S[q]), n2 = gp - gvec(sh.S[r]);
-    const T s = dot(gp, w) - hp;
-    const V3<T> n3 = (w - gp * s) * (T)2;
-    const T f1 = dot(n1, w) - (hp - sh.S[q].h), f2 = dot(n2, w) - (hp - sh.S[r].h);
-    const T f3 = dot(w, w) - rho * rho - s * s;
-    const V3<T> c23 = cross(n2, n3), c31 = cross(n3, n1), c12 = cross(n1, n2);
-    const T det = dot(n1, c23);
-    if (!(m_abs(det) > (T)0)) {
-        if (sizeof(T) == 4) atomicOr(&sh.status, NS_PREC);
-        return;
-    }
-    if constexpr (sizeof(T) == 4) {
-        const T lw = m_sqrt(dot(w, w)), lgp = m_sqrt(dot(gp, gp));
-        const T lq = m_sqrt(dot(gvec(sh.S[q]), gvec(sh.S[q]))), lr = m_sqrt(dot(gvec(sh.S[r]), gvec(sh.S[r])));
-        // |c23| f1 + |c31| f2 + |c12| f3 with each f replaced by its rounding
-        const T bound = m_sqrt(dot(c23, c23)) * (lgp + lq) * lw + m_sqrt(dot(c31, c31)) * (lgp + lr) * lw +
-                        m_sqrt(dot(c12, c12)) * (lw * lw + s * s + rho * rho);
-        if (bound * (T)kFp32Eps > (T)kVertexErr * rho * m_abs(det)) atomicOr(&sh.status, NS_PREC);
-    }
-    const V3<T> d = (c23 * f1 + c31 * f2 + c12 * f3) * ((T)-1 / det);
-    sh.vx[i] = w.x + d.x;
-    sh.vy[i] = w.y + d.y;
-    sh.vz[i] = w.z + d.z;
-}
-
-// Span of an arc from its (refined) end vertices: the chord
-// x2 - x1 = 2 sin(dt / 2) (a cos tm - b sin tm), tm = t1 + dt / 2, fixes dt
-// with the relative precision of the chord, where the difference of two
-// parameters would carry their absolute rounding.  Arcs of more than a
-// quarter turn keep the span from the trimming.
-template <typename T, typename C>
-__device__ inline void refine_span(const Shared<T, C> &sh, ArcL<T> &A)
-{
-    if (!(A.dt < (T)0.5 * Cst<T>::pi)) return;
-    const V3<T> ch = vert_pos(sh, A.ve) - vert_pos(sh, A.vs);
-    T st, ct;
-    m_sincos(A.t1 + (T)0.5 * A.dt, &st, &ct);
-    const Con<T> Cn = arc_con(A);
-    const V3<T> tg = Cn.a * ct - Cn.b * st;
-    const T den = m_sqrt(dot(tg, tg));
-    const T x = m_sqrt(dot(ch, ch)) / ((T)2 * den);
-    if (!(x < (T)1)) return;
-    A.dt = (T)2 * m_asin(x);
-    A.t2 = A.t1 + A.dt;
 }
 
 struct Params {
@@ -872,8 +823,10 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
                 int ns = 0, m = 1;
                 if (e < nent) {
                     while (sh.loop_base[m + 1] <= e) ++m;
-                    const int b0 = sh.loop_base[m];
-                    ns = sh.A[sh.loop_arc[b0 + sh.loop_ord[e]]].nseg;
+                    const int pp = sh.loop_base[m] + sh.loop_ord[e];
+                    const int aj = sh.loop_arc[pp];
+                    ns = sh.A[aj].nseg;
+                    sh.entry_arc[e] = (uint16_t)(aj | (sh.loop_dir[pp] > 0 ? 0x8000 : 0));
                 }
                 int tot;
                 const int ex = group_excl_scan<WL>(ns, &tot);
@@ -918,19 +871,21 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
             int2 *rl = sh.rec >= 0
                            ? (int2 *)(W.rec + sh.rec + (SINK ? 0 : rec_loop_word(V, E, HX, rec_table_bytes(v, nent, WIDE))))
                            : nullptr;
-            // phi key and local mesh index of sample j of loop entry e
-            auto sample = [&](int e, int j, int &li) -> T {
-                const int m = sh.entry_m[e];
-                const int pp = sh.loop_base[m] + sh.loop_ord[e];
-                const ArcL<T> &A = sh.A[sh.loop_arc[pp]];
-                const int d = sh.loop_dir[pp];
-                const int ii = d > 0 ? j : A.nseg - j;
-                li = j == 0 ? (d > 0 ? A.vs : A.ve) : interior_idx(A, ii);
-                T st, ct;
-                m_sincos(sub_param(A, ii), &st, &ct);
+            // phi key and local mesh index of sample j of loop entry e (on
+            // the loop of strut m)
+            auto sample = [&](int e, int m, int j, int &li) -> T {
+                const uint32_t ea = sh.entry_arc[e];
+                const ArcL<T> &A = sh.A[ea & 0x7fffu];
+                const bool fw = (ea & 0x8000u) != 0;
+                const int ii = fw ? j : A.nseg - j;
+                li = j == 0 ? (fw ? A.vs : A.ve) : interior_idx(A, ii);
                 // tangency circles are parametrised in the strut frame: phi
                 // is the parameter itself
-                if (A.p == 0) return phi_key(st, ct);
+                if (A.p == 0) {
+                    T st, ct;
+                    m_sincos(sub_param(A, ii), &st, &ct);
+                    return phi_key(st, ct);
+                }
                 const V3<T> w = j == 0 ? vert_pos(sh, li) : interior_pt(sh, A, ii);
                 const SL<T> &sm = sh.S[m];
                 return phi_key(dot(w, v3(sm.qx, sm.qy, sm.qz)), dot(w, v3(sm.rx, sm.ry, sm.rz)));
@@ -954,9 +909,9 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
                     }
                     const int e = lo;
                     m = sh.entry_m[e];
-                    idx = sidx - sh.entry_off[sh.loop_base[m]];
+                    idx = sidx - sh.lbase[m];
                     nloop = sh.loop_len[m];
-                    ph = sample(e, sidx - sh.entry_off[e], li);
+                    ph = sample(e, m, sidx - sh.entry_off[e], li);
                 }
                 T prev, last;
                 group_prev_last<WL>(ph, carry, prev, last);
@@ -1109,9 +1064,8 @@ finish:
         TabT *RT = (TabT *)(R + rec_table_word(V, E, HX));
         over_lanes<WL, CF::VM>(lane, 0, v, [&](int l) { RT[l] = (TabT)sh.loop_base[l + 1]; });
         for (int e = lane; e < nent; e += WL) {
-            const int m = sh.entry_m[e];
-            const int pp = sh.loop_base[m] + sh.loop_ord[e];
-            RT[v + 1 + e] = (TabT)(sh.loop_arc[pp] | (sh.loop_dir[pp] > 0 ? kFwd : 0u));
+            const uint32_t ea = sh.entry_arc[e];
+            RT[v + 1 + e] = (TabT)((ea & 0x7fffu) | ((ea & 0x8000u) ? kFwd : 0u));
         }
     }
 }
@@ -1339,7 +1293,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
                         sh.vx[vbase + rank] = w.x;
                         sh.vy[vbase + rank] = w.y;
                         sh.vz[vbase + rank] = w.z;
-                        if (F32 && orr[i] >= 0 && tie_kappa(sh.S, p, q, orr[i], w) > (T)P.kappa_max)
+                        if (F32 && orr[i] >= 0 && !tie_trusted(sh.S, p, q, orr[i], w, rho, (T)P.kappa_max))
                             atomicOr(&sh.status, NS_PREC);
                     }
                 }
@@ -1365,19 +1319,14 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
             if (A.vs < 0 || A.ve < 0) atomicOr(&sh.status, NS_TOPOLOGY);
             A.contour = -1;
         }
-        // vertices on their tie equations, then the spans and segment
-        // counts (Eq. 11) from them
-        for (int i = lane; i < V; i += WL) {
-            refine_vertex(sh, i, rho);
-            sh.vdeg[i] = 0;
-        }
+        // segment counts (Eq. 11)
+        for (int i = lane; i < V; i += WL) sh.vdeg[i] = 0;
         __syncthreads();
         for (int j = lane; j < E; j += WL) {
             ArcL<T> &A = sh.A[j];
             if (A.full) {
                 A.nseg = k;
             } else {
-                if (A.vs >= 0 && A.ve >= 0) refine_span(sh, A);
                 T u = A.dt * ((T)k * Cst<T>::inv_two_pi);
                 int ns = (int)m_floor(u) + 1;
                 A.nseg = ns < k ? ns : k;
