@@ -205,11 +205,12 @@ void carve_retri_index(lm_plan *P, Carver &c, int64_t N)
 
 // Node-record words of the whole lattice at resolution k: per node the
 // header and about 2 vertices, 3 arcs and a hole per incident strut; per
-// half-edge a loop of about k samples.
+// half-edge a loop of about k samples and about k / 2 interior points.
 int64_t rec_estimate_nk(int64_t N, int64_t S, int k)
 {
     const int64_t H = 2 * S;
-    int64_t words = N * (lm::kRecHead + 4) + H * (2 * 4 + 3 * lm::kRecArcFields + 3 + 2 * (int64_t)(k + 4));
+    int64_t words = N * (lm::kRecHead + 4) +
+                    H * (2 * 4 + 3 * lm::kRecArcFields + 3 + 2 * (int64_t)(k + 4) + 3 * (int64_t)(k / 2 + 2));
     return words + words / 8 + 4096;
 }
 int64_t rec_estimate(const lm_plan *P, int k) { return rec_estimate_nk(P->in.n_nodes, P->in.n_struts, k); }

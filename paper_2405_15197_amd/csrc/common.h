@@ -73,6 +73,10 @@ enum DevFlag : int {
 //                       vs | ve<<16, nseg | contour<<16, mbase, fbase: four
 //                       16-byte groups each
 //   holes   [H][3]      hole centres (node-local)
+//   points  [wsum-V][3] the Eq. 12 interior points (node-local, in mesh
+//                       order), as the node's precision computed them; the
+//                       loop table starts at rec_table_word(V, E, H + wsum - V)
+//                       (not in sink mode, whose records hold the loops only)
 //   loop table          bytes: loop start of each strut label 1..v+1 (v+1
 //                       bytes), then for every loop entry in loop order its
 //                       arc | 0x80 if the arc runs along the loop (header
@@ -102,8 +106,7 @@ __host__ __device__ inline int rec_table_bytes(int v, int nent, bool wide)
 {
     return (wide ? 2 : 1) * (v + 1 + nent);
 }
-constexpr uint32_t kRecFp64 = 1u << 24;  // header word 7: meshed in FP64 (its Eq. 12
-                                         // interior points follow the hole centres)
+constexpr uint32_t kRecFp64 = 1u << 24;  // header word 7: meshed in FP64
 constexpr uint32_t kRecWide = 1u << 25;  // header word 7: 16-bit loop table
 
 struct Inputs {
@@ -165,6 +168,39 @@ __host__ __device__ inline int valence_class(int64_t v, int t16 = 4, int t32 = 8
 }
 constexpr int kClasses = 4;
 
+// sin and cos of x in FP32 for every FP32 pass (one definition, so the node
+// pass, the expansion, sink-mode hashing and the adjoint evaluate the same
+// points).  Cody and Waite's reduction by pi/2 (x = q pi/2 + r, |r| <= pi/4,
+// pi/2 split into two FP32 constants applied with fused multiply-adds),
+// then the Taylor series of sin to degree 9 and of cos to degree 10 on r
+// (truncation below 3e-9) and the quadrant's sign and swap.  Absolute error
+// within about one FP32 ulp of 1 for |x| < 2^13 (measured against FP64
+// sin / cos, like the library's); the reduction loses about q * 4e-15 more
+// beyond that.  The callers' arguments are arc parameters of a few turns.
+__device__ __forceinline__ void sincos_f32(float x, float *s, float *c)
+{
+    constexpr float kTwoOverPi = 0.636619772f;
+    constexpr float kHalfPi1 = 1.57079637f;      // pi/2 rounded to FP32
+    constexpr float kHalfPi2 = -4.37113883e-8f;  // pi/2 - kHalfPi1
+    const float q = rintf(x * kTwoOverPi);
+    float r = fmaf(-q, kHalfPi1, x);
+    r = fmaf(-q, kHalfPi2, r);
+    const float r2 = r * r;
+    float ps = fmaf(r2, 2.75573192e-6f, -1.98412698e-4f);  // 1/9!, -1/7!
+    ps = fmaf(r2, ps, 8.33333333e-3f);                      // 1/5!
+    ps = fmaf(r2, ps, -1.66666667e-1f);                     // -1/3!
+    const float sn = fmaf(r * r2, ps, r);
+    float pc = fmaf(r2, -2.75573192e-7f, 2.48015873e-5f);  // -1/10!, 1/8!
+    pc = fmaf(r2, pc, -1.38888889e-3f);                     // -1/6!
+    pc = fmaf(r2, pc, 4.16666667e-2f);                      // 1/4!
+    pc = fmaf(r2, pc, -0.5f);                               // -1/2!
+    const float cs = fmaf(r2, pc, 1.0f);
+    const int i = (int)q & 3;
+    const float a = (i & 1) ? cs : sn, b = (i & 1) ? sn : cs;
+    *s = (i & 2) ? -a : a;
+    *c = ((i + 1) & 2) ? -b : b;
+}
+
 // Eq. 12 point ii (of nseg segments) of an arc x(t) = o + a sin t + b cos t,
 // t in [t1, t1 + dt], node-local, from FP32 fields.  A whole conic (no end
 // points) is evaluated directly.  An arc is evaluated from its start point
@@ -181,13 +217,13 @@ __device__ __forceinline__ float3 arc_point_f32(const float *o, const float *a, 
     if (whole) {
         const float t = t1 + dt * (float)ii / (float)nseg;
         float s, c;
-        sincosf(t, &s, &c);
+        sincos_f32(t, &s, &c);
         return make_float3(o[0] + a[0] * s + b[0] * c, o[1] + a[1] * s + b[1] * c, o[2] + a[2] * s + b[2] * c);
     }
     const float h = 0.5f * dt * (float)ii / (float)nseg;
     float sh, ch, sm, cm;
-    sincosf(h, &sh, &ch);
-    sincosf(t1 + h, &sm, &cm);
+    sincos_f32(h, &sh, &ch);
+    sincos_f32(t1 + h, &sm, &cm);
     const float ds = 2.f * cm * sh, dc = -2.f * sm * sh;
     return make_float3(x1[0] + a[0] * ds + b[0] * dc, x1[1] + a[1] * ds + b[1] * dc, x1[2] + a[2] * ds + b[2] * dc);
 }

@@ -45,8 +45,7 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
     const uint32_t *RV = R + kRecHead;
     const uint32_t *RA = RV + 4 * V;
     const uint32_t *RH = RA + kRecArcFields * E;
-    // a node meshed in FP64 stores its interior points after the hole centres
-    const bool fp64 = (R[7] & kRecFp64) != 0;
+    // the node's Eq. 12 points follow its hole centres, by mesh index
     const uint32_t *RI = RH + 3 * NC - 3 * V;
 
     // arcs: whole 16-byte groups into LDS (the arc block starts on a 16-byte
@@ -88,42 +87,13 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
     }
     __syncthreads();
 
-    // Eq. 12 point ii (1..nseg-1) of arc j (from its start vertex unless it
-    // is a whole conic)
-    auto interior = [&](int j, int ii) {
-        float o[3], a[3], b[3], x1[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            o[d] = fbits(aw(j, d));
-            a[d] = fbits(aw(j, 3 + d));
-            b[d] = fbits(aw(j, 6 + d));
-        }
-        const bool whole = (aw(j, 11) >> 16) & 1u;
-        if (!whole) {
-            const int vs = (int)(aw(j, 12) & 0xffffu);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) x1[d] = fbits(vw(vs, 1 + d));
-        }
-        return arc_point_f32(o, a, b, x1, fbits(aw(j, 9)), fbits(aw(j, 10)), ii, (int)(aw(j, 13) & 0xffffu), whole);
-    };
     // mesh vertices: meta-vertices, interior points, hole centres
     for (int i = lane; i < M; i += 64) {
         float3 w;
         if (i < V) {
             w = make_float3(fbits(vw(i, 1)), fbits(vw(i, 2)), fbits(vw(i, 3)));
-        } else if (i < wsum && fp64) {
-            w = make_float3(fbits(RI[3 * i]), fbits(RI[3 * i + 1]), fbits(RI[3 * i + 2]));
         } else if (i < wsum) {
-            int lo = 0, hi = E - 1;  // last arc with mbase <= i
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if ((int)aw(mid, 14) <= i) lo = mid;
-                else hi = mid - 1;
-            }
-            const int nseg = (int)(aw(lo, 13) & 0xffffu);
-            const bool fwd = (aw(lo, 11) >> 17) & 1u;
-            const int jc = i - (int)aw(lo, 14);
-            w = interior(lo, fwd ? jc + 1 : nseg - 1 - jc);
+            w = make_float3(fbits(RI[3 * i]), fbits(RI[3 * i + 1]), fbits(RI[3 * i + 2]));
         } else {
             const int c = i - wsum;
             w = make_float3(fbits(RH[3 * c]), fbits(RH[3 * c + 1]), fbits(RH[3 * c + 2]));

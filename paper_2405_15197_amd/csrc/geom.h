@@ -25,7 +25,7 @@ __device__ inline float m_floor(float x) { return floorf(x); }
 __device__ inline double m_floor(double x) { return floor(x); }
 __device__ inline float m_max(float a, float b) { return fmaxf(a, b); }
 __device__ inline double m_max(double a, double b) { return fmax(a, b); }
-__device__ inline void m_sincos(float t, float *s, float *c) { sincosf(t, s, c); }
+__device__ inline void m_sincos(float t, float *s, float *c) { sincos_f32(t, s, c); }
 __device__ inline void m_sincos(double t, double *s, double *c) { sincos(t, s, c); }
 
 template <typename T>

@@ -396,7 +396,7 @@ __device__ void backward_node(const BParams &P, BwdLds<VM, AC, VC> &sm, const in
     // Eq. 12 point ii of arc j and its derivative along t
     auto arc_point = [&](int j, float t, float *x, float *dx) {
         float s, c;
-        sincosf(t, &s, &c);
+        sincos_f32(t, &s, &c);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             x[d] = af(d, j) + af(3 + d, j) * s + af(6 + d, j) * c;
@@ -410,7 +410,7 @@ __device__ void backward_node(const BParams &P, BwdLds<VM, AC, VC> &sm, const in
         const float f = (float)ii / (float)nseg;
         const float t = t1 + (t2 - t1) * (float)ii / (float)nseg;
         float s, c;
-        sincosf(t, &s, &c);
+        sincos_f32(t, &s, &c);
         float g = 0.f;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -446,7 +446,7 @@ __device__ void backward_node(const BParams &P, BwdLds<VM, AC, VC> &sm, const in
             const float f = (float)ii / (float)nseg;
             const float t = t1 + (t2 - t1) * (float)ii / (float)nseg;
             float sn, cs;
-            sincosf(t, &sn, &cs);
+            sincos_f32(t, &sn, &cs);
             float g = 0.f;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {

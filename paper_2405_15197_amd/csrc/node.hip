@@ -844,8 +844,8 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
         if (lane == 0) {
             const int off = sh.entry_off[sh.loop_base[v + 1]];
             // record space: bump allocation in the node's region
-            // an FP64 node keeps its interior points after the hole centres
-            const int HX = NC + (F32 ? 0 : sh.wsum - V);
+            // the node's interior points follow its hole centres
+            const int HX = NC + sh.wsum - V;
             const int64_t words =
                 (SINK ? 0 : rec_loop_word(V, E, HX, rec_table_bytes(v, sh.loop_base[v + 1], WIDE))) +
                 (((int64_t)2 * off + 3) & ~(int64_t)3);
@@ -867,18 +867,28 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
         {
             const int nent = sh.loop_base[v + 1];
             const int ns_tot = sh.entry_off[nent];
-            const int HX = NC + (F32 ? 0 : sh.wsum - V);
+            const int HX = NC + sh.wsum - V;
             int2 *rl = sh.rec >= 0
                            ? (int2 *)(W.rec + sh.rec + (SINK ? 0 : rec_loop_word(V, E, HX, rec_table_bytes(v, nent, WIDE))))
                            : nullptr;
+            // the node's Eq. 12 points in the record (stored mode), indexed
+            // by node-local mesh index: the expansion copies them
+            uint32_t *RI = (!SINK && sh.rec >= 0) ? W.rec + sh.rec + rec_table_word(V, E, NC) - 3 * V : nullptr;
             // phi key and local mesh index of sample j of loop entry e (on
-            // the loop of strut m)
+            // the loop of strut m); an interior point is stored by the loop
+            // of its arc's label q (every arc is on that loop)
             auto sample = [&](int e, int m, int j, int &li) -> T {
                 const uint32_t ea = sh.entry_arc[e];
                 const ArcL<T> &A = sh.A[ea & 0x7fffu];
                 const bool fw = (ea & 0x8000u) != 0;
                 const int ii = fw ? j : A.nseg - j;
                 li = j == 0 ? (fw ? A.vs : A.ve) : interior_idx(A, ii);
+                const V3<T> w = j == 0 ? vert_pos(sh, li) : interior_pt(sh, A, ii);
+                if (RI && j != 0 && m == A.q) {
+                    RI[3 * li] = __float_as_uint((float)w.x);
+                    RI[3 * li + 1] = __float_as_uint((float)w.y);
+                    RI[3 * li + 2] = __float_as_uint((float)w.z);
+                }
                 // tangency circles are parametrised in the strut frame: phi
                 // is the parameter itself
                 if (A.p == 0) {
@@ -886,7 +896,6 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
                     m_sincos(sub_param(A, ii), &st, &ct);
                     return phi_key(st, ct);
                 }
-                const V3<T> w = j == 0 ? vert_pos(sh, li) : interior_pt(sh, A, ii);
                 const SL<T> &sm = sh.S[m];
                 return phi_key(dot(w, v3(sm.qx, sm.qy, sm.qz)), dot(w, v3(sm.rx, sm.ry, sm.rz)));
             };
@@ -978,7 +987,7 @@ finish:
         const int Msum = sh.wsum + NC, Fsum = sh.fsum;
         const int64_t rb = sh.rec;
         const int nent = sh.loop_base[v + 1];
-        const int HX = NC + (F32 ? 0 : sh.wsum - V);
+        const int HX = NC + sh.wsum - V;
         const int64_t lw = SINK ? 0 : rec_loop_word(V, E, HX, rec_table_bytes(v, nent, WIDE));
         if constexpr (SINK) {
             over_lanes<WL, CF::VM>(lane, 0, v - 1, [&](int l) {
@@ -1042,21 +1051,6 @@ finish:
             RH[3 * c] = __float_as_uint((float)sh.hc[c][0]);
             RH[3 * c + 1] = __float_as_uint((float)sh.hc[c][1]);
             RH[3 * c + 2] = __float_as_uint((float)sh.hc[c][2]);
-        }
-        if constexpr (!F32) {
-            // Eq. 12 points evaluated in FP64 and rounded once: the FP32 arc
-            // fields of a large conic cannot reproduce them to 1e-5 rho
-            uint32_t *RI = RH + 3 * NC - 3 * V;  // indexed by node-local mesh index
-            for (int j = lane; j < E; j += WL) {
-                const ArcL<T> &A = sh.A[j];
-                for (int ii = 1; ii < A.nseg; ++ii) {
-                    const V3<T> w = interior_pt(sh, A, ii);
-                    const int idx = interior_idx(A, ii);
-                    RI[3 * idx] = __float_as_uint((float)w.x);
-                    RI[3 * idx + 1] = __float_as_uint((float)w.y);
-                    RI[3 * idx + 2] = __float_as_uint((float)w.z);
-                }
-            }
         }
         // loop table (for re-subdivision at another resolution)
         using TabT = typename std::conditional<WIDE, uint16_t, uint8_t>::type;
@@ -1547,11 +1541,12 @@ __device__ void node_retri(const Params &P, Shared<float, CF> &sh, const int64_t
     int2 he = make_int2(0, 0);
     if (lane < v) he = W.he[row + lane];
     const uint32_t *R = sb >= 0 ? P.src_rec + sb : nullptr;
-    uint32_t h0 = 0, h1 = 0, h2 = 0, h7 = 0;
+    uint32_t h0 = 0, h1 = 0, h2 = 0, h4 = 0, h7 = 0;
     if (R) {
         h0 = R[0];
         h1 = R[1];
         h2 = R[2];
+        h4 = R[4];  // first hole-centre index: V + interior points
         h7 = R[7];
     }
     const int V = (int)h0, E = (int)h1, NC = (int)h2, nent = (int)((h7 >> 8) & 0xffffu);
@@ -1563,7 +1558,7 @@ __device__ void node_retri(const Params &P, Shared<float, CF> &sh, const int64_t
     // the record: vertices, arcs, loop table (all independent loads)
     const uint32_t *RV = R + kRecHead;
     const uint32_t *RA = RV + 4 * V;
-    const uint32_t *RT = R + rec_table_word(V, E, NC);
+    const uint32_t *RT = R + rec_table_word(V, E, NC + (int)h4 - V);
     const int twords = (v + 1 + nent + 3) >> 2;
     float4 f4 = c4;
     if (lane < v) f4 = W.node4[he.x];
