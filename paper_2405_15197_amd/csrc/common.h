@@ -10,7 +10,7 @@ namespace lm {
 // meshed by one wave (or a part of one); nodes of kVmax + 1 .. kVmaxBig by a
 // group of kBigWaves waves sharing the node's LDS.  A node beyond the limits
 // is flagged (its status bit is set) and emits nothing.
-// FP32 -> FP64 hand-over beside the condition number (kappa_max): a kept
+// FP32 -> FP64 hand-over beside the condition number (kappa_max): a seam
 // conic whose centre or semi-major axis exceeds kConicMax rho, or a vertex
 // whose FP32 error bound exceeds kVertexErr rho (kFp32Eps: unit roundoff).
 constexpr float kConicMax = 4.0f;

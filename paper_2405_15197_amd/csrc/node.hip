@@ -1151,6 +1151,14 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
             TR.ovf = 0;
             const bool ell = grp && conic_of(sh.S, rho, p, q, C);
             if (act && !ell) atomicOr(&sh.status, NS_NON_ELLIPTIC);
+            // a conic far larger than the node (kept or not): its points and
+            // the parameters of its ends would lose its size over rho in
+            // relative FP32 precision, so the node goes to FP64 before any
+            // of its conics is trimmed
+            if (F32 && act && ell &&
+                m_max(dot(C.o, C.o), dot(C.a, C.a)) > (T)(kConicMax * kConicMax) * rho * rho)
+                atomicOr(&sh.status, NS_PREC);
+            if (F32 && group_status<WL>(sh)) break;
             {
                 const V3<T> gp = p ? gvec(sh.S[p]) : zero3<T>();
                 const T hp = p ? sh.S[p].h : (T)0;
@@ -1183,12 +1191,6 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
                 if (act && ell) {
                     trim_finish(sh.S, p, q, C, gp, hp, st, TR);
                     if (TR.ovf) atomicOr(&sh.status, F32 ? NS_PREC : NS_CAPACITY);
-                    // a kept conic far larger than the node: its points (and the
-                    // parameters of its ends) lose its size over rho in relative
-                    // FP32 precision
-                    if (F32 && TR.n > 0 &&
-                        m_max(dot(C.o, C.o), dot(C.a, C.a)) > (T)(kConicMax * kConicMax) * rho * rho)
-                        atomicOr(&sh.status, NS_PREC);
                 }
             }
             // arcs of this conic, sorted by the smaller endpoint name
@@ -1737,8 +1739,9 @@ __global__ void __launch_bounds__(64) k_node32_thread(Params P, Shared<float, Cf
 // (also after a re-subdivision: these nodes are solved in full).  One
 // instantiation takes the nodes of up to kVmax struts (a wave per node), the
 // other the multi-wave class (a block of kBigWaves waves per node).
+// At most 256 registers (VGPRs and AGPRs together): two waves per SIMD.
 template <typename C, bool SINK>
-__global__ void __launch_bounds__(C::W) k_node64(Params P)
+__global__ void __launch_bounds__(C::W) __attribute__((amdgpu_waves_per_eu(2))) k_node64(Params P)
 {
     __shared__ Shared<double, C> sh;
     constexpr bool big = C::VM > kVmax;
