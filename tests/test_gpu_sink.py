@@ -8,6 +8,8 @@ coordinate sums differ from the oracle's FP64 ones by rounding only: at most
 one unit of 2^-20 per vertex plus the vertex position tolerance.
 """
 
+import types
+
 import numpy as np
 import pytest
 
@@ -82,21 +84,30 @@ def test_sink_matches_oracle_and_stored(name, make, k):
 
 
 def test_sink_billion_family_device_generated():
-    """The billion-strut family (BCC, radii 0.08 (1 +- 0.1), no jitter) at
-    24^3 cells, generated on the device: every node is meshed (the oracle
-    meshes all of them), and the totals do not depend on the chunking."""
+    """The billion-strut family (BCC, radii 0.08 (1 +- 0.1), no jitter, nodes
+    numbered layer by layer) at 24^3 cells, generated on the device: every
+    node is meshed (the oracle meshes all of them), the totals do not depend
+    on the chunking (slabs of layers, and chunks that cut layers), and the
+    stored mesh of the same lattice is closed and outward oriented with
+    chi = 2N - 2S, its triangle and vertex counts equal to the sink's."""
     import latgen.device
     from paper_2405_15197_amd import Mesher
+    from parity import check_closed, result_np
 
     lat = latgen.device.config(3, scale=24)
     M = Mesher(lat)
     try:
         tots = []
-        for chunk in (lat.n_nodes, 4099):
+        for chunk in (lat.n_nodes, 4099, 2 * (25 * 25 + 24 * 24)):
             w = M.sink(12, chunk)
             assert int(w[:, 7].sum()) == 0, "nodes without a mesh"
             with np.errstate(over="ignore"):
                 tots.append(w.sum(axis=0, dtype=np.uint64))
-        assert np.array_equal(tots[0], tots[1])
+        assert np.array_equal(tots[0], tots[1]) and np.array_equal(tots[0], tots[2])
+        G = result_np(M.run(12, meta=False), meta=False)
     finally:
         M.close()
+    assert int(tots[0][0]) == G["totals"]["n_triangles"] and int(tots[0][2]) == G["totals"]["n_mesh_vertices"]
+    host = types.SimpleNamespace(n_nodes=lat.n_nodes, n_struts=lat.n_struts)
+    chi, vol = check_closed(G, host)
+    print(f"billion family 24^3: closed, chi {chi}, volume {vol:.4g}", flush=True)
