@@ -165,7 +165,7 @@ void carve_fixed(lm_plan *P, Carver &c, int64_t N, int64_t S)
 
 void carve_grad(lm_plan *P, Carver &c, int64_t N, int64_t S)
 {
-    P->w.loss_node = c.take<double>(3 * (N + 1));
+    P->w.loss_node = c.take<double>(3 * (N + 1) + 3 * 256);  // node terms, then block partials
     P->w.grad_node = c.take<float>(4 * (N + 1));
     P->w.grad_he = c.take<float>(4 * (2 * S + 1));
 }

@@ -214,17 +214,15 @@ __global__ void __launch_bounds__(64) k_loss_node(LParams P)
 }
 
 // per-node terms -> terms, in an order that does not depend on scheduling:
-// thread t sums nodes t, t + kBlock, ... in turn, then a fixed tree
-__global__ void __launch_bounds__(256) k_loss_reduce(int64_t N, const double *node_terms, double *terms)
+// block b sums the nodes of its contiguous slice (thread t takes every
+// kBlock-th node of the slice in turn, then a fixed tree) into partial b;
+// one block then adds the kLossParts partials by the same fixed tree.
+constexpr int kLossParts = 256;
+
+__device__ inline void block_tree3(double a, double b, double c, double *out)
 {
     __shared__ double s[3][kBlock];
     const int t = threadIdx.x;
-    double a = 0.0, b = 0.0, c = 0.0;
-    for (int64_t n = t; n < N; n += kBlock) {
-        a += node_terms[3 * n];
-        b += node_terms[3 * n + 1];
-        c += node_terms[3 * n + 2];
-    }
     s[0][t] = a;
     s[1][t] = b;
     s[2][t] = c;
@@ -237,7 +235,32 @@ __global__ void __launch_bounds__(256) k_loss_reduce(int64_t N, const double *no
         }
         __syncthreads();
     }
-    if (t < 3) terms[t] = s[t][0];
+    if (t < 3) out[t] = s[t][0];
+}
+
+__global__ void __launch_bounds__(256) k_loss_partial(int64_t N, const double *node_terms, double *partial)
+{
+    const int64_t slice = (N + kLossParts - 1) / kLossParts;
+    const int64_t n0 = (int64_t)blockIdx.x * slice, n1 = n0 + slice < N ? n0 + slice : N;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t n = n0 + threadIdx.x; n < n1; n += kBlock) {
+        a += node_terms[3 * n];
+        b += node_terms[3 * n + 1];
+        c += node_terms[3 * n + 2];
+    }
+    block_tree3(a, b, c, partial + 3 * blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_loss_reduce(const double *partial, double *terms)
+{
+    const int t = threadIdx.x;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = t; i < kLossParts; i += kBlock) {
+        a += partial[3 * i];
+        b += partial[3 * i + 1];
+        c += partial[3 * i + 2];
+    }
+    block_tree3(a, b, c, terms);
 }
 
 __global__ void k_zero_f(float *p, int64_t n)
@@ -895,7 +918,9 @@ hipError_t launch_loss(const Inputs &in, const Work &w, const FillOut &o, float3
     P.dldx = dldx;
     P.terms = terms;
     k_loss_node<<<(unsigned)in.n_nodes, 64, 0, st>>>(P);
-    k_loss_reduce<<<1, kBlock, 0, st>>>(in.n_nodes, w.loss_node, terms);
+    double *partial = w.loss_node + 3 * (in.n_nodes + 1);  // kLossParts x 3 after the node terms
+    k_loss_partial<<<kLossParts, kBlock, 0, st>>>(in.n_nodes, w.loss_node, partial);
+    k_loss_reduce<<<1, kBlock, 0, st>>>(partial, terms);
     return hipGetLastError();
 }
 
