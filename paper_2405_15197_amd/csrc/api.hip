@@ -55,6 +55,8 @@ struct lm_plan {
     void *grad_mem = nullptr;                 // adjoint scratch (library-owned)
     int schedule = LM_SCHEDULE_WAVE;          // FP32 node pass of lm_count / lm_forward
     void *thread_scratch = nullptr;           // per-node scratch of the thread-centric pass
+    int64_t cls_est[4];        // nodes per valence class when the plan was made (grid sizes only)
+    bool has_cls_est = false;
     int k;          // resolution of the last count (0: none)
     float kappa_max;// FP32 -> FP64 hand-over threshold
     lm_totals last; // totals of the last lm_count
@@ -265,7 +267,8 @@ int run_count(lm_plan *P, int k, const lm::FillOut *out, const lm::Work &w, cons
             if (!P->thread_scratch) HIPCHK(hipMalloc(&P->thread_scratch, lm::node_thread_scratch_bytes()));
             HIPCHK(lm::launch_node_thread(P->in, w, k, P->kappa_max, P->thread_scratch, P->st));
         } else {
-            HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, 0, P->st, src_rec, src_node_rec, redo, redo_cnt));
+            HIPCHK(lm::launch_node(P->in, w, k, P->kappa_max, 0, P->st, src_rec, src_node_rec, redo, redo_cnt,
+                                   nullptr, P->has_cls_est ? P->cls_est : nullptr));
         }
     }
     {
@@ -395,9 +398,11 @@ int first_prepare(lm_plan *P)
         hipMemsetAsync(P->w.totals, 0, sizeof(int64_t) * 16, P->st) != hipSuccess ||
         lm::launch_prepare(P->in, P->w, P->st) != hipSuccess ||
         hipMemcpyAsync(&fl, P->w.flags + 1, sizeof(int32_t), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
+        hipMemcpyAsync(P->cls_est, P->w.cls_info, sizeof(P->cls_est), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
         hipStreamSynchronize(P->st) != hipSuccess)
         return LM_ERR_HIP;
     if (fl & lm::DF_BADLAT) return LM_ERR_BAD_LATTICE;  // set in flags[1]
+    P->has_cls_est = true;
     return LM_OK;
 }
 

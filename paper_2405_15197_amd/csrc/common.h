@@ -337,9 +337,12 @@ hipError_t launch_arc_codec(const Inputs &in, const Work &w, bool encode, const 
                             hipStream_t st);
 // With sink set, the node pass runs in sink mode (end loops only in the
 // records; vertices and fans of the nodes in [sink->n0, sink->n1) hashed).
+// cls_est (host, may be null): nodes per valence class as last read back,
+// used only to size the persistent grids (any size covers every queued node).
 hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, int fp64, hipStream_t st,
                        const uint32_t *src_rec = nullptr, const int64_t *src_node_rec = nullptr,
-                       int32_t *redo = nullptr, int32_t *redo_cnt = nullptr, const SinkOut *sink = nullptr);
+                       int32_t *redo = nullptr, int32_t *redo_cnt = nullptr, const SinkOut *sink = nullptr,
+                       const int64_t *cls_est = nullptr);
 // Node records -> meta-mesh, mesh vertices and hole fans.
 hipError_t launch_expand(const Inputs &in, const Work &w, const FillOut &o, hipStream_t st);
 hipError_t launch_band_count(const Inputs &in, const Work &w, hipStream_t st);

@@ -1759,6 +1759,7 @@ constexpr unsigned kFp64BigGrid = 512;
 constexpr int64_t kBigGrid = 2048;  // blocks of a multi-wave class launch
 constexpr int64_t kNodeGrid = 256 * 32;  // waves per class launch
 constexpr int64_t kRedoGrid = 512;       // waves per class launch over a redo list
+constexpr int64_t kMinGrid = 32;         // blocks of a class launch sized by an estimate
 
 }  // namespace
 
@@ -1789,7 +1790,7 @@ hipError_t launch_node_thread(const Inputs &in, const Work &w, int k, float kapp
 
 hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, int fp64, hipStream_t st,
                        const uint32_t *src_rec, const int64_t *src_node_rec, int32_t *redo, int32_t *redo_cnt,
-                       const SinkOut *sink)
+                       const SinkOut *sink, const int64_t *cls_est)
 {
     if (in.n_nodes == 0) return hipSuccess;
     Params P;
@@ -1813,12 +1814,23 @@ hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, 
         }
         return hipGetLastError();
     }
-    const unsigned big_grid = (unsigned)(in.n_nodes < kBigGrid ? in.n_nodes : kBigGrid);
-    // persistent grids: enough waves to fill the chip, never more than items
-    auto grid = [&](int npw, int64_t cap) {
-        int64_t items = (in.n_nodes + npw - 1) / npw;
+    // persistent grids: enough waves to fill the chip, never more than
+    // items; with a class estimate, sized by the class (at least a few
+    // blocks, so that an estimate grown stale still drains the queue)
+    auto items_of = [&](int cls, int npw) {
+        const int64_t nodes = cls_est ? cls_est[cls] : in.n_nodes;
+        return (nodes + npw - 1) / npw;
+    };
+    auto clampg = [&](int64_t items, int64_t cap) {
+        const int64_t lo = cls_est ? kMinGrid : 1;
+        items = items < lo ? lo : items;
         return (unsigned)(items < cap ? items : cap);
     };
+    auto grid = [&](int npw, int64_t cap) {
+        const int cls = npw == 4 ? 0 : npw == 2 ? 1 : 2;
+        return clampg(items_of(cls, npw), cap);
+    };
+    const unsigned big_grid = clampg(items_of(3, 1), kBigGrid);
     if (src_rec) {
         if (!redo || !redo_cnt) return hipErrorInvalidValue;
         k_node32<CfgV4, kModeRetri><<<grid(4, kNodeGrid), 64, 0, st>>>(P, 0);
