@@ -31,12 +31,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # by the kernel's sources and build flags they were taken on; a changed
 # kernel reports null.
 MEASURED_TRAFFIC = {
-    "d8599b7ed74de8f5": {"bytes": 2_323_603_584, "summary": "profiles/k_node32_bcc64_k16_hbm_counters.md"},
+    "b78b68e392916ebf": {"bytes": 2_322_052_224, "summary": "profiles/k_node32_bcc64_k16_hbm_counters.md"},
 }
 # wave64 VALU instructions per node pass (SQ_INSTS_VALU summed over the three
 # valence-class launches) from the same counter runs, keyed the same way
 MEASURED_VALU = {
-    "d8599b7ed74de8f5": {"insts": 1_389_464_823, "summary": "profiles/k_node32_bcc64_k16_hbm_counters.md"},
+    "b78b68e392916ebf": {"insts": 1_387_114_711, "summary": "profiles/k_node32_bcc64_k16_hbm_counters.md"},
 }
 # VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per
 # SIMD every 4 cycles (16 lanes wide; packed FP32 is not used)
