@@ -123,31 +123,70 @@ __device__ inline uint32_t tie_name(int p, int q, int r, int root)
     return vname3(t.x, t.y, t.z, root);
 }
 
-// exclusive scan over the W lanes of a node.  A group wider than a wave
-// (the whole block) combines the waves' totals through LDS; every lane of
-// the block must call it.
+// Lane moves within a wave by DPP (gfx9 controls): row_shr:n shifts by n
+// lanes within each row of 16, row_bcast:15 sends lane 15 of each row to the
+// next row, row_bcast:31 sends lane 31 to rows 2 and 3, wave_shr:1 shifts the
+// whole wave by one lane.  Lanes without a source, and rows left out by the
+// row mask, read 0.  They run in the vector ALU, without the LDS round trip
+// of a lane permute.
+constexpr int kDppRowShr = 0x110, kDppWaveShr1 = 0x138, kDppBcast15 = 0x142, kDppBcast31 = 0x143;
+template <int CTRL, int ROWS = 0xf>
+__device__ inline int dpp_move(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, ROWS, 0xf, true);
+}
+
+// inclusive scan over aligned groups of W = 16, 32 or 64 lanes of the wave:
+// within rows, then the rows' totals carried forward
+template <int W>
+__device__ inline int wave_incl_scan(int x)
+{
+    x += dpp_move<kDppRowShr + 1>(x);
+    x += dpp_move<kDppRowShr + 2>(x);
+    x += dpp_move<kDppRowShr + 4>(x);
+    x += dpp_move<kDppRowShr + 8>(x);
+    if constexpr (W >= 32) x += dpp_move<kDppBcast15, 0xa>(x);
+    if constexpr (W >= 64) x += dpp_move<kDppBcast31, 0xc>(x);
+    return x;
+}
+
+// x of the last lane of the lane's group of W lanes (every lane of the wave
+// holds a value)
+template <int W>
+__device__ inline int group_last_lane(int x)
+{
+    if constexpr (W == 64) {
+        return __builtin_amdgcn_readlane(x, 63);
+    } else {
+        const int g = (int)(threadIdx.x & 63) / W;
+        int r = __builtin_amdgcn_readlane(x, W - 1);
+#pragma unroll
+        for (int i = 1; i < 64 / W; ++i) {
+            const int t = __builtin_amdgcn_readlane(x, i * W + W - 1);
+            if (g == i) r = t;
+        }
+        return r;
+    }
+}
+
+// exclusive scan over the W lanes of a node; every lane of the group must
+// call it.  A group wider than a wave (the whole block) combines the waves'
+// totals through LDS.
 template <int W>
 __device__ inline int group_excl_scan(int x, int *total)
 {
-    if constexpr (W <= 64) {
-        const int lane = threadIdx.x & (W - 1);
-        int inc = x;
-#pragma unroll
-        for (int d = 1; d < W; d <<= 1) {
-            int y = __shfl_up(inc, d, W);
-            if (lane >= d) inc += y;
-        }
-        *total = __shfl(inc, W - 1, W);
+    if constexpr (W == 1) {
+        *total = x;
+        return 0;
+    } else if constexpr (W <= 64) {
+        static_assert(W >= 16, "groups of 16, 32 or 64 lanes");
+        const int inc = wave_incl_scan<W>(x);
+        *total = group_last_lane<W>(inc);
         return inc - x;
     } else {
         __shared__ int s_part[W / 64];
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        int inc = x;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            int y = __shfl_up(inc, d, 64);
-            if (lane >= d) inc += y;
-        }
+        const int inc = wave_incl_scan<64>(x);
         if (lane == 63) s_part[wv] = inc;
         __syncthreads();
         int before = 0, tot = 0;
@@ -163,15 +202,37 @@ __device__ inline int group_excl_scan(int x, int *total)
     }
 }
 
+template <int W>
+__device__ inline void prev_last_bits(int x, int carry, int &prev, int &last)
+{
+    prev = dpp_move<kDppWaveShr1>(x);
+    if ((threadIdx.x & (W - 1)) == 0) prev = carry;
+    last = group_last_lane<W>(x);
+}
+
 // x of the previous lane of the group (lane 0: carry) and of its last lane
 template <int W, typename T>
 __device__ inline void group_prev_last(T x, T carry, T &prev, T &last)
 {
     const int lane = threadIdx.x & (W - 1);
-    if constexpr (W <= 64) {
-        prev = __shfl_up(x, 1, W);
-        if (lane == 0) prev = carry;
-        last = __shfl(x, W - 1, W);
+    if constexpr (W == 1) {
+        prev = carry;
+        last = x;
+    } else if constexpr (W <= 64) {
+        static_assert(W >= 16, "groups of 16, 32 or 64 lanes");
+        if constexpr (sizeof(T) == 4) {
+            int p, l;
+            prev_last_bits<W>(__float_as_int(x), __float_as_int(carry), p, l);
+            prev = __int_as_float(p);
+            last = __int_as_float(l);
+        } else {
+            const int2 xv = *(const int2 *)&x, cv = *(const int2 *)&carry;
+            int2 pv, lv;
+            prev_last_bits<W>(xv.x, cv.x, pv.x, lv.x);
+            prev_last_bits<W>(xv.y, cv.y, pv.y, lv.y);
+            prev = *(const T *)&pv;
+            last = *(const T *)&lv;
+        }
     } else {
         __shared__ T s_x[W];
         s_x[lane] = x;
