@@ -16,18 +16,31 @@ struct XParams {
 
 __device__ inline float fbits(uint32_t u) { return __uint_as_float(u); }
 
+// Mesh vertex i of the node (node-local): a meta-vertex (record word 1..3 of
+// its 16-byte group), an Eq. 12 point (by mesh index, after the hole
+// centres) or a hole centre
+__device__ inline float3 mesh_local(const uint32_t *RV, const uint32_t *RI, const uint32_t *RH, int V, int wsum,
+                                    int i)
+{
+    const uint32_t *src = i < V ? RV + 4 * i + 1 : (i < wsum ? RI + 3 * i : RH + 3 * (i - wsum));
+    return make_float3(fbits(src[0]), fbits(src[1]), fbits(src[2]));
+}
+
+// The latency of the node's loads bounds this kernel (a few KB per node): the
+// bookkeeping words are loaded together, then the first item of each output
+// per lane (one round for most nodes) before any store, so that one wait
+// covers all of them.
 __global__ void __launch_bounds__(64) k_expand(XParams P)
 {
-    __shared__ uint4 s_arc[kAcap][kRecArcFields / 4];  // the node's arcs, staged once
-    __shared__ uint4 s_vtx[kVcap];                     // its vertices (name, xyz)
+    __shared__ uint4 s_arc[kAcap][2];  // words 8..15 of each arc, for the hole fans
     const Work &W = P.w;
     const FillOut &O = P.o;
     const int64_t N = P.in.n_nodes;
     const int64_t n = xcd_block(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
     if (n >= N) return;
-    if (W.flags[0] & (DF_CAPACITY | DF_BADLAT | DF_RECCAP)) return;
     // the record's sizes are the node's counts: no wait for its header
+    const int flags = W.flags[0];
     const int64_t rb = W.node_rec[n];
     const int64_t Np1 = N + 1;
     const int64_t voff = W.node_off[NC_VERT * Np1 + n], aoff = W.node_off[NC_ARC * Np1 + n];
@@ -39,6 +52,11 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
     const int M = (int)(W.node_off[NC_MESH * Np1 + n + 1] - moff);
     const int F = (int)(W.node_off[NC_FAN * Np1 + n + 1] - foff);
     const float4 c4 = W.node4[n];
+    // all of these are loaded before the first branch (otherwise the
+    // compiler moves loads below the exits, one wait after another)
+    asm volatile("" ::"s"(flags), "s"(rb), "s"(voff), "s"(aoff), "s"(hoff), "s"(moff), "s"(foff), "s"(V), "s"(E),
+                 "s"(NC), "s"(M), "s"(F), "s"(c4.x), "s"(c4.y), "s"(c4.z));
+    if (flags & (DF_CAPACITY | DF_BADLAT | DF_RECCAP)) return;
     if (rb < 0) return;
     const int wsum = M - NC;  // hole centres come last
     const uint32_t *R = W.rec + rb;
@@ -47,64 +65,66 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
     const uint32_t *RH = RA + kRecArcFields * E;
     // the node's Eq. 12 points follow its hole centres, by mesh index
     const uint32_t *RI = RH + 3 * NC - 3 * V;
+    const uint4 *RA4 = (const uint4 *)RA;  // the arc block starts on a 16-byte boundary
+    const bool want_arcs = O.arc_f32 != nullptr || F > 0;
+    const int64_t cA = O.cap_arc;
 
-    // arcs: whole 16-byte groups into LDS (the arc block starts on a 16-byte
-    // boundary); every later read of an arc field is an LDS read.  The arcs
-    // of a node of the multi-wave class (more than kAcap) stay in the record.
-    const bool staged = E <= kAcap;
-    if (staged)
-        for (int x = lane; x < (kRecArcFields / 4) * E; x += 64)
-            s_arc[x / (kRecArcFields / 4)][x % (kRecArcFields / 4)] = ((const uint4 *)RA)[x];
-    const bool vstaged = V <= kVcap;
-    if (vstaged)
-        for (int i = lane; i < V; i += 64) s_vtx[i] = ((const uint4 *)RV)[i];
-    __syncthreads();
-    auto aw = [&](int j, int f) -> uint32_t {
-        return staged ? ((const uint32_t *)s_arc[j])[f] : RA[kRecArcFields * j + f];
-    };
-    // word f (0 name, 1..3 xyz) of vertex i
-    auto vw = [&](int i, int f) -> uint32_t {
-        return vstaged ? ((const uint32_t *)&s_vtx[i])[f] : RV[4 * i + f];
-    };
-    if (O.vert_name) {
-        for (int i = lane; i < V; i += 64) {
-            O.vert_name[voff + i] = vw(i, 0);
-            O.vert_xyz[0 * O.cap_vert + voff + i] = fbits(vw(i, 1));
-            O.vert_xyz[1 * O.cap_vert + voff + i] = fbits(vw(i, 2));
-            O.vert_xyz[2 * O.cap_vert + voff + i] = fbits(vw(i, 3));
-        }
-    }
-    if (O.arc_f32) {
-        const int64_t cA = O.cap_arc;
-        for (int j = lane; j < E; j += 64) {
-#pragma unroll
-            for (int t = 0; t < 10; ++t) O.arc_f32[t * cA + aoff + j] = fbits(aw(j, t));
-            O.arc_f32[10 * cA + aoff + j] = fbits(aw(j, 9)) + fbits(aw(j, 10));  // t2 = t1 + dt
-            O.arc_u32[0 * cA + aoff + j] = aw(j, 11) & 0x1ffffu;  // p | q<<8 | whole<<16
-            O.arc_u32[1 * cA + aoff + j] = aw(j, 12);
-            O.arc_u32[2 * cA + aoff + j] = (uint32_t)n;
-        }
-    }
-    __syncthreads();
-
-    // mesh vertices: meta-vertices, interior points, hole centres
-    for (int i = lane; i < M; i += 64) {
-        float3 w;
-        if (i < V) {
-            w = make_float3(fbits(vw(i, 1)), fbits(vw(i, 2)), fbits(vw(i, 3)));
-        } else if (i < wsum) {
-            w = make_float3(fbits(RI[3 * i]), fbits(RI[3 * i + 1]), fbits(RI[3 * i + 2]));
-        } else {
-            const int c = i - wsum;
-            w = make_float3(fbits(RH[3 * c]), fbits(RH[3 * c + 1]), fbits(RH[3 * c + 2]));
-        }
+    auto put_mesh = [&](int i, float3 w) {
         float *dst = O.mesh_xyz + 3 * (moff + i);
         dst[0] = c4.x + w.x;
         dst[1] = c4.y + w.y;
         dst[2] = c4.z + w.z;
+    };
+    auto put_vert = [&](int i, uint4 g) {
+        O.vert_name[voff + i] = g.x;
+        O.vert_xyz[0 * O.cap_vert + voff + i] = fbits(g.y);
+        O.vert_xyz[1 * O.cap_vert + voff + i] = fbits(g.z);
+        O.vert_xyz[2 * O.cap_vert + voff + i] = fbits(g.w);
+    };
+    auto put_arc = [&](int j, uint4 g0, uint4 g1, uint4 g2, uint4 g3) {
+        const uint32_t f[13] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w, g2.x, g2.y, g2.z, g2.w, g3.x};
+#pragma unroll
+        for (int t = 0; t < 10; ++t) O.arc_f32[t * cA + aoff + j] = fbits(f[t]);
+        O.arc_f32[10 * cA + aoff + j] = fbits(f[9]) + fbits(f[10]);  // t2 = t1 + dt
+        O.arc_u32[0 * cA + aoff + j] = f[11] & 0x1ffffu;              // p | q<<8 | whole<<16
+        O.arc_u32[1 * cA + aoff + j] = f[12];
+        O.arc_u32[2 * cA + aoff + j] = (uint32_t)n;
+    };
+
+    // first round: item `lane` of every output, all loads before any store
+    float3 w0 = make_float3(0.f, 0.f, 0.f);
+    uint4 g0 = make_uint4(0, 0, 0, 0), g1 = g0, g2 = g0, g3 = g0, gv = g0;
+    if (lane < M) w0 = mesh_local(RV, RI, RH, V, wsum, lane);
+    if (want_arcs && lane < E) {
+        g0 = RA4[4 * lane];
+        g1 = RA4[4 * lane + 1];
+        g2 = RA4[4 * lane + 2];
+        g3 = RA4[4 * lane + 3];
     }
+    if (O.vert_name && lane < V) gv = ((const uint4 *)RV)[lane];
+    if (lane < M) put_mesh(lane, w0);
+    if (O.arc_f32 && lane < E) put_arc(lane, g0, g1, g2, g3);
+    if (O.vert_name && lane < V) put_vert(lane, gv);
+    // further rounds (nodes with more than 64 of an item)
+    for (int i = lane + 64; i < M; i += 64) put_mesh(i, mesh_local(RV, RI, RH, V, wsum, i));
+    if (O.arc_f32)
+        for (int j = lane + 64; j < E; j += 64) put_arc(j, RA4[4 * j], RA4[4 * j + 1], RA4[4 * j + 2], RA4[4 * j + 3]);
+    if (O.vert_name)
+        for (int i = lane + 64; i < V; i += 64) put_vert(i, ((const uint4 *)RV)[i]);
+    if (F == 0) return;
+
     // hole fans: one triangle per circular-arc segment, apex at the contour's
-    // hole centre, oriented outward
+    // hole centre, oriented outward.  Words 8..15 of the arcs go to LDS (the
+    // arcs of a multi-wave-class node, more than kAcap, stay in the record).
+    const bool staged = E <= kAcap;
+    if (staged && lane < E) {
+        s_arc[lane][0] = g2;
+        s_arc[lane][1] = g3;
+    }
+    __syncthreads();
+    auto aw = [&](int j, int f) -> uint32_t {  // word f (8..15) of arc j
+        return staged ? ((const uint32_t *)s_arc[j])[f - 8] : RA[kRecArcFields * j + f];
+    };
     const int64_t fan0 = W.band_off[P.in.n_struts] + foff;
     for (int i = lane; i < F; i += 64) {
         // last arc with fbase <= i: a circular arc (the others, after them,
