@@ -36,6 +36,8 @@
 // |det(n1, n2, n3)|) or when an FP32 consistency check fails.
 #include <type_traits>
 
+#include <utility>
+
 #include "geom.h"
 
 namespace lm {
@@ -96,6 +98,7 @@ struct Shared {
     int loop_rot[C::VM + 1];        // loop position of the smallest phi
     T ph_first[C::VM + 1], ph_last[C::VM + 1];  // phi keys of each loop's ends
     int lbase[C::VM + 2];           // loop samples before each strut's loop
+    uint8_t wmark[C::W <= 64 ? C::W : 1];  // loop entries starting in a window of samples
     int status, n_arc, n_vert, n_contour;
     int wsum, fsum, ncirc;
     int64_t rec;                    // first word of the node record, -1: none
@@ -200,6 +203,16 @@ __device__ inline int group_excl_scan(int x, int *total)
         *total = tot;
         return before + inc - x;
     }
+}
+
+// x of lane 8 g + S in the lane's group g of 8 lanes (row_newbcast:n sends
+// lane n of each row of 16 to the whole row)
+template <int S>
+__device__ inline int group8_lane(int x)
+{
+    const int a = __builtin_amdgcn_update_dpp(0, x, 0x150 + S, 0xf, 0xf, false);
+    const int b = __builtin_amdgcn_update_dpp(0, x, 0x158 + S, 0xf, 0xf, false);
+    return (threadIdx.x & 8) ? b : a;
 }
 
 template <int W>
@@ -471,6 +484,17 @@ __device__ inline void trim_step(TrimRun<T> &st, int kind, T lo, T lc, int r)
 #pragma unroll
     for (int j = 0; j < NP; ++j) st.pc[j] = out[j];
     if (no == 0) st.done = true;
+}
+
+// Split trimming round: the constraint of lane S of the group (kind, label,
+// interval) intersected in constraint order, S = 0 .. 6
+template <int... S>
+__device__ inline void split_steps(TrimRun<float> &st, int kind, int r, float lo, float lc,
+                                   std::integer_sequence<int, S...>)
+{
+    (trim_step(st, group8_lane<S>(kind), __int_as_float(group8_lane<S>(__float_as_int(lo))),
+               __int_as_float(group8_lane<S>(__float_as_int(lc))), group8_lane<S>(r)),
+     ...);
 }
 
 // final form: end directions and tie roots of every piece
@@ -965,19 +989,37 @@ __device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, c
             // step that closes a loop is checked afterwards.  A valid loop
             // has exactly one descent, just before its smallest phi.
             T carry = (T)0;
+            int e_carry = -1;  // loop entry of the sample before the window
             for (int base = 0; base < ns_tot; base += WL) {
                 const int sidx = base + lane;
                 const bool act = sidx < ns_tot;
                 int m = 1, idx = 0, nloop = 1, li = 0;
                 T ph = (T)0;
-                if (act) {
+                int e = 0;  // loop entry of sample sidx
+                if constexpr (WL >= 16 && WL <= 64) {
+                    // the entries that start in the window [base, base + WL)
+                    // are e_carry + 1, e_carry + 2, ... (every entry has a
+                    // sample): each marks its first sample, and a scan of the
+                    // marks over the lanes gives every sample its entry
+                    sh.wmark[lane] = 0;
+                    const int ec = e_carry + 1 + lane;
+                    if (ec < nent) {
+                        const int o = sh.entry_off[ec] - base;
+                        if (o < WL) sh.wmark[o] = 1;
+                    }
+                    __syncthreads();
+                    e = e_carry + wave_incl_scan<WL>((int)sh.wmark[lane]);
+                    e_carry = group_last_lane<WL>(e);
+                } else if (act) {
                     int lo = 0, hi = nent - 1;  // last entry with entry_off <= sidx
                     while (lo < hi) {
                         int mid = (lo + hi + 1) >> 1;
                         if (sh.entry_off[mid] <= sidx) lo = mid;
                         else hi = mid - 1;
                     }
-                    const int e = lo;
+                    e = lo;
+                }
+                if (act) {
                     m = sh.entry_m[e];
                     idx = sidx - sh.lbase[m];
                     nloop = sh.loop_len[m];
@@ -1232,22 +1274,17 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
                     if (myr >= q) ++myr;
                     if (ell && sub < v - 1) mykind = cons_interval(sh.S, gp, hp, myr, C, mylo, mylc);
                 }
-                const int src0 = (int)(threadIdx.x & 63) & ~7;
-                const int nsteps = split ? 7 : (act && ell ? v + 1 : 0);
+                const int nsteps = split ? 0 : (act && ell ? v + 1 : 0);
                 TrimRun<T> st;
+                if constexpr (F32) {
+                    if (split) split_steps(st, mykind, myr, mylo, mylc, std::make_integer_sequence<int, 7>{});
+                }
                 for (int s2 = 0; s2 < nsteps; ++s2) {
-                    int r2 = s2, k2 = 0;
+                    int k2 = 0;
                     T lo2 = (T)0, lc2 = (T)0;
-                    if (split) {
-                        k2 = __shfl(mykind, src0 + s2, 64);
-                        r2 = __shfl(myr, src0 + s2, 64);
-                        lo2 = __shfl(mylo, src0 + s2, 64);
-                        lc2 = __shfl(mylc, src0 + s2, 64);
-                    } else if (r2 != p && r2 != q) {
-                        k2 = cons_interval(sh.S, gp, hp, r2, C, lo2, lc2);
-                    }
-                    trim_step(st, k2, lo2, lc2, r2);
-                    if (!split && st.done) break;
+                    if (s2 != p && s2 != q) k2 = cons_interval(sh.S, gp, hp, s2, C, lo2, lc2);
+                    trim_step(st, k2, lo2, lc2, s2);
+                    if (st.done) break;
                 }
                 if (act && ell) {
                     trim_finish(sh.S, p, q, C, gp, hp, st, TR);
@@ -1492,8 +1529,10 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
         });
         __syncthreads();
         if (group_status<WL>(sh)) goto tail;
-        // position of each arc in its loop; the first arc also checks that
-        // the successor chain closes after exactly the loop's arc count
+        // position of each arc in its loop.  Every arc reached within c - 1
+        // steps from the first makes the chain a path through all c arcs; it
+        // closes into one loop exactly when the arc reached last leads back
+        // to the first.
         for (int pp = lane; pp < tot; pp += WL) {
             const int m = strut_of(pp);
             const int b0 = sh.loop_base[m], c = sh.loop_base[m + 1] - b0;
@@ -1507,14 +1546,7 @@ __device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
                 continue;
             }
             sh.loop_ord[b0 + t] = (uint8_t)(pp - b0);
-            if (pp == sh.loop_first[m]) {
-                int x = sh.loop_next[pp], steps = 1;
-                while (x != pp && steps <= c) {
-                    x = sh.loop_next[x];
-                    ++steps;
-                }
-                if (steps != c) atomicOr(&sh.status, NS_LOOP);
-            }
+            if (t == c - 1 && sh.loop_next[pp] != sh.loop_first[m]) atomicOr(&sh.status, NS_LOOP);
         }
         if (tot > 2 * CF::AC && lane == 0) atomicOr(&sh.status, NS_CAPACITY);
         __syncthreads();
