@@ -704,7 +704,7 @@ constexpr int kRetry = NS_NON_ELLIPTIC | NS_LOOP | NS_TOPOLOGY | NS_PREC | NS_CA
 // order and FP32 arithmetic) and of its hole fans, added to the node's chunk
 // or part.
 template <typename T, typename CF>
-__device__ void sink_hash_node(const Params &P, Shared<T, CF> &sh, const int64_t n, const int M, const int F)
+__device__ __forceinline__ void sink_hash_node(const Params &P, Shared<T, CF> &sh, const int64_t n, const int M, const int F)
 {
     constexpr int WL = CF::W;
     const int lane = threadIdx.x & (WL - 1);
@@ -798,7 +798,7 @@ __device__ void sink_hash_node(const Params &P, Shared<T, CF> &sh, const int64_t
 // strut end loops are kept (for the bands); the node's mesh vertices and hole
 // fans are counted and hashed here (sink mode).
 template <typename T, typename CF, bool SINK>
-__device__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, const int k, const int v,
+__device__ __forceinline__ void node_tail(const Params &P, Shared<T, CF> &sh, const int64_t n, const int k, const int v,
                           const int64_t row, const T rho, const V3<T> cen)
 {
     constexpr int WL = CF::W;
@@ -1168,7 +1168,7 @@ finish:
 }
 
 template <typename T, typename CF, bool SINK = false>
-__device__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
+__device__ __forceinline__ void node_body(const Params &P, Shared<T, CF> &sh, const int64_t n)
 {
     constexpr int WL = CF::W;
     constexpr bool F32 = sizeof(T) == 4;
@@ -1620,7 +1620,7 @@ tail:
 // one vertex and one table word per lane: E <= AC = W, V <= VC <= W) before
 // anything is written to LDS.
 template <typename CF>
-__device__ void node_retri(const Params &P, Shared<float, CF> &sh, const int64_t n, const int cls)
+__device__ __forceinline__ void node_retri(const Params &P, Shared<float, CF> &sh, const int64_t n, const int cls)
 {
     using T = float;
     constexpr int WL = CF::W;
@@ -1745,21 +1745,17 @@ __device__ void node_retri(const Params &P, Shared<float, CF> &sh, const int64_t
     node_tail<T, CF, false>(P, sh, n, k, v, row, rho, cen);
 }
 
-// FP32, one valence class: a persistent grid takes items of 64 / W queued
-// nodes from a work counter; every wave leaves once the counter has passed
-// the class's last item.  MODE 0: meta-meshing of the queue; 1:
+// FP32, one valence class: a persistent loop takes items of 64 / W queued
+// nodes from the class's work counter; every wave leaves once the counter has
+// passed the class's last item.  MODE 0: meta-meshing of the queue; 1:
 // re-subdivision of the queue; 2: meta-meshing of the redo list that mode 1
 // left (its length is read on the device); 3: meta-meshing of the queue in
 // sink mode (end loops kept, vertices and fans hashed).
 enum { kModeMesh = 0, kModeRetri = 1, kModeRedo = 2, kModeSink = 3 };
-// At most 168 VGPRs: three waves per SIMD (LDS allows as many), where one
-// register more would leave two.
 template <typename C, int MODE>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_node32(Params P, int cls)
+__device__ inline void drain_class(const Params &P, int cls, Shared<float, C> *sh, int &s_item)
 {
     constexpr int NPW = 64 / C::W;
-    __shared__ Shared<float, C> sh[NPW];
-    __shared__ int s_item;
     const int slot = threadIdx.x / C::W;
     const int64_t cnt = MODE == kModeRedo ? (int64_t)P.redo_cnt[cls] : P.w.cls_info[cls];
     const int64_t base = P.w.cls_info[4 + cls];
@@ -1781,6 +1777,33 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
         }
         __syncthreads();
     }
+}
+
+// At most 168 VGPRs: three waves per SIMD (LDS allows as many), where one
+// register more would leave two.
+template <typename C, int MODE>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_node32(Params P, int cls)
+{
+    __shared__ Shared<float, C> sh[64 / C::W];
+    __shared__ int s_item;
+    drain_class<C, MODE>(P, cls, sh, s_item);
+}
+
+// The classes v <= 4 (four nodes per wave) and 5..8 (two) in one persistent
+// launch, the heavier first: the light nodes fill the tail of the others
+// instead of running as a short launch of their own.  The two LDS layouts
+// share one block of LDS, used by one class at a time.
+union SharedV4V8 {
+    Shared<float, CfgV8> b[2];
+    Shared<float, CfgV4> a[4];
+};
+template <int MODE>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_node32_v8v4(Params P)
+{
+    __shared__ SharedV4V8 sh;
+    __shared__ int s_item;
+    drain_class<CfgV8, MODE>(P, 1, sh.b, s_item);
+    drain_class<CfgV4, MODE>(P, 0, sh.a, s_item);
 }
 
 // The multi-wave class: one node per block of kBigWaves waves, items from the
@@ -1850,8 +1873,8 @@ __global__ void __launch_bounds__(C::W) __attribute__((amdgpu_waves_per_eu(2))) 
 constexpr unsigned kFp64Grid = 2048;
 constexpr unsigned kFp64BigGrid = 512;
 constexpr int64_t kBigGrid = 2048;  // blocks of a multi-wave class launch
-constexpr int64_t kNodeGrid = 256 * 32;  // waves per class launch
-constexpr int64_t kRedoGrid = 512;       // waves per class launch over a redo list
+constexpr int64_t kNodeGrid = 256 * 32;  // waves of the one-wave classes' launch
+constexpr int64_t kRedoGrid = 512;       // waves of that launch over a redo list
 constexpr int64_t kMinGrid = 32;         // blocks of a class launch sized by an estimate
 
 }  // namespace
@@ -1919,31 +1942,27 @@ hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, 
         items = items < lo ? lo : items;
         return (unsigned)(items < cap ? items : cap);
     };
-    auto grid = [&](int npw, int64_t cap) {
-        const int cls = npw == 4 ? 0 : npw == 2 ? 1 : 2;
-        return clampg(items_of(cls, npw), cap);
-    };
+    // classes 0 and 1 share a launch: items of both
+    const int64_t light = items_of(0, 4) + items_of(1, 2);
+    const unsigned g01 = clampg(light, kNodeGrid), g01_redo = clampg(light, kRedoGrid);
+    const unsigned g2 = clampg(items_of(2, 1), kNodeGrid), g2_redo = clampg(items_of(2, 1), kRedoGrid);
     const unsigned big_grid = clampg(items_of(3, 1), kBigGrid);
     if (src_rec) {
         if (!redo || !redo_cnt) return hipErrorInvalidValue;
-        k_node32<CfgV4, kModeRetri><<<grid(4, kNodeGrid), 64, 0, st>>>(P, 0);
-        k_node32<CfgV8, kModeRetri><<<grid(2, kNodeGrid), 64, 0, st>>>(P, 1);
-        k_node32<CfgV16, kModeRetri><<<grid(1, kNodeGrid), 64, 0, st>>>(P, 2);
+        k_node32_v8v4<kModeRetri><<<g01, 64, 0, st>>>(P);
+        k_node32<CfgV16, kModeRetri><<<g2, 64, 0, st>>>(P, 2);
         k_node32_big<kModeRetri><<<big_grid, CfgBig::W, 0, st>>>(P);
         // the redo lists are short unless most nodes needed FP64 at the source
-        k_node32<CfgV4, kModeRedo><<<grid(4, kRedoGrid), 64, 0, st>>>(P, 0);
-        k_node32<CfgV8, kModeRedo><<<grid(2, kRedoGrid), 64, 0, st>>>(P, 1);
-        k_node32<CfgV16, kModeRedo><<<grid(1, kRedoGrid), 64, 0, st>>>(P, 2);
+        k_node32_v8v4<kModeRedo><<<g01_redo, 64, 0, st>>>(P);
+        k_node32<CfgV16, kModeRedo><<<g2_redo, 64, 0, st>>>(P, 2);
         k_node32_big<kModeRedo><<<big_grid, CfgBig::W, 0, st>>>(P);
     } else if (sink) {
-        k_node32<CfgV4, kModeSink><<<grid(4, kNodeGrid), 64, 0, st>>>(P, 0);
-        k_node32<CfgV8, kModeSink><<<grid(2, kNodeGrid), 64, 0, st>>>(P, 1);
-        k_node32<CfgV16, kModeSink><<<grid(1, kNodeGrid), 64, 0, st>>>(P, 2);
+        k_node32_v8v4<kModeSink><<<g01, 64, 0, st>>>(P);
+        k_node32<CfgV16, kModeSink><<<g2, 64, 0, st>>>(P, 2);
         k_node32_big<kModeSink><<<big_grid, CfgBig::W, 0, st>>>(P);
     } else {
-        k_node32<CfgV4, kModeMesh><<<grid(4, kNodeGrid), 64, 0, st>>>(P, 0);
-        k_node32<CfgV8, kModeMesh><<<grid(2, kNodeGrid), 64, 0, st>>>(P, 1);
-        k_node32<CfgV16, kModeMesh><<<grid(1, kNodeGrid), 64, 0, st>>>(P, 2);
+        k_node32_v8v4<kModeMesh><<<g01, 64, 0, st>>>(P);
+        k_node32<CfgV16, kModeMesh><<<g2, 64, 0, st>>>(P, 2);
         k_node32_big<kModeMesh><<<big_grid, CfgBig::W, 0, st>>>(P);
     }
     return hipGetLastError();
