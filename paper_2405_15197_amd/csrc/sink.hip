@@ -182,44 +182,42 @@ __global__ void __launch_bounds__(64) k_sink_zip(Work W, SinkOut P, const int32_
             while (g_t[i + 1] <= x) ++i;
             const int j = x - g_t[i];
             const int na = g_na[i], nb = g_nb[i], ra = g_ra[i], rb = g_rb[i];
+            // edge j runs along loop X (A for j < na, else B); its apex is
+            // the last sample of the other loop Y before the edge's end
+            // (strictly before for edges of A, at or before for edges of B).
+            // One path for both kinds, the loops chosen per lane.
+            const bool ea = j < na;
+            const int nx = ea ? na : nb, ny = ea ? nb : na;
+            const int rx = ea ? ra : rb, ry = ea ? rb : ra;
+            const int ox = ea ? 0 : na, oy = ea ? na : 0;  // staged: A then B
+            const int64_t lx = ea ? g_la[i] : g_lb[i], ly = ea ? g_lb[i] : g_la[i];
             // sorted-order views of both loops (LDS when staged)
-            auto A = [&](int k) -> int2 {
-                if (staged) return st[g_t[i] + k];
-                int q = ra + k;
-                return loops[g_la[i] + (q >= na ? q - na : q)];
+            auto X = [&](int k) -> int2 {
+                if (staged) return st[g_t[i] + ox + k];
+                const int q = rx + k;
+                return loops[lx + (q >= nx ? q - nx : q)];
             };
-            auto B = [&](int k) -> int2 {
-                if (staged) return st[g_t[i] + na + k];
-                int q = rb + k;
-                return loops[g_lb[i] + (q >= nb ? q - nb : q)];
+            auto Y = [&](int k) -> int2 {
+                if (staged) return st[g_t[i] + oy + k];
+                const int q = ry + k;
+                return loops[ly + (q >= ny ? q - ny : q)];
             };
-            auto pred = [&](bool onB, float xv, bool inclusive) {
-                const int n = onB ? nb : na;
-                int lo = 0, hi = n;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    const float p = __int_as_float((onB ? B(mid) : A(mid)).y);
-                    if (inclusive ? (p <= xv) : (p < xv)) lo = mid + 1;
-                    else hi = mid;
-                }
-                return lo == 0 ? n - 1 : lo - 1;
-            };
-            const int64_t na_node = sink_local_node(P, g_a[i]), nb_node = sink_local_node(P, g_b[i]);
-            if (j < na) {
-                int k0 = j - ra;
-                if (k0 < 0) k0 += na;
-                const int k1 = k0 + 1 == na ? 0 : k0 + 1;
-                const int2 u = A(k0), u2 = A(k1);
-                const int ap = pred(true, __int_as_float(u2.y), false);
-                ht += tri_key(vid_of(na_node, u.x), vid_of(na_node, u2.x), vid_of(nb_node, B(ap).x));
-            } else {
-                int k0 = j - na - rb;
-                if (k0 < 0) k0 += nb;
-                const int k1 = k0 + 1 == nb ? 0 : k0 + 1;
-                const int2 w = B(k0), w2 = B(k1);
-                const int ap = pred(false, __int_as_float(w2.y), true);
-                ht += tri_key(vid_of(nb_node, w2.x), vid_of(nb_node, w.x), vid_of(na_node, A(ap).x));
+            int k0 = j - ox - rx;
+            if (k0 < 0) k0 += nx;
+            const int k1 = k0 + 1 == nx ? 0 : k0 + 1;
+            const int2 u = X(k0), u2 = X(k1);
+            const float xv = __int_as_float(u2.y);
+            int lo = 0, hi = ny;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                const float p = __int_as_float(Y(mid).y);
+                if (ea ? (p < xv) : (p <= xv)) lo = mid + 1;
+                else hi = mid;
             }
+            const int ap = lo == 0 ? ny - 1 : lo - 1;
+            const int64_t xn = sink_local_node(P, ea ? g_a[i] : g_b[i]), yn = sink_local_node(P, ea ? g_b[i] : g_a[i]);
+            // outward: A edges run u -> u', B edges u' -> u
+            ht += tri_key(vid_of(xn, ea ? u.x : u2.x), vid_of(xn, ea ? u2.x : u.x), vid_of(yn, Y(ap).x));
             atomicAdd(&g_h[i], (unsigned long long)ht);
         }
         __syncthreads();

@@ -82,32 +82,26 @@ __device__ inline int pred_sorted(const L &lp, float x, bool inclusive)
 }
 
 // Triangle j of a band: j < na are the edges of loop A (lower node id), in
-// loop order from A's loop position 0; then the edges of loop B.
+// loop order from A's loop position 0; then the edges of loop B.  Edge
+// X[k] -> X[k+1] of loop X takes as apex the last sample of the other loop Y
+// before X[k+1]: strictly before for edges of A, at or before for edges of B.
+// One path for both kinds (lanes of a wave hold both), the loops chosen per
+// lane.
 template <typename L>
 __device__ inline void band_tri(const L &A, const L &B, int ra, int rb, int j, int32_t ma, int32_t mb, int32_t *T)
 {
-    const int na = A.n, nb = B.n;
-    if (j < na) {
-        // edge A[j] -> A[j+1]; apex: last B sample strictly before A[j+1]
-        int k0 = j - ra;
-        if (k0 < 0) k0 += na;
-        const int k1 = k0 + 1 == na ? 0 : k0 + 1;
-        const int2 u = A.at(k0), u2 = A.at(k1);
-        const int ap = pred_sorted(B, __int_as_float(u2.y), false);
-        T[0] = ma + u.x;
-        T[1] = ma + u2.x;
-        T[2] = mb + B.at(ap).x;
-    } else {
-        // edge B[e] -> B[e+1]; apex: last A sample at or before B[e+1]
-        int k0 = j - na - rb;
-        if (k0 < 0) k0 += nb;
-        const int k1 = k0 + 1 == nb ? 0 : k0 + 1;
-        const int2 w = B.at(k0), w2 = B.at(k1);
-        const int ap = pred_sorted(A, __int_as_float(w2.y), true);
-        T[0] = mb + w2.x;
-        T[1] = mb + w.x;
-        T[2] = ma + A.at(ap).x;
-    }
+    const bool ea = j < A.n;
+    const L X = ea ? A : B, Y = ea ? B : A;
+    int k0 = ea ? j - ra : j - A.n - rb;
+    if (k0 < 0) k0 += X.n;
+    const int k1 = k0 + 1 == X.n ? 0 : k0 + 1;
+    const int2 u = X.at(k0), u2 = X.at(k1);
+    const int ap = pred_sorted(Y, __int_as_float(u2.y), !ea);
+    const int32_t mx = ea ? ma : mb, my = ea ? mb : ma;
+    // outward: A edges run u -> u', B edges u' -> u
+    T[0] = mx + (ea ? u.x : u2.x);
+    T[1] = mx + (ea ? u2.x : u.x);
+    T[2] = my + Y.at(ap).x;
 }
 
 template <int G>
