@@ -256,19 +256,37 @@ __device__ inline void group_prev_last(T x, T carry, T &prev, T &last)
     }
 }
 
-// sum over the W lanes of a node (every lane gets it); a group wider than a
-// wave adds the waves' sums through LDS
+// 64-bit x moved like dpp_move (both halves)
+template <int CTRL, int ROWS = 0xf>
+__device__ inline uint64_t dpp_move64(uint64_t x)
+{
+    const uint32_t lo = (uint32_t)dpp_move<CTRL, ROWS>((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)dpp_move<CTRL, ROWS>((int)(uint32_t)(x >> 32));
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// sum modulo 2^64 over the W lanes of a node (every lane gets it): an
+// inclusive DPP scan, then the group's last lane; a group wider than a wave
+// adds the waves' sums through LDS
 template <int W>
 __device__ inline uint64_t group_sum_u64(uint64_t x)
 {
-    if constexpr (W <= 64) {
-#pragma unroll
-        for (int o = W / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, W);
+    if constexpr (W == 1) {
         return x;
+    } else if constexpr (W <= 64) {
+        static_assert(W >= 16, "groups of 16, 32 or 64 lanes");
+        x += dpp_move64<kDppRowShr + 1>(x);
+        x += dpp_move64<kDppRowShr + 2>(x);
+        x += dpp_move64<kDppRowShr + 4>(x);
+        x += dpp_move64<kDppRowShr + 8>(x);
+        if constexpr (W >= 32) x += dpp_move64<kDppBcast15, 0xa>(x);
+        if constexpr (W >= 64) x += dpp_move64<kDppBcast31, 0xc>(x);
+        const uint32_t lo = (uint32_t)group_last_lane<W>((int)(uint32_t)x);
+        const uint32_t hi = (uint32_t)group_last_lane<W>((int)(uint32_t)(x >> 32));
+        return (uint64_t)lo | ((uint64_t)hi << 32);
     } else {
         __shared__ uint64_t s_part[W / 64];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        x = group_sum_u64<64>(x);
         if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = x;
         __syncthreads();
         uint64_t t = 0;
@@ -701,54 +719,27 @@ constexpr int kRetry = NS_NON_ELLIPTIC | NS_LOOP | NS_TOPOLOGY | NS_PREC | NS_CA
 // meta-mesh (arcs, vertices, end loops, contours) is in LDS with its status.
 // Sink mode: counts and hashes of the node's mesh vertices (meta-vertices,
 // Eq. 12 interior points, Eq. 13 hole centres, in the stored mode's node-local
-// order and FP32 arithmetic) and of its hole fans, added to the node's chunk
-// or part.
+// numbering and FP32 positions) and of its hole fans, added to the node's
+// chunk or part.  The Eq. 12 points arrive already summed (hv, sx, sy, sz) by
+// the loop walk, which evaluates them anyway.
 template <typename T, typename CF>
-__device__ __forceinline__ void sink_hash_node(const Params &P, Shared<T, CF> &sh, const int64_t n, const int M, const int F)
+__device__ __forceinline__ void sink_hash_node(const Params &P, Shared<T, CF> &sh, const int64_t n, const int M,
+                                               const int F, uint64_t hv, uint64_t sx, uint64_t sy, uint64_t sz)
 {
     constexpr int WL = CF::W;
     const int lane = threadIdx.x & (WL - 1);
     const SinkOut &S = P.sink;
     const float4 c4 = P.w.node4[n];
     const int64_t ln = sink_local_node(S, n);
-    const int V = sh.n_vert, E = sh.n_arc, wsum = sh.wsum, ncirc = sh.ncirc;
-    auto ffield = [](const T *x, float *o) {
-        o[0] = (float)x[0];
-        o[1] = (float)x[1];
-        o[2] = (float)x[2];
-    };
-    uint64_t hv = 0, sx = 0, sy = 0, sz = 0, ht = 0;
-    for (int i = lane; i < M; i += WL) {
+    const int V = sh.n_vert, wsum = sh.wsum, ncirc = sh.ncirc;
+    uint64_t ht = 0;
+    // meta-vertices (local indices 0 .. V-1) and hole centres (wsum .. M-1);
+    // the Eq. 12 points between them came in with hv, sx, sy, sz
+    for (int t = lane; t < V + (M - wsum); t += WL) {
+        const int i = t < V ? t : wsum + (t - V);
         float3 w;
         if (i < V) {
             w = make_float3((float)sh.vx[i], (float)sh.vy[i], (float)sh.vz[i]);
-        } else if (i < wsum) {
-            int lo = 0, hi = E - 1;  // last arc with mbase <= i
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (sh.A[mid].mbase <= i) lo = mid;
-                else hi = mid - 1;
-            }
-            const ArcL<T> &A = sh.A[lo];
-            const bool fwd = A.full || A.ns <= A.ne;
-            const int jc = i - A.mbase;
-            if constexpr (sizeof(T) == 8) {
-                // as stored for an FP64 node: the FP64 point rounded once
-                const V3<T> wd = interior_pt(sh, A, fwd ? jc + 1 : A.nseg - 1 - jc);
-                w = make_float3((float)wd.x, (float)wd.y, (float)wd.z);
-            } else {
-            float o[3], a[3], b[3], x1[3] = {0.f, 0.f, 0.f};
-            ffield(A.o, o);
-            ffield(A.a, a);
-            ffield(A.b, b);
-            if (!A.full) {
-                x1[0] = (float)sh.vx[A.vs];
-                x1[1] = (float)sh.vy[A.vs];
-                x1[2] = (float)sh.vz[A.vs];
-            }
-            w = arc_point_f32(o, a, b, x1, (float)A.t1, (float)A.dt, fwd ? jc + 1 : A.nseg - 1 - jc, A.nseg,
-                              A.full != 0);
-            }
         } else {
             const int c = i - wsum;
             w = make_float3((float)sh.hc[c][0], (float)sh.hc[c][1], (float)sh.hc[c][2]);
@@ -813,6 +804,12 @@ __device__ __forceinline__ void node_tail(const Params &P, Shared<T, CF> &sh, co
     (void)tp;
     (void)cen;
     (void)k;
+    // sink mode: the node's Eq. 12 points are hashed where the loop walk
+    // evaluates them (each once, on the loop of its arc's label q), for
+    // nodes of the hashed range
+    uint64_t pt_v = 0, pt_x = 0, pt_y = 0, pt_z = 0;
+    const bool hash_pts = SINK && n >= P.sink.n0 && n < P.sink.n1;
+    const int64_t ln_sink = SINK ? sink_local_node(P.sink, n) : 0;
     if (group_status<WL>(sh)) goto finish;
 
     // ---- mesh-vertex layout, hole centres, loop phi check -------------------
@@ -969,10 +966,21 @@ __device__ __forceinline__ void node_tail(const Params &P, Shared<T, CF> &sh, co
                 const int ii = fw ? j : A.nseg - j;
                 li = j == 0 ? (fw ? A.vs : A.ve) : interior_idx(A, ii);
                 const V3<T> w = j == 0 ? vert_pos(sh, li) : interior_pt(sh, A, ii);
-                if (RI && j != 0 && m == A.q) {
-                    RI[3 * li] = __float_as_uint((float)w.x);
-                    RI[3 * li + 1] = __float_as_uint((float)w.y);
-                    RI[3 * li + 2] = __float_as_uint((float)w.z);
+                if (j != 0 && m == A.q) {
+                    if (RI) {
+                        RI[3 * li] = __float_as_uint((float)w.x);
+                        RI[3 * li + 1] = __float_as_uint((float)w.y);
+                        RI[3 * li + 2] = __float_as_uint((float)w.z);
+                    }
+                    if (hash_pts) {
+                        // as stored: the point rounded once, plus the centre
+                        const float x = (float)cen.x + (float)w.x, y = (float)cen.y + (float)w.y,
+                                    z = (float)cen.z + (float)w.z;
+                        pt_v += vert_key(vid_of(ln_sink, li), x, y, z);
+                        pt_x += (uint64_t)llrint((double)x * 1048576.0);
+                        pt_y += (uint64_t)llrint((double)y * 1048576.0);
+                        pt_z += (uint64_t)llrint((double)z * 1048576.0);
+                    }
                 }
                 // tangency circles are parametrised in the strut frame: phi
                 // is the parameter itself
@@ -1099,7 +1107,7 @@ finish:
             });
             if (lane == 0) W.node_rec[n] = rb;
             if (n < P.sink.n0 || n >= P.sink.n1) return;  // halo node: its loops only
-            sink_hash_node<T, CF>(P, sh, n, Msum, Fsum);
+            sink_hash_node<T, CF>(P, sh, n, Msum, Fsum, pt_v, pt_x, pt_y, pt_z);
             return;
         }
         if (lane == 0) {
