@@ -1760,8 +1760,35 @@ __device__ __forceinline__ void node_retri(const Params &P, Shared<float, CF> &s
 // left (its length is read on the device); 3: meta-meshing of the queue in
 // sink mode (end loops kept, vertices and fans hashed).
 enum { kModeMesh = 0, kModeRetri = 1, kModeRedo = 2, kModeSink = 3 };
+
+// Guided self-scheduling on a work counter shared by the grid: a block takes
+// a share of the items left (half of them over the grid, from what its last
+// grab saw), at least one and at most kGrabMax, as the range [first, end).  The counter is one address for the whole chip and its
+// atomics are serialised there: one per item throttled the node pass (a
+// pass without the trimming, the re-subdivision, took as long as a full
+// one); a few per block do not, and the last grabs are still single items.
+// Block-uniform; every thread of the block calls it.
+constexpr int kGrabMax = 16;
+__device__ inline bool grab_items(int32_t *ctr, int64_t items, int64_t &seen, int *s_grab, int64_t &first,
+                                  int64_t &end)
+{
+    if (threadIdx.x == 0) {
+        int64_t g = (items - seen) / (2 * (int64_t)gridDim.x);
+        g = g < 1 ? 1 : (g > kGrabMax ? kGrabMax : g);
+        s_grab[0] = atomicAdd(ctr, (int)g);
+        s_grab[1] = (int)g;
+    }
+    __syncthreads();
+    first = s_grab[0];
+    const int g = s_grab[1];
+    __syncthreads();
+    seen = first + g;
+    end = seen < items ? seen : items;
+    return first < items;
+}
+
 template <typename C, int MODE>
-__device__ inline void drain_class(const Params &P, int cls, Shared<float, C> *sh, int &s_item)
+__device__ inline void drain_class(const Params &P, int cls, Shared<float, C> *sh, int *s_grab)
 {
     constexpr int NPW = 64 / C::W;
     const int slot = threadIdx.x / C::W;
@@ -1770,20 +1797,18 @@ __device__ inline void drain_class(const Params &P, int cls, Shared<float, C> *s
     const int32_t *list = MODE == kModeRedo ? P.redo : P.w.queue;
     int32_t *ctr = MODE == kModeRedo ? P.redo_ctr : P.w.work_ctr;
     const int64_t items = (cnt + NPW - 1) / NPW;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(&ctr[cls], 1);
-        __syncthreads();
-        const int64_t item = s_item;
-        __syncthreads();
-        if (item >= items) break;
-        const int64_t qi = item * NPW + slot;
-        if (qi < cnt) {
-            const int64_t node = list[base + qi];
-            if (MODE == kModeRetri) node_retri<C>(P, sh[slot], node, cls);
-            else if (MODE == kModeSink) node_body<float, C, true>(P, sh[slot], node);
-            else node_body<float, C>(P, sh[slot], node);
+    int64_t seen = 0, first, end;
+    while (grab_items(&ctr[cls], items, seen, s_grab, first, end)) {
+        for (int64_t item = first; item < end; ++item) {
+            const int64_t qi = item * NPW + slot;
+            if (qi < cnt) {
+                const int64_t node = list[base + qi];
+                if (MODE == kModeRetri) node_retri<C>(P, sh[slot], node, cls);
+                else if (MODE == kModeSink) node_body<float, C, true>(P, sh[slot], node);
+                else node_body<float, C>(P, sh[slot], node);
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -1793,8 +1818,8 @@ template <typename C, int MODE>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_node32(Params P, int cls)
 {
     __shared__ Shared<float, C> sh[64 / C::W];
-    __shared__ int s_item;
-    drain_class<C, MODE>(P, cls, sh, s_item);
+    __shared__ int s_grab[2];
+    drain_class<C, MODE>(P, cls, sh, s_grab);
 }
 
 // The classes v <= 4 (four nodes per wave) and 5..8 (two) in one persistent
@@ -1809,9 +1834,9 @@ template <int MODE>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_node32_v8v4(Params P)
 {
     __shared__ SharedV4V8 sh;
-    __shared__ int s_item;
-    drain_class<CfgV8, MODE>(P, 1, sh.b, s_item);
-    drain_class<CfgV4, MODE>(P, 0, sh.a, s_item);
+    __shared__ int s_grab[2];
+    drain_class<CfgV8, MODE>(P, 1, sh.b, s_grab);
+    drain_class<CfgV4, MODE>(P, 0, sh.a, s_grab);
 }
 
 // The multi-wave class: one node per block of kBigWaves waves, items from the
@@ -1822,26 +1847,24 @@ __global__ void __launch_bounds__(64 * kBigWaves) k_node32_big(Params P)
 {
     constexpr int cls = 3;
     __shared__ Shared<float, CfgBig> sh;
-    __shared__ int s_item;
+    __shared__ int s_grab[2];
     const int64_t cnt = MODE == kModeRedo ? (int64_t)P.redo_cnt[cls] : P.w.cls_info[cls];
     const int64_t base = P.w.cls_info[4 + cls];
     const int32_t *list = MODE == kModeRedo ? P.redo : P.w.queue;
     int32_t *ctr = MODE == kModeRedo ? P.redo_ctr : P.w.work_ctr;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(&ctr[cls], 1);
-        __syncthreads();
-        const int64_t item = s_item;
-        __syncthreads();
-        if (item >= cnt) break;
-        const int64_t node = list[base + item];
-        if (MODE == kModeRetri) {
-            if (threadIdx.x == 0) P.redo[base + atomicAdd(&P.redo_cnt[cls], 1)] = (int32_t)node;
-        } else if (MODE == kModeSink) {
-            node_body<float, CfgBig, true>(P, sh, node);
-        } else {
-            node_body<float, CfgBig>(P, sh, node);
+    int64_t seen = 0, first, end;
+    while (grab_items(&ctr[cls], cnt, seen, s_grab, first, end)) {
+        for (int64_t item = first; item < end; ++item) {
+            const int64_t node = list[base + item];
+            if (MODE == kModeRetri) {
+                if (threadIdx.x == 0) P.redo[base + atomicAdd(&P.redo_cnt[cls], 1)] = (int32_t)node;
+            } else if (MODE == kModeSink) {
+                node_body<float, CfgBig, true>(P, sh, node);
+            } else {
+                node_body<float, CfgBig>(P, sh, node);
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -1881,7 +1904,9 @@ __global__ void __launch_bounds__(C::W) __attribute__((amdgpu_waves_per_eu(2))) 
 constexpr unsigned kFp64Grid = 2048;
 constexpr unsigned kFp64BigGrid = 512;
 constexpr int64_t kBigGrid = 2048;  // blocks of a multi-wave class launch
-constexpr int64_t kNodeGrid = 256 * 32;  // waves of the one-wave classes' launch
+// waves of a one-wave-class launch: as many as the chip holds at once (256
+// compute units, 12 blocks of 64 threads each by LDS)
+constexpr int64_t kNodeGrid = 256 * 12;
 constexpr int64_t kRedoGrid = 512;       // waves of that launch over a redo list
 constexpr int64_t kMinGrid = 32;         // blocks of a class launch sized by an estimate
 
