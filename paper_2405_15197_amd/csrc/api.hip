@@ -160,7 +160,7 @@ void carve_fixed(lm_plan *P, Carver &c, int64_t N, int64_t S)
     w.rec_top = c.take<unsigned long long>(lm::kRecRegions);
     w.queue = c.take<int32_t>(N + 1);
     w.cls_info = c.take<int64_t>(8);
-    w.work_ctr = c.take<int32_t>(4);
+    w.work_ctr = c.take<int32_t>(8);
     P->codec_ctr = c.take<unsigned long long>(1);
     w.node_k = nullptr;
 }
@@ -259,7 +259,7 @@ int run_count(lm_plan *P, int k, const lm::FillOut *out, const lm::Work &w, cons
     HIPCHK(hipMemsetAsync(w.flags + 2, 0, sizeof(int32_t), P->st));
     HIPCHK(hipMemsetAsync(w.totals, 0, sizeof(int64_t) * 16, P->st));
     HIPCHK(hipMemsetAsync(w.rec_top, 0, sizeof(unsigned long long) * lm::kRecRegions, P->st));
-    HIPCHK(hipMemsetAsync(w.work_ctr, 0, sizeof(int32_t) * 4, P->st));
+    HIPCHK(hipMemsetAsync(w.work_ctr, 0, sizeof(int32_t) * 8, P->st));
     {
         PhaseTimer t(P, PH_NODE32);
         if (redo_cnt) HIPCHK(hipMemsetAsync(redo_cnt, 0, sizeof(int32_t) * 8, P->st));
@@ -735,7 +735,7 @@ int sink_range(lm_plan *P, int k, int64_t r, int64_t n0, int64_t n1, int t16, in
     wc.queue = P->sk_lists;
     wc.cls_info = P->sk_info;
     HIPCHK(hipMemsetAsync(w.rec_top, 0, sizeof(unsigned long long) * lm::kRecRegions, P->st));
-    HIPCHK(hipMemsetAsync(w.work_ctr, 0, sizeof(int32_t) * 4, P->st));
+    HIPCHK(hipMemsetAsync(w.work_ctr, 0, sizeof(int32_t) * 8, P->st));
     so.n0 = n0;
     so.n1 = n1;
     {

@@ -140,7 +140,7 @@ struct Work {
     int32_t *fb_list;       // [N] nodes for the FP64 pass
     int32_t *queue;         // [N] node ids grouped by valence class
     int64_t *cls_info;      // [8] nodes per class (0..3), queue start per class (4..7)
-    int32_t *work_ctr;      // [4] per-class work counters of the node kernel
+    int32_t *work_ctr;      // [8] work counters: FP32 classes 0..3, FP64 passes 4 (one wave) and 5 (several)
     const int16_t *node_k;  // [N] per-node resolution (batched parts) or null
     // adjoint scratch (set before lm_loss / lm_backward run)
     double *loss_node;      // [N][3] loss terms per node

@@ -1767,11 +1767,14 @@ enum { kModeMesh = 0, kModeRetri = 1, kModeRedo = 2, kModeSink = 3 };
 // atomics are serialised there: one per item throttled the node pass (a
 // pass without the trimming, the re-subdivision, took as long as a full
 // one); a few per block do not, and the last grabs are still single items.
-// Block-uniform; every thread of the block calls it.
+// Block-uniform; every thread of the block calls it.  Blocks at or beyond
+// the item count take nothing (a short list leaves most of the grid idle
+// without an atomic each).
 constexpr int kGrabMax = 16;
 __device__ inline bool grab_items(int32_t *ctr, int64_t items, int64_t &seen, int *s_grab, int64_t &first,
                                   int64_t &end)
 {
+    if ((int64_t)blockIdx.x >= items) return false;
     if (threadIdx.x == 0) {
         int64_t g = (items - seen) / (2 * (int64_t)gridDim.x);
         g = g < 1 ? 1 : (g > kGrabMax ? kGrabMax : g);
@@ -1891,13 +1894,18 @@ template <typename C, bool SINK>
 __global__ void __launch_bounds__(C::W) __attribute__((amdgpu_waves_per_eu(2))) k_node64(Params P)
 {
     __shared__ Shared<double, C> sh;
+    __shared__ int s_grab[2];
     constexpr bool big = C::VM > kVmax;
-    const int cnt = P.w.flags[2];
-    for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
-        const int64_t node = P.w.fb_list[i];
-        const bool is_big = P.w.row[node + 1] - P.w.row[node] > kVmax;
-        if (is_big == big) node_body<double, C, SINK>(P, sh, node);
-        __syncthreads();
+    const int64_t cnt = P.w.flags[2];
+    // guided grabs over the hand-over list (its nodes differ in cost)
+    int64_t seen = 0, first, end;
+    while (grab_items(&P.w.work_ctr[big ? 5 : 4], cnt, seen, s_grab, first, end)) {
+        for (int64_t i = first; i < end; ++i) {
+            const int64_t node = P.w.fb_list[i];
+            const bool is_big = P.w.row[node + 1] - P.w.row[node] > kVmax;
+            if (is_big == big) node_body<double, C, SINK>(P, sh, node);
+            __syncthreads();
+        }
     }
 }
 
