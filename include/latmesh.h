@@ -56,7 +56,7 @@ extern "C" {
 #define LM_NODE_TOPOLOGY 8u        /* arc/vertex incidence or Euler check failed
                                       (e.g. an annular hole), or no hole-fan apex */
 #define LM_NODE_ISOLATED 16u       /* no incident strut */
-#define LM_NODE_VALENCE 32u        /* more incident struts than this library handles (48) */
+#define LM_NODE_VALENCE 32u        /* more incident struts than this library handles (64) */
 #define LM_NODE_DUPLICATE 64u      /* two struts join the same pair of nodes */
 #define LM_NODE_CAPACITY 128u      /* per-node arc / vertex / piece capacity exceeded */
 

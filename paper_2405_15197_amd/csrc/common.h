@@ -19,7 +19,7 @@ constexpr float kFp32Eps = 5.9604645e-8f;
 constexpr int kVmax = 16;       // incident struts per node, one-wave classes
 constexpr int kAcap = 64;       // arcs per node, one-wave classes
 constexpr int kVcap = 64;       // meta-vertices per node, one-wave classes
-constexpr int kVmaxBig = 48;    // incident struts per node, multi-wave class
+constexpr int kVmaxBig = 64;    // incident struts per node, multi-wave class
 constexpr int kAcapBig = 192;   // arcs per node, multi-wave class
 constexpr int kVcapBig = 128;   // meta-vertices per node, multi-wave class
 constexpr int kBigWaves = 4;    // waves per node of the multi-wave class

@@ -54,7 +54,7 @@ def test_knn_parity(name, make, k):
     assert st["stable"] >= 0.9 * int((R.status == 0).sum())
 
 
-@pytest.mark.parametrize("nstrut", [17, 24, 33, 40, 48])
+@pytest.mark.parametrize("nstrut", [17, 24, 33, 40, 48, 56, 64])
 def test_star_valence(nstrut):
     """A centre node with nstrut thin struts in quasi-random directions (a
     Fibonacci sphere, jittered): meshed by the multi-wave class, equal to
@@ -70,8 +70,8 @@ def test_star_valence(nstrut):
 
 
 def test_valence_beyond_limit_is_flagged():
-    i = np.arange(60) + 0.5
-    phi = np.arccos(1 - 2 * i / 60)
+    i = np.arange(72) + 0.5
+    phi = np.arccos(1 - 2 * i / 72)
     th = np.pi * (1 + 5 ** 0.5) * i
     d = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
     lat = latgen.star(d, radius=0.01)

@@ -248,8 +248,8 @@ def test_edge_cases():
     r = M.run(8)
     assert (r.node_status.cpu().numpy() & 1).all()
     M.close()
-    # valence beyond the build limit (48 struts)
-    d = np.random.default_rng(1).normal(size=(60, 3))
+    # valence beyond the build limit (64 struts)
+    d = np.random.default_rng(1).normal(size=(72, 3))
     lat = latgen.star(d, radius=0.005)
     M = Mesher(lat)
     r = M.run(8)
