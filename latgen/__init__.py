@@ -256,12 +256,13 @@ def _make_part(spec):
     return lat, res
 
 
-def parts(n_parts=512, seed=1, n_max=64, n_min=4, workers=1):
+def parts(n_parts=512, seed=1, n_max=64, n_min=4, workers=1, start="fork"):
     """The batched workload: ``n_parts`` lattice parts, each a cubic, BCC,
     octet or random k-NN lattice (uniform choice) with cells per side drawn
     from {n_min..n_max}, k-NN degree from {3..20}, node radii U[0.04, 0.12],
     and a resolution from {8, 16, 32}.  Returns a list of (Lattice, k).
-    ``workers`` > 1 builds the parts in that many processes (same result)."""
+    ``workers`` > 1 builds the parts in that many processes (same result),
+    started by ``start`` ("spawn" from a process that has used the GPU)."""
     specs = _part_specs(n_parts, seed, n_max, n_min)
     if workers <= 1 or n_parts < 2:
         return [_make_part(s) for s in specs]
@@ -269,7 +270,7 @@ def parts(n_parts=512, seed=1, n_max=64, n_min=4, workers=1):
 
     # largest parts first, so the pool's tail is short
     order = sorted(range(n_parts), key=lambda i: -specs[i][1])
-    with mp.get_context("fork").Pool(workers) as pool:
+    with mp.get_context(start).Pool(workers) as pool:
         made = pool.map(_make_part, [specs[i] for i in order], chunksize=1)
     out = [None] * n_parts
     for i, r in zip(order, made):

@@ -112,3 +112,30 @@ def test_autotune_picks_a_candidate():
     best, times = tune(parts, latgen.union, sample=8, repeats=1, groups=(64, 1 << 21))
     assert (best.v_four_per_wave, best.v_two_per_wave, best.group_nodes) in times
     assert all(t > 0 for t in times.values())
+
+
+def test_batched_512_parts_unmeshed_nodes_equal_oracle():
+    """The full 512-part workload in one batched pass: the nodes each part
+    leaves without a mesh (word 7) equal the oracle's count for that part,
+    stored in tests/golden/batched512_oracle_flags.json by
+    tests/golden/make_batched_flags.py from the oracle alone (k-NN nodes of
+    up to 52 struts included)."""
+    import json
+    import os
+
+    from paper_2405_15197_amd import Mesher
+
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batched512_oracle_flags.json")))
+    parts = latgen.parts(512, seed=1, workers=16, start="spawn")
+    assert [[p[0].n_nodes, int(p[1])] for p in parts] == [g[1:] for g in gold["per_part"]]
+    lat, off = latgen.union([p[0] for p in parts])
+    ks = np.array([p[1] for p in parts], np.int32)
+    del parts
+    M = Mesher(lat)
+    try:
+        got = M.batched(off, ks)
+    finally:
+        M.close()
+    want = [g[0] for g in gold["per_part"]]
+    assert [int(x) for x in got[:, 7]] == want, sum(int(x) for x in got[:, 7])
+    print(f"512 parts: {sum(want)} nodes without a mesh, as the oracle", flush=True)
