@@ -29,37 +29,34 @@ __device__ inline float3 mesh_local(const uint32_t *RV, const uint32_t *RI, cons
 // The latency of the node's loads bounds this kernel (a few KB per node): the
 // bookkeeping words are loaded together, then the first item of each output
 // per lane (one round for most nodes) before any store, so that one wait
-// covers all of them.
-__global__ void __launch_bounds__(64) k_expand(XParams P)
+// covers all of them.  Two nodes per block, one per wave (half the blocks to
+// dispatch).
+__global__ void __launch_bounds__(128) k_expand(XParams P)
 {
-    __shared__ uint4 s_arc[kAcap][2];  // words 8..15 of each arc, for the hole fans
+    __shared__ uint4 s_arc[2][kAcap][2];  // per wave: words 8..15 of each arc, for the hole fans
     const Work &W = P.w;
     const FillOut &O = P.o;
     const int64_t N = P.in.n_nodes;
-    const int64_t n = xcd_block(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x;
-    if (n >= N) return;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int64_t n = 2 * xcd_block(blockIdx.x, gridDim.x) + wv;
+    const bool live = n < N;
+    const int64_t nn = live ? n : 0;
     // the record's sizes are the node's counts: no wait for its header
     const int flags = W.flags[0];
-    const int64_t rb = W.node_rec[n];
+    const int64_t rb = W.node_rec[nn];
     const int64_t Np1 = N + 1;
-    const int64_t voff = W.node_off[NC_VERT * Np1 + n], aoff = W.node_off[NC_ARC * Np1 + n];
-    const int64_t hoff = W.node_off[NC_HOLE * Np1 + n];
-    const int64_t moff = W.node_off[NC_MESH * Np1 + n], foff = W.node_off[NC_FAN * Np1 + n];
-    const int V = (int)(W.node_off[NC_VERT * Np1 + n + 1] - voff);
-    const int E = (int)(W.node_off[NC_ARC * Np1 + n + 1] - aoff);
-    const int NC = (int)(W.node_off[NC_HOLE * Np1 + n + 1] - hoff);
-    const int M = (int)(W.node_off[NC_MESH * Np1 + n + 1] - moff);
-    const int F = (int)(W.node_off[NC_FAN * Np1 + n + 1] - foff);
-    const float4 c4 = W.node4[n];
-    // all of these are loaded before the first branch (otherwise the
-    // compiler moves loads below the exits, one wait after another)
-    asm volatile("" ::"s"(flags), "s"(rb), "s"(voff), "s"(aoff), "s"(hoff), "s"(moff), "s"(foff), "s"(V), "s"(E),
-                 "s"(NC), "s"(M), "s"(F), "s"(c4.x), "s"(c4.y), "s"(c4.z));
-    if (flags & (DF_CAPACITY | DF_BADLAT | DF_RECCAP)) return;
-    if (rb < 0) return;
+    const int64_t voff = W.node_off[NC_VERT * Np1 + nn], aoff = W.node_off[NC_ARC * Np1 + nn];
+    const int64_t hoff = W.node_off[NC_HOLE * Np1 + nn];
+    const int64_t moff = W.node_off[NC_MESH * Np1 + nn], foff = W.node_off[NC_FAN * Np1 + nn];
+    const int V = (int)(W.node_off[NC_VERT * Np1 + nn + 1] - voff);
+    const int E = (int)(W.node_off[NC_ARC * Np1 + nn + 1] - aoff);
+    const int NC = (int)(W.node_off[NC_HOLE * Np1 + nn + 1] - hoff);
+    const int M = (int)(W.node_off[NC_MESH * Np1 + nn + 1] - moff);
+    const int F = (int)(W.node_off[NC_FAN * Np1 + nn + 1] - foff);
+    const float4 c4 = W.node4[nn];
+    const bool go = live && !(flags & (DF_CAPACITY | DF_BADLAT | DF_RECCAP)) && rb >= 0;
     const int wsum = M - NC;  // hole centres come last
-    const uint32_t *R = W.rec + rb;
+    const uint32_t *R = W.rec + (go ? rb : 0);
     const uint32_t *RV = R + kRecHead;
     const uint32_t *RA = RV + 4 * V;
     const uint32_t *RH = RA + kRecArcFields * E;
@@ -91,39 +88,43 @@ __global__ void __launch_bounds__(64) k_expand(XParams P)
         O.arc_u32[2 * cA + aoff + j] = (uint32_t)n;
     };
 
-    // first round: item `lane` of every output, all loads before any store
-    float3 w0 = make_float3(0.f, 0.f, 0.f);
-    uint4 g0 = make_uint4(0, 0, 0, 0), g1 = g0, g2 = g0, g3 = g0, gv = g0;
-    if (lane < M) w0 = mesh_local(RV, RI, RH, V, wsum, lane);
-    if (want_arcs && lane < E) {
-        g0 = RA4[4 * lane];
-        g1 = RA4[4 * lane + 1];
-        g2 = RA4[4 * lane + 2];
-        g3 = RA4[4 * lane + 3];
+    uint4 g2 = make_uint4(0, 0, 0, 0), g3 = g2;
+    if (go) {
+        // first round: item `lane` of every output, all loads before any store
+        float3 w0 = make_float3(0.f, 0.f, 0.f);
+        uint4 g0 = g2, g1 = g2, gv = g2;
+        if (lane < M) w0 = mesh_local(RV, RI, RH, V, wsum, lane);
+        if (want_arcs && lane < E) {
+            g0 = RA4[4 * lane];
+            g1 = RA4[4 * lane + 1];
+            g2 = RA4[4 * lane + 2];
+            g3 = RA4[4 * lane + 3];
+        }
+        if (O.vert_name && lane < V) gv = ((const uint4 *)RV)[lane];
+        if (lane < M) put_mesh(lane, w0);
+        if (O.arc_f32 && lane < E) put_arc(lane, g0, g1, g2, g3);
+        if (O.vert_name && lane < V) put_vert(lane, gv);
+        // further rounds (nodes with more than 64 of an item)
+        for (int i = lane + 64; i < M; i += 64) put_mesh(i, mesh_local(RV, RI, RH, V, wsum, i));
+        if (O.arc_f32)
+            for (int j = lane + 64; j < E; j += 64) put_arc(j, RA4[4 * j], RA4[4 * j + 1], RA4[4 * j + 2], RA4[4 * j + 3]);
+        if (O.vert_name)
+            for (int i = lane + 64; i < V; i += 64) put_vert(i, ((const uint4 *)RV)[i]);
     }
-    if (O.vert_name && lane < V) gv = ((const uint4 *)RV)[lane];
-    if (lane < M) put_mesh(lane, w0);
-    if (O.arc_f32 && lane < E) put_arc(lane, g0, g1, g2, g3);
-    if (O.vert_name && lane < V) put_vert(lane, gv);
-    // further rounds (nodes with more than 64 of an item)
-    for (int i = lane + 64; i < M; i += 64) put_mesh(i, mesh_local(RV, RI, RH, V, wsum, i));
-    if (O.arc_f32)
-        for (int j = lane + 64; j < E; j += 64) put_arc(j, RA4[4 * j], RA4[4 * j + 1], RA4[4 * j + 2], RA4[4 * j + 3]);
-    if (O.vert_name)
-        for (int i = lane + 64; i < V; i += 64) put_vert(i, ((const uint4 *)RV)[i]);
-    if (F == 0) return;
-
     // hole fans: one triangle per circular-arc segment, apex at the contour's
-    // hole centre, oriented outward.  Words 8..15 of the arcs go to LDS (the
-    // arcs of a multi-wave-class node, more than kAcap, stay in the record).
+    // hole centre, oriented outward.  Words 8..15 of the arcs go to the wave's
+    // LDS (the arcs of a multi-wave-class node, more than kAcap, stay in the
+    // record).  Both waves of the block reach the barrier.
+    const bool fans = go && F > 0;
     const bool staged = E <= kAcap;
-    if (staged && lane < E) {
-        s_arc[lane][0] = g2;
-        s_arc[lane][1] = g3;
+    if (fans && staged && lane < E) {
+        s_arc[wv][lane][0] = g2;
+        s_arc[wv][lane][1] = g3;
     }
     __syncthreads();
+    if (!fans) return;
     auto aw = [&](int j, int f) -> uint32_t {  // word f (8..15) of arc j
-        return staged ? ((const uint32_t *)s_arc[j])[f - 8] : RA[kRecArcFields * j + f];
+        return staged ? ((const uint32_t *)s_arc[wv][j])[f - 8] : RA[kRecArcFields * j + f];
     };
     const int64_t fan0 = W.band_off[P.in.n_struts] + foff;
     for (int i = lane; i < F; i += 64) {
@@ -163,7 +164,7 @@ hipError_t launch_expand(const Inputs &in, const Work &w, const FillOut &o, hipS
     P.in = in;
     P.w = w;
     P.o = o;
-    k_expand<<<(unsigned)in.n_nodes, 64, 0, st>>>(P);
+    k_expand<<<(unsigned)((in.n_nodes + 1) / 2), 128, 0, st>>>(P);
     return hipGetLastError();
 }
 
