@@ -20,12 +20,6 @@ namespace {
 constexpr int kSlots = kSinkSlots;
 constexpr int kWords = kSinkWords;
 
-__device__ inline uint64_t wave_sum_u64(uint64_t x)
-{
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-
 // Wave-aggregated append of `value` to list `k` (when active): one atomic
 // per list and wave.  All lanes of the wave must call it.
 __device__ inline void append(bool active, int k, int32_t value, int32_t *lists, int64_t cap, int32_t *cnt)
@@ -42,20 +36,69 @@ __device__ inline void append(bool active, int k, int32_t value, int32_t *lists,
     }
 }
 
-// Chunk node list in valence classes: the range, then the halo (marked
-// with the chunk's epoch so that each halo node is listed once).
-__global__ void __launch_bounds__(256) k_chunk_list(int64_t n0, int64_t n1, const int64_t *row, const int2 *he,
-                                                    int32_t *mark, int32_t epoch, int32_t *lists, int64_t cap,
-                                                    int32_t *cnt, int t16, int t32)
+// The list builders run in blocks of kListBlock threads (four waves).
+constexpr int kListBlock = 256;
+constexpr int kListWaves = kListBlock / 64;
+
+// Inclusive sum over the wave (lanes below first).
+template <typename T>
+__device__ inline T wave_incl_sum(T x)
 {
-    const int64_t n = n0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    for (int d = 1; d < 64; d <<= 1) {
+        const T y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Exclusive sum of x over the block and the block's total: the waves' own
+// sums meet in LDS.  All threads of the block call it.
+template <typename T>
+__device__ inline T block_excl_sum(T x, T &total)
+{
+    __shared__ T s_w[kListWaves];
+    const int wv = threadIdx.x >> 6;
+    const T inc = wave_incl_sum(x);
+    if ((threadIdx.x & 63) == 63) s_w[wv] = inc;
+    __syncthreads();
+    T pre = 0, tot = 0;
+    for (int w = 0; w < kListWaves; ++w) {
+        const T t = s_w[w];
+        if (w < wv) pre += t;
+        tot += t;
+    }
+    total = tot;
+    return pre + inc - x;
+}
+
+// Chunk node list in valence classes: the range (entries reserved per block,
+// one atomic per class and block; a thread's class is a 16-bit field of a
+// packed count), then the halo (marked with the chunk's epoch so that each
+// halo node is listed once; few nodes, appended per wave).
+__global__ void __launch_bounds__(kListBlock) k_chunk_list(int64_t n0, int64_t n1, const int64_t *row, const int2 *he,
+                                                           int32_t *mark, int32_t epoch, int32_t *lists, int64_t cap,
+                                                           int32_t *cnt, int t16, int t32)
+{
+    static_assert(kClasses * 16 <= 64 && kListBlock < 65536, "class counts are 16-bit fields of one word");
+    __shared__ int32_t s_base[kClasses];
+    const int64_t n = n0 + (int64_t)blockIdx.x * kListBlock + threadIdx.x;
     const bool in = n < n1;
     int64_t r0 = 0, r1 = 0;
     if (in) {
         r0 = row[n];
         r1 = row[n + 1];
     }
-    append(in, valence_class(r1 - r0, t16, t32), (int32_t)n, lists, cap, cnt);
+    const int cls = in ? valence_class(r1 - r0, t16, t32) : 0;
+    const uint64_t one = in ? 1ull << (16 * cls) : 0ull;
+    uint64_t tot;
+    const uint64_t ex = block_excl_sum(one, tot);
+    if (threadIdx.x < kClasses) {
+        const int c = (int)((tot >> (16 * threadIdx.x)) & 0xffff);
+        s_base[threadIdx.x] = c ? atomicAdd(&cnt[threadIdx.x], c) : 0;
+    }
+    __syncthreads();
+    if (in) lists[cls * cap + s_base[cls] + (int64_t)((ex >> (16 * cls)) & 0xffff)] = (int32_t)n;
     int deg = (int)(r1 - r0);
     int maxdeg = deg;
     for (int o = 32; o > 0; o >>= 1) maxdeg = max(maxdeg, __shfl_xor(maxdeg, o, 64));
@@ -82,31 +125,41 @@ __global__ void k_chunk_info(const int32_t *cnt, int64_t cap, int64_t *info)
     }
 }
 
-// Struts whose lower end is in the range and whose ends both have a mesh.
-__global__ void __launch_bounds__(256) k_chunk_struts(int64_t n0, int64_t n1, const int64_t *row, const int2 *he,
-                                                      const int64_t *node_rec, int32_t *list, int32_t *cnt)
+// Struts whose lower end is in the range and whose ends both have a mesh:
+// each thread counts its node's, the block reserves its entries with one
+// atomic, and the thread writes them (the first 64 half-edges' verdicts are
+// kept as a mask, later ones tested again).
+__global__ void __launch_bounds__(kListBlock) k_chunk_struts(int64_t n0, int64_t n1, const int64_t *row,
+                                                             const int2 *he, const int64_t *node_rec, int32_t *list,
+                                                             int32_t *cnt)
 {
-    const int64_t n = n0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = n < n1;
+    __shared__ int32_t s_base;
+    const int64_t n = n0 + (int64_t)blockIdx.x * kListBlock + threadIdx.x;
     int64_t r0 = 0, r1 = 0;
-    bool ok = false;
-    if (in) {
+    if (n < n1 && node_rec[n] >= 0) {
         r0 = row[n];
         r1 = row[n + 1];
-        ok = node_rec[n] >= 0;
     }
-    int deg = (int)(r1 - r0);
-    int maxdeg = deg;
-    for (int o = 32; o > 0; o >>= 1) maxdeg = max(maxdeg, __shfl_xor(maxdeg, o, 64));
-    for (int i = 0; i < maxdeg; ++i) {
-        bool add = false;
-        int32_t s = 0;
-        if (i < deg && ok) {
-            const int2 h = he[r0 + i];
-            add = (int64_t)h.x > n && node_rec[h.x] >= 0;
-            s = h.y;
+    auto owned = [&](const int2 h) { return (int64_t)h.x > n && node_rec[h.x] >= 0; };
+    int c = 0;
+    uint64_t m = 0;
+    for (int64_t r = r0; r < r1; ++r)
+        if (owned(he[r])) {
+            ++c;
+            if (r - r0 < 64) m |= 1ull << (r - r0);
         }
-        append(add, 0, s, list, 0, cnt);
+    int tot;
+    int32_t at = block_excl_sum(c, tot);
+    if (threadIdx.x == 0) s_base = tot ? atomicAdd(cnt, tot) : 0;
+    __syncthreads();
+    at += s_base;
+    while (m) {
+        list[at++] = he[r0 + __builtin_ctzll(m)].y;
+        m &= m - 1;
+    }
+    for (int64_t r = r0 + 64; r < r1; ++r) {
+        const int2 h = he[r];
+        if (owned(h)) list[at++] = h.y;
     }
 }
 
@@ -324,8 +377,8 @@ hipError_t launch_chunk_list(const Work &w, int64_t n0, int64_t n1, int32_t *mar
                              int64_t cap, int32_t *cnt, int64_t *info, int t16, int t32, hipStream_t st)
 {
     if (n1 > n0)
-        k_chunk_list<<<grid_for(n1 - n0, 256), 256, 0, st>>>(n0, n1, w.row, w.he, mark, epoch, lists, cap, cnt, t16,
-                                                             t32);
+        k_chunk_list<<<grid_for(n1 - n0, kListBlock), kListBlock, 0, st>>>(n0, n1, w.row, w.he, mark, epoch, lists,
+                                                                           cap, cnt, t16, t32);
     k_chunk_info<<<1, 64, 0, st>>>(cnt, cap, info);
     return hipGetLastError();
 }
@@ -334,8 +387,8 @@ hipError_t launch_sink_bands(const Inputs &in, const Work &w, int64_t n0, int64_
                              int32_t *strut_cnt, const SinkOut &so, hipStream_t st)
 {
     if (n1 > n0) {
-        k_chunk_struts<<<grid_for(n1 - n0, 256), 256, 0, st>>>(n0, n1, w.row, w.he, w.node_rec, strut_list,
-                                                                 strut_cnt);
+        k_chunk_struts<<<grid_for(n1 - n0, kListBlock), kListBlock, 0, st>>>(n0, n1, w.row, w.he, w.node_rec,
+                                                                             strut_list, strut_cnt);
         // a fixed grid of waves (enough to fill the chip) walks the strut
         // list; no more groups than the lattice has struts
         auto grid = [&](int g) {
