@@ -53,7 +53,8 @@ __device__ inline T wave_incl_sum(T x)
 }
 
 // Exclusive sum of x over the block and the block's total: the waves' own
-// sums meet in LDS.  All threads of the block call it.
+// sums meet in LDS.  All threads of the block call it, once per kernel (a
+// second call could overwrite the wave sums before every wave has read them).
 template <typename T>
 __device__ inline T block_excl_sum(T x, T &total)
 {
