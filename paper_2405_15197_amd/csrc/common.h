@@ -23,6 +23,12 @@ constexpr int kVmaxBig = 64;    // incident struts per node, multi-wave class
 constexpr int kAcapBig = 192;   // arcs per node, multi-wave class
 constexpr int kVcapBig = 128;   // meta-vertices per node, multi-wave class
 constexpr int kBigWaves = 4;    // waves per node of the multi-wave class
+// The FP64 pass splits the multi-wave class: nodes of kVmax + 1 .. kVmaxMid
+// struts run on two waves with capacities for that many (a node that does
+// not fit them goes on to the four-wave kernel), larger ones on four.
+constexpr int kVmaxMid = 32;
+constexpr int kAcapMid = 96;
+constexpr int kVcapMid = 64;
 constexpr int kPieces = 4;      // kept arcs per conic
 
 constexpr float kTwoPi = 6.28318530717958647692f;
@@ -140,7 +146,7 @@ struct Work {
     int32_t *fb_list;       // [N] nodes for the FP64 pass
     int32_t *queue;         // [N] node ids grouped by valence class
     int64_t *cls_info;      // [8] nodes per class (0..3), queue start per class (4..7)
-    int32_t *work_ctr;      // [8] work counters: FP32 classes 0..3, FP64 passes 4 (one wave) and 5 (several)
+    int32_t *work_ctr;      // [8] work counters: FP32 classes 0..3, FP64 passes 4 (one wave), 5 (four waves) and 6 (two waves)
     const int16_t *node_k;  // [N] per-node resolution (batched parts) or null
     // adjoint scratch (set before lm_loss / lm_backward run)
     double *loss_node;      // [N][3] loss terms per node

@@ -72,6 +72,8 @@ using CfgV16 = Cfg<kVmax, kAcap, kVcap, 64>;
 // all its waves over the node's conics and samples, the node's data in the
 // block's LDS (the paper's several warps per heavy workload, Sec. 4.3.3)
 using CfgBig = Cfg<kVmaxBig, kAcapBig, kVcapBig, 64 * kBigWaves>;
+// FP64 pass only: v = kVmax + 1 .. kVmaxMid on two waves
+using CfgMid = Cfg<kVmaxMid, kAcapMid, kVcapMid, 128>;
 
 template <typename T, typename C>
 struct Shared {
@@ -1088,8 +1090,12 @@ finish:
                 // hand the node to the FP64 pass when precision may be at fault
                 const bool retry = F32 && (status & kRetry);
                 if (retry) W.fb_list[atomicAdd(&W.flags[2], 1)] = (int32_t)n;
+                // FP64, two-wave class: a node beyond its capacities goes on
+                // to the four-wave kernel (the caller marks its list entry)
+                constexpr bool kHandOn = !F32 && CF::VM > kVmax && CF::VM < kVmaxBig;
+                const bool handed = kHandOn && (status & NS_CAPACITY);
                 // sink mode: a node of the range left without a mesh
-                if (SINK && !retry && n >= P.sink.n0 && n < P.sink.n1)
+                if (SINK && !retry && !handed && n >= P.sink.n0 && n < P.sink.n1)
                     sink_add(P.sink, P.sink.node_part ? P.sink.node_part[n] : 0, 7, 1);
             }
             over_lanes<WL, CF::VM>(lane, 0, v - 1, [&](int l) { W.he_len[row + l] = 0; });
@@ -1895,21 +1901,35 @@ __global__ void __launch_bounds__(C::W) __attribute__((amdgpu_waves_per_eu(2))) 
 {
     __shared__ Shared<double, C> sh;
     __shared__ int s_grab[2];
-    constexpr bool big = C::VM > kVmax;
+    // the kernel's class: 0 one wave (v <= kVmax), 1 two waves (v <= kVmaxMid),
+    // 2 four waves; the launches run in that order
+    constexpr int cls = C::VM <= kVmax ? 0 : (C::VM <= kVmaxMid ? 1 : 2);
+    constexpr int ctr = cls == 0 ? 4 : (cls == 1 ? 6 : 5);
     const int64_t cnt = P.w.flags[2];
     // guided grabs over the hand-over list (its nodes differ in cost)
     int64_t seen = 0, first, end;
-    while (grab_items(&P.w.work_ctr[big ? 5 : 4], cnt, seen, s_grab, first, end)) {
+    while (grab_items(&P.w.work_ctr[ctr], cnt, seen, s_grab, first, end)) {
         for (int64_t i = first; i < end; ++i) {
-            const int64_t node = P.w.fb_list[i];
-            const bool is_big = P.w.row[node + 1] - P.w.row[node] > kVmax;
-            if (is_big == big) node_body<double, C, SINK>(P, sh, node);
+            // an entry the two-wave kernel could not hold is stored negated
+            // (~node): the four-wave kernel takes it whatever its valence
+            const int32_t e = P.w.fb_list[i];
+            const int64_t node = e < 0 ? ~e : e;
+            const int64_t v = P.w.row[node + 1] - P.w.row[node];
+            const int ncls = e < 0 ? 2 : (v <= kVmax ? 0 : (v <= kVmaxMid ? 1 : 2));
+            if (ncls == cls) {
+                node_body<double, C, SINK>(P, sh, node);
+                if constexpr (cls == 1) {
+                    __syncthreads();
+                    if (threadIdx.x == 0 && (sh.status & NS_CAPACITY)) P.w.fb_list[i] = ~(int32_t)node;
+                }
+            }
             __syncthreads();
         }
     }
 }
 
 constexpr unsigned kFp64Grid = 2048;
+constexpr unsigned kFp64MidGrid = 1024;
 constexpr unsigned kFp64BigGrid = 512;
 constexpr int64_t kBigGrid = 2048;  // blocks of a multi-wave class launch
 // waves of a one-wave-class launch: as many as the chip holds at once (256
@@ -1964,9 +1984,11 @@ hipError_t launch_node(const Inputs &in, const Work &w, int k, float kappa_max, 
     if (fp64) {
         if (sink) {
             k_node64<CfgV16, true><<<kFp64Grid, 64, 0, st>>>(P);
+            k_node64<CfgMid, true><<<kFp64MidGrid, CfgMid::W, 0, st>>>(P);
             k_node64<CfgBig, true><<<kFp64BigGrid, CfgBig::W, 0, st>>>(P);
         } else {
             k_node64<CfgV16, false><<<kFp64Grid, 64, 0, st>>>(P);
+            k_node64<CfgMid, false><<<kFp64MidGrid, CfgMid::W, 0, st>>>(P);
             k_node64<CfgBig, false><<<kFp64BigGrid, CfgBig::W, 0, st>>>(P);
         }
         return hipGetLastError();
