@@ -31,12 +31,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # by the kernel's sources and build flags they were taken on; a changed
 # kernel reports null.
 MEASURED_TRAFFIC = {
-    "816a09c33f5d4aca": {"bytes": 2_342_665_168, "summary": "profiles/k_node32_bcc64_k16_hbm_counters.md"},
+    "7722bb1d9b107fad": {"bytes": 2_354_991_016, "summary": "profiles/k_node32_bcc64_k16_hbm_counters.md"},
 }
 # wave64 VALU instructions per node pass (SQ_INSTS_VALU summed over its
 # launches) from the same counter runs, keyed the same way
 MEASURED_VALU = {
-    "816a09c33f5d4aca": {"insts": 1_353_821_698, "summary": "profiles/k_node32_bcc64_k16_hbm_counters.md"},
+    "7722bb1d9b107fad": {"insts": 1_353_826_481, "summary": "profiles/k_node32_bcc64_k16_hbm_counters.md"},
 }
 # VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per
 # SIMD every 4 cycles (16 lanes wide; packed FP32 is not used)
