@@ -69,6 +69,21 @@ def test_star_valence(nstrut):
     assert st["stable"] == lat.n_nodes
 
 
+@pytest.mark.parametrize("nstrut", [20, 32, 33, 48])
+def test_star_valence_all_fp64(nstrut):
+    """kappa_max = 0: the star's node meshed by the FP64 pass, on two waves
+    up to 32 struts and on four above; equal to the oracle."""
+    i = np.arange(nstrut) + 0.5
+    phi = np.arccos(1 - 2 * i / nstrut)
+    th = np.pi * (1 + 5 ** 0.5) * i + 0.1 * np.sin(7 * i)
+    d = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
+    lat = latgen.star(d, radius=0.05)
+    st = compare(lat, 12, tau=1e-8, geom_tol=1e-6, kappa_max=0.0)
+    _line(f"star {nstrut}, FP64: {st}")
+    assert st["fp64_nodes"] == lat.n_nodes
+    assert st["stable"] == lat.n_nodes
+
+
 def test_valence_beyond_limit_is_flagged():
     i = np.arange(72) + 0.5
     phi = np.arccos(1 - 2 * i / 72)
