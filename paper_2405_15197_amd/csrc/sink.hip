@@ -399,6 +399,8 @@ hipError_t launch_sink_bands(const Inputs &in, const Work &w, int64_t n0, int64_
         // a band has about 2 (k + 4) samples
         if (k_max <= 24)
             k_sink_zip<8><<<grid(8), 64, 0, st>>>(w, so, strut_list, strut_cnt, in.sa, in.sb);
+        else if (k_max <= 32)
+            k_sink_zip<6><<<grid(6), 64, 0, st>>>(w, so, strut_list, strut_cnt, in.sa, in.sb);
         else if (k_max <= 56)
             k_sink_zip<4><<<grid(4), 64, 0, st>>>(w, so, strut_list, strut_cnt, in.sa, in.sb);
         else

@@ -261,6 +261,7 @@ hipError_t launch_zip(const Inputs &in, const Work &w, const FillOut &o, int k, 
                                                               w.he_rot, loop, in.sa, in.sb, mo, o.tri, w.flags);
     };
     if (k <= 24) go(std::integral_constant<int, 8>{});
+    else if (k <= 32) go(std::integral_constant<int, 6>{});
     else if (k <= 56) go(std::integral_constant<int, 4>{});
     else go(std::integral_constant<int, 2>{});
     return hipGetLastError();
